@@ -1,0 +1,262 @@
+"""FP64 CPU oracle of the SOAP hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It wraps ``soap_oracle.c`` (plain C, double precision,
+written from the paper's definitions; see the header of that file) through
+ctypes and shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "soap_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libsoap_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP over centres, generic x86-64)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        d, i, i64, u8 = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_uint8
+        P = ctypes.POINTER
+        L.orc_fcut.restype = d
+        L.orc_fcut.argtypes = [d, d, d, P(d)]
+        L.orc_gto_constants.argtypes = [i, d, P(d), P(d), P(d)]
+        L.orc_overlap.argtypes = [i, d, P(d)]
+        L.orc_inverse_sqrt.restype = i
+        L.orc_inverse_sqrt.argtypes = [i, P(d), P(d)]
+        L.orc_hyp1f1.restype = d
+        L.orc_hyp1f1.argtypes = [d, d, d]
+        L.orc_radial_integral.argtypes = [i, i, d, d, d, P(d), P(d)]
+        L.orc_orth_matrix.restype = i
+        L.orc_orth_matrix.argtypes = [i, d, P(d)]
+        L.orc_radial_integral_orth.restype = i
+        L.orc_radial_integral_orth.argtypes = [i, i, d, d, d, P(d), P(d)]
+        L.orc_ylm.argtypes = [i, P(d), P(d), P(d)]
+        L.orc_neighbors.restype = i
+        L.orc_neighbors.argtypes = [i, P(i64), P(d), P(d), P(u8), P(ctypes.c_int32), d, P(i64),
+                                    P(ctypes.c_int32), P(ctypes.c_int32), P(d)]
+        hy = [i, i, i, i, d, d, d]
+        L.orc_expansion.restype = i
+        L.orc_expansion.argtypes = hy + [P(ctypes.c_int32), P(i64), P(ctypes.c_int32), P(d), i64, P(i64), P(d)]
+        L.orc_power_spectrum.argtypes = [i, i, i, i64, P(d), P(d)]
+        L.orc_gradients.restype = i
+        L.orc_gradients.argtypes = hy + [P(ctypes.c_int32), P(i64), P(ctypes.c_int32), P(d), i64, P(i64),
+                                         P(d), P(d), P(d), P(d)]
+        L.orc_vjp.restype = i
+        L.orc_vjp.argtypes = hy + [i64, P(ctypes.c_int32), P(i64), P(ctypes.c_int32), P(d), P(d), P(d), P(d)]
+        _lib = L
+    return _lib
+
+
+def _p(a, ct=ctypes.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _hy(h):
+    return (int(h["n_species"]), int(h["nmax"]), int(h["lmax"]), int(h.get("include_center", 1)),
+            float(h["rcut"]), float(h.get("cutoff_width", 0.5)), float(h["sigma"]))
+
+
+# ---------------------------------------------------------------- elements
+def fcut(r, rcut, width):
+    df = ctypes.c_double()
+    f = lib().orc_fcut(float(r), float(rcut), float(width), ctypes.byref(df))
+    return f, df.value
+
+
+def gto_constants(nmax, rcut):
+    s, d, n = np.zeros(nmax), np.zeros(nmax), np.zeros(nmax)
+    lib().orc_gto_constants(nmax, rcut, _p(s), _p(d), _p(n))
+    return s, d, n
+
+
+def overlap(nmax, rcut):
+    S = np.zeros((nmax, nmax))
+    lib().orc_overlap(nmax, rcut, _p(S))
+    return S
+
+
+def inverse_sqrt(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    X = np.zeros_like(A)
+    st = lib().orc_inverse_sqrt(A.shape[0], _p(A), _p(X))
+    if st:
+        raise ValueError("matrix not positive definite")
+    return X
+
+
+def orth_matrix(nmax, rcut):
+    X = np.zeros((nmax, nmax))
+    if lib().orc_orth_matrix(nmax, rcut, _p(X)):
+        raise ValueError("overlap not positive definite")
+    return X
+
+
+def hyp1f1(a, b, z):
+    return lib().orc_hyp1f1(float(a), float(b), float(z))
+
+
+def radial_integral(nmax, lmax, rcut, sigma, r, deriv=False):
+    I = np.zeros((nmax, lmax + 1))
+    dI = np.zeros((nmax, lmax + 1)) if deriv else None
+    lib().orc_radial_integral(nmax, lmax, rcut, sigma, float(r), _p(I), _p(dI))
+    return (I, dI) if deriv else I
+
+
+def radial_integral_orth(nmax, lmax, rcut, sigma, r, deriv=False):
+    I = np.zeros((nmax, lmax + 1))
+    dI = np.zeros((nmax, lmax + 1)) if deriv else None
+    lib().orc_radial_integral_orth(nmax, lmax, rcut, sigma, float(r), _p(I), _p(dI))
+    return (I, dI) if deriv else I
+
+
+def ylm(lmax, v, deriv=False):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    L2 = (lmax + 1) ** 2
+    Y = np.zeros(L2)
+    dY = np.zeros((3, L2)) if deriv else None
+    lib().orc_ylm(lmax, _p(v), _p(Y), _p(dY))
+    return (Y, dY) if deriv else Y
+
+
+# ---------------------------------------------------------------- pipeline
+class Neighbors:
+    def __init__(self, pair_offsets, pair_j, pair_shift, pair_vec):
+        self.pair_offsets, self.pair_j, self.pair_shift, self.pair_vec = pair_offsets, pair_j, pair_shift, pair_vec
+
+    @property
+    def n_pairs(self):
+        return int(self.pair_offsets[-1])
+
+
+def neighbors(batch, rcut=None):
+    rcut = float(batch.hypers["rcut"] if rcut is None else rcut)
+    N = batch.n_atoms
+    offs = np.zeros(N + 1, dtype=np.int64)
+    pos = np.ascontiguousarray(batch.positions, dtype=np.float64)
+    cells = np.ascontiguousarray(batch.cells, dtype=np.float64)
+    pbc = np.ascontiguousarray(batch.pbc, dtype=np.uint8)
+    spc = np.ascontiguousarray(batch.species, dtype=np.int32)
+    ao = np.ascontiguousarray(batch.atom_offsets, dtype=np.int64)
+    L = lib()
+    args = (batch.n_structures, _p(ao, ctypes.c_int64), _p(pos), _p(cells), _p(pbc, ctypes.c_uint8),
+            _p(spc, ctypes.c_int32), rcut)
+    st = L.orc_neighbors(*args, _p(offs, ctypes.c_int64), None, None, None)
+    if st:
+        raise ValueError(f"oracle neighbours failed ({st})")
+    P = int(offs[-1])
+    pj = np.zeros(max(P, 1), dtype=np.int32)
+    ps = np.zeros((max(P, 1), 3), dtype=np.int32)
+    pv = np.zeros((max(P, 1), 3))
+    st = L.orc_neighbors(*args, _p(offs, ctypes.c_int64), _p(pj, ctypes.c_int32), _p(ps, ctypes.c_int32), _p(pv))
+    if st:
+        raise ValueError(f"oracle neighbours failed ({st})")
+    return Neighbors(offs, pj[:P], ps[:P], pv[:P])
+
+
+def _centres(nl, centres):
+    N = nl.pair_offsets.shape[0] - 1
+    if centres is None:
+        centres = np.arange(N, dtype=np.int64)
+    return np.ascontiguousarray(centres, dtype=np.int64)
+
+
+def expansion(hypers, species, nl, centres=None):
+    S, nmax, lmax = int(hypers["n_species"]), int(hypers["nmax"]), int(hypers["lmax"])
+    cen = _centres(nl, centres)
+    c = np.zeros((cen.shape[0], S, nmax, (lmax + 1) ** 2))
+    spc = np.ascontiguousarray(species, dtype=np.int32)
+    pv = np.ascontiguousarray(nl.pair_vec, dtype=np.float64).reshape(-1, 3)
+    if pv.shape[0] == 0:
+        pv = np.zeros((1, 3))
+    pj = nl.pair_j if nl.pair_j.shape[0] else np.zeros(1, dtype=np.int32)
+    st = lib().orc_expansion(*_hy(hypers), _p(spc, ctypes.c_int32), _p(nl.pair_offsets, ctypes.c_int64),
+                             _p(np.ascontiguousarray(pj), ctypes.c_int32), _p(pv), cen.shape[0],
+                             _p(cen, ctypes.c_int64), _p(c))
+    if st:
+        raise ValueError("oracle expansion failed")
+    return c
+
+
+def power_spectrum(hypers, coeffs):
+    S, nmax, lmax = int(hypers["n_species"]), int(hypers["nmax"]), int(hypers["lmax"])
+    K = S * nmax
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    n = c.shape[0]
+    p = np.zeros((n, lmax + 1, K * (K + 1) // 2))
+    lib().orc_power_spectrum(S, nmax, lmax, n, _p(c), _p(p))
+    return p
+
+
+def gradients(hypers, species, nl, centres=None):
+    """Forward-mode gradient rows for the listed centres.  Returns
+    (dc [rows,3,nmax,L2], dc_self [n,3,S,nmax,L2], dp [rows,3,lmax+1,KK],
+    dp_self [n,3,lmax+1,KK]) with the pair rows of the centres concatenated
+    in their pair order."""
+    S, nmax, lmax = int(hypers["n_species"]), int(hypers["nmax"]), int(hypers["lmax"])
+    K, L2 = S * nmax, (lmax + 1) ** 2
+    KK = K * (K + 1) // 2
+    cen = _centres(nl, centres)
+    rows = int(sum(nl.pair_offsets[c + 1] - nl.pair_offsets[c] for c in cen))
+    dc = np.zeros((max(rows, 1), 3, nmax, L2))
+    dcs = np.zeros((cen.shape[0], 3, S, nmax, L2))
+    dp = np.zeros((max(rows, 1), 3, lmax + 1, KK))
+    dps = np.zeros((cen.shape[0], 3, lmax + 1, KK))
+    spc = np.ascontiguousarray(species, dtype=np.int32)
+    pv = np.ascontiguousarray(nl.pair_vec, dtype=np.float64).reshape(-1, 3)
+    if pv.shape[0] == 0:
+        pv = np.zeros((1, 3))
+    pj = nl.pair_j if nl.pair_j.shape[0] else np.zeros(1, dtype=np.int32)
+    st = lib().orc_gradients(*_hy(hypers), _p(spc, ctypes.c_int32), _p(nl.pair_offsets, ctypes.c_int64),
+                             _p(np.ascontiguousarray(pj), ctypes.c_int32), _p(pv), cen.shape[0],
+                             _p(cen, ctypes.c_int64), _p(dc), _p(dcs), _p(dp), _p(dps))
+    if st:
+        raise ValueError("oracle gradients failed")
+    return dc[:rows], dcs, dp[:rows], dps
+
+
+def vjp(hypers, species, nl, grad_p):
+    """dL/dr [N,3] and dL/dr_ji [P,3] for L = sum_i <grad_p_i, p_i>."""
+    N = nl.pair_offsets.shape[0] - 1
+    P = nl.n_pairs
+    g = np.ascontiguousarray(grad_p, dtype=np.float64)
+    out = np.zeros((N, 3))
+    gp = np.zeros((max(P, 1), 3))
+    spc = np.ascontiguousarray(species, dtype=np.int32)
+    pv = np.ascontiguousarray(nl.pair_vec, dtype=np.float64).reshape(-1, 3)
+    if pv.shape[0] == 0:
+        pv = np.zeros((1, 3))
+    pj = nl.pair_j if nl.pair_j.shape[0] else np.zeros(1, dtype=np.int32)
+    st = lib().orc_vjp(*_hy(hypers), N, _p(spc, ctypes.c_int32), _p(nl.pair_offsets, ctypes.c_int64),
+                       _p(np.ascontiguousarray(pj), ctypes.c_int32), _p(pv), _p(g), _p(out), _p(gp))
+    if st:
+        raise ValueError("oracle vjp failed")
+    return out, gp[:P]
+
+
+def features(batch, centres=None):
+    """Neighbours, coefficients and power spectrum of a batch (FP64)."""
+    nl = neighbors(batch)
+    c = expansion(batch.hypers, batch.species, nl, centres)
+    return nl, c, power_spectrum(batch.hypers, c)

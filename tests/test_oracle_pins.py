@@ -1,0 +1,581 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test ties one function of the oracle to something the paper or the
+mathematics fixes: arbitrary-precision 1F1 (mpmath), terminating Kummer
+forms, numerical quadrature of the integral definitions, scipy's complex
+spherical harmonics, the addition theorem, a Y_lm-free pair-sum form of the
+power spectrum, symmetry invariances, finite differences and brute-force
+lattice sums.  A dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle
+import synthetic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------- 1F1
+@pytest.mark.parametrize("n", [0, 1, 3, 7, 11])
+@pytest.mark.parametrize("l", [0, 1, 4, 8, 12])
+def test_hyp1f1_matches_mpmath(n, l):
+    """App. A: the series must reproduce 1F1 for the (a, b) the radial
+    integral uses, a = (n+l+3)/2, b = l+3/2, over the z range of the
+    workloads (z_max = c^2 rcut^2 / (c + d_n) < 80)."""
+    a, b = 0.5 * (n + l + 3), l + 1.5
+    for z in [0.0, 1e-3, 0.7, 5.0, 23.0, 48.0, 79.0]:
+        ref = float(mpmath.hyp1f1(mpmath.mpf(a), mpmath.mpf(b), mpmath.mpf(z)))
+        assert abs(oracle.hyp1f1(a, b, z) - ref) <= 1e-13 * abs(ref)
+
+
+@pytest.mark.parametrize("n,l", [(2, 0), (4, 0), (3, 1), (5, 1), (6, 2), (11, 3), (8, 6)])
+def test_hyp1f1_terminating_kummer(n, l):
+    """Kummer's transformation 1F1(a;b;z) = e^z 1F1(b-a;b;-z) terminates when
+    b - a = (l - n)/2 is a non-positive integer (n - l even)."""
+    a, b = 0.5 * (n + l + 3), l + 1.5
+    k = (n - l) // 2
+    for z in [0.3, 4.0, 17.0, 60.0]:
+        s, term = 0.0, 1.0
+        for j in range(k + 1):
+            if j:
+                term *= (b - a + j - 1) * (-z) / ((b + j - 1) * j)
+            s += term
+        ref = math.exp(z) * s
+        assert abs(oracle.hyp1f1(a, b, z) - ref) <= 1e-12 * abs(ref)
+
+
+def test_hyp1f1_special_values():
+    assert oracle.hyp1f1(2.5, 3.5, 0.0) == 1.0
+    for z in [0.1, 3.0, 40.0]:
+        assert abs(oracle.hyp1f1(4.5, 4.5, z) - math.exp(z)) <= 1e-14 * math.exp(z)
+
+
+# -------------------------------------------------------------- GTO basis
+def _gto(n, x, sig, d, nn):
+    return nn[n] * x ** n * np.exp(-d[n] * x * x)
+
+
+@pytest.mark.parametrize("nmax,rcut", [(6, 4.0), (8, 5.0), (10, 6.0), (12, 5.0)])
+def test_gto_normalised_and_overlap_by_quadrature(nmax, rcut):
+    """Sec. 4.B Eq. (GTO): N_n normalises R_n; the analytic overlap equals
+    the quadrature of r^2 R_n R_n'."""
+    sig, d, nn = oracle.gto_constants(nmax, rcut)
+    S = oracle.overlap(nmax, rcut)
+    for n in range(nmax):
+        for m in range(n, nmax):
+            q = integrate.quad(lambda x: x * x * _gto(n, x, sig, d, nn) * _gto(m, x, sig, d, nn),
+                               0, np.inf, epsabs=0, epsrel=1e-13, limit=400)[0]
+            assert abs(S[n, m] - q) <= 1e-11
+            assert S[n, m] == S[m, n]
+    assert np.allclose(np.diag(S), 1.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("nmax,rcut", [(6, 4.0), (8, 5.0), (10, 6.0), (12, 5.0)])
+def test_inverse_sqrt(nmax, rcut):
+    """S^{-1/2}: symmetric, positive, X S X = I, and equal to scipy's
+    eigendecomposition-based inverse square root."""
+    S = oracle.overlap(nmax, rcut)
+    X = oracle.orth_matrix(nmax, rcut)
+    assert np.allclose(X, X.T, atol=0, rtol=1e-12)
+    cond = np.linalg.cond(S)
+    assert np.abs(X @ S @ X - np.eye(nmax)).max() <= 1e-15 * cond * 50
+    w, V = np.linalg.eigh(S)
+    Xref = (V / np.sqrt(w)) @ V.T
+    assert np.abs(X - Xref).max() <= 1e-14 * cond * np.abs(Xref).max()
+
+
+def test_orthonormal_basis_by_quadrature():
+    """The o-GTO functions sum_n' X_nn' R_n' are orthonormal on [0, inf)."""
+    nmax, rcut = 8, 5.0
+    sig, d, nn = oracle.gto_constants(nmax, rcut)
+    X = oracle.orth_matrix(nmax, rcut)
+    x, w = np.polynomial.legendre.leggauss(400)
+    x = 0.5 * (x + 1) * 25.0
+    w = 0.5 * w * 25.0
+    R = np.stack([_gto(n, x, sig, d, nn) for n in range(nmax)])
+    Rt = X @ R
+    G = (Rt * x * x * w) @ Rt.T
+    assert np.abs(G - np.eye(nmax)).max() <= 1e-9
+
+
+# ------------------------------------------------------- radial integral
+def _radial_quad(n, l, r, rcut, sigma, nmax):
+    """Eq. (radial-integral-gaussian-density) by adaptive quadrature:
+    4 pi e^{-c r^2} int x^2 R_n(x) e^{-c x^2} i_l(2 c x r) dx, evaluated with
+    the exponentially scaled Bessel function to stay in range."""
+    sig, d, nn = oracle.gto_constants(nmax, rcut)
+    c = 1.0 / (2 * sigma * sigma)
+
+    def f(x):
+        if r == 0.0:
+            il = 1.0 if l == 0 else 0.0
+            return x * x * _gto(n, x, sig, d, nn) * math.exp(-c * x * x) * il
+        z = 2 * c * x * r
+        if z == 0.0:
+            return 0.0
+        scaled = math.sqrt(math.pi / (2 * z)) * special.ive(l + 0.5, z)   # i_l(z) e^{-z}
+        return x * x * _gto(n, x, sig, d, nn) * math.exp(-c * (x - r) ** 2) * scaled
+
+    hi = r + 12 * sigma + 30.0
+    v = integrate.quad(f, 0, hi, epsabs=0, epsrel=1e-13, limit=500, points=[r] if r > 0 else None)[0]
+    return 4 * math.pi * v
+
+
+@pytest.mark.parametrize("r", [0.0, 0.37, 1.9, 3.3, 4.99])
+def test_radial_integral_closed_form_vs_quadrature(r):
+    """Eq. (rad-int-gto-1) equals Eq. (radial-integral-gaussian-density) for
+    the GTO basis (the Gaussian density read as unnormalised exp(-x^2/2s^2))."""
+    nmax, lmax, rcut, sigma = 6, 6, 5.0, 0.5
+    I = oracle.radial_integral(nmax, lmax, rcut, sigma, r)
+    for n in range(nmax):
+        for l in range(lmax + 1):
+            q = _radial_quad(n, l, r, rcut, sigma, nmax)
+            assert abs(I[n, l] - q) <= 1e-10 * max(1.0, abs(q)), (n, l, I[n, l], q)
+
+
+def test_radial_integral_at_zero():
+    """At r = 0 only l = 0 survives: I_n0(0) = pi^{3/2} N_n G((n+3)/2)/G(3/2)
+    (c+d_n)^{-(n+3)/2}."""
+    nmax, lmax, rcut, sigma = 8, 6, 5.0, 0.5
+    sig, d, nn = oracle.gto_constants(nmax, rcut)
+    c = 1 / (2 * sigma ** 2)
+    I = oracle.radial_integral(nmax, lmax, rcut, sigma, 0.0)
+    for n in range(nmax):
+        ref = math.pi ** 1.5 * nn[n] * math.gamma((n + 3) / 2) / math.gamma(1.5) * (c + d[n]) ** (-(n + 3) / 2)
+        assert abs(I[n, 0] - ref) <= 1e-14 * ref
+    assert np.all(I[:, 1:] == 0.0)
+
+
+@pytest.mark.parametrize("r", [0.05, 1.3, 2.8, 4.4])
+def test_radial_derivative_fd(r):
+    nmax, lmax, rcut, sigma = 10, 8, 6.0, 0.5
+    I, dI = oracle.radial_integral(nmax, lmax, rcut, sigma, r, deriv=True)
+    h = 1e-5
+    fd = (oracle.radial_integral(nmax, lmax, rcut, sigma, r + h) -
+          oracle.radial_integral(nmax, lmax, rcut, sigma, r - h)) / (2 * h)
+    assert np.abs(dI - fd).max() <= 1e-8 * max(1.0, np.abs(dI).max())
+    It, dIt = oracle.radial_integral_orth(nmax, lmax, rcut, sigma, r, deriv=True)
+    fdt = (oracle.radial_integral_orth(nmax, lmax, rcut, sigma, r + h) -
+           oracle.radial_integral_orth(nmax, lmax, rcut, sigma, r - h)) / (2 * h)
+    assert np.abs(dIt - fdt).max() <= 1e-7 * max(1.0, np.abs(dIt).max())
+
+
+# ------------------------------------------------------- harmonics
+def _scipy_real_ylm(lmax, v):
+    r = np.linalg.norm(v)
+    theta = math.acos(v[2] / r)
+    phi = math.atan2(v[1], v[0])
+    out = np.zeros((lmax + 1) ** 2)
+    for l in range(lmax + 1):
+        for m in range(0, l + 1):
+            y = complex(special.sph_harm_y(l, m, theta, phi))
+            if m == 0:
+                out[l * l + l] = y.real
+            else:
+                out[l * l + l + m] = math.sqrt(2) * (-1) ** m * y.real
+                out[l * l + l - m] = math.sqrt(2) * (-1) ** m * y.imag
+    return out
+
+
+def test_ylm_matches_scipy_convention():
+    """Real orthonormal harmonics: Y_{l,m} = sqrt2 (-1)^m Re Y_l^m,
+    Y_{l,-m} = sqrt2 (-1)^m Im Y_l^m of scipy's complex (Condon-Shortley)
+    harmonics; so Y_{1,-1}, Y_{1,0}, Y_{1,1} ~ y, z, x."""
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        v = rng.normal(size=3) * rng.uniform(0.2, 5)
+        Y = oracle.ylm(12, v)
+        assert np.abs(Y - _scipy_real_ylm(12, v)).max() <= 1e-12
+    Y = oracle.ylm(1, np.array([0.3, -0.5, 0.8]))
+    u = np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8])
+    assert np.allclose(Y[1:], math.sqrt(3 / (4 * math.pi)) * np.array([u[1], u[2], u[0]]), atol=1e-15)
+
+
+def test_ylm_orthonormal_by_quadrature():
+    lmax = 8
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    nphi = 40
+    phis = 2 * np.pi * np.arange(nphi) / nphi
+    G = np.zeros(((lmax + 1) ** 2,) * 2)
+    for ct, w in zip(xg, wg):
+        st = math.sqrt(1 - ct * ct)
+        for ph in phis:
+            Y = oracle.ylm(lmax, np.array([st * math.cos(ph), st * math.sin(ph), ct]))
+            G += np.outer(Y, Y) * w * 2 * np.pi / nphi
+    assert np.abs(G - np.eye(G.shape[0])).max() <= 1e-12
+
+
+def test_ylm_addition_theorem():
+    rng = np.random.default_rng(3)
+    lmax = 12
+    for _ in range(10):
+        u, v = rng.normal(size=3), rng.normal(size=3)
+        Yu, Yv = oracle.ylm(lmax, u), oracle.ylm(lmax, v)
+        cos = u @ v / np.linalg.norm(u) / np.linalg.norm(v)
+        for l in range(lmax + 1):
+            s = Yu[l * l:(l + 1) ** 2] @ Yv[l * l:(l + 1) ** 2]
+            assert abs(s - (2 * l + 1) / (4 * math.pi) * special.eval_legendre(l, cos)) <= 1e-12
+
+
+def test_ylm_gradient_fd():
+    rng = np.random.default_rng(11)
+    lmax = 9
+    for _ in range(10):
+        v = rng.normal(size=3) * 2
+        Y, dY = oracle.ylm(lmax, v, deriv=True)
+        h = 1e-6
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd = (oracle.ylm(lmax, v + e) - oracle.ylm(lmax, v - e)) / (2 * h)
+            assert np.abs(dY[a] - fd).max() <= 2e-8
+        # the gradient of a function of the direction is tangential
+        assert np.abs(v @ dY).max() <= 1e-12
+
+
+def test_ylm_at_poles():
+    Y, dY = oracle.ylm(6, np.array([0.0, 0.0, 2.0]), deriv=True)
+    for l in range(7):
+        for m in range(-l, l + 1):
+            ref = math.sqrt((2 * l + 1) / (4 * math.pi)) if m == 0 else 0.0
+            assert abs(Y[l * l + l + m] - ref) <= 1e-14
+    assert np.all(np.isfinite(dY))
+
+
+# ------------------------------------------------------------- cutoff
+def test_cutoff_function():
+    f, df = oracle.fcut(4.99999, 5.0, 0.5)
+    assert f < 1e-9 and abs(df) < 3e-4      # both vanish at rcut (C^1 cutoff)
+    assert oracle.fcut(4.5, 5.0, 0.5) == (1.0, 0.0)
+    assert oracle.fcut(5.0, 5.0, 0.5) == (0.0, 0.0)
+    f, df = oracle.fcut(4.75, 5.0, 0.5)
+    assert abs(f - 0.5) < 1e-15 and abs(df + math.pi / 2 / 0.5) < 1e-12
+    h = 1e-6
+    for r in [4.6, 4.8, 4.95]:
+        fd = (oracle.fcut(r + h, 5.0, 0.5)[0] - oracle.fcut(r - h, 5.0, 0.5)[0]) / (2 * h)
+        assert abs(oracle.fcut(r, 5.0, 0.5)[1] - fd) < 1e-8
+
+
+# ----------------------------------------------- coefficients (3-D quadrature)
+def _scipy_real_ylm_grid(lmax, theta, phi):
+    out = []
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            y = special.sph_harm_y(l, abs(m), theta, phi)
+            if m == 0:
+                out.append(y.real)
+            elif m > 0:
+                out.append(math.sqrt(2) * (-1) ** m * y.real)
+            else:
+                out.append(math.sqrt(2) * (-1) ** m * y.imag)
+    return np.stack(out)
+
+
+def test_coefficients_by_3d_quadrature():
+    """Eq. (density-nlm) evaluated as a plain 3-D integral of the density of
+    Eq. (density-x) against o-GTO x real Y_lm, with the basis orthogonalised
+    by numpy's eigh and the harmonics from scipy -- nothing here comes from
+    the oracle.  Two neighbours of two species, one beyond rcut - w."""
+    nmax, lmax, rcut, sigma, width = 4, 3, 4.0, 0.5, 0.5
+    hyp = dict(n_species=2, nmax=nmax, lmax=lmax, rcut=rcut, sigma=sigma, cutoff_width=width,
+               include_center=0)
+    vecs = np.array([[0.9, -1.1, 0.6], [-2.3, 0.4, 2.7]])
+    spc_nb = [0, 1]
+    # independent GTO basis + orthogonalisation (paper Sec. 4.B)
+    sig_n = np.array([rcut * max(math.sqrt(n), 1) / nmax for n in range(nmax)])
+    d_n = 1 / (2 * sig_n ** 2)
+    N_n = np.sqrt(2 / (sig_n ** (2 * np.arange(nmax) + 3) * special.gamma(np.arange(nmax) + 1.5)))
+    xr, wr = np.polynomial.legendre.leggauss(120)
+    xr = 0.5 * (xr + 1) * 9.0
+    wr = 0.5 * wr * 9.0
+    R = np.stack([N_n[n] * xr ** n * np.exp(-d_n[n] * xr ** 2) for n in range(nmax)])
+    xf, wf = np.polynomial.legendre.leggauss(400)      # overlap on [0, 30 A]: the GTOs reach past 9 A
+    xf, wf = 0.5 * (xf + 1) * 30.0, 0.5 * wf * 30.0
+    Rf = np.stack([N_n[n] * xf ** n * np.exp(-d_n[n] * xf ** 2) for n in range(nmax)])
+    S = (Rf * xf ** 2 * wf) @ Rf.T
+    w, V = np.linalg.eigh(S)
+    Rt = ((V / np.sqrt(w)) @ V.T) @ R
+    ct, wt = np.polynomial.legendre.leggauss(90)
+    nphi = 180
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    TH, PH = np.meshgrid(np.arccos(ct), phi, indexing="ij")
+    Yg = _scipy_real_ylm_grid(lmax, TH, PH)                       # [L2, nt, nphi]
+    dirs = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1)
+    wang = wt[:, None] * (2 * np.pi / nphi)
+    ref = np.zeros((2, nmax, (lmax + 1) ** 2))
+    for v, a in zip(vecs, spc_nb):
+        r = np.linalg.norm(v)
+        fc = oracle.fcut(r, rcut, width)[0]
+        for ir, x in enumerate(xr):
+            pts = x * dirs
+            g = np.exp(-np.sum((pts - v) ** 2, -1) / (2 * sigma ** 2))   # unnormalised Gaussian
+            ang = np.einsum("lij,ij->l", Yg, g * wang)                   # [L2]
+            ref[a] += fc * wr[ir] * x * x * np.outer(Rt[:, ir], ang)
+    # the oracle on the same environment
+    nl = oracle.Neighbors(np.array([0, 2], dtype=np.int64), np.array([1, 2], dtype=np.int32),
+                          np.zeros((2, 3), dtype=np.int32), vecs.copy())
+    species = np.array([0, 0, 1], dtype=np.int32)
+    c = oracle.expansion(hyp, species, nl, centres=[0])[0]
+    assert np.abs(c - ref).max() <= 1e-12 * np.abs(ref).max(), np.abs(c - ref).max()
+    assert oracle.fcut(np.linalg.norm(vecs[1]), rcut, width)[0] < 1.0
+
+
+def test_centre_term():
+    """include_center adds I~_n0(0) Y_00 to the centre's own species channel
+    and nothing else."""
+    hyp = dict(n_species=2, nmax=5, lmax=3, rcut=4.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+    nl = oracle.Neighbors(np.array([0, 0], dtype=np.int64), np.zeros(0, dtype=np.int32),
+                          np.zeros((0, 3), dtype=np.int32), np.zeros((0, 3)))
+    c = oracle.expansion(hyp, np.array([1], dtype=np.int32), nl)[0]
+    It0 = oracle.radial_integral_orth(5, 3, 4.0, 0.5, 0.0)[:, 0]
+    assert np.abs(c[0]).max() == 0.0
+    assert np.allclose(c[1, :, 0], It0 / math.sqrt(4 * math.pi), rtol=1e-15, atol=0)
+    assert np.abs(c[1, :, 1:]).max() == 0.0
+
+
+# ------------------------------------------------------- power spectrum
+def test_power_spectrum_pair_sum_form():
+    """Without harmonics: by the addition theorem
+    p_{k1 k2 l} = (2l+1)/4pi sum_j sum_j' f_j f_j' I~_{n1 l}(r_j) I~_{n2 l}(r_j')
+    P_l(r^_j . r^_j'), j of species a1, j' of species a2."""
+    b = synthetic.random_cell_structure(5, 10, np.diag([7.0, 6.5, 8.0]), 3, min_sep=1.0,
+                                        hypers=dict(n_species=3, nmax=4, lmax=5, rcut=4.0, sigma=0.5,
+                                                    cutoff_width=0.5, include_center=0))
+    h = b.hypers
+    nl, c, p = oracle.features(b)
+    K = 3 * 4
+    for i in [0, 3, 7]:
+        q0, q1 = nl.pair_offsets[i], nl.pair_offsets[i + 1]
+        vs = nl.pair_vec[q0:q1]
+        aj = b.species[nl.pair_j[q0:q1]]
+        rs = np.linalg.norm(vs, axis=1)
+        fs = np.array([oracle.fcut(r, 4.0, 0.5)[0] for r in rs])
+        It = np.stack([oracle.radial_integral_orth(4, 5, 4.0, 0.5, r) for r in rs])   # [J, n, l]
+        cos = np.clip((vs / rs[:, None]) @ (vs / rs[:, None]).T, -1, 1)
+        for l in range(6):
+            Pl = special.eval_legendre(l, cos)
+            for k1 in range(K):
+                for k2 in range(k1, K):
+                    a1, n1, a2, n2 = k1 // 4, k1 % 4, k2 // 4, k2 % 4
+                    m1, m2 = aj == a1, aj == a2
+                    ref = (2 * l + 1) / (4 * math.pi) * np.einsum(
+                        "j,k,jk->", fs[m1] * It[m1, n1, l], fs[m2] * It[m2, n2, l], Pl[np.ix_(m1, m2)])
+                    idx = k1 * K - k1 * (k1 - 1) // 2 + (k2 - k1)
+                    assert abs(p[i, l, idx] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_single_neighbour_power_spectrum_is_direction_free():
+    hyp = dict(n_species=1, nmax=6, lmax=6, rcut=5.0, sigma=0.5, cutoff_width=0.5, include_center=0)
+    for v in [np.array([1.0, 2.0, -0.5]), np.array([0.0, 0.0, -2.29129]), np.array([-2.29129, 0, 0])]:
+        nl = oracle.Neighbors(np.array([0, 1], dtype=np.int64), np.array([1], dtype=np.int32),
+                              np.zeros((1, 3), dtype=np.int32), v[None, :].copy())
+        c = oracle.expansion(hyp, np.zeros(2, dtype=np.int32), nl, centres=[0])
+        p = oracle.power_spectrum(hyp, c)[0]
+        r = np.linalg.norm(v)
+        f = oracle.fcut(r, 5.0, 0.5)[0]
+        It = oracle.radial_integral_orth(6, 6, 5.0, 0.5, r)
+        for l in range(7):
+            ref = f * f * np.outer(It[:, l], It[:, l]) * (2 * l + 1) / (4 * math.pi)
+            iu = np.triu_indices(6)
+            assert np.allclose(p[l], ref[iu], rtol=1e-13, atol=1e-15)
+
+
+def _rotation(rng, reflect=False):
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    if reflect:
+        q = q @ np.diag([1, 1, -1])
+    return q
+
+
+@pytest.mark.parametrize("reflect", [False, True])
+def test_invariances(reflect):
+    """p is invariant under rotation, reflection and translation of a
+    cluster and permutes with its atoms; each |c_{a n l .}| is invariant."""
+    b = synthetic.clusters_2species().subset([0, 1])
+    nl, c, p = oracle.features(b)
+    rng = np.random.default_rng(2 if reflect else 1)
+    Q = _rotation(rng, reflect)
+    b2 = synthetic.Batch(b.positions @ Q.T + np.array([3.0, -7.0, 1.5]), b.species, b.atom_offsets,
+                         b.cells, b.pbc, b.hypers)
+    nl2, c2, p2 = oracle.features(b2)
+    assert np.abs(p2 - p).max() <= 1e-12 * np.abs(p).max()
+    lmax = b.hypers["lmax"]
+    for l in range(lmax + 1):
+        n1 = np.linalg.norm(c[..., l * l:(l + 1) ** 2], axis=-1)
+        n2 = np.linalg.norm(c2[..., l * l:(l + 1) ** 2], axis=-1)
+        assert np.abs(n1 - n2).max() <= 1e-12 * max(1.0, n1.max())
+    perm = rng.permutation(b.n_atoms // 2)
+    perm = np.concatenate([perm, perm + b.n_atoms // 2])
+    b3 = synthetic.Batch(b.positions[perm], b.species[perm], b.atom_offsets, b.cells, b.pbc, b.hypers)
+    nl3, c3, p3 = oracle.features(b3)
+    assert np.abs(p3 - p[perm]).max() <= 1e-12 * np.abs(p).max()
+
+
+def test_feature_counts_from_paper():
+    with open(os.path.join(GOLDEN, "feature_counts.json")) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        hyp = dict(n_species=case["n_species"], nmax=case["nmax"], lmax=case["lmax"], rcut=4.0,
+                   sigma=0.5, cutoff_width=0.5, include_center=1)
+        nl = oracle.Neighbors(np.array([0, 0], dtype=np.int64), np.zeros(0, dtype=np.int32),
+                              np.zeros((0, 3), dtype=np.int32), np.zeros((0, 3)))
+        c = oracle.expansion(hyp, np.zeros(1, dtype=np.int32), nl)
+        p = oracle.power_spectrum(hyp, c)
+        assert p[0].size == case["n_features"]
+
+
+# --------------------------------------------------------- neighbours
+def _brute_pairs(b, s, rcut, R=6):
+    a0, a1 = b.atom_offsets[s], b.atom_offsets[s + 1]
+    pos = b.positions[a0:a1]
+    H = b.cells[s]
+    rng = [range(-R, R + 1) if b.pbc[s][k] else range(1) for k in range(3)]
+    shifts = np.array([(x, y, z) for x in rng[0] for y in rng[1] for z in rng[2]])
+    out = set()
+    for i in range(pos.shape[0]):
+        d = pos[None, :, None, :] - pos[i][None, None, None, :] + (shifts @ H)[None, None, :, :]
+        r = np.linalg.norm(d[0], axis=-1)
+        for j, k in zip(*np.nonzero(r < rcut)):
+            if j == i and not shifts[k].any():
+                continue
+            out.add((i + a0, j + a0, *shifts[k]))
+    return out
+
+
+@pytest.mark.parametrize("cell", [
+    np.array([[0.0, 2.715, 2.715], [2.715, 0.0, 2.715], [2.715, 2.715, 0.0]]),   # diamond primitive
+    np.array([[3.1, 0.0, 0.0], [1.2, 2.9, 0.0], [-0.7, 0.9, 3.4]]),             # triclinic
+])
+def test_neighbors_brute_force_lattice_sum(cell):
+    """Tiny (triclinic) cells whose images reach far beyond one cell: the
+    list equals a plain enumeration of +-6 cells, self-images included, and
+    is closed under (i, j, s) -> (j, i, -s)."""
+    b = synthetic.random_cell_structure(3, 2, cell, 2, min_sep=1.0)
+    nl = oracle.neighbors(b, rcut=5.0)
+    got = set()
+    for i in range(b.n_atoms):
+        for q in range(nl.pair_offsets[i], nl.pair_offsets[i + 1]):
+            got.add((i, int(nl.pair_j[q]), *map(int, nl.pair_shift[q])))
+            v = b.positions[nl.pair_j[q]] + nl.pair_shift[q] @ b.cells[0] - b.positions[i]
+            assert np.allclose(v, nl.pair_vec[q], atol=1e-12)
+    assert got == _brute_pairs(b, 0, 5.0)
+    assert any(i == j for (i, j, *_s) in got)
+    for (i, j, s0, s1, s2) in got:
+        assert (j, i, -s0, -s1, -s2) in got
+
+
+def test_neighbors_periodic_bulk_and_clusters():
+    b = synthetic.diamond_bulk()
+    nl = oracle.neighbors(b)
+    assert 27.0 < nl.n_pairs / b.n_atoms < 29.0
+    sub = synthetic.clusters_2species().subset([0])
+    nl = oracle.neighbors(sub)
+    assert nl.pair_offsets[-1] > 0
+    got = {(i, int(nl.pair_j[q]), *map(int, nl.pair_shift[q])) for i in range(sub.n_atoms)
+           for q in range(nl.pair_offsets[i], nl.pair_offsets[i + 1])}
+    assert got == _brute_pairs(sub, 0, 4.0)
+    # canonical order inside each centre: (species_j, j, shift)
+    for i in range(sub.n_atoms):
+        q0, q1 = nl.pair_offsets[i], nl.pair_offsets[i + 1]
+        keys = [(int(sub.species[nl.pair_j[q]]), int(nl.pair_j[q])) for q in range(q0, q1)]
+        assert keys == sorted(keys)
+
+
+# ---------------------------------------------------------- gradients
+def _small_periodic():
+    cell = np.array([[5.2, 0.0, 0.0], [0.8, 4.9, 0.0], [0.3, -0.6, 5.5]])
+    hyp = dict(n_species=2, nmax=4, lmax=4, rcut=4.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+    return synthetic.random_cell_structure(17, 5, cell, 2, min_sep=1.1, hypers=hyp)
+
+
+def test_gradient_rows_match_finite_differences():
+    """Sum of the rows tagged with atom k (pair rows of neighbour k, self
+    row of centre k) equals the FD derivative of c_i and p_i when every
+    periodic image of k moves together (App. B)."""
+    b = _small_periodic()
+    h = b.hypers
+    nl, c, p = oracle.features(b)
+    dc, dcs, dp, dps = oracle.gradients(h, b.species, nl)
+    N, S, nmax, lmax = b.n_atoms, h["n_species"], h["nmax"], h["lmax"]
+    L2 = (lmax + 1) ** 2
+    eps = 1e-5
+    for k in range(N):
+        for x in range(3):
+            pos_p, pos_m = b.positions.copy(), b.positions.copy()
+            pos_p[k, x] += eps
+            pos_m[k, x] -= eps
+            bp = synthetic.Batch(pos_p, b.species, b.atom_offsets, b.cells, b.pbc, h)
+            bm = synthetic.Batch(pos_m, b.species, b.atom_offsets, b.cells, b.pbc, h)
+            _, cp_, pp_ = oracle.features(bp)
+            _, cm_, pm_ = oracle.features(bm)
+            fd_c = (cp_ - cm_) / (2 * eps)
+            fd_p = (pp_ - pm_) / (2 * eps)
+            an_c = np.zeros_like(c)
+            an_p = np.zeros_like(p)
+            for i in range(N):
+                for q in range(nl.pair_offsets[i], nl.pair_offsets[i + 1]):
+                    if nl.pair_j[q] == k:
+                        an_c[i, b.species[k]] += dc[q, x]
+                        an_p[i] += dp[q, x]
+                if i == k:
+                    an_c[i] += dcs[i, x]
+                    an_p[i] += dps[i, x]
+            assert np.abs(an_c - fd_c).max() <= 1e-7 * max(1, np.abs(fd_c).max())
+            assert np.abs(an_p - fd_p).max() <= 1e-7 * max(1, np.abs(fd_p).max())
+
+
+def test_gradient_rows_sum_to_zero():
+    """Translation invariance: for each centre, the self row cancels the
+    pair rows exactly in c and in p."""
+    b = _small_periodic()
+    nl = oracle.neighbors(b)
+    dc, dcs, dp, dps = oracle.gradients(b.hypers, b.species, nl)
+    for i in range(b.n_atoms):
+        q0, q1 = nl.pair_offsets[i], nl.pair_offsets[i + 1]
+        tot = dps[i] + dp[q0:q1].sum(0)
+        assert np.abs(tot).max() <= 1e-12 * max(1, np.abs(dp).max())
+
+
+def test_vjp_matches_finite_differences():
+    b = _small_periodic()
+    h = b.hypers
+    nl, c, p = oracle.features(b)
+    W = np.random.default_rng(0).normal(size=p.shape)
+    g, gpair = oracle.vjp(h, b.species, nl, W)
+    eps = 1e-5
+    for k in range(b.n_atoms):
+        for x in range(3):
+            pp, pm = b.positions.copy(), b.positions.copy()
+            pp[k, x] += eps
+            pm[k, x] -= eps
+            Lp = np.sum(W * oracle.features(synthetic.Batch(pp, b.species, b.atom_offsets, b.cells, b.pbc, h))[2])
+            Lm = np.sum(W * oracle.features(synthetic.Batch(pm, b.species, b.atom_offsets, b.cells, b.pbc, h))[2])
+            assert abs(g[k, x] - (Lp - Lm) / (2 * eps)) <= 1e-6 * max(1, np.abs(g).max())
+    # per-pair vectors assemble the per-atom gradient
+    acc = np.zeros_like(g)
+    for i in range(b.n_atoms):
+        for q in range(nl.pair_offsets[i], nl.pair_offsets[i + 1]):
+            acc[nl.pair_j[q]] += gpair[q]
+            acc[i] -= gpair[q]
+    assert np.allclose(acc, g, rtol=1e-12, atol=1e-12)
+
+
+def test_torque_free_cluster_gradient():
+    """For an isolated cluster sum_k r_k x dL/dr_k = 0 (rotation invariance)."""
+    b = synthetic.clusters_2species().subset([3])
+    nl, c, p = oracle.features(b)
+    W = np.random.default_rng(1).normal(size=p.shape)
+    g, _ = oracle.vjp(b.hypers, b.species, nl, W)
+    torque = np.cross(b.positions, g).sum(0)
+    assert np.abs(torque).max() <= 1e-9 * np.abs(g).max() * np.abs(b.positions).max()
+    assert np.abs(g.sum(0)).max() <= 1e-10 * np.abs(g).max()
