@@ -1,0 +1,256 @@
+/*
+ * soap_mi355x.h -- C ABI of the MI355X (gfx950) SOAP library.
+ *
+ * The library computes, on one AMD Instinct MI355X, the hot path of the
+ * atom-density representation of Musil et al., "Efficient implementation of
+ * atom-density representations" (arXiv 2101.08814):
+ *
+ *   neighbours   A_i = {(j, s) : 0 < |r_j + s.H - r_i| < rcut}        (App. B)
+ *   expansion    c_{i,a,n,lm} = sum_{j in A_i, a_j = a}
+ *                  f_cut(r_ji) I~_nl(r_ji) Y_lm(r^_ji)
+ *                                   (Sec. 4.A Eq. spherical_expansion_
+ *                                    coefficients_gaussians, Sec. 4.B-D)
+ *   power spec.  p_{i,l,k1<=k2} = sum_m c_{i,k1,lm} c_{i,k2,lm},
+ *                  k = a * nmax + n                (Sec. 2 Eq. nu2-basis-coupled)
+ *   gradients    forward-mode rows d c_i / d r_j and d p_i / d r_j (Sec. 4.G)
+ *                and the reverse-mode (vector-Jacobian) products
+ *                (App. B Eq. energy-derivative).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Radial basis: GTO (Sec. 4.B Eq. GTO), orthogonalised with S^{-1/2};
+ *   the radial integral of a Gaussian density exp(-x^2 / 2 sigma^2)
+ *   (Eq. rad-int-gto-1) is tabulated as a clamped cubic spline on a uniform
+ *   grid over [0, rcut] (Sec. 4.D) with max error <= spline_accuracy.
+ * - Cutoff: shifted cosine, 1 below rcut - cutoff_width, 0 at rcut.
+ * - Harmonics: real, orthonormal, index lm = l*l + l + m, m = -l..l;
+ *   Y_{1,-1}, Y_{1,0}, Y_{1,1} are proportional to y, z, x.
+ * - L2 = (lmax+1)^2, K = n_species * nmax, KK = K (K+1) / 2.
+ * - Arrays are dense, row-major, and (unless marked [host]) device pointers
+ *   on the current HIP device.  The caller owns every array; the library
+ *   allocates only its spline tables (once per device, at the first call
+ *   on that device or at soap_calculator_upload).
+ * - Every device call is asynchronous on exec->stream.  Host-side argument
+ *   errors return immediately with nothing enqueued; soap_last_error()
+ *   then holds a message.  Errors found on the device (pair capacity
+ *   exceeded, coincident atoms, species out of range) are stored as a
+ *   nonzero soap_status into *exec->dev_status (caller-zeroed device int32);
+ *   soap_read_device_status() synchronises the stream and returns it.
+ *   Kernels that read a neighbour list whose total exceeds the capacity
+ *   they are given store SOAP_ECAPACITY and write nothing else.
+ * - Floating-point type: SOAP_F64 -> double, SOAP_F32 -> float for
+ *   pair_vec, coefficients, features and gradients.  SOAP_BF16_F32ACC is
+ *   accepted by soap_power_spectrum only: c and p are float in memory and
+ *   the contraction runs on MFMA with bfloat16 hi/lo operands and float
+ *   accumulation.
+ * - A calculator is immutable after creation and may be shared by threads
+ *   and streams.  Calls enqueued on the same stream with overlapping
+ *   outputs race only if the caller makes them race.
+ */
+#ifndef SOAP_MI355X_H
+#define SOAP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SOAP_ABI_VERSION 1
+
+typedef enum {
+    SOAP_OK = 0,
+    SOAP_EINVAL = -1,        /* bad argument (host)                          */
+    SOAP_ECAPACITY = -2,     /* neighbour list larger than the given capacity */
+    SOAP_EDEVICE = -3,       /* HIP runtime error                             */
+    SOAP_ENOMEM = -4,        /* allocation of the spline tables failed        */
+    SOAP_EUNSUPPORTED = -5,  /* valid request this build does not implement   */
+    SOAP_EGEOMETRY = -6,     /* two distinct atoms (or images) coincide       */
+    SOAP_ESPECIES = -7       /* species index outside [0, n_species)          */
+} soap_status;
+
+typedef enum { SOAP_F64 = 0, SOAP_F32 = 1, SOAP_BF16_F32ACC = 2 } soap_precision;
+
+/* Hyper-parameters (Sec. 3 and 4: species, rcut, smoothing, sigma, nmax,
+ * lmax).  Limits: 1 <= n_species <= 64, 1 <= nmax <= 16, 0 <= lmax <= 12,
+ * rcut > 0, 0 < cutoff_width <= rcut, sigma > 0, include_center in {0, 1}
+ * (1: the central atom adds its own r = 0 term, l = 0 only, to channel
+ * a_i), 0 < spline_accuracy (the paper uses 1e-8, Fig. ri-qm9 caption). */
+typedef struct {
+    int32_t n_species;
+    int32_t nmax;
+    int32_t lmax;
+    int32_t include_center;
+    double rcut;
+    double cutoff_width;
+    double sigma;
+    double spline_accuracy;
+} soap_hypers;
+
+/* Facts about a calculator's spline table (host). */
+typedef struct {
+    int64_t n_intervals;        /* M: grid r_k = k * rcut / M, k = 0..M       */
+    double delta;               /* rcut / M                                   */
+    double max_error;           /* max |spline - exact| of I~ at 4 interior
+                                   points per interval                        */
+    double max_error_deriv;     /* same for d I~ / dr                         */
+    double overlap_condition;   /* condition number of the GTO overlap S      */
+    int64_t table_bytes_f64;    /* device bytes of the double table           */
+    int64_t table_bytes_f32;    /* device bytes of the float table            */
+} soap_table_info;
+
+typedef struct soap_calculator soap_calculator;
+
+/* Per-call execution context (caller-owned, host struct). */
+typedef struct {
+    void* stream;          /* hipStream_t; NULL is the null stream           */
+    int32_t* dev_status;   /* device int32, zeroed by the caller; may be NULL,
+                              then device-side errors are not reported       */
+} soap_exec;
+
+int32_t soap_abi_version(void);
+
+/* Thread-local message of the last failed call on this thread. */
+const char* soap_last_error(void);
+
+/* Builds the GTO constants, S^{-1/2} and the spline tables in FP64 on the
+ * host (Sec. 4.B, 4.D, App. A).  *out receives a new calculator; free it
+ * with soap_calculator_destroy.  No device work. */
+soap_status soap_calculator_create(const soap_hypers* hypers, soap_calculator** out);
+soap_status soap_calculator_destroy(soap_calculator* calc);
+soap_status soap_calculator_info(const soap_calculator* calc, soap_table_info* info);
+
+/* Uploads the tables to the current device now (otherwise done at the
+ * first call on that device; that call then synchronises once). */
+soap_status soap_calculator_upload(const soap_calculator* calc);
+
+/* Host evaluation of the library's radial integral I~_nl(r) and d/dr for
+ * n_r radii [host]: exact=1 uses the library's own 1F1 recurrence
+ * (App. A), exact=0 the FP64 spline the kernels use.  Outputs
+ * [n_r][nmax][lmax+1] [host]; dI may be NULL. */
+soap_status soap_radial_integral_host(const soap_calculator* calc, int32_t exact, int64_t n_r,
+                                      const double* r, double* I, double* dI);
+
+/* Device bytes of scratch soap_compute_neighbors needs for these
+ * structures.  atom_offsets [n_structures+1], cells [n_structures][3][3]
+ * (rows h1, h2, h3) and pbc [n_structures][3] are [host] arrays. */
+soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures,
+                                          const int64_t* atom_offsets, const double* cells,
+                                          const uint8_t* pbc, size_t* bytes);
+
+/* Full neighbour list with periodic images (App. B; Sec. 3 Fig. 1).
+ *
+ * For every centre i, every (j, s) with s integer on periodic axes (0 on
+ * the others) and 0 < |r_ji| < rcut, r_ji = r_j + s0 h1 + s1 h2 + s2 h3 - r_i.
+ * j = i is kept when s != 0 (self-images).  Structures never interact.
+ * If any axis of a structure is periodic its cell must be non-singular.
+ *
+ * [host] n_structures, atom_offsets [n_structures+1], cells, pbc.
+ * [dev]  positions double [N][3], species int32 [N] in [0, n_species),
+ *        workspace of >= soap_neighbors_workspace_size bytes.
+ * out [dev] pair_offsets int64 [N+1] (CSR over centres; pair_offsets[N] is
+ *        the number of pairs P even when P > capacity),
+ *        pair_j int32 [capacity], pair_shift int32 [capacity][3],
+ *        pair_vec [capacity][3] (double or float per vec_precision,
+ *        always formed in double), pair_transpose int32 [capacity] or NULL
+ *        (index of the pair (j, i, -s)).
+ * Pairs of one centre are ordered by (species_j, j, s0, s1, s2).
+ * Device errors: SOAP_ECAPACITY if P > capacity (pair arrays then hold
+ * nothing usable), SOAP_EGEOMETRY for coincident distinct atoms.
+ * Non-periodic axes are searched without binning (all pairs within the
+ * structure along that axis).                                          */
+soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec* exec,
+                                   int32_t n_structures, const int64_t* atom_offsets,
+                                   const double* cells, const uint8_t* pbc,
+                                   const double* positions, const int32_t* species,
+                                   void* workspace, size_t workspace_bytes, int64_t capacity,
+                                   soap_precision vec_precision, int64_t* pair_offsets,
+                                   int32_t* pair_j, int32_t* pair_shift, void* pair_vec,
+                                   int32_t* pair_transpose);
+
+/* Spherical expansion (Sec. 4.A Eq. spherical_expansion_coefficients_
+ * gaussians with the splined radial integral of Sec. 4.D and real Y_lm of
+ * Sec. 4.E), optionally with forward-mode gradient rows (Sec. 4.G).
+ *
+ * in  n_atoms, species [N], pair_offsets [N+1], pair_j [P], pair_vec [P][3]
+ *     (type per precision), pair_capacity = length of the pair arrays.
+ * out coeffs [N][n_species][nmax][L2].
+ *     dcoeffs [P][3][nmax][L2] or NULL: row q of centre i is
+ *       d c_{i, a_j, n, lm} / d r_ji  (the only nonzero species block);
+ *     dcoeffs_self [N][3][n_species][nmax][L2] or NULL: d c_i / d r_i
+ *       = - sum of the rows of i (images of i included, App. B).
+ *     dcoeffs and dcoeffs_self are both NULL or both given.
+ * precision: SOAP_F64 or SOAP_F32.                                      */
+soap_status soap_spherical_expansion(const soap_calculator* calc, const soap_exec* exec,
+                                     soap_precision precision, int64_t n_atoms,
+                                     const int32_t* species, const int64_t* pair_offsets,
+                                     const int32_t* pair_j, const void* pair_vec,
+                                     int64_t pair_capacity, void* coeffs, void* dcoeffs,
+                                     void* dcoeffs_self);
+
+/* Power spectrum p [N][lmax+1][KK] from coeffs [N][n_species][nmax][L2]
+ * (Sec. 2 Eq. nu2-basis-coupled times sqrt(2l+1); packed k1 <= k2,
+ * row-major, no sqrt(2) on off-diagonal entries).
+ * Optional forward-mode rows (Sec. 4.G), product rule on the rows of
+ * soap_spherical_expansion:
+ *   dp [P][3][lmax+1][KK] from dcoeffs, dp_self [N][3][lmax+1][KK] from
+ *   dcoeffs_self; both NULL or both given (then species, pair_offsets,
+ *   pair_j, dcoeffs, dcoeffs_self are read).
+ * precision: SOAP_F64, SOAP_F32, or SOAP_BF16_F32ACC (MFMA, bfloat16 hi/lo
+ * split of c with float accumulation; no gradient rows).             */
+soap_status soap_power_spectrum(const soap_calculator* calc, const soap_exec* exec,
+                                soap_precision precision, int64_t n_atoms, const void* coeffs,
+                                void* p, const int32_t* species, const int64_t* pair_offsets,
+                                const int32_t* pair_j, int64_t pair_capacity,
+                                const void* dcoeffs, const void* dcoeffs_self, void* dp,
+                                void* dp_self);
+
+/* Expansion and power spectrum in one launch, optionally with both kinds
+ * of forward-mode rows; the coefficient rows never make a round trip
+ * through memory before the power-spectrum rows use them.  Arguments as
+ * in the two calls above; p is required, dcoeffs/dcoeffs_self/dp/dp_self
+ * are all NULL or all given.  precision: SOAP_F64 or SOAP_F32.        */
+soap_status soap_features(const soap_calculator* calc, const soap_exec* exec,
+                          soap_precision precision, int64_t n_atoms, const int32_t* species,
+                          const int64_t* pair_offsets, const int32_t* pair_j,
+                          const void* pair_vec, int64_t pair_capacity, void* coeffs, void* p,
+                          void* dcoeffs, void* dcoeffs_self, void* dp, void* dp_self);
+
+/* Reverse mode of the power spectrum (chain rule of Sec. 4.G):
+ *   grad_coeffs_{k,lm} = sum_k' W_{k k'} c_{k',lm},
+ *   W_{k k'} = grad_p_{min,max} (k != k'),  W_{k k} = 2 grad_p_{k k},
+ * grad_p [N][lmax+1][KK], coeffs and grad_coeffs [N][n_species][nmax][L2].
+ * precision: SOAP_F64 or SOAP_F32.                                     */
+soap_status soap_power_spectrum_backward(const soap_calculator* calc, const soap_exec* exec,
+                                         soap_precision precision, int64_t n_atoms,
+                                         const void* coeffs, const void* grad_p,
+                                         void* grad_coeffs);
+
+/* Reverse mode of the expansion with respect to positions (App. B Eq.
+ * energy-derivative):
+ *   g_q = sum_{n,lm} grad_coeffs_{i,a_j,n,lm} d/dr_ji [f I~_nl Y_lm]
+ *   grad_positions_k = sum_{q: j_q = k} g_q - sum_{q of centre k} g_q
+ * (all images of k move together; an image of i contributes nothing to
+ * d/dr_i).  The per-atom sums are taken in a fixed order through
+ * pair_transpose (no atomics: results are bitwise reproducible).
+ * out grad_pair_vec [P][3] (g_q = dL/dr_ji, input of a virial; required),
+ *     grad_positions [N][3] (overwritten).
+ * precision: SOAP_F64 or SOAP_F32.                                     */
+soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const soap_exec* exec,
+                                              soap_precision precision, int64_t n_atoms,
+                                              const int32_t* species, const int64_t* pair_offsets,
+                                              const int32_t* pair_j, const void* pair_vec,
+                                              const int32_t* pair_transpose, int64_t pair_capacity,
+                                              const void* grad_coeffs, void* grad_pair_vec,
+                                              void* grad_positions);
+
+/* Synchronises exec->stream and returns *exec->dev_status (SOAP_OK if
+ * dev_status is NULL), or SOAP_EDEVICE on a runtime error.             */
+soap_status soap_read_device_status(const soap_exec* exec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOAP_MI355X_H */

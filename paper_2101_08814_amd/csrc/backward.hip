@@ -1,0 +1,197 @@
+// Reverse mode (vector-Jacobian products) of the power spectrum and of the
+// expansion with respect to the positions.
+//
+// Power spectrum (chain rule of Sec. 4.G): with W_l the packed upstream
+// gradient of p_{i,l,.} unpacked into a symmetric K x K matrix whose
+// diagonal is doubled,
+//   dL/dc_{k,lm} = sum_k' W_{l,k k'} c_{k',lm}.
+// One work-group per centre; W_l is staged row by row through LDS.
+//
+// Expansion (App. B Eq. energy-derivative): for pair q = (i, j, s)
+//   g_q = dL/dr_ji = sum_{n,lm} G_{i,a_j,n,lm} [(f I~)'_nl Y_lm u + f I~_nl grad Y_lm]
+// with G = dL/dc.  The per-pair factors are recomputed (the same LDS staging
+// as the forward pass) instead of being stored: the model-side sum is
+// contracted first, as the paper recommends for forces.  Then
+//   dL/dr_k = sum_{q: j_q = k} g_q - sum_{q of centre k} g_q,
+// and because the full neighbour list holds (j, i, -s) for every (i, j, s),
+// the first sum runs over the centre's own pairs through pair_transpose:
+// each atom adds its terms in a fixed order, with no atomics.
+#include "chunk.hpp"
+
+namespace soap {
+namespace {
+
+using namespace dev;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ps_backward(FeatureArgs a, const T* grad_p, T* grad_c)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const Dims d = make_dims(a.S, a.nmax, a.lmax);
+    const int KL2 = d.K * d.L2;
+    T* c = sm;            // [K][L2]
+    T* w = c + KL2;       // [KK] packed W_l
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
+    for (int e = tid; e < KL2; e += kThreads) c[e] = c_in[e];
+    T* g_out = grad_c + i * KL2;
+    const int K = d.K;
+    for (int l = 0; l <= d.lmax; ++l) {
+        const T* wl = grad_p + (i * (d.lmax + 1) + l) * d.KK;
+        __syncthreads();
+        for (int64_t e = tid; e < d.KK; e += kThreads) w[e] = wl[e];
+        __syncthreads();
+        const int nm = 2 * l + 1;
+        for (int t = tid; t < K * nm; t += kThreads) {
+            int k = t / nm, m = t - k * nm;
+            T acc = T(0);
+            for (int kp = 0; kp < K; ++kp) {
+                int lo = k < kp ? k : kp, hi = k < kp ? kp : k;
+                T wv = w[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
+                if (kp == k) wv += wv;
+                acc += wv * c[kp * d.L2 + l * l + m];
+            }
+            g_out[k * d.L2 + l * l + m] = acc;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, int chunk, Layout L, const T* grad_c,
+                                                                 T* grad_pair)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* base = reinterpret_cast<T*>(smem_raw);
+    Smem<T> s(base, L);
+    const Dims d = make_dims(a.S, a.nmax, a.lmax);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t i = blockIdx.x;
+    if (a.pair_offsets[a.n_atoms] > a.pair_capacity) {
+        if (tid == 0) put_status(a.status, SOAP_ECAPACITY);
+        return;
+    }
+    const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lmax + 1;
+    const T* g_in = grad_c + i * KL2;
+    for (int e = tid; e < KL2; e += kThreads) s.c[e] = g_in[e];   // the c slot holds dL/dc here
+    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
+    const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
+    for (int ck = 0; ck < n_chunks; ++ck) {
+        int64_t q0 = q_begin + int64_t(ck) * chunk;
+        int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
+        stage_chunk<T, true>(a, d, s, q0, nc);
+        for (int p = wave; p < nc; p += kWaves) {
+            const T* G = s.c + s.spc[p] * nL2;
+            T gx = T(0), gy = T(0), gz = T(0);
+            for (int e = lane; e < nL2; e += 64) {
+                int n = e / d.L2, lm = e - n * d.L2;
+                int rl = n * lm1 + l_of(lm);
+                T Gv = G[e];
+                T t = Gv * s.dR[p * d.nl + rl] * s.Y[p * d.L2 + lm];
+                T r = Gv * s.R[p * d.nl + rl];
+                gx += t * s.ux[p] + r * s.dY[(p * 3 + 0) * d.L2 + lm];
+                gy += t * s.uy[p] + r * s.dY[(p * 3 + 1) * d.L2 + lm];
+                gz += t * s.uz[p] + r * s.dY[(p * 3 + 2) * d.L2 + lm];
+            }
+            gx = wave_sum(gx);
+            gy = wave_sum(gy);
+            gz = wave_sum(gz);
+            if (lane == 0) {
+                int64_t q = q0 + p;
+                grad_pair[3 * q] = gx;
+                grad_pair[3 * q + 1] = gy;
+                grad_pair[3 * q + 2] = gz;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_exp_backward_gather(FeatureArgs a, const int32_t* transpose, const T* grad_pair, T* grad_pos)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= a.n_atoms) return;
+    T gx = T(0), gy = T(0), gz = T(0);
+    if (a.pair_offsets[a.n_atoms] <= a.pair_capacity) {
+        for (int64_t q = a.pair_offsets[k]; q < a.pair_offsets[k + 1]; ++q) {
+            int32_t t = transpose[q];
+            if (t < 0 || t >= a.pair_capacity) { put_status(a.status, SOAP_EGEOMETRY); continue; }
+            gx += grad_pair[3 * int64_t(t)] - grad_pair[3 * q];
+            gy += grad_pair[3 * int64_t(t) + 1] - grad_pair[3 * q + 1];
+            gz += grad_pair[3 * int64_t(t) + 2] - grad_pair[3 * q + 2];
+        }
+    }
+    grad_pos[3 * k] = gx;
+    grad_pos[3 * k + 1] = gy;
+    grad_pos[3 * k + 2] = gz;
+}
+
+template <typename T>
+hipError_t ps_backward_t(const FeatureArgs& a, const void* grad_p, void* grad_c, hipStream_t stream)
+{
+    Dims d = make_dims(a.S, a.nmax, a.lmax);
+    size_t lds = (size_t(d.K) * d.L2 + size_t(d.KK)) * sizeof(T);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ps_backward<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ps_backward<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads), lds, stream, a,
+                       static_cast<const T*>(grad_p), static_cast<T*>(grad_c));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const void* grad_c, void* grad_pair,
+                          void* grad_pos, hipStream_t stream)
+{
+    Dims d = make_dims(a.S, a.nmax, a.lmax);
+    int chunk = 32;
+    Layout L = make_layout(d, chunk, true, false, false);
+    while (chunk > 4 && L.total * sizeof(T) > 65536) {
+        chunk /= 2;
+        L = make_layout(d, chunk, true, false, false);
+    }
+    size_t lds = size_t(L.total) * sizeof(T);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_exp_backward_pairs<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    if (a.pair_capacity > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_pairs<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads), lds,
+                           stream, a, chunk, L, static_cast<const T*>(grad_c), static_cast<T*>(grad_pair));
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_gather<T>), dim3(unsigned((a.n_atoms + 255) / 256)), dim3(256),
+                       0, stream, a, transpose, static_cast<const T*>(grad_pair), static_cast<T*>(grad_pos));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const void* grad_p, void* grad_coeffs,
+                                          hipStream_t stream)
+{
+    return f64 ? ps_backward_t<double>(a, grad_p, grad_coeffs, stream)
+               : ps_backward_t<float>(a, grad_p, grad_coeffs, stream);
+}
+
+hipError_t launch_expansion_backward(const FeatureArgs& a, bool f64, const int32_t* pair_transpose,
+                                     const void* grad_coeffs, void* grad_pair_vec, void* grad_positions,
+                                     hipStream_t stream)
+{
+    return f64 ? exp_backward_t<double>(a, pair_transpose, grad_coeffs, grad_pair_vec, grad_positions, stream)
+               : exp_backward_t<float>(a, pair_transpose, grad_coeffs, grad_pair_vec, grad_positions, stream);
+}
+
+}  // namespace soap

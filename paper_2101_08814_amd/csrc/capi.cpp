@@ -1,0 +1,592 @@
+// C ABI of the library: argument validation, error reporting, spline-table
+// upload and kernel dispatch.  Every array argument is checked on the host
+// before anything is enqueued; device-detected errors go to exec->dev_status.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "soap_internal.hpp"
+
+namespace soap {
+
+namespace {
+thread_local char g_error[512] = "";
+}
+
+soap_status fail(soap_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof(g_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+void clear_error() { g_error[0] = '\0'; }
+
+soap_status device_tables(const soap_calculator* calc, const DeviceTables** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SOAP_EDEVICE, "no HIP device available");
+    std::lock_guard<std::mutex> lock(calc->mu);
+    if (int(calc->dev.size()) <= dev) calc->dev.resize(dev + 1);
+    DeviceTables& t = calc->dev[dev];
+    if (!t.ready) {
+        size_t b64 = calc->coef64.size() * sizeof(double), b32 = calc->coef32.size() * sizeof(float);
+        size_t c64 = calc->center.size() * sizeof(double), c32 = calc->center.size() * sizeof(float);
+        std::vector<float> cf(calc->center.begin(), calc->center.end());
+        if (hipMalloc(&t.coef64, b64) != hipSuccess || hipMalloc(&t.coef32, b32) != hipSuccess ||
+            hipMalloc(&t.center64, c64) != hipSuccess || hipMalloc(&t.center32, c32) != hipSuccess)
+            return fail(SOAP_ENOMEM, "allocation of the spline tables failed on device %d", dev);
+        if (hipMemcpy(t.coef64, calc->coef64.data(), b64, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(t.coef32, calc->coef32.data(), b32, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(t.center64, calc->center.data(), c64, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(t.center32, cf.data(), c32, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
+        t.ready = true;
+    }
+    *out = &t;
+    return SOAP_OK;
+}
+
+}  // namespace soap
+
+using namespace soap;
+
+namespace {
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+#define REQUIRE(cond, ...)                                  \
+    do {                                                    \
+        if (!(cond)) return fail(SOAP_EINVAL, __VA_ARGS__); \
+    } while (0)
+
+soap_status check_ptr(const void* p, size_t align, const char* name, bool nullable = false)
+{
+    if (!p) return nullable ? SOAP_OK : fail(SOAP_EINVAL, "%s must not be NULL", name);
+    if (!aligned(p, align)) return fail(SOAP_EINVAL, "%s is not %zu-byte aligned", name, align);
+    return SOAP_OK;
+}
+
+#define CHECK(expr)                          \
+    do {                                     \
+        soap_status st__ = (expr);           \
+        if (st__ != SOAP_OK) return st__;    \
+    } while (0)
+
+hipStream_t stream_of(const soap_exec* e) { return e ? static_cast<hipStream_t>(e->stream) : nullptr; }
+int32_t* status_of(const soap_exec* e) { return e ? e->dev_status : nullptr; }
+
+size_t elem_size(soap_precision p) { return p == SOAP_F64 ? 8 : 4; }
+
+soap_status launched(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) return fail(SOAP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    hipError_t last = hipGetLastError();
+    if (last != hipSuccess) return fail(SOAP_EDEVICE, "%s: %s", what, hipGetErrorString(last));
+    return SOAP_OK;
+}
+
+soap_status check_calc(const soap_calculator* c)
+{
+    if (!c) return fail(SOAP_EINVAL, "calculator must not be NULL");
+    return SOAP_OK;
+}
+
+FeatureArgs base_args(const soap_calculator* calc, const soap_exec* exec, bool f64, const DeviceTables* t)
+{
+    FeatureArgs a{};
+    a.S = calc->h.n_species;
+    a.nmax = calc->h.nmax;
+    a.lmax = calc->h.lmax;
+    a.include_center = calc->h.include_center;
+    a.rcut = calc->h.rcut;
+    a.width = calc->h.cutoff_width;
+    a.M = calc->M;
+    a.inv_delta = calc->inv_delta;
+    a.coef = f64 ? static_cast<const void*>(t->coef64) : static_cast<const void*>(t->coef32);
+    a.center = f64 ? static_cast<const void*>(t->center64) : static_cast<const void*>(t->center32);
+    a.status = status_of(exec);
+    return a;
+}
+
+// host geometry of one structure
+soap_status make_geom(const soap_calculator* calc, int s, const double* cell, const uint8_t* pbc, StructGeom& g)
+{
+    std::memset(&g, 0, sizeof(g));
+    bool any = false;
+    for (int k = 0; k < 3; ++k) {
+        g.pbc[k] = pbc[k] ? 1 : 0;
+        any = any || pbc[k];
+    }
+    if (!any) {
+        for (int k = 0; k < 9; ++k) g.H[k] = g.Hinv[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        for (int k = 0; k < 3; ++k) { g.nbin[k] = 1; g.reach[k] = 0; }
+        return SOAP_OK;
+    }
+    const double* H = cell;
+    for (int k = 0; k < 9; ++k) {
+        if (!std::isfinite(H[k])) return fail(SOAP_EINVAL, "cell of structure %d is not finite", s);
+        g.H[k] = H[k];
+    }
+    double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                 H[2] * (H[3] * H[7] - H[4] * H[6]);
+    double scale = 0.0;
+    for (int k = 0; k < 9; ++k) scale = std::max(scale, std::fabs(H[k]));
+    if (!(std::fabs(det) > 1e-10 * scale * scale * scale) || scale == 0.0)
+        return fail(SOAP_EINVAL, "cell of periodic structure %d is singular (det = %g)", s, det);
+    double* Hi = g.Hinv;
+    Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
+    Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+    Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+    Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
+    Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+    Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+    Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
+    Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+    Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    double rcut = calc->h.rcut;
+    for (int k = 0; k < 3; ++k) {
+        if (!pbc[k]) { g.nbin[k] = 1; g.reach[k] = 0; continue; }
+        // perpendicular width of the cell along lattice direction k
+        double gk = std::sqrt(Hi[0 * 3 + k] * Hi[0 * 3 + k] + Hi[1 * 3 + k] * Hi[1 * 3 + k] + Hi[2 * 3 + k] * Hi[2 * 3 + k]);
+        double width = 1.0 / gk;
+        int nb = int(std::floor(width / rcut));
+        nb = std::max(1, std::min(nb, 128));
+        double need = rcut * nb / width;
+        int reach = int(std::ceil(need * (1.0 + 1e-12)));
+        if (reach > 4096) return fail(SOAP_EINVAL, "cell of structure %d is too thin for rcut", s);
+        g.nbin[k] = nb;
+        g.reach[k] = std::max(reach, 1);
+    }
+    return SOAP_OK;
+}
+
+struct NbLayout {
+    size_t geom, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, centre_count, total;
+};
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+NbLayout nb_layout(int32_t n_struct, int64_t N, int64_t B)
+{
+    NbLayout L{};
+    size_t o = 0;
+    L.geom = o; o = up256(o + sizeof(StructGeom) * size_t(n_struct));
+    L.atom_struct = o; o = up256(o + 4 * size_t(N));
+    L.atom_bin = o; o = up256(o + 4 * size_t(N));
+    L.atom_wrap = o; o = up256(o + 12 * size_t(N));
+    L.bin_count = o; o = up256(o + 4 * size_t(B + 1));
+    L.bin_start = o; o = up256(o + 4 * size_t(B + 1));
+    L.bin_cursor = o; o = up256(o + 4 * size_t(B + 1));
+    L.bin_atoms = o; o = up256(o + 4 * size_t(N));
+    L.centre_count = o; o = up256(o + 8 * size_t(N + 1));
+    L.total = o;
+    return L;
+}
+
+soap_status build_geoms(const soap_calculator* calc, int32_t n_structures, const int64_t* atom_offsets,
+                        const double* cells, const uint8_t* pbc, std::vector<StructGeom>& geoms, int64_t& B)
+{
+    REQUIRE(n_structures >= 0, "n_structures must be >= 0 (got %d)", n_structures);
+    CHECK(check_ptr(atom_offsets, 8, "atom_offsets"));
+    if (n_structures > 0) {
+        CHECK(check_ptr(cells, 8, "cells"));
+        CHECK(check_ptr(pbc, 1, "pbc"));
+    }
+    REQUIRE(atom_offsets[0] == 0, "atom_offsets[0] must be 0");
+    geoms.resize(n_structures);
+    B = 0;
+    for (int s = 0; s < n_structures; ++s) {
+        REQUIRE(atom_offsets[s + 1] >= atom_offsets[s], "atom_offsets must be non-decreasing (structure %d)", s);
+        CHECK(make_geom(calc, s, cells + 9 * s, pbc + 3 * s, geoms[s]));
+        geoms[s].atom_lo = atom_offsets[s];
+        geoms[s].atom_hi = atom_offsets[s + 1];
+        geoms[s].bin_lo = B;
+        B += int64_t(geoms[s].nbin[0]) * geoms[s].nbin[1] * geoms[s].nbin[2];
+    }
+    REQUIRE(atom_offsets[n_structures] < (int64_t(1) << 31), "at most 2^31 - 1 atoms are supported");
+    return SOAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t soap_abi_version(void) { return SOAP_ABI_VERSION; }
+
+const char* soap_last_error(void) { return g_error; }
+
+soap_status soap_calculator_create(const soap_hypers* h, soap_calculator** out)
+{
+    clear_error();
+    REQUIRE(h != nullptr, "hypers must not be NULL");
+    REQUIRE(out != nullptr, "out must not be NULL");
+    *out = nullptr;
+    REQUIRE(h->n_species >= 1 && h->n_species <= 64, "n_species must be in [1, 64] (got %d)", h->n_species);
+    REQUIRE(h->nmax >= 1 && h->nmax <= 16, "nmax must be in [1, 16] (got %d)", h->nmax);
+    REQUIRE(h->lmax >= 0 && h->lmax <= 12, "lmax must be in [0, 12] (got %d)", h->lmax);
+    REQUIRE(std::isfinite(h->rcut) && h->rcut > 0, "rcut must be > 0");
+    REQUIRE(std::isfinite(h->cutoff_width) && h->cutoff_width > 0 && h->cutoff_width <= h->rcut,
+            "cutoff_width must be in (0, rcut]");
+    REQUIRE(std::isfinite(h->sigma) && h->sigma > 0, "sigma must be > 0");
+    REQUIRE(h->include_center == 0 || h->include_center == 1, "include_center must be 0 or 1");
+    REQUIRE(std::isfinite(h->spline_accuracy) && h->spline_accuracy > 0, "spline_accuracy must be > 0");
+    soap_calculator* c = new (std::nothrow) soap_calculator();
+    if (!c) return fail(SOAP_ENOMEM, "out of host memory");
+    c->h = *h;
+    c->L2 = (h->lmax + 1) * (h->lmax + 1);
+    c->K = h->n_species * h->nmax;
+    c->KK = int64_t(c->K) * (c->K + 1) / 2;
+    c->nl = h->nmax * (h->lmax + 1);
+    soap_status st = build_tables(c);
+    if (st != SOAP_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SOAP_OK;
+}
+
+soap_status soap_calculator_destroy(soap_calculator* calc)
+{
+    clear_error();
+    if (!calc) return SOAP_OK;
+    int cur = 0;
+    bool have = hipGetDevice(&cur) == hipSuccess;
+    for (size_t d = 0; d < calc->dev.size(); ++d) {
+        DeviceTables& t = calc->dev[d];
+        if (!t.ready) continue;
+        if (have) (void)hipSetDevice(int(d));
+        (void)hipFree(t.coef64);
+        (void)hipFree(t.coef32);
+        (void)hipFree(t.center64);
+        (void)hipFree(t.center32);
+    }
+    if (have) (void)hipSetDevice(cur);
+    delete calc;
+    return SOAP_OK;
+}
+
+soap_status soap_calculator_info(const soap_calculator* calc, soap_table_info* info)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(info != nullptr, "info must not be NULL");
+    *info = calc->info;
+    return SOAP_OK;
+}
+
+soap_status soap_calculator_upload(const soap_calculator* calc)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    const DeviceTables* t = nullptr;
+    return device_tables(calc, &t);
+}
+
+soap_status soap_radial_integral_host(const soap_calculator* calc, int32_t exact, int64_t n_r, const double* r,
+                                      double* I, double* dI)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(n_r >= 0, "n_r must be >= 0");
+    if (n_r == 0) return SOAP_OK;
+    CHECK(check_ptr(r, 8, "r"));
+    CHECK(check_ptr(I, 8, "I"));
+    CHECK(check_ptr(dI, 8, "dI", true));
+    for (int64_t k = 0; k < n_r; ++k)
+        REQUIRE(std::isfinite(r[k]) && r[k] >= 0 && r[k] <= calc->h.rcut, "r[%lld] outside [0, rcut]", (long long)k);
+    int nl = calc->nl;
+    if (exact) {
+        radial_exact(calc, n_r, r, I, dI);
+    } else {
+        for (int64_t k = 0; k < n_r; ++k) radial_spline_host(calc, r[k], I + k * nl, dI ? dI + k * nl : nullptr);
+    }
+    return SOAP_OK;
+}
+
+soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures,
+                                          const int64_t* atom_offsets, const double* cells, const uint8_t* pbc,
+                                          size_t* bytes)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(bytes != nullptr, "bytes must not be NULL");
+    std::vector<StructGeom> g;
+    int64_t B = 0;
+    CHECK(build_geoms(calc, n_structures, atom_offsets, cells, pbc, g, B));
+    *bytes = nb_layout(n_structures, atom_offsets[n_structures], B).total;
+    return SOAP_OK;
+}
+
+soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec* exec, int32_t n_structures,
+                                   const int64_t* atom_offsets, const double* cells, const uint8_t* pbc,
+                                   const double* positions, const int32_t* species, void* workspace,
+                                   size_t workspace_bytes, int64_t capacity, soap_precision vec_precision,
+                                   int64_t* pair_offsets, int32_t* pair_j, int32_t* pair_shift, void* pair_vec,
+                                   int32_t* pair_transpose)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(vec_precision == SOAP_F64 || vec_precision == SOAP_F32, "vec_precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(capacity >= 0 && capacity < (int64_t(1) << 31), "capacity must be in [0, 2^31)");
+    std::vector<StructGeom> geoms;
+    int64_t B = 0;
+    CHECK(build_geoms(calc, n_structures, atom_offsets, cells, pbc, geoms, B));
+    int64_t N = atom_offsets[n_structures];
+    CHECK(check_ptr(pair_offsets, 8, "pair_offsets"));
+    if (N > 0) {
+        CHECK(check_ptr(positions, 8, "positions"));
+        CHECK(check_ptr(species, 4, "species"));
+    }
+    if (capacity > 0) {
+        CHECK(check_ptr(pair_j, 4, "pair_j"));
+        CHECK(check_ptr(pair_shift, 4, "pair_shift"));
+        CHECK(check_ptr(pair_vec, elem_size(vec_precision), "pair_vec"));
+        CHECK(check_ptr(pair_transpose, 4, "pair_transpose", true));
+    }
+    NbLayout L = nb_layout(n_structures, N, B);
+    REQUIRE(workspace_bytes >= L.total, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, L.total);
+    CHECK(check_ptr(workspace, 256, "workspace"));
+    hipStream_t stream = stream_of(exec);
+    char* ws = static_cast<char*>(workspace);
+    // The geometry goes to the device through a small host staging buffer
+    // that stays alive on this thread until its next-but-three call.
+    thread_local std::vector<StructGeom> staging[4];
+    thread_local int slot = 0;
+    std::vector<StructGeom>& host = staging[slot];
+    slot = (slot + 1) & 3;
+    host = geoms;
+    if (n_structures > 0) {
+        hipError_t e = hipMemcpyAsync(ws + L.geom, host.data(), sizeof(StructGeom) * n_structures,
+                                      hipMemcpyHostToDevice, stream);
+        CHECK(launched(e, "geometry upload"));
+    }
+    NeighborArgs a{};
+    a.n_structures = n_structures;
+    a.n_atoms = N;
+    a.total_bins = B;
+    a.rcut = calc->h.rcut;
+    a.geom = reinterpret_cast<const StructGeom*>(ws + L.geom);
+    a.positions = positions;
+    a.species = species;
+    a.n_species = calc->h.n_species;
+    a.atom_struct = reinterpret_cast<int32_t*>(ws + L.atom_struct);
+    a.atom_bin = reinterpret_cast<int32_t*>(ws + L.atom_bin);
+    a.atom_wrap = reinterpret_cast<int32_t*>(ws + L.atom_wrap);
+    a.bin_count = reinterpret_cast<int32_t*>(ws + L.bin_count);
+    a.bin_start = reinterpret_cast<int32_t*>(ws + L.bin_start);
+    a.bin_atoms = reinterpret_cast<int32_t*>(ws + L.bin_atoms);
+    a.centre_count = reinterpret_cast<int64_t*>(ws + L.centre_count);
+    a.bin_cursor = reinterpret_cast<int32_t*>(ws + L.bin_cursor);
+    a.capacity = capacity;
+    a.pair_offsets = pair_offsets;
+    a.pair_j = pair_j;
+    a.pair_shift = pair_shift;
+    a.pair_vec = pair_vec;
+    a.vec_f64 = vec_precision == SOAP_F64;
+    a.pair_transpose = pair_transpose;
+    a.status = status_of(exec);
+    return launched(launch_neighbors(a, stream), "neighbour kernels");
+}
+
+static soap_status check_pairs(const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
+                               const void* pair_vec, int64_t pair_capacity, size_t es, bool need_vec = true)
+{
+    CHECK(check_ptr(species, 4, "species"));
+    CHECK(check_ptr(pair_offsets, 8, "pair_offsets"));
+    REQUIRE(pair_capacity >= 0 && pair_capacity < (int64_t(1) << 31), "pair_capacity must be in [0, 2^31)");
+    if (pair_capacity > 0) {
+        CHECK(check_ptr(pair_j, 4, "pair_j"));
+        if (need_vec) CHECK(check_ptr(pair_vec, es, "pair_vec"));
+    }
+    return SOAP_OK;
+}
+
+soap_status soap_spherical_expansion(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                     int64_t n_atoms, const int32_t* species, const int64_t* pair_offsets,
+                                     const int32_t* pair_j, const void* pair_vec, int64_t pair_capacity,
+                                     void* coeffs, void* dcoeffs, void* dcoeffs_self)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE((dcoeffs == nullptr) == (dcoeffs_self == nullptr), "dcoeffs and dcoeffs_self: both or neither");
+    if (n_atoms == 0) return SOAP_OK;
+    size_t es = elem_size(precision);
+    CHECK(check_pairs(species, pair_offsets, pair_j, pair_vec, pair_capacity, es));
+    CHECK(check_ptr(coeffs, es, "coeffs"));
+    CHECK(check_ptr(dcoeffs, es, "dcoeffs", true));
+    CHECK(check_ptr(dcoeffs_self, es, "dcoeffs_self", true));
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
+    a.n_atoms = n_atoms;
+    a.species = species;
+    a.pair_offsets = pair_offsets;
+    a.pair_j = pair_j;
+    a.pair_vec = pair_vec;
+    a.pair_capacity = pair_capacity;
+    a.coeffs = coeffs;
+    a.dcoeffs = dcoeffs;
+    a.dcoeffs_self = dcoeffs_self;
+    return launched(launch_features(a, precision == SOAP_F64, stream_of(exec)), "spherical expansion");
+}
+
+soap_status soap_power_spectrum(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                int64_t n_atoms, const void* coeffs, void* p, const int32_t* species,
+                                const int64_t* pair_offsets, const int32_t* pair_j, int64_t pair_capacity,
+                                const void* dcoeffs, const void* dcoeffs_self, void* dp, void* dp_self)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32 || precision == SOAP_BF16_F32ACC,
+            "precision must be SOAP_F64, SOAP_F32 or SOAP_BF16_F32ACC");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE((dp == nullptr) == (dp_self == nullptr), "dp and dp_self: both or neither");
+    REQUIRE(!(precision == SOAP_BF16_F32ACC && dp), "gradient rows are not produced on the bfloat16 path");
+    if (n_atoms == 0) return SOAP_OK;
+    size_t es = elem_size(precision);
+    CHECK(check_ptr(coeffs, es, "coeffs"));
+    CHECK(check_ptr(p, es, "p"));
+    if (dp) {
+        CHECK(check_pairs(species, pair_offsets, pair_j, nullptr, pair_capacity, es, false));
+        CHECK(check_ptr(dp, es, "dp"));
+        CHECK(check_ptr(dp_self, es, "dp_self"));
+        CHECK(check_ptr(dcoeffs_self, es, "dcoeffs_self"));
+        if (pair_capacity > 0) CHECK(check_ptr(dcoeffs, es, "dcoeffs"));
+    }
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
+    a.n_atoms = n_atoms;
+    a.species = species;
+    a.pair_offsets = pair_offsets;
+    a.pair_j = pair_j;
+    a.pair_capacity = pair_capacity;
+    a.coeffs = const_cast<void*>(coeffs);
+    a.p = p;
+    a.dcoeffs = const_cast<void*>(dcoeffs);
+    a.dcoeffs_self = const_cast<void*>(dcoeffs_self);
+    a.dp = dp;
+    a.dp_self = dp_self;
+    return launched(launch_power_spectrum(a, precision, stream_of(exec)), "power spectrum");
+}
+
+soap_status soap_features(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                          int64_t n_atoms, const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
+                          const void* pair_vec, int64_t pair_capacity, void* coeffs, void* p, void* dcoeffs,
+                          void* dcoeffs_self, void* dp, void* dp_self)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    bool grads = dcoeffs || dcoeffs_self || dp || dp_self;
+    REQUIRE(!grads || (dcoeffs_self && dp && dp_self && (dcoeffs || pair_capacity == 0)),
+            "dcoeffs, dcoeffs_self, dp and dp_self: all or none");
+    if (n_atoms == 0) return SOAP_OK;
+    size_t es = elem_size(precision);
+    CHECK(check_pairs(species, pair_offsets, pair_j, pair_vec, pair_capacity, es));
+    CHECK(check_ptr(coeffs, es, "coeffs"));
+    CHECK(check_ptr(p, es, "p"));
+    if (grads) {
+        CHECK(check_ptr(dcoeffs, es, "dcoeffs", pair_capacity == 0));
+        CHECK(check_ptr(dcoeffs_self, es, "dcoeffs_self"));
+        CHECK(check_ptr(dp, es, "dp"));
+        CHECK(check_ptr(dp_self, es, "dp_self"));
+    }
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
+    a.n_atoms = n_atoms;
+    a.species = species;
+    a.pair_offsets = pair_offsets;
+    a.pair_j = pair_j;
+    a.pair_vec = pair_vec;
+    a.pair_capacity = pair_capacity;
+    a.coeffs = coeffs;
+    a.p = p;
+    a.dcoeffs = grads ? dcoeffs : nullptr;
+    a.dcoeffs_self = grads ? dcoeffs_self : nullptr;
+    a.dp = grads ? dp : nullptr;
+    a.dp_self = grads ? dp_self : nullptr;
+    return launched(launch_features(a, precision == SOAP_F64, stream_of(exec)), "features");
+}
+
+soap_status soap_power_spectrum_backward(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                         int64_t n_atoms, const void* coeffs, const void* grad_p, void* grad_coeffs)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    if (n_atoms == 0) return SOAP_OK;
+    size_t es = elem_size(precision);
+    CHECK(check_ptr(coeffs, es, "coeffs"));
+    CHECK(check_ptr(grad_p, es, "grad_p"));
+    CHECK(check_ptr(grad_coeffs, es, "grad_coeffs"));
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
+    a.n_atoms = n_atoms;
+    a.coeffs = const_cast<void*>(coeffs);
+    return launched(launch_power_spectrum_backward(a, precision == SOAP_F64, grad_p, grad_coeffs, stream_of(exec)),
+                    "power spectrum backward");
+}
+
+soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const soap_exec* exec,
+                                              soap_precision precision, int64_t n_atoms, const int32_t* species,
+                                              const int64_t* pair_offsets, const int32_t* pair_j,
+                                              const void* pair_vec, const int32_t* pair_transpose,
+                                              int64_t pair_capacity, const void* grad_coeffs, void* grad_pair_vec,
+                                              void* grad_positions)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    if (n_atoms == 0) return SOAP_OK;
+    size_t es = elem_size(precision);
+    CHECK(check_pairs(species, pair_offsets, pair_j, pair_vec, pair_capacity, es));
+    if (pair_capacity > 0) {
+        CHECK(check_ptr(pair_transpose, 4, "pair_transpose"));
+        CHECK(check_ptr(grad_pair_vec, es, "grad_pair_vec"));
+    }
+    CHECK(check_ptr(grad_coeffs, es, "grad_coeffs"));
+    CHECK(check_ptr(grad_positions, es, "grad_positions"));
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
+    a.n_atoms = n_atoms;
+    a.species = species;
+    a.pair_offsets = pair_offsets;
+    a.pair_j = pair_j;
+    a.pair_vec = pair_vec;
+    a.pair_capacity = pair_capacity;
+    return launched(launch_expansion_backward(a, precision == SOAP_F64, pair_transpose, grad_coeffs, grad_pair_vec,
+                                              grad_positions, stream_of(exec)),
+                    "expansion backward");
+}
+
+soap_status soap_read_device_status(const soap_exec* exec)
+{
+    clear_error();
+    hipError_t e = hipStreamSynchronize(stream_of(exec));
+    if (e != hipSuccess) return fail(SOAP_EDEVICE, "stream synchronisation failed: %s", hipGetErrorString(e));
+    if (!exec || !exec->dev_status) return SOAP_OK;
+    int32_t v = 0;
+    e = hipMemcpy(&v, exec->dev_status, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(SOAP_EDEVICE, "status read failed: %s", hipGetErrorString(e));
+    if (v != 0) fail(soap_status(v), "device reported status %d", v);
+    return soap_status(v);
+}
+
+}  // extern "C"

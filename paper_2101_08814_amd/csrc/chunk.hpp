@@ -1,0 +1,171 @@
+// Per-centre LDS staging of a chunk of pairs, shared by the forward
+// (expansion, power spectrum, gradient rows) and reverse-mode kernels.
+//
+// A work-group of kThreads lanes owns one centre.  For a chunk of its pairs
+// the staging step leaves in LDS, per pair p: the unit vector u, r, 1/r,
+// f_cut and f'_cut, the species of j, the splined radial integral times the
+// cutoff R_nl = f I~_nl and (with gradients) its r-derivative dR_nl, the real
+// harmonics Y_lm and (with gradients) their gradients with respect to the
+// pair vector, dY_{x,lm}.  One lane per pair computes the geometry, one lane
+// per (pair, m) a column of the Legendre table, one lane per (pair, n, l)
+// evaluates the spline, one lane per (pair, lm) the harmonics.
+#pragma once
+
+#include "soap_internal.hpp"
+#include "sph.hpp"
+
+namespace soap {
+namespace dev {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ void put_status(int32_t* st, int v)
+{
+    if (st) *st = v;
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Dims {
+    int S, nmax, lmax, L2, nl, K, nq;
+    int64_t KK;
+};
+
+__host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
+{
+    Dims d;
+    d.S = S;
+    d.nmax = nmax;
+    d.lmax = lmax;
+    d.L2 = (lmax + 1) * (lmax + 1);
+    d.nl = nmax * (lmax + 1);
+    d.K = S * nmax;
+    d.nq = (lmax + 1) * (lmax + 2) / 2;
+    d.KK = int64_t(d.K) * (d.K + 1) / 2;
+    return d;
+}
+
+// LDS layout in elements of T (ints counted as T-sized slots).
+struct Layout {
+    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, total;
+};
+
+__host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, bool rows_p, bool self_rows = true)
+{
+    Layout L;
+    int o = 0;
+    L.c = o; o += d.K * d.L2;
+    L.dcs = o; o += (grad && self_rows) ? 3 * d.K * d.L2 : 0;
+    L.ux = o; o += ch;
+    L.uy = o; o += ch;
+    L.uz = o; o += ch;
+    L.r = o; o += ch;
+    L.rinv = o; o += ch;
+    L.f = o; o += ch;
+    L.df = o; o += ch;
+    L.R = o; o += ch * d.nl;
+    L.dR = o; o += grad ? ch * d.nl : 0;
+    L.Y = o; o += ch * d.L2;
+    L.dY = o; o += grad ? 3 * ch * d.L2 : 0;
+    L.qt = o; o += ch * d.nq;
+    L.cre = o; o += ch * (d.lmax + 1);
+    L.cim = o; o += ch * (d.lmax + 1);
+    L.yz = o; o += (grad && rows_p) ? kWaves * 4 * (d.lmax + 1) * d.K : 0;
+    L.spc = o; o += ch;
+    L.seg = o; o += 2 * d.S;
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+struct Smem {
+    T *c, *dcs, *ux, *uy, *uz, *r, *rinv, *f, *df, *R, *dR, *Y, *dY, *qt, *cre, *cim, *yz;
+    int *spc, *seg;
+    __device__ Smem(T* base, const Layout& L)
+        : c(base + L.c), dcs(base + L.dcs), ux(base + L.ux), uy(base + L.uy), uz(base + L.uz), r(base + L.r), rinv(base + L.rinv),
+          f(base + L.f), df(base + L.df), R(base + L.R), dR(base + L.dR), Y(base + L.Y), dY(base + L.dY),
+          qt(base + L.qt), cre(base + L.cre), cim(base + L.cim), yz(base + L.yz),
+          spc(reinterpret_cast<int*>(base + L.spc)), seg(reinterpret_cast<int*>(base + L.seg))
+    {
+    }
+};
+
+// Stage nc pairs starting at q0 (all lanes of the block take part).
+template <typename T, bool GRAD>
+__device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int64_t q0, int nc)
+{
+    const int tid = threadIdx.x;
+    const T* vec = static_cast<const T*>(a.pair_vec);
+    if (tid < nc) {
+        int64_t q = q0 + tid;
+        T vx = vec[3 * q], vy = vec[3 * q + 1], vz = vec[3 * q + 2];
+        T r = sqrt(vx * vx + vy * vy + vz * vz);
+        int j = a.pair_j[q];
+        bool bad_j = j < 0 || j >= a.n_atoms;
+        if (bad_j) put_status(a.status, SOAP_EINVAL);
+        int sp = bad_j ? -1 : a.species[j];
+        bool bad_sp = sp < 0 || sp >= d.S;
+        if (bad_sp) { if (!bad_j) put_status(a.status, SOAP_ESPECIES); sp = 0; }
+        T f = T(0), df = T(0);
+        if (!(r > T(1e-8))) {
+            put_status(a.status, SOAP_EGEOMETRY);
+            s.ux[tid] = T(0); s.uy[tid] = T(0); s.uz[tid] = T(1); s.rinv[tid] = T(0);
+        } else {
+            T ri = T(1) / r;
+            s.ux[tid] = vx * ri; s.uy[tid] = vy * ri; s.uz[tid] = vz * ri; s.rinv[tid] = ri;
+            if (!bad_sp) f = dev::fcut<T>(r, T(a.rcut), T(a.width), df);
+        }
+        s.f[tid] = f;
+        s.df[tid] = df;
+        s.spc[tid] = sp;
+        s.r[tid] = r;
+    }
+    __syncthreads();
+    // Qt columns and (x + i y)^m: one lane per (pair, m); species segments
+    const int lm1 = d.lmax + 1;
+    for (int t = tid; t < nc * lm1; t += kThreads) {
+        int p = t / lm1, m = t - p * lm1;
+        dev::q_column<T>(m, d.lmax, s.ux[p], s.uy[p], s.uz[p], s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1);
+    }
+    for (int sp = tid; sp < d.S; sp += kThreads) {
+        int lo = nc, hi = 0;
+        for (int p = 0; p < nc; ++p)
+            if (s.spc[p] == sp) { lo = p < lo ? p : lo; hi = p + 1; }
+        s.seg[2 * sp] = lo;
+        s.seg[2 * sp + 1] = hi;
+    }
+    // radial spline: one lane per (pair, n, l)
+    const T* coef = static_cast<const T*>(a.coef);
+    for (int t = tid; t < nc * d.nl; t += kThreads) {
+        int p = t / d.nl, j = t - p * d.nl;
+        T r = s.r[p];
+        T v, dv;
+        dev::spline_eval<T>(coef, a.M, T(a.inv_delta), d.nl, j, r, v, dv);
+        s.R[p * d.nl + j] = s.f[p] * v;
+        if (GRAD) s.dR[p * d.nl + j] = s.df[p] * v + s.f[p] * dv;
+    }
+    __syncthreads();
+    // harmonics and gradients: one lane per (pair, lm)
+    for (int t = tid; t < nc * d.L2; t += kThreads) {
+        int p = t / d.L2, lm = t - p * d.L2;
+        T Y, gx, gy, gz;
+        dev::ylm_and_grad<T>(lm, s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1, s.ux[p], s.uy[p], s.uz[p],
+                             s.rinv[p], Y, gx, gy, gz);
+        s.Y[p * d.L2 + lm] = Y;
+        if (GRAD) {
+            s.dY[(p * 3 + 0) * d.L2 + lm] = gx;
+            s.dY[(p * 3 + 1) * d.L2 + lm] = gy;
+            s.dY[(p * 3 + 2) * d.L2 + lm] = gz;
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace dev
+}  // namespace soap

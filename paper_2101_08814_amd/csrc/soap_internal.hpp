@@ -1,0 +1,130 @@
+// Internal declarations shared by the host side of the library and the
+// kernel launchers.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "soap_mi355x.h"
+
+namespace soap {
+
+// Tables of one calculator on one device.
+struct DeviceTables {
+    bool ready = false;
+    double* coef64 = nullptr;    // [M][nmax][lmax+1][4] local-t cubic coefficients
+    float* coef32 = nullptr;
+    double* center64 = nullptr;  // [nmax]  I~_n0(0) * Y_00
+    float* center32 = nullptr;
+};
+
+// Geometry of one structure for the neighbour search (host-built, copied to
+// the start of the neighbour workspace).
+struct StructGeom {
+    double H[9];        // rows are lattice vectors h1, h2, h3 (identity if no pbc)
+    double Hinv[9];     // inverse of H: fractional f = r . Hinv
+    int32_t nbin[3];    // bins per axis (1 on non-periodic axes)
+    int32_t reach[3];   // stencil half-width in bins per axis (0 on non-periodic axes)
+    int32_t pbc[3];
+    int32_t pad0;
+    int64_t atom_lo, atom_hi;
+    int64_t bin_lo;     // first global bin of this structure
+    int64_t pad1;
+};
+
+}  // namespace soap
+
+struct soap_calculator {
+    soap_hypers h;
+    int L2 = 0, K = 0, nl = 0;
+    int64_t KK = 0;
+    int64_t M = 0;
+    double delta = 0.0, inv_delta = 0.0;
+    std::vector<double> coef64;       // host copy of the FP64 table
+    std::vector<float> coef32;
+    std::vector<double> center;       // [nmax]
+    std::vector<double> orth;         // S^{-1/2}, [nmax][nmax]
+    soap_table_info info{};
+    mutable std::mutex mu;
+    mutable std::vector<soap::DeviceTables> dev;
+};
+
+namespace soap {
+
+// error reporting (thread-local message)
+soap_status fail(soap_status st, const char* fmt, ...);
+void clear_error();
+
+// tables.cpp
+soap_status build_tables(soap_calculator* calc);
+void radial_exact(const soap_calculator* calc, int64_t n, const double* r, double* I, double* dI);
+void radial_spline_host(const soap_calculator* calc, double r, double* I, double* dI);
+soap_status device_tables(const soap_calculator* calc, const DeviceTables** out);
+
+// launchers (kernels in the .hip files); each returns a hipError_t
+struct FeatureArgs {
+    int S, nmax, lmax, include_center;
+    double rcut, width;
+    int64_t M;
+    double inv_delta;
+    int64_t n_atoms;
+    const int32_t* species;
+    const int64_t* pair_offsets;
+    const int32_t* pair_j;
+    const void* pair_vec;
+    int64_t pair_capacity;
+    const void* coef;       // table of the working precision
+    const void* center;     // [nmax]
+    void* coeffs;
+    void* p;
+    void* dcoeffs;
+    void* dcoeffs_self;
+    void* dp;
+    void* dp_self;
+    int32_t* status;
+};
+
+hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream);
+hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipStream_t stream);
+hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream);
+hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const void* grad_p,
+                                          void* grad_coeffs, hipStream_t stream);
+hipError_t launch_expansion_backward(const FeatureArgs& a, bool f64, const int32_t* pair_transpose,
+                                     const void* grad_coeffs, void* grad_pair_vec,
+                                     void* grad_positions, hipStream_t stream);
+
+struct NeighborArgs {
+    int32_t n_structures;
+    int64_t n_atoms;
+    int64_t total_bins;
+    double rcut;
+    const StructGeom* geom;       // device copy (in the workspace)
+    const double* positions;
+    const int32_t* species;
+    int32_t n_species;
+    // workspace arrays
+    int32_t* atom_struct;         // [N]
+    int32_t* atom_bin;            // [N] global bin index
+    int32_t* atom_wrap;           // [N][3] integer wrap of the fractional coordinates
+    int32_t* bin_count;           // [total_bins + 1]
+    int32_t* bin_start;           // [total_bins + 1]
+    int32_t* bin_atoms;           // [N]
+    int64_t* centre_count;        // [N]
+    int32_t* bin_cursor;          // [total_bins]
+    int64_t capacity;
+    int64_t* pair_offsets;
+    int32_t* pair_j;
+    int32_t* pair_shift;
+    void* pair_vec;
+    bool vec_f64;
+    int32_t* pair_transpose;
+    int32_t* status;
+};
+
+hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream);
+
+}  // namespace soap

@@ -1,0 +1,425 @@
+// Host-side FP64 construction of the radial spline tables.
+//
+// Sec. 4.B: GTO radial basis, analytic overlap, Loewdin orthogonalisation
+//           S^{-1/2} (here: Householder tridiagonalisation followed by
+//           shifted QR sweeps on the tridiagonal matrix).
+// App. A:   the radial integral through the restricted function
+//             G(a, b, r) = Gamma(a)/Gamma(b) exp(-c r^2) 1F1(a; b; alpha r^2),
+//           alpha = c^2 / (c + d_n), evaluated directly only at the two
+//           largest l of each n (power series below a switch point found by
+//           bisection, the large-z asymptotic expansion above it) and by the
+//           two-step downward recurrence in l for the rest; dG/dr from G at
+//           (a+1, b+1).
+// Sec. 4.D: the orthogonalised radial integral tabulated on a uniform grid
+//           over [0, rcut] and interpolated by a cubic spline (clamped with
+//           the exact end derivatives).  The grid is doubled, from 1024
+//           intervals, until the spline error at four interior points of
+//           every interval is below the requested accuracy.  Each interval
+//           is stored as the cubic a0 + t (a1 + t (a2 + t a3)) in the local
+//           coordinate t = (r - r_k) / delta, the form the kernels evaluate.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "soap_internal.hpp"
+
+namespace soap {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// ---------------------------------------------------------------- basis
+struct Gto {
+    std::vector<double> sigma, d, norm;
+    explicit Gto(int nmax, double rcut) : sigma(nmax), d(nmax), norm(nmax)
+    {
+        for (int n = 0; n < nmax; ++n) {
+            double s = rcut * std::max(std::sqrt(double(n)), 1.0) / nmax;
+            sigma[n] = s;
+            d[n] = 0.5 / (s * s);
+            // N_n^2 = 2 / (sigma_n^(2n+3) Gamma(n + 3/2))
+            norm[n] = std::exp(0.5 * (std::log(2.0) - (2.0 * n + 3.0) * std::log(s) - std::lgamma(n + 1.5)));
+        }
+    }
+};
+
+// S_nm = N_n N_m Gamma((n+m+3)/2) / (2 (d_n + d_m)^((n+m+3)/2))
+std::vector<double> gto_overlap(const Gto& g, int nmax)
+{
+    std::vector<double> S(nmax * nmax);
+    for (int n = 0; n < nmax; ++n)
+        for (int m = 0; m < nmax; ++m) {
+            double e = 0.5 * (n + m + 3);
+            S[n * nmax + m] = g.norm[n] * g.norm[m] * std::exp(std::lgamma(e) - e * std::log(g.d[n] + g.d[m])) / 2.0;
+        }
+    return S;
+}
+
+// Symmetric eigen-decomposition A = Q diag(w) Q^T of a small dense matrix.
+// Householder reflections bring A to tridiagonal form; implicit QR sweeps
+// with a Wilkinson shift (Golub & Van Loan, Sec. 8.3) diagonalise it.  The
+// rotations are applied to the dense matrix: n <= 16 here, so simplicity
+// wins over the O(n) tridiagonal update.
+void sym_eigen(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& Q)
+{
+    auto at = [n](std::vector<double>& M, int i, int j) -> double& { return M[i * n + j]; };
+    Q.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+    // Householder: zero column k below the subdiagonal.
+    for (int k = 0; k + 2 < n; ++k) {
+        std::vector<double> v(n, 0.0);
+        double norm = 0.0;
+        for (int i = k + 1; i < n; ++i) { v[i] = at(A, i, k); norm += v[i] * v[i]; }
+        norm = std::sqrt(norm);
+        if (norm == 0.0) continue;
+        double alpha = v[k + 1] > 0 ? -norm : norm;
+        v[k + 1] -= alpha;
+        double vn = 0.0;
+        for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
+        if (vn == 0.0) continue;
+        vn = std::sqrt(vn);
+        for (int i = k + 1; i < n; ++i) v[i] /= vn;
+        // A <- (I - 2vv^T) A (I - 2vv^T);  Q <- Q (I - 2vv^T)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int i = k + 1; i < n; ++i) s += v[i] * at(A, i, j);
+            for (int i = k + 1; i < n; ++i) at(A, i, j) -= 2.0 * v[i] * s;
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += at(A, i, j) * v[j];
+            for (int j = k + 1; j < n; ++j) at(A, i, j) -= 2.0 * s * v[j];
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += at(Q, i, j) * v[j];
+            for (int j = k + 1; j < n; ++j) at(Q, i, j) -= 2.0 * s * v[j];
+        }
+    }
+    // rotation in the (p, p+1) plane applied as A <- G A G^T, Q <- Q G^T
+    auto rotate = [&](int p, double c, double s) {
+        for (int j = 0; j < n; ++j) {
+            double x = at(A, p, j), y = at(A, p + 1, j);
+            at(A, p, j) = c * x + s * y;
+            at(A, p + 1, j) = -s * x + c * y;
+        }
+        for (int i = 0; i < n; ++i) {
+            double x = at(A, i, p), y = at(A, i, p + 1);
+            at(A, i, p) = c * x + s * y;
+            at(A, i, p + 1) = -s * x + c * y;
+        }
+        for (int i = 0; i < n; ++i) {
+            double x = at(Q, i, p), y = at(Q, i, p + 1);
+            at(Q, i, p) = c * x + s * y;
+            at(Q, i, p + 1) = -s * x + c * y;
+        }
+    };
+    const double eps = 2.220446049250313e-16;
+    int hi = n - 1;
+    for (int iter = 0; hi > 0 && iter < 100 * n; ++iter) {
+        // deflate negligible subdiagonal entries
+        for (int i = 0; i < hi; ++i)
+            if (std::fabs(at(A, i + 1, i)) <= eps * (std::fabs(at(A, i, i)) + std::fabs(at(A, i + 1, i + 1)))) {
+                at(A, i + 1, i) = at(A, i, i + 1) = 0.0;
+            }
+        while (hi > 0 && at(A, hi, hi - 1) == 0.0) --hi;
+        if (hi == 0) break;
+        int lo = hi - 1;
+        while (lo > 0 && at(A, lo, lo - 1) != 0.0) --lo;
+        // Wilkinson shift from the trailing 2x2 block
+        double a = at(A, hi - 1, hi - 1), b = at(A, hi, hi - 1), cc = at(A, hi, hi);
+        double delta = 0.5 * (a - cc);
+        double sgn = delta >= 0 ? 1.0 : -1.0;
+        double mu = cc - b * b / (delta + sgn * std::sqrt(delta * delta + b * b));
+        double x = at(A, lo, lo) - mu, z = at(A, lo + 1, lo);
+        for (int k = lo; k < hi; ++k) {
+            double r = std::hypot(x, z);
+            double c = r == 0 ? 1.0 : x / r, s = r == 0 ? 0.0 : z / r;
+            rotate(k, c, s);
+            if (k + 1 < hi) { x = at(A, k + 1, k); z = at(A, k + 2, k); }
+        }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = at(A, i, i);
+}
+
+// ------------------------------------------------------- restricted 1F1
+// G(a, b, r) = Gamma(a)/Gamma(b) exp(-c r^2) 1F1(a; b; alpha r^2).
+class GFunction {
+public:
+    GFunction(double a, double b, double c, double alpha) : a_(a), b_(b), c_(c), alpha_(alpha)
+    {
+        lgr_ = std::lgamma(a) - std::lgamma(b);
+        // Switch point: smallest z (found by bisection) above which the
+        // truncated asymptotic expansion agrees with the series to 1e-14.
+        double lo = 0.0, hi = 690.0;
+        if (!agree(hi)) {
+            zswitch_ = hi;
+        } else {
+            for (int it = 0; it < 60; ++it) {
+                double mid = 0.5 * (lo + hi);
+                (agree(mid) ? hi : lo) = mid;
+            }
+            zswitch_ = hi;
+        }
+    }
+    double zswitch() const { return zswitch_; }
+    double operator()(double r) const
+    {
+        double z = alpha_ * r * r;
+        if (z < zswitch_) return std::exp(lgr_ - c_ * r * r) * series(z);
+        // exp(z - c r^2) z^(a-b) sum_s (b-a)_s (1-a)_s / s! z^-s; the
+        // Gamma ratio of the asymptotic form cancels the one in G.
+        return std::exp(z - c_ * r * r + (a_ - b_) * std::log(z)) * asym_sum(z);
+    }
+
+private:
+    double series(double z) const
+    {
+        double term = 1.0, sum = 1.0;
+        for (int s = 1; s < 100000; ++s) {
+            term *= (a_ + s - 1) * z / ((b_ + s - 1) * s);
+            sum += term;
+            if (term < 1e-17 * sum) break;
+        }
+        return sum;
+    }
+    double asym_sum(double z) const
+    {
+        double term = 1.0, sum = 1.0, prev = 1e300;
+        for (int s = 1; s < 1000; ++s) {
+            term *= (b_ - a_ + s - 1) * (1.0 - a_ + s - 1) / (s * z);
+            if (std::fabs(term) >= prev || term == 0.0) break;   // divergent tail starts
+            sum += term;
+            prev = std::fabs(term);
+            if (prev < 1e-17 * std::fabs(sum)) break;
+        }
+        return sum;
+    }
+    bool agree(double z) const
+    {
+        if (z <= 0) return false;
+        // compare e^{-z} 1F1 in both forms (Gamma(a)/Gamma(b) scaled out)
+        double s = series(z) * std::exp(-z);
+        double as = std::exp((a_ - b_) * std::log(z) - lgr_) * asym_sum(z);
+        return std::fabs(as - s) <= 1e-14 * std::fabs(s);
+    }
+    double a_, b_, c_, alpha_, lgr_, zswitch_;
+};
+
+struct RadialExact {
+    int nmax, lmax;
+    double c;
+    Gto gto;
+    std::vector<double> alpha, pref;          // per n: alpha_n; per (n,l): prefactor
+    std::vector<GFunction> top;               // per n: G and H at l = lmax, lmax-1
+    std::vector<double> X;                    // S^{-1/2}
+
+    RadialExact(const soap_hypers& h, const std::vector<double>& orth)
+        : nmax(h.nmax), lmax(h.lmax), c(0.5 / (h.sigma * h.sigma)), gto(h.nmax, h.rcut), X(orth)
+    {
+        alpha.resize(nmax);
+        pref.resize(nmax * (lmax + 1));
+        for (int n = 0; n < nmax; ++n) {
+            alpha[n] = c * c / (c + gto.d[n]);
+            for (int l = 0; l <= lmax; ++l) {
+                double a = 0.5 * (n + l + 3);
+                // pi^{3/2} N_n c^l (c + d_n)^{-a}
+                pref[n * (lmax + 1) + l] = std::pow(kPi, 1.5) * gto.norm[n] *
+                                           std::exp(l * std::log(c) - a * std::log(c + gto.d[n]));
+            }
+            for (int L = lmax; L >= std::max(0, lmax - 1); --L) {
+                double a = 0.5 * (n + L + 3), b = L + 1.5;
+                top.emplace_back(a, b, c, alpha[n]);              // G(a, b)
+                top.emplace_back(a + 1, b + 1, c, alpha[n]);      // H = G(a+1, b+1)
+            }
+        }
+    }
+
+    // raw (non-orthogonal) I_nl(r) and dI_nl/dr
+    void raw(double r, double* I, double* dI) const
+    {
+        int per_n = (lmax >= 1) ? 4 : 2;
+        std::vector<double> G(lmax + 3), H(lmax + 3);
+        for (int n = 0; n < nmax; ++n) {
+            double z = alpha[n] * r * r;
+            const GFunction* t = &top[n * per_n];
+            G[lmax] = t[0](r);
+            H[lmax] = t[1](r);
+            if (lmax >= 1) {
+                G[lmax - 1] = t[2](r);
+                H[lmax - 1] = t[3](r);
+            }
+            // two-step downward recurrence (App. A Eq. 1f1-recurrence):
+            //   H_l = z H_{l+2} + (b_l + 1) G_{l+2}
+            //   G_l = z (a - b)/a G_{l+2} + (b/a) H_l
+            for (int l = lmax - 2; l >= 0; --l) {
+                double a = 0.5 * (n + l + 3), b = l + 1.5;
+                H[l] = z * H[l + 2] + (b + 1) * G[l + 2];
+                G[l] = z * (a - b) / a * G[l + 2] + (b / a) * H[l];
+            }
+            for (int l = 0; l <= lmax; ++l) {
+                double P = pref[n * (lmax + 1) + l];
+                double rl = (l == 0) ? 1.0 : std::pow(r, l);
+                I[n * (lmax + 1) + l] = P * rl * G[l];
+                if (dI) {
+                    // dG/dr = 2 alpha r H - 2 c r G
+                    double dG = 2.0 * alpha[n] * r * H[l] - 2.0 * c * r * G[l];
+                    double drl = (l == 0) ? 0.0 : (l == 1 ? 1.0 : l * std::pow(r, l - 1));
+                    dI[n * (lmax + 1) + l] = P * (drl * G[l] + rl * dG);
+                }
+            }
+        }
+    }
+
+    void orth(double r, double* I, double* dI) const
+    {
+        int nl = nmax * (lmax + 1);
+        std::vector<double> raw_I(nl), raw_dI(nl);
+        raw(r, raw_I.data(), dI ? raw_dI.data() : nullptr);
+        for (int n = 0; n < nmax; ++n)
+            for (int l = 0; l <= lmax; ++l) {
+                double s = 0.0, ds = 0.0;
+                for (int m = 0; m < nmax; ++m) {
+                    s += X[n * nmax + m] * raw_I[m * (lmax + 1) + l];
+                    if (dI) ds += X[n * nmax + m] * raw_dI[m * (lmax + 1) + l];
+                }
+                I[n * (lmax + 1) + l] = s;
+                if (dI) dI[n * (lmax + 1) + l] = ds;
+            }
+    }
+};
+
+// Clamped cubic spline through y_0..y_M on a uniform grid of step h; returns
+// the second derivatives at the knots (tridiagonal solve).
+std::vector<double> clamped_second_derivatives(const std::vector<double>& y, double h, double d0, double dM)
+{
+    size_t M = y.size() - 1;
+    std::vector<double> diag(M + 1), rhs(M + 1), sub(M + 1), sup(M + 1);
+    diag[0] = h / 3.0; sup[0] = h / 6.0;
+    rhs[0] = (y[1] - y[0]) / h - d0;
+    for (size_t k = 1; k < M; ++k) {
+        sub[k] = h / 6.0; diag[k] = 2.0 * h / 3.0; sup[k] = h / 6.0;
+        rhs[k] = (y[k + 1] - 2.0 * y[k] + y[k - 1]) / h;
+    }
+    sub[M] = h / 6.0; diag[M] = h / 3.0;
+    rhs[M] = dM - (y[M] - y[M - 1]) / h;
+    // Thomas algorithm
+    for (size_t k = 1; k <= M; ++k) {
+        double w = sub[k] / diag[k - 1];
+        diag[k] -= w * sup[k - 1];
+        rhs[k] -= w * rhs[k - 1];
+    }
+    std::vector<double> m2(M + 1);
+    m2[M] = rhs[M] / diag[M];
+    for (size_t k = M; k-- > 0;) m2[k] = (rhs[k] - sup[k] * m2[k + 1]) / diag[k];
+    return m2;
+}
+
+}  // namespace
+
+soap_status build_tables(soap_calculator* calc)
+{
+    const soap_hypers& h = calc->h;
+    int nmax = h.nmax, lmax = h.lmax, nl = nmax * (lmax + 1);
+    Gto gto(nmax, h.rcut);
+    std::vector<double> S = gto_overlap(gto, nmax), w, Q;
+    sym_eigen(nmax, S, w, Q);
+    double wmin = *std::min_element(w.begin(), w.end()), wmax = *std::max_element(w.begin(), w.end());
+    if (!(wmin > 0)) return fail(SOAP_EINVAL, "GTO overlap matrix is not positive definite (nmax=%d)", nmax);
+    calc->orth.assign(nmax * nmax, 0.0);
+    for (int i = 0; i < nmax; ++i)
+        for (int j = 0; j < nmax; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < nmax; ++k) s += Q[i * nmax + k] * Q[j * nmax + k] / std::sqrt(w[k]);
+            calc->orth[i * nmax + j] = s;
+        }
+    calc->info.overlap_condition = wmax / wmin;
+
+    RadialExact ex(h, calc->orth);
+    std::vector<double> I0(nl), dI0(nl);
+    ex.orth(0.0, I0.data(), dI0.data());
+    calc->center.resize(nmax);
+    for (int n = 0; n < nmax; ++n) calc->center[n] = I0[n * (lmax + 1)] / std::sqrt(4.0 * kPi);
+
+    double acc = h.spline_accuracy;
+    for (int64_t M = 1024; M <= (int64_t(1) << 16); M *= 2) {
+        double dr = h.rcut / double(M);
+        // exact values on the knots, derivatives at both ends
+        std::vector<double> knots((M + 1) * nl), dend0(nl), dendM(nl), tmp(nl);
+        for (int64_t k = 0; k <= M; ++k) {
+            double r = (k == M) ? h.rcut : k * dr;
+            ex.orth(r, &knots[k * nl], k == 0 ? dend0.data() : (k == M ? dendM.data() : nullptr));
+        }
+        std::vector<double> coef(M * nl * 4);
+        std::vector<double> y(M + 1);
+        for (int j = 0; j < nl; ++j) {
+            for (int64_t k = 0; k <= M; ++k) y[k] = knots[k * nl + j];
+            std::vector<double> m2 = clamped_second_derivatives(y, dr, dend0[j], dendM[j]);
+            double h26 = dr * dr / 6.0;
+            for (int64_t k = 0; k < M; ++k) {
+                double* cf = &coef[(k * nl + j) * 4];
+                // y(t) = A y_k + B y_k+1 + ((A^3-A) y''_k + (B^3-B) y''_k+1) h^2/6,
+                // A = 1 - t, B = t, expanded in powers of t
+                cf[0] = y[k];
+                cf[1] = (y[k + 1] - y[k]) - h26 * (2.0 * m2[k] + m2[k + 1]);
+                cf[2] = 3.0 * h26 * m2[k];
+                cf[3] = h26 * (m2[k + 1] - m2[k]);
+            }
+        }
+        // error at four interior points per interval
+        double err = 0.0, derr = 0.0;
+        std::vector<double> Ie(nl), dIe(nl);
+        for (int64_t k = 0; k < M; ++k)
+            for (int q = 1; q <= 4; ++q) {
+                double t = q / 5.0, r = (k + t) * dr;
+                ex.orth(r, Ie.data(), dIe.data());
+                for (int j = 0; j < nl; ++j) {
+                    const double* cf = &coef[(k * nl + j) * 4];
+                    double v = cf[0] + t * (cf[1] + t * (cf[2] + t * cf[3]));
+                    double dv = (cf[1] + t * (2.0 * cf[2] + 3.0 * t * cf[3])) / dr;
+                    err = std::max(err, std::fabs(v - Ie[j]));
+                    derr = std::max(derr, std::fabs(dv - dIe[j]));
+                }
+            }
+        if (err <= acc || M == (int64_t(1) << 16)) {
+            if (err > acc) return fail(SOAP_EINVAL, "spline accuracy %.3g not reached (%.3g at M=%lld)", acc, err, (long long)M);
+            calc->M = M;
+            calc->delta = dr;
+            calc->inv_delta = double(M) / h.rcut;
+            calc->coef64 = std::move(coef);
+            calc->coef32.resize(calc->coef64.size());
+            for (size_t i = 0; i < calc->coef64.size(); ++i) calc->coef32[i] = float(calc->coef64[i]);
+            calc->info.n_intervals = M;
+            calc->info.delta = dr;
+            calc->info.max_error = err;
+            calc->info.max_error_deriv = derr;
+            calc->info.table_bytes_f64 = int64_t(calc->coef64.size() * sizeof(double));
+            calc->info.table_bytes_f32 = int64_t(calc->coef32.size() * sizeof(float));
+            return SOAP_OK;
+        }
+    }
+    return fail(SOAP_EINVAL, "spline refinement failed");
+}
+
+void radial_exact(const soap_calculator* calc, int64_t n, const double* r, double* I, double* dI)
+{
+    RadialExact ex(calc->h, calc->orth);
+    for (int64_t k = 0; k < n; ++k) ex.orth(r[k], I + k * calc->nl, dI ? dI + k * calc->nl : nullptr);
+}
+
+void radial_spline_host(const soap_calculator* calc, double r, double* I, double* dI)
+{
+    int nl = calc->nl;
+    double x = r * calc->inv_delta;
+    int64_t k = std::min<int64_t>(std::max<int64_t>(int64_t(std::floor(x)), 0), calc->M - 1);
+    double t = x - double(k);
+    for (int j = 0; j < nl; ++j) {
+        const double* cf = &calc->coef64[(k * nl + j) * 4];
+        I[j] = cf[0] + t * (cf[1] + t * (cf[2] + t * cf[3]));
+        if (dI) dI[j] = (cf[1] + t * (2.0 * cf[2] + 3.0 * t * cf[3])) * calc->inv_delta;
+    }
+}
+
+}  // namespace soap

@@ -1,0 +1,317 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Every numerical step runs in the HIP kernels of libsoap_mi355x.so; torch
+supplies device memory and the current stream.  Names follow the C entry
+points (soap_compute_neighbors -> Calculator.compute_neighbors, ...).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SOAP_BF16_F32ACC, SOAP_F32, SOAP_F64, check, soap_exec, soap_hypers, soap_table_info
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _precision(dtype) -> int:
+    if dtype in (torch.float64, "f64", SOAP_F64):
+        return SOAP_F64
+    if dtype in (torch.float32, "f32", SOAP_F32):
+        return SOAP_F32
+    if dtype in ("bf16", SOAP_BF16_F32ACC):
+        return SOAP_BF16_F32ACC
+    raise ValueError(f"unsupported precision {dtype!r}")
+
+
+def _torch_dtype(prec: int):
+    return torch.float64 if prec == SOAP_F64 else torch.float32
+
+
+@dataclasses.dataclass
+class Neighbors:
+    """Device neighbour list (CSR over centres)."""
+    pair_offsets: torch.Tensor   # int64 [N+1]
+    pair_j: torch.Tensor         # int32 [P]
+    pair_shift: torch.Tensor     # int32 [P, 3]
+    pair_vec: torch.Tensor       # float [P, 3]
+    pair_transpose: Optional[torch.Tensor]  # int32 [P]
+    n_pairs: int
+
+    @property
+    def capacity(self) -> int:
+        return int(self.pair_j.shape[0])
+
+    def count(self) -> int:
+        """Number of pairs (reads pair_offsets[N] from the device)."""
+        if self.n_pairs < 0:
+            self.n_pairs = int(self.pair_offsets[-1].item())
+        return self.n_pairs
+
+
+class Calculator:
+    """Owns a soap_calculator (hyper-parameters + spline tables)."""
+
+    def __init__(self, n_species: int, nmax: int, lmax: int, rcut: float, sigma: float,
+                 cutoff_width: float = 0.5, include_center: int = 1, spline_accuracy: float = 1e-8):
+        self._L = _lib.lib()
+        h = soap_hypers(int(n_species), int(nmax), int(lmax), int(include_center), float(rcut),
+                        float(cutoff_width), float(sigma), float(spline_accuracy))
+        handle = ctypes.c_void_p()
+        check(self._L.soap_calculator_create(ctypes.byref(h), ctypes.byref(handle)))
+        self.handle = handle
+        self.hypers = dict(n_species=int(n_species), nmax=int(nmax), lmax=int(lmax), rcut=float(rcut),
+                           sigma=float(sigma), cutoff_width=float(cutoff_width),
+                           include_center=int(include_center), spline_accuracy=float(spline_accuracy))
+        self.S, self.nmax, self.lmax = int(n_species), int(nmax), int(lmax)
+        self.L2 = (self.lmax + 1) ** 2
+        self.K = self.S * self.nmax
+        self.KK = self.K * (self.K + 1) // 2
+        self._status = None
+        self._ws = None
+
+    @classmethod
+    def from_hypers(cls, h: dict) -> "Calculator":
+        return cls(h["n_species"], h["nmax"], h["lmax"], h["rcut"], h["sigma"], h.get("cutoff_width", 0.5),
+                   h.get("include_center", 1), h.get("spline_accuracy", 1e-8))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and self.handle.value:
+                self._L.soap_calculator_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ host info
+    def info(self) -> dict:
+        inf = soap_table_info()
+        check(self._L.soap_calculator_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in soap_table_info._fields_}
+
+    def radial_integral_host(self, r, exact: bool = False):
+        r = np.ascontiguousarray(np.atleast_1d(r), dtype=np.float64)
+        I = np.zeros((r.shape[0], self.nmax, self.lmax + 1))
+        dI = np.zeros_like(I)
+        check(self._L.soap_radial_integral_host(self.handle, int(exact), r.shape[0], _np_ptr(r), _np_ptr(I),
+                                                _np_ptr(dI)))
+        return I, dI
+
+    # ------------------------------------------------------------ execution
+    def _exec(self, status: Optional[torch.Tensor] = None, device=None) -> soap_exec:
+        stream = torch.cuda.current_stream(device).cuda_stream
+        if status is None:
+            if self._status is None or self._status.device != torch.device("cuda", torch.cuda.current_device()):
+                self._status = torch.zeros(1, dtype=torch.int32, device="cuda")
+            status = self._status
+        return soap_exec(ctypes.c_void_p(stream), ctypes.c_void_p(status.data_ptr()))
+
+    def reset_status(self):
+        if self._status is not None:
+            self._status.zero_()
+
+    def device_status(self) -> int:
+        """Synchronises the current stream and returns the device status word."""
+        e = self._exec()
+        return int(self._L.soap_read_device_status(ctypes.byref(e)))
+
+    def check_device(self):
+        st = self.device_status()
+        if st != 0:
+            raise _lib.SoapError(st, "device-side error")
+
+    def neighbors_workspace_size(self, atom_offsets, cells, pbc) -> int:
+        ao, ce, pb = _host_struct(atom_offsets, cells, pbc)
+        n = ctypes.c_size_t()
+        check(self._L.soap_neighbors_workspace_size(self.handle, ao.shape[0] - 1, _np_ptr(ao), _np_ptr(ce),
+                                                    _np_ptr(pb), ctypes.byref(n)))
+        return int(n.value)
+
+    def compute_neighbors(self, positions: torch.Tensor, species: torch.Tensor, atom_offsets, cells, pbc,
+                          vec_dtype=torch.float32, capacity: Optional[int] = None, transpose: bool = True,
+                          out: Optional[Neighbors] = None) -> Neighbors:
+        """soap_compute_neighbors.  With capacity None the list is sized
+        exactly: a counting call, one 8-byte read of the total, a filling call."""
+        ao, ce, pb = _host_struct(atom_offsets, cells, pbc)
+        N = int(ao[-1])
+        assert positions.dtype == torch.float64 and positions.is_cuda and positions.shape == (N, 3)
+        assert species.dtype == torch.int32 and species.is_cuda and species.shape == (N,)
+        positions = positions.contiguous()
+        species = species.contiguous()
+        dev = positions.device
+        ws_bytes = self.neighbors_workspace_size(ao, ce, pb)
+        if self._ws is None or self._ws.numel() < ws_bytes or self._ws.device != dev:
+            self._ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+        prec = _precision(vec_dtype)
+        if out is not None:
+            # refill existing buffers in place: no allocation, no synchronisation
+            self._call_neighbors(ao, ce, pb, positions, species, out.capacity, prec, out.pair_offsets, out.pair_j,
+                                 out.pair_shift, out.pair_vec, out.pair_transpose)
+            return out
+        offsets = torch.empty(N + 1, dtype=torch.int64, device=dev)
+        exact = capacity is None
+        if exact:
+            self._call_neighbors(ao, ce, pb, positions, species, 0, prec, offsets, None, None, None, None)
+            capacity = int(offsets[-1].item())
+            self.reset_status()
+        cap = max(int(capacity), 1)
+        pj = torch.empty(cap, dtype=torch.int32, device=dev)
+        ps = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        pv = torch.empty((cap, 3), dtype=_torch_dtype(prec), device=dev)
+        pt = torch.empty(cap, dtype=torch.int32, device=dev) if transpose else None
+        self._call_neighbors(ao, ce, pb, positions, species, cap, prec, offsets, pj, ps, pv, pt)
+        return Neighbors(offsets, pj, ps, pv, pt, int(capacity) if exact else -1)
+
+    def _call_neighbors(self, ao, ce, pb, positions, species, capacity, prec, offsets, pj, ps, pv, pt):
+        e = self._exec()
+        check(self._L.soap_compute_neighbors(self.handle, ctypes.byref(e), ao.shape[0] - 1, _np_ptr(ao), _np_ptr(ce),
+                                             _np_ptr(pb), _ptr(positions), _ptr(species), _ptr(self._ws),
+                                             self._ws.numel(), int(capacity), prec, _ptr(offsets), _ptr(pj),
+                                             _ptr(ps), _ptr(pv), _ptr(pt)))
+
+    def spherical_expansion(self, nl: Neighbors, species: torch.Tensor, dtype=torch.float32, gradients=False):
+        prec = _precision(dtype)
+        N = nl.pair_offsets.shape[0] - 1
+        td = _torch_dtype(prec)
+        dev = nl.pair_offsets.device
+        c = torch.empty((N, self.S, self.nmax, self.L2), dtype=td, device=dev)
+        dc = dcs = None
+        if gradients:
+            dc = torch.empty((max(nl.capacity, 1), 3, self.nmax, self.L2), dtype=td, device=dev)
+            dcs = torch.empty((N, 3, self.S, self.nmax, self.L2), dtype=td, device=dev)
+        vec = _vec_as(nl, td)
+        e = self._exec()
+        check(self._L.soap_spherical_expansion(self.handle, ctypes.byref(e), prec, N, _ptr(species),
+                                               _ptr(nl.pair_offsets), _ptr(nl.pair_j), _ptr(vec), nl.capacity,
+                                               _ptr(c), _ptr(dc), _ptr(dcs)))
+        return (c, dc, dcs) if gradients else c
+
+    def power_spectrum(self, coeffs: torch.Tensor, precision=None, rows=None, nl: Optional[Neighbors] = None,
+                       species: Optional[torch.Tensor] = None):
+        """rows = (dc, dcs) gives forward-mode dp rows as well."""
+        prec = _precision(precision if precision is not None else coeffs.dtype)
+        N = coeffs.shape[0]
+        dev = coeffs.device
+        td = torch.float64 if prec == SOAP_F64 else torch.float32
+        assert coeffs.dtype == td and coeffs.is_contiguous()
+        p = torch.empty((N, self.lmax + 1, self.KK), dtype=td, device=dev)
+        dp = dps = None
+        dc = dcs = None
+        if rows is not None:
+            dc, dcs = rows
+            dp = torch.empty((max(nl.capacity, 1), 3, self.lmax + 1, self.KK), dtype=td, device=dev)
+            dps = torch.empty((N, 3, self.lmax + 1, self.KK), dtype=td, device=dev)
+        e = self._exec()
+        check(self._L.soap_power_spectrum(self.handle, ctypes.byref(e), prec, N, _ptr(coeffs), _ptr(p),
+                                          _ptr(species), _ptr(nl.pair_offsets) if nl else None,
+                                          _ptr(nl.pair_j) if nl else None, nl.capacity if nl else 0,
+                                          _ptr(dc), _ptr(dcs), _ptr(dp), _ptr(dps)))
+        return (p, dp, dps) if rows is not None else p
+
+    def features(self, nl: Neighbors, species: torch.Tensor, dtype=torch.float32, gradients=False, out=None):
+        """soap_features: c and p (and all four gradient row arrays) in one launch."""
+        prec = _precision(dtype)
+        td = _torch_dtype(prec)
+        N = nl.pair_offsets.shape[0] - 1
+        dev = nl.pair_offsets.device
+        if out is None:
+            out = self.allocate_features(N, nl.capacity, td, dev, gradients)
+        c, p = out[0], out[1]
+        dc, dcs, dp, dps = (out[2:] if gradients else (None,) * 4)
+        vec = _vec_as(nl, td)
+        e = self._exec()
+        check(self._L.soap_features(self.handle, ctypes.byref(e), prec, N, _ptr(species), _ptr(nl.pair_offsets),
+                                    _ptr(nl.pair_j), _ptr(vec), nl.capacity, _ptr(c), _ptr(p), _ptr(dc),
+                                    _ptr(dcs), _ptr(dp), _ptr(dps)))
+        return out
+
+    def allocate_features(self, N, capacity, td, dev, gradients):
+        c = torch.empty((N, self.S, self.nmax, self.L2), dtype=td, device=dev)
+        p = torch.empty((N, self.lmax + 1, self.KK), dtype=td, device=dev)
+        if not gradients:
+            return (c, p)
+        dc = torch.empty((max(capacity, 1), 3, self.nmax, self.L2), dtype=td, device=dev)
+        dcs = torch.empty((N, 3, self.S, self.nmax, self.L2), dtype=td, device=dev)
+        dp = torch.empty((max(capacity, 1), 3, self.lmax + 1, self.KK), dtype=td, device=dev)
+        dps = torch.empty((N, 3, self.lmax + 1, self.KK), dtype=td, device=dev)
+        return (c, p, dc, dcs, dp, dps)
+
+    def power_spectrum_backward(self, coeffs: torch.Tensor, grad_p: torch.Tensor) -> torch.Tensor:
+        prec = _precision(coeffs.dtype)
+        N = coeffs.shape[0]
+        grad_p = grad_p.contiguous().to(coeffs.dtype)
+        gc = torch.empty_like(coeffs)
+        e = self._exec()
+        check(self._L.soap_power_spectrum_backward(self.handle, ctypes.byref(e), prec, N, _ptr(coeffs),
+                                                   _ptr(grad_p), _ptr(gc)))
+        return gc
+
+    def spherical_expansion_backward(self, nl: Neighbors, species: torch.Tensor, grad_coeffs: torch.Tensor):
+        prec = _precision(grad_coeffs.dtype)
+        td = grad_coeffs.dtype
+        N = nl.pair_offsets.shape[0] - 1
+        dev = grad_coeffs.device
+        grad_coeffs = grad_coeffs.contiguous()
+        gpair = torch.empty((max(nl.capacity, 1), 3), dtype=td, device=dev)
+        gpos = torch.empty((N, 3), dtype=td, device=dev)
+        vec = _vec_as(nl, td)
+        e = self._exec()
+        check(self._L.soap_spherical_expansion_backward(self.handle, ctypes.byref(e), prec, N, _ptr(species),
+                                                        _ptr(nl.pair_offsets), _ptr(nl.pair_j), _ptr(vec),
+                                                        _ptr(nl.pair_transpose), nl.capacity, _ptr(grad_coeffs),
+                                                        _ptr(gpair), _ptr(gpos)))
+        return gpos, gpair
+
+
+def _vec_as(nl: Neighbors, td) -> torch.Tensor:
+    if nl.pair_vec.dtype != td:
+        raise ValueError(f"pair_vec is {nl.pair_vec.dtype}, the call needs {td}: build the list with vec_dtype={td}")
+    return nl.pair_vec
+
+
+def _host_struct(atom_offsets, cells, pbc):
+    ao = np.ascontiguousarray(np.asarray(atom_offsets), dtype=np.int64)
+    ce = np.ascontiguousarray(np.asarray(cells), dtype=np.float64).reshape(-1, 3, 3)
+    pb = np.ascontiguousarray(np.asarray(pbc), dtype=np.uint8).reshape(-1, 3)
+    return ao, ce, pb
+
+
+class SOAPFunction(torch.autograd.Function):
+    """positions -> power spectrum, differentiable with respect to positions
+    through the hand-written adjoint kernels (soap_power_spectrum_backward
+    followed by soap_spherical_expansion_backward).  The neighbour list is
+    built once per forward call and reused by the backward call."""
+
+    @staticmethod
+    def forward(ctx, positions, calc: Calculator, species, atom_offsets, cells, pbc, dtype=torch.float32):
+        nl = calc.compute_neighbors(positions.detach(), species, atom_offsets, cells, pbc, vec_dtype=dtype)
+        c, p = calc.features(nl, species, dtype=dtype)
+        ctx.calc, ctx.nl, ctx.species = calc, nl, species
+        ctx.save_for_backward(c)
+        return p
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        (c,) = ctx.saved_tensors
+        gc = ctx.calc.power_spectrum_backward(c, grad_p.to(c.dtype))
+        gpos, _ = ctx.calc.spherical_expansion_backward(ctx.nl, ctx.species, gc)
+        return gpos.to(torch.float64), None, None, None, None, None, None
+
+
+def soap_power_spectrum_of_positions(positions, calc, species, atom_offsets, cells, pbc, dtype=torch.float32):
+    return SOAPFunction.apply(positions, calc, species, atom_offsets, cells, pbc, dtype)

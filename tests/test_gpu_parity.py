@@ -1,0 +1,363 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative Frobenius error of each result tensor, ||d||_F/||ref||_F,
+plus the worst single centre):
+  FP64 path                         <= 1e-7   (spline accuracy 1e-8 dominates)
+  FP32 path, c and p                <= 1e-6   (the stated FP32 bound on p)
+  FP32 gradient rows / adjoint      <= 1e-5   (derivatives lose ~1 digit)
+  bfloat16 hi/lo MFMA power spectrum <= 2e-3  (the stated bound; ~1e-5 expected)
+Neighbour lists (integers) are compared bit-exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+import paper_2101_08814_amd as P
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    assert P.LIB_PATH
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def worst_centre(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1)
+    nb = np.linalg.norm(b, axis=1)
+    scale = np.maximum(nb, 1e-3 * np.linalg.norm(b) / math.sqrt(b.shape[0]) + 1e-300)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / scale))
+
+
+def to_dev(batch):
+    pos = torch.tensor(batch.positions, dtype=torch.float64, device="cuda")
+    spc = torch.tensor(batch.species, dtype=torch.int32, device="cuda")
+    return pos, spc
+
+
+def gpu_neighbors(calc, batch, dtype=torch.float32):
+    pos, spc = to_dev(batch)
+    nl = calc.compute_neighbors(pos, spc, batch.atom_offsets, batch.cells, batch.pbc, vec_dtype=dtype)
+    assert calc.device_status() == 0
+    return nl, pos, spc
+
+
+def assert_same_list(nl, ref, batch, f64):
+    P_ = ref.n_pairs
+    assert nl.count() == P_
+    assert np.array_equal(nl.pair_offsets.cpu().numpy(), ref.pair_offsets)
+    assert np.array_equal(nl.pair_j[:P_].cpu().numpy(), ref.pair_j)
+    assert np.array_equal(nl.pair_shift[:P_].cpu().numpy(), ref.pair_shift)
+    vec = nl.pair_vec[:P_].double().cpu().numpy()
+    tol = 1e-12 if f64 else 4e-7
+    assert np.abs(vec - ref.pair_vec).max() <= tol * max(1.0, np.abs(ref.pair_vec).max())
+    if nl.pair_transpose is not None and P_:
+        t = nl.pair_transpose[:P_].cpu().numpy().astype(np.int64)
+        centre = np.repeat(np.arange(batch.n_atoms), np.diff(ref.pair_offsets))
+        assert np.array_equal(ref.pair_j[t], centre)
+        assert np.array_equal(ref.pair_shift[t], -ref.pair_shift)
+        assert np.array_equal(t[t], np.arange(P_))
+
+
+# ------------------------------------------------------------------ neighbours
+NEIGHBOR_CASES = {
+    "clusters": lambda: synthetic.clusters_2species(),
+    "diamond": lambda: synthetic.diamond_bulk(),
+    "molecules": lambda: synthetic.molecule_batch(),
+    "liquid": lambda: synthetic.liquid_bulk(),
+    "multispecies_64cells": lambda: synthetic.multi_species_cells().subset(list(range(64))),
+    "triclinic_self_images": lambda: synthetic.random_cell_structure(
+        3, 2, np.array([[3.1, 0.0, 0.0], [1.2, 2.9, 0.0], [-0.7, 0.9, 3.4]]), 2, min_sep=1.0,
+        hypers=dict(n_species=2, nmax=4, lmax=3, rcut=5.0, sigma=0.5, cutoff_width=0.5, include_center=1)),
+    "diamond_primitive": lambda: synthetic.random_cell_structure(
+        4, 2, np.array([[0.0, 2.715, 2.715], [2.715, 0.0, 2.715], [2.715, 2.715, 0.0]]), 1, min_sep=1.0,
+        hypers=dict(n_species=1, nmax=4, lmax=3, rcut=5.0, sigma=0.5, cutoff_width=0.5, include_center=1)),
+    "slab_pbc_xy": lambda: synthetic.random_cell_structure(
+        5, 40, np.array([[9.0, 0.0, 0.0], [0.0, 8.0, 0.0], [0.0, 0.0, 12.0]]), 2, min_sep=1.2, pbc=(1, 1, 0),
+        hypers=dict(n_species=2, nmax=4, lmax=3, rcut=3.5, sigma=0.5, cutoff_width=0.5, include_center=1)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NEIGHBOR_CASES))
+@pytest.mark.parametrize("f64", [False, True])
+def test_neighbors_match_oracle(name, f64):
+    print(f"[neighbors] case={name} f64={f64}", flush=True)
+    b = NEIGHBOR_CASES[name]()
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, _, _ = gpu_neighbors(calc, b, torch.float64 if f64 else torch.float32)
+    ref = oracle.neighbors(b)
+    assert_same_list(nl, ref, b, f64)
+
+
+def test_neighbors_unwrapped_positions_and_empty_structures():
+    """Positions outside the cell (any number of cells away) and structures
+    with zero or one atom."""
+    b = synthetic.random_cell_structure(9, 12, np.array([[6.0, 0, 0], [0.5, 5.5, 0], [0, -0.4, 6.5]]), 2,
+                                        min_sep=1.0)
+    shifts = np.random.default_rng(0).integers(-3, 4, size=(12, 3))
+    pos = b.positions + shifts @ b.cells[0]
+    lone = synthetic.clusters_2species().subset([0])
+    parts = [synthetic.Batch(pos, b.species, b.atom_offsets, b.cells, b.pbc, b.hypers)]
+    empty = synthetic.Batch(np.zeros((0, 3)), np.zeros(0, np.int32), np.array([0, 0]), np.zeros((1, 3, 3)),
+                            np.zeros((1, 3), np.uint8), b.hypers)
+    single = synthetic.Batch(np.array([[1.0, 2.0, 3.0]]), np.array([1], np.int32), np.array([0, 1]),
+                             np.zeros((1, 3, 3)), np.zeros((1, 3), np.uint8), b.hypers)
+    parts += [empty, single, lone]
+    pos = np.concatenate([p.positions for p in parts])
+    spc = np.concatenate([p.species for p in parts]).astype(np.int32)
+    offs = np.cumsum([0] + [p.n_atoms for p in parts])
+    cells = np.concatenate([p.cells for p in parts])
+    pbc = np.concatenate([p.pbc for p in parts])
+    batch = synthetic.Batch(pos, spc, offs, cells, pbc, b.hypers)
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, _, _ = gpu_neighbors(calc, batch, torch.float64)
+    assert_same_list(nl, oracle.neighbors(batch), batch, True)
+
+
+# ------------------------------------------------------------ expansion + p
+def run_features(batch, dtype, gradients=False):
+    calc = P.Calculator.from_hypers(batch.hypers)
+    nl, pos, spc = gpu_neighbors(calc, batch, dtype)
+    out = calc.features(nl, spc, dtype, gradients)
+    assert calc.device_status() == 0
+    return calc, nl, spc, [o.double().cpu().numpy() for o in out]
+
+
+def test_clusters_fp64_full_parity():
+    """8 x 64-atom clusters, 2 species, FP64: c and p against the oracle."""
+    b = synthetic.clusters_2species()
+    calc, nl, spc, (c, p) = run_features(b, torch.float64)
+    ref_nl, ref_c, ref_p = oracle.features(b)
+    ec, ep = rel(c, ref_c), rel(p, ref_p)
+    print(f"[clusters f64] rel c={ec:.3e} p={ep:.3e} worst-centre p={worst_centre(p, ref_p):.3e}")
+    assert ec <= 1e-7 and ep <= 1e-7
+    assert worst_centre(p, ref_p) <= 1e-7
+
+
+def test_diamond_fp32_gradients_full_parity():
+    """1024-atom periodic diamond, FP32: c, p and all forward-mode gradient
+    rows against the oracle, at the size and launch the benchmark times."""
+    b = synthetic.diamond_bulk()
+    calc, nl, spc, (c, p, dc, dcs, dp, dps) = run_features(b, torch.float32, gradients=True)
+    ref_nl = oracle.neighbors(b)
+    ref_c = oracle.expansion(b.hypers, b.species, ref_nl)
+    ref_p = oracle.power_spectrum(b.hypers, ref_c)
+    rdc, rdcs, rdp, rdps = oracle.gradients(b.hypers, b.species, ref_nl)
+    P_ = ref_nl.n_pairs
+    errs = dict(c=rel(c, ref_c), p=rel(p, ref_p), dc=rel(dc[:P_], rdc), dcs=rel(dcs, rdcs), dp=rel(dp[:P_], rdp),
+                dps=rel(dps, rdps), p_worst=worst_centre(p, ref_p))
+    print("[diamond f32 grads] " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
+    assert errs["c"] <= 1e-6 and errs["p"] <= 1e-6 and errs["p_worst"] <= 1e-6
+    assert errs["dc"] <= 1e-5 and errs["dcs"] <= 1e-5 and errs["dp"] <= 1e-5 and errs["dps"] <= 1e-5
+
+
+def test_separate_entry_points_match_fused():
+    """soap_spherical_expansion + soap_power_spectrum (with rows) give the
+    results of soap_features; checked on a multi-species periodic structure
+    against the oracle."""
+    hyp = dict(n_species=3, nmax=5, lmax=4, rcut=4.5, sigma=0.45, cutoff_width=0.5, include_center=1)
+    b = synthetic.random_cell_structure(21, 60, np.array([[11.0, 0, 0], [1.0, 10.5, 0], [0.5, -0.8, 12.0]]), 3,
+                                        min_sep=1.3, hypers=hyp)
+    for dt in (torch.float32, torch.float64):
+        calc = P.Calculator.from_hypers(hyp)
+        nl, pos, spc = gpu_neighbors(calc, b, dt)
+        c, dc, dcs = calc.spherical_expansion(nl, spc, dt, gradients=True)
+        p, dp, dps = calc.power_spectrum(c, dt, rows=(dc, dcs), nl=nl, species=spc)
+        fused = calc.features(nl, spc, dt, gradients=True)
+        assert calc.device_status() == 0
+        ref_nl = oracle.neighbors(b)
+        ref_c = oracle.expansion(hyp, b.species, ref_nl)
+        ref_p = oracle.power_spectrum(hyp, ref_c)
+        rdc, rdcs, rdp, rdps = oracle.gradients(hyp, b.species, ref_nl)
+        Pn = ref_nl.n_pairs
+        tol = 1e-7 if dt == torch.float64 else 1e-5
+        for got, ref in [(c, ref_c), (p, ref_p), (dc[:Pn], rdc), (dcs, rdcs), (dp[:Pn], rdp), (dps, rdps)]:
+            assert rel(got.double().cpu().numpy(), ref) <= tol
+        for a, f in zip([c, p, dc, dcs, dp, dps], fused):
+            assert rel(a.double().cpu().numpy(), f.double().cpu().numpy()) <= (1e-12 if dt == torch.float64 else 1e-6)
+
+
+def test_molecules_bf16_mfma_power_spectrum():
+    """256 molecules of 20-200 atoms, 4 species, one launch: p from the
+    bfloat16 hi/lo MFMA contraction against the FP64 oracle (bound 2e-3)."""
+    b = synthetic.molecule_batch()
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, pos, spc = gpu_neighbors(calc, b, torch.float32)
+    c = calc.spherical_expansion(nl, spc, torch.float32)
+    p_bf16 = calc.power_spectrum(c, "bf16")
+    p_f32 = calc.power_spectrum(c, torch.float32)
+    assert calc.device_status() == 0
+    ref_nl, ref_c, ref_p = oracle.features(b)
+    e16 = rel(p_bf16.double().cpu().numpy(), ref_p)
+    e32 = rel(p_f32.double().cpu().numpy(), ref_p)
+    ec = rel(c.double().cpu().numpy(), ref_c)
+    w16 = worst_centre(p_bf16.double().cpu().numpy(), ref_p)
+    print(f"[molecules] rel c={ec:.3e} p_f32={e32:.3e} p_bf16={e16:.3e} worst-centre bf16={w16:.3e}")
+    assert ec <= 1e-6 and e32 <= 1e-6
+    assert e16 <= 2e-3 and w16 <= 2e-3
+
+
+@pytest.mark.parametrize("n_cells", [8])
+def test_multispecies_fp32_parity(n_cells):
+    """8 species, nmax 12, lmax 8 (K = 96, 41904 features per centre)."""
+    b = synthetic.multi_species_cells().subset(list(range(n_cells)))
+    calc, nl, spc, (c, p) = run_features(b, torch.float32)
+    ref_nl, ref_c, ref_p = oracle.features(b)
+    ec, ep = rel(c, ref_c), rel(p, ref_p)
+    print(f"[multispecies {n_cells} cells] rel c={ec:.3e} p={ep:.3e}")
+    assert ec <= 1e-6 and ep <= 1e-6
+
+
+def test_rotation_invariance_on_gpu():
+    b = synthetic.clusters_2species().subset([2, 5])
+    _, _, _, (c, p) = run_features(b, torch.float32)
+    q, _ = np.linalg.qr(np.random.default_rng(4).normal(size=(3, 3)))
+    b2 = synthetic.Batch(b.positions @ q.T + 1.7, b.species, b.atom_offsets, b.cells, b.pbc, b.hypers)
+    _, _, _, (c2, p2) = run_features(b2, torch.float32)
+    assert rel(p2, p) <= 1e-6
+
+
+def test_results_are_bitwise_reproducible():
+    b = synthetic.diamond_bulk()
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, pos, spc = gpu_neighbors(calc, b)
+    a = [t.clone() for t in calc.features(nl, spc, torch.float32, gradients=True)]
+    nl2 = calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc, out=nl)
+    b_ = calc.features(nl2, spc, torch.float32, gradients=True)
+    for x, y in zip(a, b_):
+        assert torch.equal(x, y)
+
+
+# ------------------------------------------------------------ adjoint
+def _liquid_small():
+    return synthetic.liquid_bulk(n_atoms=512)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_vjp_matches_oracle(dt):
+    """dL/dr for L = <W, p> with W ~ N(0, 1) (seed 2004), 2 species, nmax 10,
+    lmax 8, rcut 6, at the liquid density (512 atoms)."""
+    b = _liquid_small()
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, pos, spc = gpu_neighbors(calc, b, dt)
+    c, p = calc.features(nl, spc, dt)
+    W = np.random.default_rng(2004).normal(size=tuple(p.shape))
+    gc = calc.power_spectrum_backward(c, torch.tensor(W, dtype=dt, device="cuda"))
+    gpos, gpair = calc.spherical_expansion_backward(nl, spc, gc)
+    assert calc.device_status() == 0
+    ref_nl = oracle.neighbors(b)
+    g_ref, gp_ref = oracle.vjp(b.hypers, b.species, ref_nl, W)
+    e = rel(gpos.double().cpu().numpy(), g_ref)
+    ep = rel(gpair[:ref_nl.n_pairs].double().cpu().numpy(), gp_ref)
+    print(f"[vjp {dt}] rel dL/dr={e:.3e} per-pair={ep:.3e}")
+    assert e <= (1e-7 if dt == torch.float64 else 1e-5)
+    assert ep <= (1e-7 if dt == torch.float64 else 1e-5)
+
+
+def test_vjp_full_size_against_finite_differences():
+    """4096-atom liquid (2 species, nmax 10, lmax 8, rcut 6): the FP32 adjoint
+    against central differences (h = 1e-4 A) of the FP64 GPU forward on 32
+    seeded coordinates; the FP64 adjoint against the same differences."""
+    b = synthetic.liquid_bulk()
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    rng = np.random.default_rng(2004)
+    ao, ce, pb = b.atom_offsets, b.cells, b.pbc
+    nl64 = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float64)
+    c64, p64 = calc.features(nl64, spc, torch.float64)
+    W = torch.tensor(rng.normal(size=tuple(p64.shape)), dtype=torch.float64, device="cuda")
+    g64, _ = calc.spherical_expansion_backward(nl64, spc, calc.power_spectrum_backward(c64, W))
+    nl32 = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32)
+    c32, p32 = calc.features(nl32, spc, torch.float32)
+    g32, _ = calc.spherical_expansion_backward(nl32, spc, calc.power_spectrum_backward(c32, W.float()))
+    assert calc.device_status() == 0
+    h = 1e-4
+    picks = [(int(k), int(x)) for k, x in zip(rng.integers(0, b.n_atoms, 32), rng.integers(0, 3, 32))]
+    fd = []
+    for k, x in picks:
+        vals = []
+        for sgn in (1, -1):
+            pp = pos.clone()
+            pp[k, x] += sgn * h
+            nlp = calc.compute_neighbors(pp, spc, ao, ce, pb, vec_dtype=torch.float64)
+            _, pp_ = calc.features(nlp, spc, torch.float64)
+            vals.append(float((W * pp_).sum()))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    fd = np.array(fd)
+    a64 = np.array([float(g64[k, x]) for k, x in picks])
+    a32 = np.array([float(g32[k, x]) for k, x in picks])
+    scale = np.abs(g64.cpu().numpy()).max()
+    print(f"[fd] max|fd-a64|/scale={np.abs(fd - a64).max() / scale:.3e} "
+          f"max|a32-a64|/scale={np.abs(a32 - a64).max() / scale:.3e}")
+    assert np.abs(fd - a64).max() <= 1e-6 * scale
+    assert rel(g32.double().cpu().numpy(), g64.cpu().numpy()) <= 1e-5
+
+
+def test_autograd_function_matches_adjoint():
+    b = synthetic.liquid_bulk(n_atoms=256)
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    x = pos.clone().requires_grad_(True)
+    p = P.soap_power_spectrum_of_positions(x, calc, spc, b.atom_offsets, b.cells, b.pbc, torch.float32)
+    W = torch.randn(p.shape, device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    (g,) = torch.autograd.grad((W * p).sum(), x)
+    ref_nl = oracle.neighbors(b)
+    g_ref, _ = oracle.vjp(b.hypers, b.species, ref_nl, W.double().cpu().numpy())
+    assert rel(g.cpu().numpy(), g_ref) <= 1e-5
+
+
+# ------------------------------------------------------------ device errors
+def test_capacity_exceeded_reports_status():
+    b = synthetic.diamond_bulk()
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    nl = calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc, capacity=1000)
+    assert calc.device_status() == P._lib.SOAP_ECAPACITY
+    assert int(nl.pair_offsets[-1]) > 1000
+    calc.reset_status()
+    calc.features(nl, spc, torch.float32)
+    assert calc.device_status() == P._lib.SOAP_ECAPACITY
+
+
+def test_species_out_of_range_reports_status():
+    b = synthetic.clusters_2species().subset([0])
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    spc[3] = 5
+    calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc)
+    assert calc.device_status() == P._lib.SOAP_ESPECIES
+
+
+def test_coincident_atoms_report_status():
+    b = synthetic.clusters_2species().subset([0])
+    pos = b.positions.copy()
+    pos[1] = pos[0]
+    calc = P.Calculator.from_hypers(b.hypers)
+    p_, s_ = to_dev(synthetic.Batch(pos, b.species, b.atom_offsets, b.cells, b.pbc, b.hypers))
+    calc.compute_neighbors(p_, s_, b.atom_offsets, b.cells, b.pbc)
+    assert calc.device_status() == P._lib.SOAP_EGEOMETRY
+
+
+def test_isolated_atoms_and_absent_species():
+    """Atoms with no neighbours get only the centre term; a species with no
+    atoms gives zero channels."""
+    hyp = dict(n_species=3, nmax=4, lmax=3, rcut=3.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+    pos = np.array([[0.0, 0, 0], [10.0, 0, 0], [10.0, 1.5, 0]])
+    b = synthetic.Batch(pos, np.array([0, 0, 2], np.int32), np.array([0, 3]), np.zeros((1, 3, 3)),
+                        np.zeros((1, 3), np.uint8), hyp)
+    _, nl, _, (c, p) = run_features(b, torch.float64)
+    ref_nl, ref_c, ref_p = oracle.features(b)
+    assert rel(c, ref_c) <= 1e-7 and rel(p, ref_p) <= 1e-7
+    assert np.all(c[:, 1] == 0.0)
