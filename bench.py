@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the SOAP hot path on one MI355X, in atom-centres per second.
+
+Workload (one step): a periodic perturbed-diamond cell of 1024 atoms
+(4 x 4 x 8 conventional cells, a = 5.43 A, 0.1 A Gaussian displacements),
+1 species, rcut 5 A, cutoff width 0.5 A, sigma 0.5 A, nmax 8, lmax 6:
+full neighbour list with periodic images, FP32 spherical expansion, power
+spectrum and forward-mode position gradients of both (every pair row and
+every self row).  Inputs are resident in HBM when the timed region starts;
+each step runs the neighbour list and the fused feature kernel as two
+replayed HIP graphs.
+
+Prints ONE JSON line on stdout; diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+DOMINANT_KERNEL = "k_features<float, true, true>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "features_diamond1024_traffic.txt")
+KERNEL_SOURCES = ["features.hip", "chunk.hpp", "sph.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2101_08814_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_launch_bytes_alg: float):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.lstrip().startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def algorithmic_bytes(N: int, P: int, S: int, nmax: int, lmax: int, es: int = 4) -> int:
+    """Bytes the fused feature kernel must move per launch: inputs read once
+    (pair vector, neighbour index, species of the neighbour, CSR offset and
+    species of the centre) and every output written once (c, p, the four
+    gradient-row arrays).  The L2-resident spline table is not counted."""
+    L2 = (lmax + 1) ** 2
+    K = S * nmax
+    KK = K * (K + 1) // 2
+    per_centre = es * (K * L2 + (lmax + 1) * KK + 3 * K * L2 + 3 * (lmax + 1) * KK) + 8 + 4
+    per_pair = es * (3 * nmax * L2 + 3 * (lmax + 1) * KK) + 12 + 4 + 4
+    return N * per_centre + P * per_pair
+
+
+def cpu_baseline(batch, seconds: float):
+    """The FP64 oracle, as it stands, on the host cores: the same step
+    (neighbours, expansion, power spectrum, every gradient row) repeated on
+    the whole workload until `seconds` have passed."""
+    import oracle
+    oracle.lib()
+    h = batch.hypers
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        nl = oracle.neighbors(batch)
+        c = oracle.expansion(h, batch.species, nl)
+        oracle.power_spectrum(h, c)
+        oracle.gradients(h, batch.species, nl)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": batch.n_atoms * reps / el, "unit": "atom-centres/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} full passes of the same 1024-atom step (neighbours, expansion, power spectrum, "
+                      f"all gradient rows) in FP64, {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly instead of replaying graphs")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding over several GPUs is not "
+                                   "built", "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    import paper_2101_08814_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    batch = synthetic.diamond_bulk()
+    h = batch.hypers
+    calc = P.Calculator.from_hypers(h)
+    dev = torch.device("cuda", 0)
+    pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
+    spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
+    ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
+    nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32)
+    N, Pn = batch.n_atoms, nl.count()
+    out = calc.allocate_features(N, nl.capacity, torch.float32, dev, True)
+    calc.reset_status()
+
+    def step_neighbors():
+        calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32, out=nl)
+
+    def step_features():
+        calc.features(nl, spc, torch.float32, gradients=True, out=out)
+
+    # eager warm-up (also sets LDS attributes before any capture)
+    for _ in range(3):
+        step_neighbors()
+        step_features()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in out]
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step_neighbors()
+            step_features()
+        torch.cuda.current_stream().wait_stream(side)
+        g_nl, g_feat = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_nl):
+            step_neighbors()
+        with torch.cuda.graph(g_feat):
+            step_features()
+        run_nl, run_feat = g_nl.replay, g_feat.replay
+    else:
+        run_nl, run_feat = step_neighbors, step_features
+
+    for _ in range(args.warmup):
+        run_nl()
+        run_feat()
+    torch.cuda.synchronize()
+    for a, b in zip(out, ref):
+        if not torch.equal(a, b):
+            log("graph replay differs from the eager result")
+            return 3
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start_all = torch.cuda.Event(enable_timing=True)
+    end_all = torch.cuda.Event(enable_timing=True)
+    start_all.record()
+    for k in range(K):
+        run_nl()
+        ev[k][0].record()
+        run_feat()
+        ev[k][1].record()
+    end_all.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start_all.elapsed_time(end_all)
+    feat_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    status = calc.device_status()
+    if status != 0:
+        log(f"device status {status}")
+        return 4
+    for a, b in zip(out, ref):
+        if not torch.equal(a, b):
+            log("timed results differ from the eager result")
+            return 5
+
+    ms_per_step = total_ms / K
+    value = N / (ms_per_step * 1e-3)
+    alg = algorithmic_bytes(N, Pn, h["n_species"], h["nmax"], h["lmax"])
+    achieved = alg / (feat_ms * 1e-3) / 1e9
+    traffic = measured_traffic(alg)
+    log(f"[bench] N={N} P={Pn} steps={K} total={total_ms:.2f} ms (host wall {wall * 1e3:.1f} ms) "
+        f"step={ms_per_step * 1e3:.1f} us  feature kernel={feat_ms * 1e3:.1f} us  neighbours+gaps="
+        f"{(ms_per_step - feat_ms) * 1e3:.1f} us  alg bytes/launch={alg / 1e6:.1f} MB  {achieved:.0f} GB/s")
+
+    line = {
+        "metric": "atom-centres/s (expansion+power spectrum+grads) at stated error vs FP64 oracle",
+        "value": value,
+        "unit": "atom-centres/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "periodic perturbed diamond, 1024 atoms (4x4x8 cells, a=5.43 A, 0.1 A displacements), "
+                        "1 species, rcut 5 A, sigma 0.5 A, nmax 8, lmax 6; neighbour list with images + FP32 "
+                        "expansion + power spectrum + forward-mode position gradients",
+            "centres": N, "pairs": Pn, "n_species": h["n_species"], "nmax": h["nmax"], "lmax": h["lmax"],
+            "rcut": h["rcut"], "sigma": h["sigma"], "graphs": not args.no_graph,
+            "parity": "FP32 vs FP64 oracle: p <= 1e-6, gradient rows <= 1e-5 relative (tests/test_gpu_parity.py)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": DOMINANT_KERNEL,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel_ms": feat_ms,
+            "algorithmic_bytes_per_launch": alg,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -132,12 +132,11 @@ soap_status soap_calculator_upload(const soap_calculator* calc);
 soap_status soap_radial_integral_host(const soap_calculator* calc, int32_t exact, int64_t n_r,
                                       const double* r, double* I, double* dI);
 
-/* Device bytes of scratch soap_compute_neighbors needs for these
- * structures.  atom_offsets [n_structures+1], cells [n_structures][3][3]
- * (rows h1, h2, h3) and pbc [n_structures][3] are [host] arrays. */
-soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures,
-                                          const int64_t* atom_offsets, const double* cells,
-                                          const uint8_t* pbc, size_t* bytes);
+/* Device bytes of scratch soap_compute_neighbors needs for n_structures
+ * structures holding n_atoms atoms in total (independent of positions and
+ * cells, so one workspace serves a whole trajectory). */
+soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures, int64_t n_atoms,
+                                          size_t* bytes);
 
 /* Full neighbour list with periodic images (App. B; Sec. 3 Fig. 1).
  *
@@ -145,10 +144,14 @@ soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n
  * the others) and 0 < |r_ji| < rcut, r_ji = r_j + s0 h1 + s1 h2 + s2 h3 - r_i.
  * j = i is kept when s != 0 (self-images).  Structures never interact.
  * If any axis of a structure is periodic its cell must be non-singular.
+ * Positions may lie outside the cell (any number of cells away).
  *
- * [host] n_structures, atom_offsets [n_structures+1], cells, pbc.
- * [dev]  positions double [N][3], species int32 [N] in [0, n_species),
- *        workspace of >= soap_neighbors_workspace_size bytes.
+ * [host] n_structures, n_atoms, capacity, vec_precision, workspace_bytes.
+ * [dev]  atom_offsets int64 [n_structures+1] (0 = first, n_atoms = last),
+ *        cells double [n_structures][3][3] (rows h1, h2, h3; ignored for
+ *        structures without periodic axes), pbc uint8 [n_structures][3],
+ *        positions double [N][3], species int32 [N] in [0, n_species),
+ *        workspace of >= soap_neighbors_workspace_size bytes (256-aligned).
  * out [dev] pair_offsets int64 [N+1] (CSR over centres; pair_offsets[N] is
  *        the number of pairs P even when P > capacity),
  *        pair_j int32 [capacity], pair_shift int32 [capacity][3],
@@ -156,12 +159,15 @@ soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n
  *        always formed in double), pair_transpose int32 [capacity] or NULL
  *        (index of the pair (j, i, -s)).
  * Pairs of one centre are ordered by (species_j, j, s0, s1, s2).
- * Device errors: SOAP_ECAPACITY if P > capacity (pair arrays then hold
- * nothing usable), SOAP_EGEOMETRY for coincident distinct atoms.
+ * Nothing is copied between host and device, so the call can be captured
+ * in a graph.  Device errors: SOAP_ECAPACITY if P > capacity (the pair
+ * arrays then hold nothing usable), SOAP_EGEOMETRY for coincident distinct
+ * atoms, SOAP_ESPECIES, SOAP_EINVAL for inconsistent atom_offsets, a
+ * singular periodic cell or one thinner than rcut / 1024 (then P = 0).
  * Non-periodic axes are searched without binning (all pairs within the
  * structure along that axis).                                          */
 soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec* exec,
-                                   int32_t n_structures, const int64_t* atom_offsets,
+                                   int32_t n_structures, int64_t n_atoms, const int64_t* atom_offsets,
                                    const double* cells, const uint8_t* pbc,
                                    const double* positions, const int32_t* species,
                                    void* workspace, size_t workspace_bytes, int64_t capacity,

@@ -37,6 +37,7 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         d, i, i64, u8 = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_uint8
         P = ctypes.POINTER
+        L.orc_num_threads.restype = i
         L.orc_fcut.restype = d
         L.orc_fcut.argtypes = [d, d, d, P(d)]
         L.orc_gto_constants.argtypes = [i, d, P(d), P(d), P(d)]
@@ -79,6 +80,10 @@ def _hy(h):
 
 
 # ---------------------------------------------------------------- elements
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
 def fcut(r, rcut, width):
     df = ctypes.c_double()
     f = lib().orc_fcut(float(r), float(rcut), float(width), ctypes.byref(df))

@@ -41,8 +41,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.141592653589793238462643383279502884
+
+/* Number of threads the parallel loops over centres use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------- */
 /* Cutoff function (reading: shifted cosine of width w, see header).        */

@@ -76,10 +76,10 @@ def lib():
     L.soap_radial_integral_host.restype = st
     L.soap_radial_integral_host.argtypes = [vp, i32, i64, vp, vp, vp]
     L.soap_neighbors_workspace_size.restype = st
-    L.soap_neighbors_workspace_size.argtypes = [vp, i32, vp, vp, vp, P(ctypes.c_size_t)]
+    L.soap_neighbors_workspace_size.argtypes = [vp, i32, i64, P(ctypes.c_size_t)]
     L.soap_compute_neighbors.restype = st
-    L.soap_compute_neighbors.argtypes = [vp, P(soap_exec), i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, i64, st,
-                                         vp, vp, vp, vp, vp]
+    L.soap_compute_neighbors.argtypes = [vp, P(soap_exec), i32, i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, i64,
+                                         st, vp, vp, vp, vp, vp]
     L.soap_spherical_expansion.restype = st
     L.soap_spherical_expansion.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp, vp, i64, vp, vp, vp]
     L.soap_power_spectrum.restype = st

@@ -115,69 +115,22 @@ FeatureArgs base_args(const soap_calculator* calc, const soap_exec* exec, bool f
     return a;
 }
 
-// host geometry of one structure
-soap_status make_geom(const soap_calculator* calc, int s, const double* cell, const uint8_t* pbc, StructGeom& g)
-{
-    std::memset(&g, 0, sizeof(g));
-    bool any = false;
-    for (int k = 0; k < 3; ++k) {
-        g.pbc[k] = pbc[k] ? 1 : 0;
-        any = any || pbc[k];
-    }
-    if (!any) {
-        for (int k = 0; k < 9; ++k) g.H[k] = g.Hinv[k] = (k % 4 == 0) ? 1.0 : 0.0;
-        for (int k = 0; k < 3; ++k) { g.nbin[k] = 1; g.reach[k] = 0; }
-        return SOAP_OK;
-    }
-    const double* H = cell;
-    for (int k = 0; k < 9; ++k) {
-        if (!std::isfinite(H[k])) return fail(SOAP_EINVAL, "cell of structure %d is not finite", s);
-        g.H[k] = H[k];
-    }
-    double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
-                 H[2] * (H[3] * H[7] - H[4] * H[6]);
-    double scale = 0.0;
-    for (int k = 0; k < 9; ++k) scale = std::max(scale, std::fabs(H[k]));
-    if (!(std::fabs(det) > 1e-10 * scale * scale * scale) || scale == 0.0)
-        return fail(SOAP_EINVAL, "cell of periodic structure %d is singular (det = %g)", s, det);
-    double* Hi = g.Hinv;
-    Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
-    Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
-    Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
-    Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
-    Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
-    Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
-    Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
-    Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
-    Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
-    double rcut = calc->h.rcut;
-    for (int k = 0; k < 3; ++k) {
-        if (!pbc[k]) { g.nbin[k] = 1; g.reach[k] = 0; continue; }
-        // perpendicular width of the cell along lattice direction k
-        double gk = std::sqrt(Hi[0 * 3 + k] * Hi[0 * 3 + k] + Hi[1 * 3 + k] * Hi[1 * 3 + k] + Hi[2 * 3 + k] * Hi[2 * 3 + k]);
-        double width = 1.0 / gk;
-        int nb = int(std::floor(width / rcut));
-        nb = std::max(1, std::min(nb, 128));
-        double need = rcut * nb / width;
-        int reach = int(std::ceil(need * (1.0 + 1e-12)));
-        if (reach > 4096) return fail(SOAP_EINVAL, "cell of structure %d is too thin for rcut", s);
-        g.nbin[k] = nb;
-        g.reach[k] = std::max(reach, 1);
-    }
-    return SOAP_OK;
-}
-
 struct NbLayout {
-    size_t geom, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, centre_count, total;
+    size_t geom, ok, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, centre_count, total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-NbLayout nb_layout(int32_t n_struct, int64_t N, int64_t B)
+// at most one bin per atom per structure, and one for an empty structure
+int64_t max_bins(int32_t n_struct, int64_t N) { return N + n_struct; }
+
+NbLayout nb_layout(int32_t n_struct, int64_t N)
 {
+    int64_t B = max_bins(n_struct, N);
     NbLayout L{};
     size_t o = 0;
     L.geom = o; o = up256(o + sizeof(StructGeom) * size_t(n_struct));
+    L.ok = o; o = up256(o + 4);
     L.atom_struct = o; o = up256(o + 4 * size_t(N));
     L.atom_bin = o; o = up256(o + 4 * size_t(N));
     L.atom_wrap = o; o = up256(o + 12 * size_t(N));
@@ -188,30 +141,6 @@ NbLayout nb_layout(int32_t n_struct, int64_t N, int64_t B)
     L.centre_count = o; o = up256(o + 8 * size_t(N + 1));
     L.total = o;
     return L;
-}
-
-soap_status build_geoms(const soap_calculator* calc, int32_t n_structures, const int64_t* atom_offsets,
-                        const double* cells, const uint8_t* pbc, std::vector<StructGeom>& geoms, int64_t& B)
-{
-    REQUIRE(n_structures >= 0, "n_structures must be >= 0 (got %d)", n_structures);
-    CHECK(check_ptr(atom_offsets, 8, "atom_offsets"));
-    if (n_structures > 0) {
-        CHECK(check_ptr(cells, 8, "cells"));
-        CHECK(check_ptr(pbc, 1, "pbc"));
-    }
-    REQUIRE(atom_offsets[0] == 0, "atom_offsets[0] must be 0");
-    geoms.resize(n_structures);
-    B = 0;
-    for (int s = 0; s < n_structures; ++s) {
-        REQUIRE(atom_offsets[s + 1] >= atom_offsets[s], "atom_offsets must be non-decreasing (structure %d)", s);
-        CHECK(make_geom(calc, s, cells + 9 * s, pbc + 3 * s, geoms[s]));
-        geoms[s].atom_lo = atom_offsets[s];
-        geoms[s].atom_hi = atom_offsets[s + 1];
-        geoms[s].bin_lo = B;
-        B += int64_t(geoms[s].nbin[0]) * geoms[s].nbin[1] * geoms[s].nbin[2];
-    }
-    REQUIRE(atom_offsets[n_structures] < (int64_t(1) << 31), "at most 2^31 - 1 atoms are supported");
-    return SOAP_OK;
 }
 
 }  // namespace
@@ -311,37 +240,39 @@ soap_status soap_radial_integral_host(const soap_calculator* calc, int32_t exact
     return SOAP_OK;
 }
 
-soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures,
-                                          const int64_t* atom_offsets, const double* cells, const uint8_t* pbc,
+soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures, int64_t n_atoms,
                                           size_t* bytes)
 {
     clear_error();
     CHECK(check_calc(calc));
     REQUIRE(bytes != nullptr, "bytes must not be NULL");
-    std::vector<StructGeom> g;
-    int64_t B = 0;
-    CHECK(build_geoms(calc, n_structures, atom_offsets, cells, pbc, g, B));
-    *bytes = nb_layout(n_structures, atom_offsets[n_structures], B).total;
+    REQUIRE(n_structures >= 0, "n_structures must be >= 0 (got %d)", n_structures);
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    *bytes = nb_layout(n_structures, n_atoms).total;
     return SOAP_OK;
 }
 
 soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec* exec, int32_t n_structures,
-                                   const int64_t* atom_offsets, const double* cells, const uint8_t* pbc,
-                                   const double* positions, const int32_t* species, void* workspace,
-                                   size_t workspace_bytes, int64_t capacity, soap_precision vec_precision,
-                                   int64_t* pair_offsets, int32_t* pair_j, int32_t* pair_shift, void* pair_vec,
-                                   int32_t* pair_transpose)
+                                   int64_t n_atoms, const int64_t* atom_offsets, const double* cells,
+                                   const uint8_t* pbc, const double* positions, const int32_t* species,
+                                   void* workspace, size_t workspace_bytes, int64_t capacity,
+                                   soap_precision vec_precision, int64_t* pair_offsets, int32_t* pair_j,
+                                   int32_t* pair_shift, void* pair_vec, int32_t* pair_transpose)
 {
     clear_error();
     CHECK(check_calc(calc));
     REQUIRE(vec_precision == SOAP_F64 || vec_precision == SOAP_F32, "vec_precision must be SOAP_F64 or SOAP_F32");
     REQUIRE(capacity >= 0 && capacity < (int64_t(1) << 31), "capacity must be in [0, 2^31)");
-    std::vector<StructGeom> geoms;
-    int64_t B = 0;
-    CHECK(build_geoms(calc, n_structures, atom_offsets, cells, pbc, geoms, B));
-    int64_t N = atom_offsets[n_structures];
+    REQUIRE(n_structures >= 0, "n_structures must be >= 0 (got %d)", n_structures);
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(n_structures > 0 || n_atoms == 0, "atoms without structures");
+    CHECK(check_ptr(atom_offsets, 8, "atom_offsets"));
     CHECK(check_ptr(pair_offsets, 8, "pair_offsets"));
-    if (N > 0) {
+    if (n_structures > 0) {
+        CHECK(check_ptr(cells, 8, "cells"));
+        CHECK(check_ptr(pbc, 1, "pbc"));
+    }
+    if (n_atoms > 0) {
         CHECK(check_ptr(positions, 8, "positions"));
         CHECK(check_ptr(species, 4, "species"));
     }
@@ -351,40 +282,31 @@ soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec*
         CHECK(check_ptr(pair_vec, elem_size(vec_precision), "pair_vec"));
         CHECK(check_ptr(pair_transpose, 4, "pair_transpose", true));
     }
-    NbLayout L = nb_layout(n_structures, N, B);
+    NbLayout L = nb_layout(n_structures, n_atoms);
     REQUIRE(workspace_bytes >= L.total, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, L.total);
     CHECK(check_ptr(workspace, 256, "workspace"));
-    hipStream_t stream = stream_of(exec);
     char* ws = static_cast<char*>(workspace);
-    // The geometry goes to the device through a small host staging buffer
-    // that stays alive on this thread until its next-but-three call.
-    thread_local std::vector<StructGeom> staging[4];
-    thread_local int slot = 0;
-    std::vector<StructGeom>& host = staging[slot];
-    slot = (slot + 1) & 3;
-    host = geoms;
-    if (n_structures > 0) {
-        hipError_t e = hipMemcpyAsync(ws + L.geom, host.data(), sizeof(StructGeom) * n_structures,
-                                      hipMemcpyHostToDevice, stream);
-        CHECK(launched(e, "geometry upload"));
-    }
     NeighborArgs a{};
     a.n_structures = n_structures;
-    a.n_atoms = N;
-    a.total_bins = B;
+    a.n_atoms = n_atoms;
+    a.max_bins = max_bins(n_structures, n_atoms);
     a.rcut = calc->h.rcut;
-    a.geom = reinterpret_cast<const StructGeom*>(ws + L.geom);
+    a.atom_offsets = atom_offsets;
+    a.cells = cells;
+    a.pbc = pbc;
     a.positions = positions;
     a.species = species;
     a.n_species = calc->h.n_species;
+    a.geom = reinterpret_cast<StructGeom*>(ws + L.geom);
+    a.ok = reinterpret_cast<int32_t*>(ws + L.ok);
     a.atom_struct = reinterpret_cast<int32_t*>(ws + L.atom_struct);
     a.atom_bin = reinterpret_cast<int32_t*>(ws + L.atom_bin);
     a.atom_wrap = reinterpret_cast<int32_t*>(ws + L.atom_wrap);
     a.bin_count = reinterpret_cast<int32_t*>(ws + L.bin_count);
     a.bin_start = reinterpret_cast<int32_t*>(ws + L.bin_start);
+    a.bin_cursor = reinterpret_cast<int32_t*>(ws + L.bin_cursor);
     a.bin_atoms = reinterpret_cast<int32_t*>(ws + L.bin_atoms);
     a.centre_count = reinterpret_cast<int64_t*>(ws + L.centre_count);
-    a.bin_cursor = reinterpret_cast<int32_t*>(ws + L.bin_cursor);
     a.capacity = capacity;
     a.pair_offsets = pair_offsets;
     a.pair_j = pair_j;
@@ -393,7 +315,7 @@ soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec*
     a.vec_f64 = vec_precision == SOAP_F64;
     a.pair_transpose = pair_transpose;
     a.status = status_of(exec);
-    return launched(launch_neighbors(a, stream), "neighbour kernels");
+    return launched(launch_neighbors(a, stream_of(exec)), "neighbour kernels");
 }
 
 static soap_status check_pairs(const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,

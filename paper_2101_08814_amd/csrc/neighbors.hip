@@ -11,7 +11,9 @@
 // distinct (bin, cell shift) pair, so each image is seen exactly once even
 // in cells thinner than rcut.
 //
-// Phases (one launch each, all on the caller's stream):
+// Phases (one launch each, all on the caller's stream, no host copies):
+//   geometry - per structure: inverse cell, bins per axis, stencil reach and
+//              first bin (one work-group, scan over structures)
 //   assign  - structure, wrap and bin of every atom, bin occupancy counts
 //   scan    - bin starts
 //   bins    - atoms scattered into their bins
@@ -39,6 +41,99 @@ __device__ __forceinline__ int floordiv(int a, int b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+// Per-structure geometry.  Bins per periodic axis: floor(width / rcut),
+// capped so that a structure never has more bins than atoms (the workspace
+// then holds at most N + n_structures bins); the reach is the number of
+// bins that spans rcut.  Any invalid input clears *ok and every later phase
+// produces an empty list.
+__device__ bool make_geometry(const NeighborArgs& a, int s, StructGeom& g)
+{
+    int64_t lo = a.atom_offsets[s], hi = a.atom_offsets[s + 1];
+    g.atom_lo = lo;
+    g.atom_hi = hi;
+    bool valid = lo >= 0 && hi >= lo && hi <= a.n_atoms;
+    int64_t ns = valid ? hi - lo : 0;
+    bool any = false;
+    for (int k = 0; k < 3; ++k) {
+        g.pbc[k] = a.pbc[3 * s + k] ? 1 : 0;
+        any = any || g.pbc[k];
+    }
+    for (int k = 0; k < 9; ++k) g.H[k] = g.Hinv[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    for (int k = 0; k < 3; ++k) { g.nbin[k] = 1; g.reach[k] = 0; }
+    if (!any) return valid;
+    const double* H = a.cells + 9 * s;
+    double scale = 0.0;
+    for (int k = 0; k < 9; ++k) {
+        g.H[k] = H[k];
+        scale = fmax(scale, fabs(H[k]));
+    }
+    double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                 H[2] * (H[3] * H[7] - H[4] * H[6]);
+    if (!(fabs(det) > 1e-10 * scale * scale * scale) || !(scale > 0.0) || !isfinite(det)) return false;
+    double* Hi = g.Hinv;
+    Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
+    Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+    Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+    Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
+    Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+    Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+    Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
+    Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+    Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    int cap = 1;
+    while (int64_t(cap + 1) * (cap + 1) * (cap + 1) <= ns && cap < 128) ++cap;
+    for (int k = 0; k < 3; ++k) {
+        if (!g.pbc[k]) continue;
+        double gk = sqrt(Hi[0 * 3 + k] * Hi[0 * 3 + k] + Hi[1 * 3 + k] * Hi[1 * 3 + k] + Hi[2 * 3 + k] * Hi[2 * 3 + k]);
+        double width = 1.0 / gk;
+        double nbf = floor(width / a.rcut);
+        int nb = nbf < 1.0 ? 1 : (nbf > double(cap) ? cap : int(nbf));
+        double need = ceil(a.rcut * nb / width * (1.0 + 1e-12));
+        if (!(need <= 1024.0)) return false;
+        g.nbin[k] = nb;
+        g.reach[k] = need < 1.0 ? 1 : int(need);
+    }
+    return valid;
+}
+
+__global__ void __launch_bounds__(1024) k_geometry(NeighborArgs a)
+{
+    __shared__ int64_t part[1024];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t == 0) bad = (a.atom_offsets[0] != 0 || a.atom_offsets[a.n_structures] != a.n_atoms) ? 1 : 0;
+    __syncthreads();
+    const int64_t n = a.n_structures;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
+    int64_t sum = 0;
+    for (int64_t s = b; s < e; ++s) {
+        StructGeom g;
+        if (!make_geometry(a, int(s), g)) bad = 1;
+        sum += int64_t(g.nbin[0]) * g.nbin[1] * g.nbin[2];
+        a.geom[s] = g;
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int64_t s = b; s < e; ++s) {
+        a.geom[s].bin_lo = run;
+        run += int64_t(a.geom[s].nbin[0]) * a.geom[s].nbin[1] * a.geom[s].nbin[2];
+    }
+    __syncthreads();
+    if (t == 0) {
+        if (part[1023] > a.max_bins) bad = 1;
+        *a.ok = bad ? 0 : 1;
+        if (bad) put_status(a.status, SOAP_EINVAL);
+    }
+}
+
 __global__ void k_zero_i32(int32_t* p, int64_t n)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -48,7 +143,7 @@ __global__ void k_zero_i32(int32_t* p, int64_t n)
 __global__ void k_assign(NeighborArgs a)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms) return;
+    if (i >= a.n_atoms || !*a.ok) return;
     // structure of atom i: first s with atom_hi > i
     int lo = 0, hi = a.n_structures - 1;
     while (lo < hi) {
@@ -113,7 +208,7 @@ __global__ void __launch_bounds__(1024) k_scan(const Tin* in, Tout* out, Tout* o
 __global__ void k_bins(NeighborArgs a)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms) return;
+    if (i >= a.n_atoms || !*a.ok) return;
     int pos = atomicAdd(&a.bin_cursor[a.atom_bin[i]], 1);
     a.bin_atoms[pos] = int32_t(i);
 }
@@ -166,14 +261,14 @@ __global__ void k_count(NeighborArgs a)
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_atoms) return;
     int64_t n = 0;
-    visit(a, i, [&](int, int, int, int) { ++n; });
+    if (*a.ok) visit(a, i, [&](int, int, int, int) { ++n; });
     a.centre_count[i] = n;
 }
 
 __global__ void k_fill(NeighborArgs a)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms) return;
+    if (i >= a.n_atoms || !*a.ok) return;
     if (a.pair_offsets[a.n_atoms] > a.capacity) return;
     int64_t o = a.pair_offsets[i];
     visit(a, i, [&](int j, int s0, int s1, int s2) {
@@ -312,12 +407,13 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
 {
     const int T = 256;
     int64_t N = a.n_atoms;
+    hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
     if (N == 0) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream,
                            a.centre_count, a.pair_offsets, (int64_t*)nullptr, int64_t(0), a.capacity, a.status);
         return hipGetLastError();
     }
-    int64_t B = a.total_bins;
+    int64_t B = a.max_bins;
     hipLaunchKernelGGL(k_zero_i32, dim3(blocks(B + 1, T)), dim3(T), 0, stream, a.bin_count, B + 1);
     hipLaunchKernelGGL(k_assign, dim3(blocks(N, T)), dim3(T), 0, stream, a);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int32_t, int32_t>), dim3(1), dim3(1024), 0, stream, a.bin_count,

@@ -22,8 +22,8 @@ struct DeviceTables {
     float* center32 = nullptr;
 };
 
-// Geometry of one structure for the neighbour search (host-built, copied to
-// the start of the neighbour workspace).
+// Geometry of one structure for the neighbour search (built on the device
+// from the caller's cells, pbc flags and atom offsets).
 struct StructGeom {
     double H[9];        // rows are lattice vectors h1, h2, h3 (identity if no pbc)
     double Hinv[9];     // inverse of H: fractional f = r . Hinv
@@ -100,21 +100,25 @@ hipError_t launch_expansion_backward(const FeatureArgs& a, bool f64, const int32
 struct NeighborArgs {
     int32_t n_structures;
     int64_t n_atoms;
-    int64_t total_bins;
+    int64_t max_bins;             // bound on the total number of bins (workspace size)
     double rcut;
-    const StructGeom* geom;       // device copy (in the workspace)
+    const int64_t* atom_offsets;  // [n_structures + 1]
+    const double* cells;          // [n_structures][3][3]
+    const uint8_t* pbc;           // [n_structures][3]
     const double* positions;
     const int32_t* species;
     int32_t n_species;
     // workspace arrays
+    StructGeom* geom;             // [n_structures]
     int32_t* atom_struct;         // [N]
     int32_t* atom_bin;            // [N] global bin index
     int32_t* atom_wrap;           // [N][3] integer wrap of the fractional coordinates
-    int32_t* bin_count;           // [total_bins + 1]
-    int32_t* bin_start;           // [total_bins + 1]
+    int32_t* bin_count;           // [max_bins + 1]
+    int32_t* bin_start;           // [max_bins + 1]
+    int32_t* bin_cursor;          // [max_bins + 1]
     int32_t* bin_atoms;           // [N]
-    int64_t* centre_count;        // [N]
-    int32_t* bin_cursor;          // [total_bins]
+    int64_t* centre_count;        // [N + 1]
+    int32_t* ok;                  // set by the geometry phase: 1 if the input is valid
     int64_t capacity;
     int64_t* pair_offsets;
     int32_t* pair_j;

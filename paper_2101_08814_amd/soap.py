@@ -135,38 +135,41 @@ class Calculator:
         if st != 0:
             raise _lib.SoapError(st, "device-side error")
 
-    def neighbors_workspace_size(self, atom_offsets, cells, pbc) -> int:
-        ao, ce, pb = _host_struct(atom_offsets, cells, pbc)
+    def neighbors_workspace_size(self, n_structures: int, n_atoms: int) -> int:
         n = ctypes.c_size_t()
-        check(self._L.soap_neighbors_workspace_size(self.handle, ao.shape[0] - 1, _np_ptr(ao), _np_ptr(ce),
-                                                    _np_ptr(pb), ctypes.byref(n)))
+        check(self._L.soap_neighbors_workspace_size(self.handle, int(n_structures), int(n_atoms), ctypes.byref(n)))
         return int(n.value)
 
     def compute_neighbors(self, positions: torch.Tensor, species: torch.Tensor, atom_offsets, cells, pbc,
                           vec_dtype=torch.float32, capacity: Optional[int] = None, transpose: bool = True,
                           out: Optional[Neighbors] = None) -> Neighbors:
-        """soap_compute_neighbors.  With capacity None the list is sized
-        exactly: a counting call, one 8-byte read of the total, a filling call."""
-        ao, ce, pb = _host_struct(atom_offsets, cells, pbc)
-        N = int(ao[-1])
+        """soap_compute_neighbors.  atom_offsets, cells and pbc may be host
+        arrays (copied to the device here) or device tensors (used as they
+        are; then the call copies nothing and can be graph-captured).  With
+        capacity None the list is sized exactly: a counting call, one 8-byte
+        read of the total, a filling call.  With out given, its buffers are
+        refilled in place."""
+        dev = positions.device
+        ao, ce, pb = structures_to_device(atom_offsets, cells, pbc, dev)
+        N = int(positions.shape[0])
+        n_struct = int(ao.shape[0] - 1)
         assert positions.dtype == torch.float64 and positions.is_cuda and positions.shape == (N, 3)
         assert species.dtype == torch.int32 and species.is_cuda and species.shape == (N,)
         positions = positions.contiguous()
         species = species.contiguous()
-        dev = positions.device
-        ws_bytes = self.neighbors_workspace_size(ao, ce, pb)
+        ws_bytes = self.neighbors_workspace_size(n_struct, N)
         if self._ws is None or self._ws.numel() < ws_bytes or self._ws.device != dev:
             self._ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
         prec = _precision(vec_dtype)
+        args = (n_struct, N, ao, ce, pb, positions, species)
         if out is not None:
-            # refill existing buffers in place: no allocation, no synchronisation
-            self._call_neighbors(ao, ce, pb, positions, species, out.capacity, prec, out.pair_offsets, out.pair_j,
-                                 out.pair_shift, out.pair_vec, out.pair_transpose)
+            self._call_neighbors(*args, out.capacity, prec, out.pair_offsets, out.pair_j, out.pair_shift,
+                                 out.pair_vec, out.pair_transpose)
             return out
         offsets = torch.empty(N + 1, dtype=torch.int64, device=dev)
         exact = capacity is None
         if exact:
-            self._call_neighbors(ao, ce, pb, positions, species, 0, prec, offsets, None, None, None, None)
+            self._call_neighbors(*args, 0, prec, offsets, None, None, None, None)
             capacity = int(offsets[-1].item())
             self.reset_status()
         cap = max(int(capacity), 1)
@@ -174,15 +177,15 @@ class Calculator:
         ps = torch.empty((cap, 3), dtype=torch.int32, device=dev)
         pv = torch.empty((cap, 3), dtype=_torch_dtype(prec), device=dev)
         pt = torch.empty(cap, dtype=torch.int32, device=dev) if transpose else None
-        self._call_neighbors(ao, ce, pb, positions, species, cap, prec, offsets, pj, ps, pv, pt)
+        self._call_neighbors(*args, cap, prec, offsets, pj, ps, pv, pt)
         return Neighbors(offsets, pj, ps, pv, pt, int(capacity) if exact else -1)
 
-    def _call_neighbors(self, ao, ce, pb, positions, species, capacity, prec, offsets, pj, ps, pv, pt):
+    def _call_neighbors(self, n_struct, N, ao, ce, pb, positions, species, capacity, prec, offsets, pj, ps, pv, pt):
         e = self._exec()
-        check(self._L.soap_compute_neighbors(self.handle, ctypes.byref(e), ao.shape[0] - 1, _np_ptr(ao), _np_ptr(ce),
-                                             _np_ptr(pb), _ptr(positions), _ptr(species), _ptr(self._ws),
-                                             self._ws.numel(), int(capacity), prec, _ptr(offsets), _ptr(pj),
-                                             _ptr(ps), _ptr(pv), _ptr(pt)))
+        check(self._L.soap_compute_neighbors(self.handle, ctypes.byref(e), n_struct, N, _ptr(ao), _ptr(ce), _ptr(pb),
+                                             _ptr(positions), _ptr(species), _ptr(self._ws), self._ws.numel(),
+                                             int(capacity), prec, _ptr(offsets), _ptr(pj), _ptr(ps), _ptr(pv),
+                                             _ptr(pt)))
 
     def spherical_expansion(self, nl: Neighbors, species: torch.Tensor, dtype=torch.float32, gradients=False):
         prec = _precision(dtype)
@@ -284,11 +287,17 @@ def _vec_as(nl: Neighbors, td) -> torch.Tensor:
     return nl.pair_vec
 
 
-def _host_struct(atom_offsets, cells, pbc):
-    ao = np.ascontiguousarray(np.asarray(atom_offsets), dtype=np.int64)
-    ce = np.ascontiguousarray(np.asarray(cells), dtype=np.float64).reshape(-1, 3, 3)
-    pb = np.ascontiguousarray(np.asarray(pbc), dtype=np.uint8).reshape(-1, 3)
-    return ao, ce, pb
+def structures_to_device(atom_offsets, cells, pbc, device):
+    """(atom_offsets int64 [S+1], cells float64 [S,3,3], pbc uint8 [S,3]) on the device."""
+    def conv(x, dtype, shape):
+        if isinstance(x, torch.Tensor) and x.is_cuda:
+            assert x.dtype == dtype and x.is_contiguous()
+            return x
+        a = np.ascontiguousarray(np.asarray(x.cpu() if isinstance(x, torch.Tensor) else x))
+        return torch.tensor(a.reshape(shape), dtype=dtype, device=device)
+    ao = conv(atom_offsets, torch.int64, (-1,))
+    n = int(ao.shape[0] - 1)
+    return ao, conv(cells, torch.float64, (n, 3, 3)), conv(pbc, torch.uint8, (n, 3))
 
 
 class SOAPFunction(torch.autograd.Function):

@@ -240,6 +240,43 @@ def test_results_are_bitwise_reproducible():
         assert torch.equal(x, y)
 
 
+def test_graph_replays_match_eager():
+    """The neighbour list and the fused feature kernel captured in HIP graphs:
+    several replays, with eager work and synchronisations in between, each
+    equal to the eager result."""
+    b = synthetic.diamond_bulk()
+    calc = P.Calculator.from_hypers(b.hypers)
+    dev = torch.device("cuda")
+    pos, spc = to_dev(b)
+    ao, ce, pb = P.soap.structures_to_device(b.atom_offsets, b.cells, b.pbc, dev)
+    nl = calc.compute_neighbors(pos, spc, ao, ce, pb)
+    out = calc.allocate_features(b.n_atoms, nl.capacity, torch.float32, dev, True)
+    calc.features(nl, spc, torch.float32, gradients=True, out=out)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in out]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        calc.compute_neighbors(pos, spc, ao, ce, pb, out=nl)
+        calc.features(nl, spc, torch.float32, gradients=True, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        calc.compute_neighbors(pos, spc, ao, ce, pb, out=nl)
+        calc.features(nl, spc, torch.float32, gradients=True, out=out)
+    for rep in range(4):
+        for t in out:
+            t.zero_()
+        nl.pair_j.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, r in zip(out, ref):
+            assert torch.equal(a, r), f"replay {rep}"
+        _ = (pos * 2).sum().item()      # eager work between replays
+    assert calc.device_status() == 0
+
+
 # ------------------------------------------------------------ adjoint
 def _liquid_small():
     return synthetic.liquid_bulk(n_atoms=512)
@@ -338,6 +375,21 @@ def test_species_out_of_range_reports_status():
     spc[3] = 5
     calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc)
     assert calc.device_status() == P._lib.SOAP_ESPECIES
+
+
+@pytest.mark.parametrize("what", ["singular_cell", "bad_offsets"])
+def test_invalid_structures_report_status(what):
+    b = synthetic.diamond_bulk()
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    cells, offs = b.cells.copy(), b.atom_offsets.copy()
+    if what == "singular_cell":
+        cells[0, 2] = cells[0, 0]
+    else:
+        offs[-1] -= 1
+    nl = calc.compute_neighbors(pos, spc, offs, cells, b.pbc, capacity=100)
+    assert calc.device_status() == P._lib.SOAP_EINVAL
+    assert int(nl.pair_offsets[-1]) == 0
 
 
 def test_coincident_atoms_report_status():

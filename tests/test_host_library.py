@@ -70,41 +70,38 @@ def calc():
 
 def _nb_call(calc, **over):
     L = _lib.lib()
-    ao = np.array([0, 4], dtype=np.int64)
-    cells = np.eye(3) * 10.0
-    pbc = np.ones(3, dtype=np.uint8)
     dummy = ctypes.c_void_p(256)   # never dereferenced: validation fails first
-    args = dict(n_structures=1, atom_offsets=ao, cells=cells, pbc=pbc, positions=dummy, species=dummy,
-                workspace=dummy, workspace_bytes=1 << 30, capacity=100, prec=_lib.SOAP_F32,
+    args = dict(n_structures=1, n_atoms=4, atom_offsets=dummy, cells=dummy, pbc=dummy, positions=dummy,
+                species=dummy, workspace=dummy, workspace_bytes=1 << 30, capacity=100, prec=_lib.SOAP_F32,
                 pair_offsets=dummy, pair_j=dummy, pair_shift=dummy, pair_vec=dummy, pair_transpose=None)
     args.update(over)
     e = _lib.soap_exec(None, None)
-    ptr = lambda a: ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else a
-    return L.soap_compute_neighbors(calc.handle, ctypes.byref(e), args["n_structures"], ptr(args["atom_offsets"]),
-                                    ptr(args["cells"]), ptr(args["pbc"]), args["positions"], args["species"],
-                                    args["workspace"], args["workspace_bytes"], args["capacity"], args["prec"],
-                                    args["pair_offsets"], args["pair_j"], args["pair_shift"], args["pair_vec"],
-                                    args["pair_transpose"])
+    return L.soap_compute_neighbors(calc.handle, ctypes.byref(e), args["n_structures"], args["n_atoms"],
+                                    args["atom_offsets"], args["cells"], args["pbc"], args["positions"],
+                                    args["species"], args["workspace"], args["workspace_bytes"], args["capacity"],
+                                    args["prec"], args["pair_offsets"], args["pair_j"], args["pair_shift"],
+                                    args["pair_vec"], args["pair_transpose"])
 
 
 @pytest.mark.parametrize("over", [
-    dict(capacity=-1), dict(n_structures=-1), dict(prec=_lib.SOAP_BF16_F32ACC),
-    dict(cells=np.zeros((3, 3))),                                    # singular periodic cell
-    dict(cells=np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 1.0]])),   # rank-deficient
-    dict(atom_offsets=np.array([1, 4], dtype=np.int64)),
-    dict(atom_offsets=np.array([0, -1], dtype=np.int64)),
-    dict(workspace_bytes=16), dict(positions=None), dict(pair_offsets=None), dict(pair_j=None),
+    dict(capacity=-1), dict(n_structures=-1), dict(n_atoms=-1), dict(prec=_lib.SOAP_BF16_F32ACC),
+    dict(n_structures=0), dict(workspace_bytes=16), dict(positions=None), dict(pair_offsets=None),
+    dict(pair_j=None), dict(atom_offsets=None), dict(cells=None),
     dict(pair_vec=ctypes.c_void_p(258)),                             # misaligned
+    dict(workspace=ctypes.c_void_p(264)),                            # workspace must be 256-aligned
 ])
 def test_neighbor_host_errors(calc, over):
     assert _nb_call(calc, **over) == _lib.SOAP_EINVAL
     assert _lib.lib().soap_last_error()
 
 
-def test_workspace_size_and_nonperiodic_cells_ignored(calc):
-    n1 = calc.neighbors_workspace_size([0, 10], np.zeros((1, 3, 3)), np.zeros((1, 3)))
-    n2 = calc.neighbors_workspace_size([0, 10], np.eye(3)[None] * 40.0, np.ones((1, 3)))
-    assert n1 > 0 and n2 > n1          # a 40 A cell with rcut 4 has 10^3 bins
+def test_workspace_size(calc):
+    n1 = calc.neighbors_workspace_size(1, 10)
+    n2 = calc.neighbors_workspace_size(4, 1000)
+    assert 0 < n1 < n2
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    assert L.soap_neighbors_workspace_size(calc.handle, -1, 10, ctypes.byref(n)) == _lib.SOAP_EINVAL
 
 
 def test_feature_entry_points_host_errors(calc):
