@@ -7,8 +7,9 @@ Workload (one step): a periodic perturbed-diamond cell of 1024 atoms
 full neighbour list with periodic images, FP32 spherical expansion, power
 spectrum and forward-mode position gradients of both (every pair row and
 every self row).  Inputs are resident in HBM when the timed region starts;
-each step runs the neighbour list and the fused feature kernel as two
-replayed HIP graphs.
+each step launches three phases on one stream: the neighbour list, the
+per-centre pass (c, p and the self rows, soap_features) and the pair rows
+(soap_gradient_rows, the kernel that writes ~97% of the bytes).
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -25,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-DOMINANT_KERNEL = "k_features<float, true, true>"
+DOMINANT_KERNEL = "k_rows<float, true, true>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "features_diamond1024_traffic.txt")
 KERNEL_SOURCES = ["features.hip", "chunk.hpp", "sph.hpp"]
 
@@ -61,17 +62,20 @@ def measured_traffic(n_launch_bytes_alg: float):
         return None
 
 
-def algorithmic_bytes(N: int, P: int, S: int, nmax: int, lmax: int, es: int = 4) -> int:
-    """Bytes the fused feature kernel must move per launch: inputs read once
-    (pair vector, neighbour index, species of the neighbour, CSR offset and
-    species of the centre) and every output written once (c, p, the four
-    gradient-row arrays).  The L2-resident spline table is not counted."""
+def algorithmic_bytes(N: int, P: int, S: int, nmax: int, lmax: int, es: int = 4):
+    """Bytes each pass must move per launch, inputs read once and outputs
+    written once; the L2-resident spline table is not counted.
+    Per-centre pass: pair vectors, neighbour indices and species, CSR
+    offsets, centre species in; c, p and both self rows out.
+    Row pass: pair vectors, neighbour indices and species, CSR offsets and c
+    of each centre in; the dc and dp rows of every pair out."""
     L2 = (lmax + 1) ** 2
     K = S * nmax
     KK = K * (K + 1) // 2
-    per_centre = es * (K * L2 + (lmax + 1) * KK + 3 * K * L2 + 3 * (lmax + 1) * KK) + 8 + 4
-    per_pair = es * (3 * nmax * L2 + 3 * (lmax + 1) * KK) + 12 + 4 + 4
-    return N * per_centre + P * per_pair
+    pair_in = 12 + 4 + 4
+    centres = N * (es * (K * L2 + (lmax + 1) * KK + 3 * K * L2 + 3 * (lmax + 1) * KK) + 8 + 4) + P * pair_in
+    rows = N * (es * K * L2 + 8) + P * (es * (3 * nmax * L2 + 3 * (lmax + 1) * KK) + pair_in)
+    return centres, rows
 
 
 def cpu_baseline(batch, seconds: float):
@@ -102,7 +106,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly instead of replaying graphs")
+    ap.add_argument("--graph", action="store_true", help="replay the three phases as HIP graphs instead of "
+                    "launching them eagerly (measured slower: each graph launch adds a gap)")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only copy 256 MiB device-to-device five times "
+                    "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -119,6 +126,14 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[calibrate] copied {src.numel() * 4} bytes 5 times")
+        return 0
     batch = synthetic.diamond_bulk()
     h = batch.hypers
     calc = P.Calculator.from_hypers(h)
@@ -126,7 +141,8 @@ def main() -> int:
     pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
     spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
     ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
-    nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32)
+    # forward-mode rows need no reverse-pair index, so the step does not build it
+    nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32, transpose=False)
     N, Pn = batch.n_atoms, nl.count()
     out = calc.allocate_features(N, nl.capacity, torch.float32, dev, True)
     calc.reset_status()
@@ -134,34 +150,38 @@ def main() -> int:
     def step_neighbors():
         calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32, out=nl)
 
-    def step_features():
-        calc.features(nl, spc, torch.float32, gradients=True, out=out)
+    def step_centres():
+        calc.features(nl, spc, torch.float32, gradients=True, out=out, rows=False)
 
+    def step_rows():
+        calc.gradient_rows(nl, spc, out[0], dc=out[2], dp=out[4])
+
+    steps = [step_neighbors, step_centres, step_rows]
     # eager warm-up (also sets LDS attributes before any capture)
     for _ in range(3):
-        step_neighbors()
-        step_features()
+        for f in steps:
+            f()
     torch.cuda.synchronize()
     ref = [t.clone() for t in out]
-    if not args.no_graph:
+    if args.graph:
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            step_neighbors()
-            step_features()
+            for f in steps:
+                f()
         torch.cuda.current_stream().wait_stream(side)
-        g_nl, g_feat = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g_nl):
-            step_neighbors()
-        with torch.cuda.graph(g_feat):
-            step_features()
-        run_nl, run_feat = g_nl.replay, g_feat.replay
+        graphs = [torch.cuda.CUDAGraph() for _ in steps]
+        for g, f in zip(graphs, steps):
+            with torch.cuda.graph(g):
+                f()
+        run_nl, run_centres, run_rows = [g.replay for g in graphs]
     else:
-        run_nl, run_feat = step_neighbors, step_features
+        run_nl, run_centres, run_rows = steps
 
     for _ in range(args.warmup):
         run_nl()
-        run_feat()
+        run_centres()
+        run_rows()
     torch.cuda.synchronize()
     for a, b in zip(out, ref):
         if not torch.equal(a, b):
@@ -169,7 +189,7 @@ def main() -> int:
             return 3
 
     K = args.steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
@@ -178,13 +198,16 @@ def main() -> int:
     for k in range(K):
         run_nl()
         ev[k][0].record()
-        run_feat()
+        run_centres()
         ev[k][1].record()
+        run_rows()
+        ev[k][2].record()
     end_all.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = start_all.elapsed_time(end_all)
-    feat_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    centres_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    rows_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     status = calc.device_status()
     if status != 0:
         log(f"device status {status}")
@@ -196,12 +219,13 @@ def main() -> int:
 
     ms_per_step = total_ms / K
     value = N / (ms_per_step * 1e-3)
-    alg = algorithmic_bytes(N, Pn, h["n_species"], h["nmax"], h["lmax"])
-    achieved = alg / (feat_ms * 1e-3) / 1e9
+    alg_centres, alg = algorithmic_bytes(N, Pn, h["n_species"], h["nmax"], h["lmax"])
+    achieved = alg / (rows_ms * 1e-3) / 1e9
     traffic = measured_traffic(alg)
     log(f"[bench] N={N} P={Pn} steps={K} total={total_ms:.2f} ms (host wall {wall * 1e3:.1f} ms) "
-        f"step={ms_per_step * 1e3:.1f} us  feature kernel={feat_ms * 1e3:.1f} us  neighbours+gaps="
-        f"{(ms_per_step - feat_ms) * 1e3:.1f} us  alg bytes/launch={alg / 1e6:.1f} MB  {achieved:.0f} GB/s")
+        f"step={ms_per_step * 1e3:.1f} us  centres={centres_ms * 1e3:.1f} us "
+        f"({alg_centres / (centres_ms * 1e-3) / 1e9:.0f} GB/s)  rows={rows_ms * 1e3:.1f} us ({achieved:.0f} GB/s)  "
+        f"neighbours+gaps={(ms_per_step - rows_ms - centres_ms) * 1e3:.1f} us  row bytes/launch={alg / 1e6:.1f} MB")
 
     line = {
         "metric": "atom-centres/s (expansion+power spectrum+grads) at stated error vs FP64 oracle",
@@ -221,7 +245,7 @@ def main() -> int:
                         "1 species, rcut 5 A, sigma 0.5 A, nmax 8, lmax 6; neighbour list with images + FP32 "
                         "expansion + power spectrum + forward-mode position gradients",
             "centres": N, "pairs": Pn, "n_species": h["n_species"], "nmax": h["nmax"], "lmax": h["lmax"],
-            "rcut": h["rcut"], "sigma": h["sigma"], "graphs": not args.no_graph,
+            "rcut": h["rcut"], "sigma": h["sigma"], "graphs": bool(args.graph),
             "parity": "FP32 vs FP64 oracle: p <= 1e-6, gradient rows <= 1e-5 relative (tests/test_gpu_parity.py)",
         },
         "roofline": {
@@ -232,7 +256,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel_ms": feat_ms,
+            "kernel_ms": rows_ms,
             "algorithmic_bytes_per_launch": alg,
         },
     }

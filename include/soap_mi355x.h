@@ -212,16 +212,33 @@ soap_status soap_power_spectrum(const soap_calculator* calc, const soap_exec* ex
                                 const void* dcoeffs, const void* dcoeffs_self, void* dp,
                                 void* dp_self);
 
-/* Expansion and power spectrum in one launch, optionally with both kinds
- * of forward-mode rows; the coefficient rows never make a round trip
- * through memory before the power-spectrum rows use them.  Arguments as
- * in the two calls above; p is required, dcoeffs/dcoeffs_self/dp/dp_self
- * are all NULL or all given.  precision: SOAP_F64 or SOAP_F32.        */
+/* Expansion and power spectrum, optionally with forward-mode rows, in one
+ * call: a per-centre pass (c, p, and the self rows dcoeffs_self / dp_self)
+ * and, if dcoeffs / dp are given, the pair-row pass of
+ * soap_gradient_rows.  The coefficient rows are never read back.
+ * Arguments as in the calls above; p is required; dcoeffs_self and dp_self
+ * are both NULL or both given, and so are dcoeffs and dp.
+ * precision: SOAP_F64 or SOAP_F32.                                     */
 soap_status soap_features(const soap_calculator* calc, const soap_exec* exec,
                           soap_precision precision, int64_t n_atoms, const int32_t* species,
                           const int64_t* pair_offsets, const int32_t* pair_j,
                           const void* pair_vec, int64_t pair_capacity, void* coeffs, void* p,
                           void* dcoeffs, void* dcoeffs_self, void* dp, void* dp_self);
+
+/* Forward-mode pair rows alone (Sec. 4.G), given the coefficients of every
+ * centre (as written by soap_spherical_expansion or soap_features):
+ *   dcoeffs [P][3][nmax][L2]        d c_{i,a_j,.} / d r_ji
+ *   dp      [P][3][lmax+1][KK]      d p_i / d r_ji, by the product rule
+ *           sum_m dc_{x,k1,lm} c_{k2,lm} + c_{k1,lm} dc_{x,k2,lm}
+ *           summed as (f I~)'_nl u_x y_{l,k} + f I~_nl z_{x,l,k} with
+ *           y = sum_m Y_lm c_{k,lm} and z = sum_m dY_{x,lm} c_{k,lm}.
+ * Either output may be NULL (not both).  coeffs is read only for dp.
+ * precision: SOAP_F64 or SOAP_F32.                                     */
+soap_status soap_gradient_rows(const soap_calculator* calc, const soap_exec* exec,
+                               soap_precision precision, int64_t n_atoms, const int32_t* species,
+                               const int64_t* pair_offsets, const int32_t* pair_j,
+                               const void* pair_vec, int64_t pair_capacity, const void* coeffs,
+                               void* dcoeffs, void* dp);
 
 /* Reverse mode of the power spectrum (chain rule of Sec. 4.G):
  *   grad_coeffs_{k,lm} = sum_k' W_{k k'} c_{k',lm},

@@ -23,7 +23,7 @@ EXPORTS = [
     "soap_abi_version", "soap_last_error", "soap_calculator_create", "soap_calculator_destroy",
     "soap_calculator_info", "soap_calculator_upload", "soap_radial_integral_host",
     "soap_neighbors_workspace_size", "soap_compute_neighbors", "soap_spherical_expansion",
-    "soap_power_spectrum", "soap_features", "soap_power_spectrum_backward",
+    "soap_power_spectrum", "soap_features", "soap_gradient_rows", "soap_power_spectrum_backward",
     "soap_spherical_expansion_backward", "soap_read_device_status",
 ]
 
@@ -86,6 +86,8 @@ def lib():
     L.soap_power_spectrum.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp]
     L.soap_features.restype = st
     L.soap_features.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.soap_gradient_rows.restype = st
+    L.soap_gradient_rows.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp, vp, i64, vp, vp, vp]
     L.soap_power_spectrum_backward.restype = st
     L.soap_power_spectrum_backward.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp]
     L.soap_spherical_expansion_backward.restype = st

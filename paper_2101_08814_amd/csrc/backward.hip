@@ -66,7 +66,7 @@ __device__ __forceinline__ T wave_sum(T v)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, int chunk, Layout L, const T* grad_c,
+__global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, Layout L, const T* grad_c,
                                                                  T* grad_pair)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -80,6 +80,8 @@ __global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, 
         return;
     }
     const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lmax + 1;
+    const int chunk = L.chunk;
+    init_tables<T>(a, d, L, s);
     const T* g_in = grad_c + i * KL2;
     for (int e = tid; e < KL2; e += kThreads) s.c[e] = g_in[e];   // the c slot holds dL/dc here
     const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, 
             T gx = T(0), gy = T(0), gz = T(0);
             for (int e = lane; e < nL2; e += 64) {
                 int n = e / d.L2, lm = e - n * d.L2;
-                int rl = n * lm1 + l_of(lm);
+                int rl = n * lm1 + s.lof[lm];
                 T Gv = G[e];
                 T t = Gv * s.dR[p * d.nl + rl] * s.Y[p * d.L2 + lm];
                 T r = Gv * s.R[p * d.nl + rl];
@@ -156,14 +158,9 @@ hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const 
                           void* grad_pos, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
-    int chunk = 32;
-    Layout L = make_layout(d, chunk, true, false, false);
-    while (chunk > 4 && L.total * sizeof(T) > 65536) {
-        chunk /= 2;
-        L = make_layout(d, chunk, true, false, false);
-    }
+    Layout L = choose_layout<T>(d, true, false, false, false);
+    if (L.total == 0) return hipErrorInvalidValue;
     size_t lds = size_t(L.total) * sizeof(T);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_exp_backward_pairs<T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -171,7 +168,7 @@ hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const 
     }
     if (a.pair_capacity > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_pairs<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads), lds,
-                           stream, a, chunk, L, static_cast<const T*>(grad_c), static_cast<T*>(grad_pair));
+                           stream, a, L, static_cast<const T*>(grad_c), static_cast<T*>(grad_pair));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_gather<T>), dim3(unsigned((a.n_atoms + 255) / 256)), dim3(256),
                        0, stream, a, transpose, static_cast<const T*>(grad_pair), static_cast<T*>(grad_pos));
     return hipGetLastError();

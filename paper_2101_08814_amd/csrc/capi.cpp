@@ -411,20 +411,17 @@ soap_status soap_features(const soap_calculator* calc, const soap_exec* exec, so
     CHECK(check_calc(calc));
     REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
     REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
-    bool grads = dcoeffs || dcoeffs_self || dp || dp_self;
-    REQUIRE(!grads || (dcoeffs_self && dp && dp_self && (dcoeffs || pair_capacity == 0)),
-            "dcoeffs, dcoeffs_self, dp and dp_self: all or none");
+    REQUIRE((dcoeffs_self == nullptr) == (dp_self == nullptr), "dcoeffs_self and dp_self: both or neither");
+    REQUIRE((dcoeffs == nullptr) == (dp == nullptr), "dcoeffs and dp: both or neither");
     if (n_atoms == 0) return SOAP_OK;
     size_t es = elem_size(precision);
     CHECK(check_pairs(species, pair_offsets, pair_j, pair_vec, pair_capacity, es));
     CHECK(check_ptr(coeffs, es, "coeffs"));
     CHECK(check_ptr(p, es, "p"));
-    if (grads) {
-        CHECK(check_ptr(dcoeffs, es, "dcoeffs", pair_capacity == 0));
-        CHECK(check_ptr(dcoeffs_self, es, "dcoeffs_self"));
-        CHECK(check_ptr(dp, es, "dp"));
-        CHECK(check_ptr(dp_self, es, "dp_self"));
-    }
+    CHECK(check_ptr(dcoeffs, es, "dcoeffs", true));
+    CHECK(check_ptr(dcoeffs_self, es, "dcoeffs_self", true));
+    CHECK(check_ptr(dp, es, "dp", true));
+    CHECK(check_ptr(dp_self, es, "dp_self", true));
     const DeviceTables* t = nullptr;
     CHECK(device_tables(calc, &t));
     FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
@@ -436,11 +433,44 @@ soap_status soap_features(const soap_calculator* calc, const soap_exec* exec, so
     a.pair_capacity = pair_capacity;
     a.coeffs = coeffs;
     a.p = p;
-    a.dcoeffs = grads ? dcoeffs : nullptr;
-    a.dcoeffs_self = grads ? dcoeffs_self : nullptr;
-    a.dp = grads ? dp : nullptr;
-    a.dp_self = grads ? dp_self : nullptr;
+    a.dcoeffs = dcoeffs;
+    a.dcoeffs_self = dcoeffs_self;
+    a.dp = dp;
+    a.dp_self = dp_self;
     return launched(launch_features(a, precision == SOAP_F64, stream_of(exec)), "features");
+}
+
+soap_status soap_gradient_rows(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                               int64_t n_atoms, const int32_t* species, const int64_t* pair_offsets,
+                               const int32_t* pair_j, const void* pair_vec, int64_t pair_capacity, const void* coeffs,
+                               void* dcoeffs, void* dp)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(dcoeffs != nullptr || dp != nullptr, "dcoeffs and dp must not both be NULL");
+    if (n_atoms == 0) return SOAP_OK;
+    size_t es = elem_size(precision);
+    CHECK(check_pairs(species, pair_offsets, pair_j, pair_vec, pair_capacity, es));
+    if (dp) CHECK(check_ptr(coeffs, es, "coeffs"));
+    if (pair_capacity > 0) {
+        CHECK(check_ptr(dcoeffs, es, "dcoeffs", true));
+        CHECK(check_ptr(dp, es, "dp", true));
+    }
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    FeatureArgs a = base_args(calc, exec, precision == SOAP_F64, t);
+    a.n_atoms = n_atoms;
+    a.species = species;
+    a.pair_offsets = pair_offsets;
+    a.pair_j = pair_j;
+    a.pair_vec = pair_vec;
+    a.pair_capacity = pair_capacity;
+    a.coeffs = const_cast<void*>(coeffs);
+    a.dcoeffs = dcoeffs;
+    a.dp = dp;
+    return launched(launch_gradient_rows(a, precision == SOAP_F64, stream_of(exec)), "gradient rows");
 }
 
 soap_status soap_power_spectrum_backward(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,

@@ -9,6 +9,12 @@
 // pair vector, dY_{x,lm}.  One lane per pair computes the geometry, one lane
 // per (pair, m) a column of the Legendre table, one lane per (pair, n, l)
 // evaluates the spline, one lane per (pair, lm) the harmonics.
+//
+// Small per-block tables (filled once by init_tables): the degree l of each
+// packed lm, the harmonic normalisation K_lm (built on the host), and the
+// (k1, k2) of each packed
+// upper-triangle index, so no lane divides or takes a square root to decode
+// an index.
 #pragma once
 
 #include "soap_internal.hpp"
@@ -19,6 +25,7 @@ namespace dev {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kTriMax = 8192;    // largest K (K+1)/2 kept as an LDS table
 
 __device__ __forceinline__ void put_status(int32_t* st, int v)
 {
@@ -33,8 +40,8 @@ __device__ __forceinline__ void wave_sync()
 }
 
 struct Dims {
-    int S, nmax, lmax, L2, nl, K, nq;
-    int64_t KK;
+    int S, nmax, lmax, L2, nl, K, nq, lm1;
+    int KK;
 };
 
 __host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
@@ -43,22 +50,27 @@ __host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
     d.S = S;
     d.nmax = nmax;
     d.lmax = lmax;
+    d.lm1 = lmax + 1;
     d.L2 = (lmax + 1) * (lmax + 1);
     d.nl = nmax * (lmax + 1);
     d.K = S * nmax;
     d.nq = (lmax + 1) * (lmax + 2) / 2;
-    d.KK = int64_t(d.K) * (d.K + 1) / 2;
+    d.KK = d.K * (d.K + 1) / 2;
     return d;
 }
 
-// LDS layout in elements of T (ints counted as T-sized slots).
+// LDS layout in elements of T (ints occupy T-sized slots).
 struct Layout {
-    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, total;
+    int chunk, sub;                     // pairs per staged chunk, pairs per y/z batch
+    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, total;
 };
 
-__host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, bool rows_p, bool self_rows = true)
+__host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, bool rows_p, bool self_rows = true,
+                                              bool want_tri = false)
 {
     Layout L;
+    L.chunk = ch;
+    L.sub = ch < 8 ? ch : 8;
     int o = 0;
     L.c = o; o += d.K * d.L2;
     L.dcs = o; o += (grad && self_rows) ? 3 * d.K * d.L2 : 0;
@@ -73,30 +85,86 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     L.dR = o; o += grad ? ch * d.nl : 0;
     L.Y = o; o += ch * d.L2;
     L.dY = o; o += grad ? 3 * ch * d.L2 : 0;
-    L.qt = o; o += ch * d.nq;
-    L.cre = o; o += ch * (d.lmax + 1);
-    L.cim = o; o += ch * (d.lmax + 1);
-    L.yz = o; o += (grad && rows_p) ? kWaves * 4 * (d.lmax + 1) * d.K : 0;
+    // the Legendre table is dead once the harmonics are staged; the y/z
+    // contractions of the gradient rows reuse its space
+    int scratch = ch * (d.nq + 2 * d.lm1);
+    int yz = (grad && rows_p) ? L.sub * 4 * d.lm1 * d.K : 0;
+    L.qt = o;
+    L.cre = o + ch * d.nq;
+    L.cim = L.cre + ch * d.lm1;
+    L.yz = o;
+    o += scratch > yz ? scratch : yz;
     L.spc = o; o += ch;
     L.seg = o; o += 2 * d.S;
+    L.ynorm = o; o += d.L2;
+    L.lof = o; o += d.L2;
+    L.tri = o; o += (want_tri && d.KK <= kTriMax) ? d.KK : 0;
     L.total = o;
+    return L;
+}
+
+// Largest chunk (<= 32 pairs) whose layout fits 64 KB of LDS, else 160 KB;
+// total = 0 if nothing fits.
+template <typename T>
+inline Layout choose_layout(const Dims& d, bool grad, bool rows_p, bool self_rows, bool want_tri)
+{
+    int ch = 32;
+    Layout L = make_layout(d, ch, grad, rows_p, self_rows, want_tri);
+    while (ch > 2 && size_t(L.total) * sizeof(T) > 65536) {
+        ch /= 2;
+        L = make_layout(d, ch, grad, rows_p, self_rows, want_tri);
+    }
+    if (size_t(L.total) * sizeof(T) > 160 * 1024) L.total = 0;
     return L;
 }
 
 template <typename T>
 struct Smem {
-    T *c, *dcs, *ux, *uy, *uz, *r, *rinv, *f, *df, *R, *dR, *Y, *dY, *qt, *cre, *cim, *yz;
-    int *spc, *seg;
+    T *c, *dcs, *ux, *uy, *uz, *r, *rinv, *f, *df, *R, *dR, *Y, *dY, *qt, *cre, *cim, *yz, *ynorm;
+    int *spc, *seg, *lof, *tri;
     __device__ Smem(T* base, const Layout& L)
-        : c(base + L.c), dcs(base + L.dcs), ux(base + L.ux), uy(base + L.uy), uz(base + L.uz), r(base + L.r), rinv(base + L.rinv),
-          f(base + L.f), df(base + L.df), R(base + L.R), dR(base + L.dR), Y(base + L.Y), dY(base + L.dY),
-          qt(base + L.qt), cre(base + L.cre), cim(base + L.cim), yz(base + L.yz),
-          spc(reinterpret_cast<int*>(base + L.spc)), seg(reinterpret_cast<int*>(base + L.seg))
+        : c(base + L.c), dcs(base + L.dcs), ux(base + L.ux), uy(base + L.uy), uz(base + L.uz), r(base + L.r),
+          rinv(base + L.rinv), f(base + L.f), df(base + L.df), R(base + L.R), dR(base + L.dR), Y(base + L.Y),
+          dY(base + L.dY), qt(base + L.qt), cre(base + L.cre), cim(base + L.cim), yz(base + L.yz),
+          ynorm(base + L.ynorm), spc(reinterpret_cast<int*>(base + L.spc)),
+          seg(reinterpret_cast<int*>(base + L.seg)), lof(reinterpret_cast<int*>(base + L.lof)),
+          tri(reinterpret_cast<int*>(base + L.tri))
     {
     }
 };
 
-// Stage nc pairs starting at q0 (all lanes of the block take part).
+// l of each lm, K_lm, and (when present) the packed-triangle decode table
+// tri[kk] = k1 | k2 << 16.  Caller synchronises afterwards.
+template <typename T>
+__device__ void init_tables(const FeatureArgs& a, const Dims& d, const Layout& L, Smem<T>& s)
+{
+    const int tid = threadIdx.x;
+    const T* knorm = static_cast<const T*>(a.center) + d.nmax;
+    for (int lm = tid; lm < d.L2; lm += kThreads) {
+        s.lof[lm] = l_of(lm);
+        s.ynorm[lm] = knorm[lm];
+    }
+    if (L.tri != L.total)
+        for (int k1 = tid; k1 < d.K; k1 += kThreads) {
+            int start = k1 * d.K - k1 * (k1 - 1) / 2;
+            for (int k2 = k1; k2 < d.K; ++k2) s.tri[start + k2 - k1] = k1 | (k2 << 16);
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void tri_pair(const Dims& d, const Smem<T>& s, bool table, int kk, int& k1, int& k2)
+{
+    if (table) {
+        int v = s.tri[kk];
+        k1 = v & 0xFFFF;
+        k2 = v >> 16;
+    } else {
+        tri_decode(d.K, kk, k1, k2);
+    }
+}
+
+// Stage nc pairs starting at q0 (all lanes of the block take part; the
+// tables must be initialised).
 template <typename T, bool GRAD>
 __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int64_t q0, int nc)
 {
@@ -119,7 +187,7 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
         } else {
             T ri = T(1) / r;
             s.ux[tid] = vx * ri; s.uy[tid] = vy * ri; s.uz[tid] = vz * ri; s.rinv[tid] = ri;
-            if (!bad_sp) f = dev::fcut<T>(r, T(a.rcut), T(a.width), df);
+            if (!bad_sp) f = fcut<T>(r, T(a.rcut), T(a.width), df);
         }
         s.f[tid] = f;
         s.df[tid] = df;
@@ -128,10 +196,10 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
     }
     __syncthreads();
     // Qt columns and (x + i y)^m: one lane per (pair, m); species segments
-    const int lm1 = d.lmax + 1;
+    const int lm1 = d.lm1;
     for (int t = tid; t < nc * lm1; t += kThreads) {
         int p = t / lm1, m = t - p * lm1;
-        dev::q_column<T>(m, d.lmax, s.ux[p], s.uy[p], s.uz[p], s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1);
+        q_column<T>(m, d.lmax, s.ux[p], s.uy[p], s.uz[p], s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1);
     }
     for (int sp = tid; sp < d.S; sp += kThreads) {
         int lo = nc, hi = 0;
@@ -144,9 +212,8 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
     const T* coef = static_cast<const T*>(a.coef);
     for (int t = tid; t < nc * d.nl; t += kThreads) {
         int p = t / d.nl, j = t - p * d.nl;
-        T r = s.r[p];
         T v, dv;
-        dev::spline_eval<T>(coef, a.M, T(a.inv_delta), d.nl, j, r, v, dv);
+        spline_eval<T>(coef, a.M, T(a.inv_delta), d.nl, j, s.r[p], v, dv);
         s.R[p * d.nl + j] = s.f[p] * v;
         if (GRAD) s.dR[p * d.nl + j] = s.df[p] * v + s.f[p] * dv;
     }
@@ -155,8 +222,8 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
     for (int t = tid; t < nc * d.L2; t += kThreads) {
         int p = t / d.L2, lm = t - p * d.L2;
         T Y, gx, gy, gz;
-        dev::ylm_and_grad<T>(lm, s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1, s.ux[p], s.uy[p], s.uz[p],
-                             s.rinv[p], Y, gx, gy, gz);
+        ylm_and_grad<T>(lm, s.lof[lm], s.ynorm[lm], s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1, s.ux[p],
+                        s.uy[p], s.uz[p], s.rinv[p], Y, gx, gy, gz);
         s.Y[p * d.L2 + lm] = Y;
         if (GRAD) {
             s.dY[(p * 3 + 0) * d.L2 + lm] = gx;

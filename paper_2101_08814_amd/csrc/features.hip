@@ -24,6 +24,8 @@
 //   y_{l,k} = sum_m Y_lm c_{k,lm},  z_{x,l,k} = sum_m dY_{x,lm} c_{k,lm},
 // so a row costs O(K L2) instead of O(K^2 L2) and the dc row is written to
 // memory but never read back.
+#include <type_traits>
+
 #include "chunk.hpp"
 
 namespace soap {
@@ -31,53 +33,87 @@ namespace {
 
 using namespace dev;
 
-template <typename T, bool GRAD, bool WANT_P>
-__global__ void __launch_bounds__(kThreads) k_features(FeatureArgs a, int chunk, Layout L)
+// Kernels are instantiated with the degree lmax as a template parameter LM
+// (0..12) for float, so index decoding and strides fold to constants; LM = -1
+// takes lmax at run time (the double path and anything else).
+__device__ __forceinline__ int lmax_of(const FeatureArgs& a, int LM) { return LM >= 0 ? LM : a.lmax; }
+
+// ---------------------------------------------------------------------------
+// Per-centre pass: c, p and (with gradients) the self rows of c and p.
+// One thread owns a species channel and an lm and accumulates every n of it
+// over the centre's pairs of that species.
+// ---------------------------------------------------------------------------
+template <typename T, int LM, bool GRAD, bool WANT_P>
+__global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* base = reinterpret_cast<T*>(smem_raw);
     Smem<T> s(base, L);
-    const Dims d = make_dims(a.S, a.nmax, a.lmax);
+    const Dims d = make_dims(a.S, a.nmax, lmax_of(a, LM));
     const int tid = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (a.pair_offsets[a.n_atoms] > a.pair_capacity) {
         if (tid == 0) put_status(a.status, SOAP_ECAPACITY);
         return;
     }
+    const int chunk = L.chunk;
+    init_tables<T>(a, d, L, s);
     const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
-    const int n_pairs = int(q_end - q_begin);
-    const int n_chunks = (n_pairs + chunk - 1) / chunk;
-    const int KL2 = d.K * d.L2;
-    const int nL2 = d.nmax * d.L2;
+    const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
+    const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
     for (int e = tid; e < KL2; e += kThreads) {
         s.c[e] = T(0);
         if (GRAD) { s.dcs[e] = T(0); s.dcs[KL2 + e] = T(0); s.dcs[2 * KL2 + e] = T(0); }
     }
-    // ---------------------------------------------------- expansion
+    // items (species, n pair, lm): two n per thread share the Y and dY loads
+    const int ng = (d.nmax + 1) / 2;
+    const int items = d.S * ng * d.L2;
     for (int ck = 0; ck < n_chunks; ++ck) {
         int64_t q0 = q_begin + int64_t(ck) * chunk;
         int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
         stage_chunk<T, GRAD>(a, d, s, q0, nc);
-        for (int e = tid; e < KL2; e += kThreads) {
-            int sp = e / nL2, rem = e - sp * nL2, n = rem / d.L2, lm = rem - n * d.L2;
-            int l = dev::l_of(lm);
-            int rl = n * (d.lmax + 1) + l;
-            T acc = s.c[e];
-            T g0 = T(0), g1 = T(0), g2 = T(0);
-            int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
+        for (int t = tid; t < items; t += kThreads) {
+            const int sp = t / (ng * d.L2), rem = t - sp * (ng * d.L2), g = rem / d.L2, lm = rem - g * d.L2;
+            const int n0 = 2 * g, two = n0 + 1 < d.nmax;
+            const int l = s.lof[lm];
+            const int e0 = (sp * d.nmax + n0) * d.L2 + lm;
+            T c0 = T(0), c1 = T(0);
+            T a0 = T(0), a1 = T(0), a2 = T(0), b0 = T(0), b1 = T(0), b2 = T(0);
+            const int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
             for (int p = p0; p < p1; ++p) {
                 if (s.spc[p] != sp) continue;
-                T Rv = s.R[p * d.nl + rl], Yv = s.Y[p * d.L2 + lm];
-                acc += Rv * Yv;
+                const T Yv = s.Y[p * d.L2 + lm];
+                const T* Rp = s.R + p * d.nl + n0 * lm1 + l;
+                const T R0 = Rp[0], R1 = two ? Rp[lm1] : T(0);
+                c0 += R0 * Yv;
+                c1 += R1 * Yv;
                 if (GRAD) {
-                    T t = s.dR[p * d.nl + rl] * Yv;
-                    g0 += t * s.ux[p] + Rv * s.dY[(p * 3 + 0) * d.L2 + lm];
-                    g1 += t * s.uy[p] + Rv * s.dY[(p * 3 + 1) * d.L2 + lm];
-                    g2 += t * s.uz[p] + Rv * s.dY[(p * 3 + 2) * d.L2 + lm];
+                    // d c_i / d r_i = -sum over pairs of [(f I~)' Y u + f I~ grad Y]
+                    const T* dRp = s.dR + p * d.nl + n0 * lm1 + l;
+                    const T* D = s.dY + p * 3 * d.L2 + lm;
+                    const T D0 = D[0], D1 = D[d.L2], D2 = D[2 * d.L2];
+                    const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
+                    const T t0 = dRp[0] * Yv, t1 = (two ? dRp[lm1] : T(0)) * Yv;
+                    a0 += t0 * ux + R0 * D0;
+                    a1 += t0 * uy + R0 * D1;
+                    a2 += t0 * uz + R0 * D2;
+                    b0 += t1 * ux + R1 * D0;
+                    b1 += t1 * uy + R1 * D1;
+                    b2 += t1 * uz + R1 * D2;
                 }
             }
-            s.c[e] = acc;
-            if (GRAD) { s.dcs[e] -= g0; s.dcs[KL2 + e] -= g1; s.dcs[2 * KL2 + e] -= g2; }
+            s.c[e0] += c0;
+            if (two) s.c[e0 + d.L2] += c1;
+            if (GRAD) {
+                s.dcs[e0] -= a0;
+                s.dcs[KL2 + e0] -= a1;
+                s.dcs[2 * KL2 + e0] -= a2;
+                if (two) {
+                    s.dcs[e0 + d.L2] -= b0;
+                    s.dcs[KL2 + e0 + d.L2] -= b1;
+                    s.dcs[2 * KL2 + e0 + d.L2] -= b2;
+                }
+            }
         }
         if (ck + 1 < n_chunks) __syncthreads();
     }
@@ -94,97 +130,141 @@ __global__ void __launch_bounds__(kThreads) k_features(FeatureArgs a, int chunk,
         T* dcs_out = static_cast<T*>(a.dcoeffs_self) + i * 3 * KL2;
         for (int e = tid; e < 3 * KL2; e += kThreads) dcs_out[e] = s.dcs[e];
     }
-    // ---------------------------------------------------- power spectrum
-    const int lm1 = d.lmax + 1;
-    const int64_t PL = int64_t(lm1) * d.KK;
-    if (WANT_P) {
-        T* p_out = static_cast<T*>(a.p) + i * PL;
-        for (int64_t o = tid; o < PL; o += kThreads) {
-            int l = int(o / d.KK);
-            int kk = int(o - int64_t(l) * d.KK);
-            int k1, k2;
-            dev::tri_decode(d.K, kk, k1, k2);
-            const T* c1 = s.c + k1 * d.L2 + l * l;
-            const T* c2 = s.c + k2 * d.L2 + l * l;
-            T acc = T(0);
-            for (int m = 0; m < 2 * l + 1; ++m) acc += c1[m] * c2[m];
-            p_out[o] = acc;
-        }
+    if (!WANT_P) return;
+    const int KK = d.KK, PL = lm1 * KK;
+    const bool tri_tab = L.tri != L.total;
+    T* p_out = static_cast<T*>(a.p) + i * int64_t(PL);
+    T* dps_out = GRAD ? static_cast<T*>(a.dp_self) + i * int64_t(3 * PL) : nullptr;
+    int l = tid / KK, kk = tid - (tid / KK) * KK;
+    for (int o = tid; o < PL; o += kThreads) {
+        int k1, k2;
+        tri_pair(d, s, tri_tab, kk, k1, k2);
+        const T* c1 = s.c + k1 * d.L2 + l * l;
+        const T* c2 = s.c + k2 * d.L2 + l * l;
+        T acc = T(0);
+        for (int m = 0; m < 2 * l + 1; ++m) acc += c1[m] * c2[m];
+        p_out[o] = acc;
         if (GRAD) {
-            T* dps_out = static_cast<T*>(a.dp_self) + i * 3 * PL;
-            for (int64_t o = tid; o < 3 * PL; o += kThreads) {
-                int x = int(o / PL);
-                int64_t r0 = o - x * PL;
-                int l = int(r0 / d.KK);
-                int kk = int(r0 - int64_t(l) * d.KK);
-                int k1, k2;
-                dev::tri_decode(d.K, kk, k1, k2);
-                const T* c1 = s.c + k1 * d.L2 + l * l;
-                const T* c2 = s.c + k2 * d.L2 + l * l;
+            // self rows of p: the product rule on the self rows of c
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
                 const T* g1 = s.dcs + x * KL2 + k1 * d.L2 + l * l;
                 const T* g2 = s.dcs + x * KL2 + k2 * d.L2 + l * l;
-                T acc = T(0);
-                for (int m = 0; m < 2 * l + 1; ++m) acc += g1[m] * c2[m] + c1[m] * g2[m];
-                dps_out[o] = acc;
+                T acc2 = T(0);
+                for (int m = 0; m < 2 * l + 1; ++m) acc2 += g1[m] * c2[m] + c1[m] * g2[m];
+                dps_out[x * PL + o] = acc2;
             }
+        }
+        kk += kThreads;
+        while (kk >= KK) { kk -= KK; ++l; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient rows of every pair: grid (centres, groups); group g of centre i
+// takes a contiguous share of its pairs, restages them and streams out
+//   dc_{x,n,lm} = (f I~)'_nl u_x Y_lm + f I~_nl dY_{x,lm}
+// (one thread per (pair, x, lm) writes the nmax values of that (x, lm)) and,
+// with WANT_DP, the dp row in the reordered product-rule form (one thread
+// per packed position (l, k1, k2) of a pair writes its three components).
+// c of the centre (written by k_centres) is read back into LDS for dp.
+// ---------------------------------------------------------------------------
+template <typename T, int LM, bool WANT_DC, bool WANT_DP>
+__global__ void __launch_bounds__(kThreads) k_rows(FeatureArgs a, Layout L)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* base = reinterpret_cast<T*>(smem_raw);
+    Smem<T> s(base, L);
+    const Dims d = make_dims(a.S, a.nmax, lmax_of(a, LM));
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (a.pair_offsets[a.n_atoms] > a.pair_capacity) return;
+    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
+    const int n_pairs = int(q_end - q_begin);
+    const int G = gridDim.y, g = blockIdx.y;
+    const int share = (n_pairs + G - 1) / G;
+    const int p_lo = g * share, p_hi = (g + 1) * share < n_pairs ? (g + 1) * share : n_pairs;
+    if (p_lo >= p_hi) return;
+    init_tables<T>(a, d, L, s);
+    const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
+    const int KK = d.KK, PL = lm1 * KK;
+    if (WANT_DP) {
+        const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
+        for (int e = tid; e < KL2; e += kThreads) s.c[e] = c_in[e];
+        // packed positions of a dp row: l | k1 << 4 | k2 << 14
+        for (int o = tid; o < PL; o += kThreads) {
+            int l = o / KK, kk = o - l * KK, k1, k2;
+            tri_decode(d.K, kk, k1, k2);
+            s.tri[o] = l | (k1 << 4) | (k2 << 14);
         }
     }
-    if (!GRAD) return;
-    // ---------------------------------------------------- gradient rows
-    const int wave = tid >> 6, lane = tid & 63;
-    T* yz = s.yz + wave * 4 * lm1 * d.K;
+    const int EDC = 3 * nL2;
     const int yzn = lm1 * d.K;
-    for (int ck = n_chunks - 1; ck >= 0; --ck) {
-        int64_t q0 = q_begin + int64_t(ck) * chunk;
-        int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
-        if (ck != n_chunks - 1) {
-            __syncthreads();
-            stage_chunk<T, GRAD>(a, d, s, q0, nc);
+    for (int c0 = p_lo; c0 < p_hi; c0 += L.chunk) {
+        const int nc = p_hi - c0 < L.chunk ? p_hi - c0 : L.chunk;
+        const int64_t q0 = q_begin + c0;
+        if (c0 != p_lo) __syncthreads();
+        stage_chunk<T, true>(a, d, s, q0, nc);
+        if (WANT_DC) {
+            T* dc_base = static_cast<T*>(a.dcoeffs) + q0 * EDC;
+            const int per_pair = 3 * d.L2;
+            for (int t = tid; t < nc * per_pair; t += kThreads) {
+                const int p = t / per_pair, rem = t - p * per_pair, x = rem / d.L2, lm = rem - x * d.L2;
+                const int l = s.lof[lm];
+                const T u = x == 0 ? s.ux[p] : (x == 1 ? s.uy[p] : s.uz[p]);
+                const T alpha = u * s.Y[p * d.L2 + lm];
+                const T beta = s.dY[(p * 3 + x) * d.L2 + lm];
+                const T* dRp = s.dR + p * d.nl + l;
+                const T* Rp = s.R + p * d.nl + l;
+                T* out = dc_base + int64_t(p) * EDC + x * nL2 + lm;
+                for (int n = 0; n < d.nmax; ++n) out[n * d.L2] = dRp[n * lm1] * alpha + Rp[n * lm1] * beta;
+            }
         }
-        for (int p = wave; p < nc; p += kWaves) {
-            const int64_t q = q0 + p;
-            const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
-            const int blk = s.spc[p] * d.nmax;
-            if (WANT_P) {
-                for (int t = lane; t < 4 * yzn; t += 64) {
-                    int comp = t / yzn, rem = t - comp * yzn, l = rem / d.K, k = rem - l * d.K;
-                    const T* src = comp == 0 ? s.Y + p * d.L2 : s.dY + (p * 3 + comp - 1) * d.L2;
-                    const T* ck_ = s.c + k * d.L2 + l * l;
-                    src += l * l;
-                    T acc = T(0);
-                    for (int m = 0; m < 2 * l + 1; ++m) acc += src[m] * ck_[m];
-                    yz[t] = acc;
+        if (WANT_DP) {
+            // y_{l,k} = sum_m Y_lm c_{k,lm},  z_{x,l,k} = sum_m dY_{x,lm} c_{k,lm}
+            for (int t = tid; t < nc * yzn; t += kThreads) {
+                int p = t / yzn, rem = t - p * yzn, l = rem / d.K, k = rem - l * d.K;
+                const T* ck_ = s.c + k * d.L2 + l * l;
+                const T* Yp = s.Y + p * d.L2 + l * l;
+                const T* Dx = s.dY + (p * 3 + 0) * d.L2 + l * l;
+                const T* Dy = Dx + d.L2;
+                const T* Dz = Dy + d.L2;
+                T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
+                for (int m = 0; m < 2 * l + 1; ++m) {
+                    T cv = ck_[m];
+                    y += Yp[m] * cv;
+                    z0 += Dx[m] * cv;
+                    z1 += Dy[m] * cv;
+                    z2 += Dz[m] * cv;
                 }
-                wave_sync();
+                T* out = s.yz + p * 4 * yzn + l * d.K + k;
+                out[0] = y;
+                out[yzn] = z0;
+                out[2 * yzn] = z1;
+                out[3 * yzn] = z2;
             }
-            T* dc_row = static_cast<T*>(a.dcoeffs) + q * 3 * nL2;
-            for (int e = lane; e < 3 * nL2; e += 64) {
-                int x = e / nL2, rem = e - x * nL2, n = rem / d.L2, lm = rem - n * d.L2;
-                int rl = n * lm1 + dev::l_of(lm);
-                T u = x == 0 ? ux : (x == 1 ? uy : uz);
-                dc_row[e] = s.dR[p * d.nl + rl] * u * s.Y[p * d.L2 + lm] + s.R[p * d.nl + rl] * s.dY[(p * 3 + x) * d.L2 + lm];
-            }
-            if (WANT_P) {
-                T* dp_row = static_cast<T*>(a.dp) + q * 3 * PL;
-                for (int64_t o = lane; o < 3 * PL; o += 64) {
-                    int x = int(o / PL);
-                    int64_t r0 = o - x * PL;
-                    int l = int(r0 / d.KK);
-                    int kk = int(r0 - int64_t(l) * d.KK);
-                    int k1, k2;
-                    dev::tri_decode(d.K, kk, k1, k2);
-                    T u = x == 0 ? ux : (x == 1 ? uy : uz);
-                    const T* y = yz + l * d.K;
-                    const T* z = yz + (1 + x) * yzn + l * d.K;
-                    T v = T(0);
-                    int n1 = k1 - blk, n2 = k2 - blk;
-                    if (n1 >= 0 && n1 < d.nmax)
-                        v += s.dR[p * d.nl + n1 * lm1 + l] * u * y[k2] + s.R[p * d.nl + n1 * lm1 + l] * z[k2];
-                    if (n2 >= 0 && n2 < d.nmax)
-                        v += s.dR[p * d.nl + n2 * lm1 + l] * u * y[k1] + s.R[p * d.nl + n2 * lm1 + l] * z[k1];
-                    dp_row[o] = v;
+            __syncthreads();
+            T* dp_base = static_cast<T*>(a.dp) + q0 * int64_t(3 * PL);
+            for (int p = 0; p < nc; ++p) {
+                const int blk = s.spc[p] * d.nmax;
+                const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
+                const T* Rp = s.R + p * d.nl;
+                const T* dRp = s.dR + p * d.nl;
+                const T* ybase = s.yz + p * 4 * yzn;
+                T* row = dp_base + int64_t(p) * (3 * PL);
+                for (int o = tid; o < PL; o += kThreads) {
+                    const int v = s.tri[o];
+                    const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
+                    const int n1 = k1 - blk, n2 = k2 - blk;
+                    const bool in1 = n1 >= 0 && n1 < d.nmax, in2 = n2 >= 0 && n2 < d.nmax;
+                    const T* yb = ybase + l * d.K;
+                    const T A1 = in1 ? dRp[n1 * lm1 + l] : T(0), B1 = in1 ? Rp[n1 * lm1 + l] : T(0);
+                    const T A2 = in2 ? dRp[n2 * lm1 + l] : T(0), B2 = in2 ? Rp[n2 * lm1 + l] : T(0);
+                    const T a0 = A1 * yb[k2] + A2 * yb[k1];
+                    row[o] = ux * a0 + B1 * yb[yzn + k2] + B2 * yb[yzn + k1];
+                    row[PL + o] = uy * a0 + B1 * yb[2 * yzn + k2] + B2 * yb[2 * yzn + k1];
+                    row[2 * PL + o] = uz * a0 + B1 * yb[3 * yzn + k2] + B2 * yb[3 * yzn + k1];
                 }
-                wave_sync();
             }
         }
     }
@@ -305,40 +385,128 @@ hipError_t launch_dyn(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s
 }
 
 template <typename K>
-hipError_t launch_feat(K kernel, size_t lds, hipStream_t stream, const FeatureArgs& a, int chunk, const Layout& L)
+hipError_t launch_feat(K kernel, size_t lds, hipStream_t stream, const FeatureArgs& a, const Layout& L)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kernel, dim3(unsigned(a.n_atoms)), dim3(kThreads), lds, stream, a, chunk, L);
+    hipLaunchKernelGGL(kernel, dim3(unsigned(a.n_atoms)), dim3(kThreads), lds, stream, a, L);
     return hipGetLastError();
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+template <typename K>
+hipError_t launch_rows(K kernel, size_t lds, hipStream_t stream, const FeatureArgs& a, const Layout& L, int groups)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, dim3(unsigned(a.n_atoms), unsigned(groups)), dim3(kThreads), lds, stream, a, L);
+    return hipGetLastError();
+}
+
+
+template <typename T, int LM>
+hipError_t rows_launch(const FeatureArgs& a, const Layout& R, size_t lds, int groups, hipStream_t stream)
+{
+    const bool want_dc = a.dcoeffs != nullptr, want_dp = a.dp != nullptr;
+    if (want_dc && want_dp) return launch_rows(k_rows<T, LM, true, true>, lds, stream, a, R, groups);
+    if (want_dc) return launch_rows(k_rows<T, LM, true, false>, lds, stream, a, R, groups);
+    return launch_rows(k_rows<T, LM, false, true>, lds, stream, a, R, groups);
+}
+
+template <typename T, int LM>
+hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, hipStream_t stream)
+{
+    const bool grad = a.dcoeffs_self != nullptr, want_p = a.p != nullptr;
+    if (grad)
+        return want_p ? launch_feat(k_centres<T, LM, true, true>, lds, stream, a, L)
+                      : launch_feat(k_centres<T, LM, true, false>, lds, stream, a, L);
+    return want_p ? launch_feat(k_centres<T, LM, false, true>, lds, stream, a, L)
+                  : launch_feat(k_centres<T, LM, false, false>, lds, stream, a, L);
+}
+
+// float kernels specialised on lmax, everything else generic
+template <typename T, template <typename, int> class Fn, typename... Args>
+hipError_t by_lmax(int lmax, Args&&... args)
+{
+    if (!std::is_same<T, float>::value) return Fn<T, -1>::run(args...);
+    switch (lmax) {
+    case 0: return Fn<T, 0>::run(args...);
+    case 1: return Fn<T, 1>::run(args...);
+    case 2: return Fn<T, 2>::run(args...);
+    case 3: return Fn<T, 3>::run(args...);
+    case 4: return Fn<T, 4>::run(args...);
+    case 5: return Fn<T, 5>::run(args...);
+    case 6: return Fn<T, 6>::run(args...);
+    case 7: return Fn<T, 7>::run(args...);
+    case 8: return Fn<T, 8>::run(args...);
+    case 9: return Fn<T, 9>::run(args...);
+    case 10: return Fn<T, 10>::run(args...);
+    case 11: return Fn<T, 11>::run(args...);
+    case 12: return Fn<T, 12>::run(args...);
+    default: return Fn<T, -1>::run(args...);
+    }
+}
+
+template <typename T, int LM>
+struct RowsFn {
+    static hipError_t run(const FeatureArgs& a, const Layout& R, size_t lds, int groups, hipStream_t st)
+    {
+        return rows_launch<T, LM>(a, R, lds, groups, st);
+    }
+};
+
+template <typename T, int LM>
+struct CentresFn {
+    static hipError_t run(const FeatureArgs& a, const Layout& L, size_t lds, hipStream_t st)
+    {
+        return centres_launch<T, LM>(a, L, lds, st);
+    }
+};
+
+constexpr int kRowChunk = 8;   // pairs a row group stages at a time
+
+template <typename T>
+hipError_t rows_t(const FeatureArgs& a, hipStream_t stream)
+{
+    Dims d = make_dims(a.S, a.nmax, a.lmax);
+    const bool want_dc = a.dcoeffs != nullptr, want_dp = a.dp != nullptr;
+    if (a.pair_capacity == 0 || a.n_atoms == 0 || (!want_dc && !want_dp)) return hipSuccess;
+    Layout R = make_layout(d, kRowChunk, true, want_dp, false, false);
+    R.sub = kRowChunk;
+    // the dp-row position table replaces the triangle table
+    R.tri = R.total;
+    R.total += want_dp ? (d.lmax + 1) * d.KK : 0;
+    size_t lds = size_t(R.total) * sizeof(T);
+    if (lds > kMaxLds || (want_dp && d.K > 1023)) return hipErrorInvalidValue;
+    // row groups of about kRowChunk pairs at the mean neighbour count
+    int64_t mean = (a.pair_capacity + a.n_atoms - 1) / a.n_atoms;
+    int groups = int((mean + kRowChunk - 1) / kRowChunk);
+    groups = groups < 1 ? 1 : (groups > 64 ? 64 : groups);
+    return by_lmax<T, RowsFn>(a.lmax, a, R, lds, groups, stream);
+}
+
+// per-centre pass (c, p, self rows) then, if asked for, the pair rows
 template <typename T>
 hipError_t features_t(const FeatureArgs& a, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
     bool grad = a.dcoeffs_self != nullptr;
     bool want_p = a.p != nullptr;
-    // largest chunk (<= 32 pairs) whose layout fits 64 KB, else 160 KB
-    int chunk = 32;
-    Layout L = make_layout(d, chunk, grad, want_p);
-    while (chunk > 4 && L.total * sizeof(T) > 65536) {
-        chunk /= 2;
-        L = make_layout(d, chunk, grad, want_p);
-    }
+    Layout L = choose_layout<T>(d, grad, false, true, want_p);
+    if (L.total == 0) return hipErrorInvalidValue;
     size_t lds = size_t(L.total) * sizeof(T);
-    if (lds > kMaxLds) return hipErrorInvalidValue;
-    if (grad) {
-        if (want_p) return launch_feat(k_features<T, true, true>, lds, stream, a, chunk, L);
-        return launch_feat(k_features<T, true, false>, lds, stream, a, chunk, L);
-    }
-    if (want_p) return launch_feat(k_features<T, false, true>, lds, stream, a, chunk, L);
-    return launch_feat(k_features<T, false, false>, lds, stream, a, chunk, L);
+    FeatureArgs c = a;
+    c.dp_self = want_p ? a.dp_self : nullptr;
+    hipError_t e = by_lmax<T, CentresFn>(a.lmax, c, L, lds, stream);
+    if (e != hipSuccess) return e;
+    return rows_t<T>(a, stream);
 }
 
 template <typename T>
@@ -359,22 +527,14 @@ hipError_t power_spectrum_t(const FeatureArgs& a, hipStream_t stream)
 
 }  // namespace
 
-size_t features_lds_bytes(int S, int nmax, int lmax, bool f64, bool grad, bool want_p)
-{
-    Dims d = make_dims(S, nmax, lmax);
-    int chunk = 32;
-    size_t es = f64 ? 8 : 4;
-    Layout L = make_layout(d, chunk, grad, want_p);
-    while (chunk > 4 && L.total * es > 65536) {
-        chunk /= 2;
-        L = make_layout(d, chunk, grad, want_p);
-    }
-    return size_t(L.total) * es;
-}
-
 hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream)
 {
     return f64 ? features_t<double>(a, stream) : features_t<float>(a, stream);
+}
+
+hipError_t launch_gradient_rows(const FeatureArgs& a, bool f64, hipStream_t stream)
+{
+    return f64 ? rows_t<double>(a, stream) : rows_t<float>(a, stream);
 }
 
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream)

@@ -11,24 +11,24 @@
 // distinct (bin, cell shift) pair, so each image is seen exactly once even
 // in cells thinner than rcut.
 //
-// Phases (one launch each, all on the caller's stream, no host copies):
-//   geometry - per structure: inverse cell, bins per axis, stencil reach and
-//              first bin (one work-group, scan over structures)
-//   assign  - structure, wrap and bin of every atom, bin occupancy counts
-//   scan    - bin starts
-//   bins    - atoms scattered into their bins
-//   count   - pairs per centre
-//   scan    - pair_offsets (the total is checked against the capacity)
-//   fill    - (j, s) of each centre's pairs, in visiting order
-//   sort    - per centre, rank by (species_j, j, s) and rewrite; pair
-//             vectors formed in double from the positions
-//   transpose (optional) - index of the reverse pair (j, i, -s)
-// Integer atomics are used only for bin occupancy; the final order does not
-// depend on them, so the output is deterministic.
+// Bin build: one work-group when the system has at most kSmallBins bins
+// (occupancy counted in LDS), otherwise five small launches (geometry,
+// clear, assign with integer atomics, scan, scatter).
+// Pair list: one wave per centre.  The wave reads the sizes of its stencil
+// bins in one round, scans them across lanes, and then tests 64 candidates
+// per round; hits are compacted with a ballot.  A counting launch, a scan
+// of the counts (pair_offsets), and a filling launch that ranks the
+// centre's pairs by (species_j, j, s) in LDS and writes them sorted, with
+// pair vectors formed in double from the positions.  Optionally the index
+// of the reverse pair (j, i, -s).  The bin contents may be in any order; the
+// sorted output does not depend on it, so the list is deterministic.
 #include "soap_internal.hpp"
 
 namespace soap {
 namespace {
+
+constexpr int kSmallBins = 8192;   // single-work-group bin build up to this many bins
+constexpr int kSortCap = 512;      // pairs per centre ranked in LDS
 
 __device__ __forceinline__ void put_status(int32_t* st, int v)
 {
@@ -41,11 +41,10 @@ __device__ __forceinline__ int floordiv(int a, int b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
-// Per-structure geometry.  Bins per periodic axis: floor(width / rcut),
-// capped so that a structure never has more bins than atoms (the workspace
-// then holds at most N + n_structures bins); the reach is the number of
-// bins that spans rcut.  Any invalid input clears *ok and every later phase
-// produces an empty list.
+// ------------------------------------------------------------- geometry
+// Bins per periodic axis: floor(width / rcut), capped so that a structure
+// never has more bins than atoms (the workspace then holds at most
+// N + n_structures bins); the reach is the number of bins that spans rcut.
 __device__ bool make_geometry(const NeighborArgs& a, int s, StructGeom& g)
 {
     int64_t lo = a.atom_offsets[s], hi = a.atom_offsets[s + 1];
@@ -89,17 +88,51 @@ __device__ bool make_geometry(const NeighborArgs& a, int s, StructGeom& g)
         double nbf = floor(width / a.rcut);
         int nb = nbf < 1.0 ? 1 : (nbf > double(cap) ? cap : int(nbf));
         double need = ceil(a.rcut * nb / width * (1.0 + 1e-12));
-        if (!(need <= 1024.0)) return false;
+        if (!(need <= 64.0)) return false;
         g.nbin[k] = nb;
         g.reach[k] = need < 1.0 ? 1 : int(need);
     }
     return valid;
 }
 
-__global__ void __launch_bounds__(1024) k_geometry(NeighborArgs a)
+// Exclusive scan of n values by one block of 1024 threads (each owns a
+// contiguous chunk); out[n] = total.  Returns the total in every thread.
+template <typename Tin, typename Tout>
+__device__ Tout block_scan(const Tin* in, Tout* out, Tout* out2, int64_t n)
 {
-    __shared__ int64_t part[1024];
+    __shared__ Tout part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
+    Tout s = 0;
+    for (int64_t k = b; k < e; ++k) s += Tout(in[k]);
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        Tout v = t >= off ? part[t - off] : Tout(0);
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    Tout run = part[t] - s;
+    for (int64_t k = b; k < e; ++k) {
+        Tout v = Tout(in[k]);
+        out[k] = run;
+        if (out2) out2[k] = run;
+        run += v;
+    }
+    Tout total = part[1023];
+    if (t == 1023) out[n] = total;
+    __syncthreads();
+    return total;
+}
+
+// Geometry of every structure (one block of 1024 threads).  Returns true in
+// every thread when the input is valid; writes *a.ok.
+__device__ bool geometry_block(const NeighborArgs& a)
+{
     __shared__ int bad;
+    __shared__ int64_t nb[1024];
     const int t = threadIdx.x;
     if (t == 0) bad = (a.atom_offsets[0] != 0 || a.atom_offsets[a.n_structures] != a.n_atoms) ? 1 : 0;
     __syncthreads();
@@ -113,38 +146,32 @@ __global__ void __launch_bounds__(1024) k_geometry(NeighborArgs a)
         sum += int64_t(g.nbin[0]) * g.nbin[1] * g.nbin[2];
         a.geom[s] = g;
     }
-    part[t] = sum;
+    nb[t] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        int64_t v = t >= off ? part[t - off] : 0;
+        int64_t v = t >= off ? nb[t - off] : 0;
         __syncthreads();
-        part[t] += v;
+        nb[t] += v;
         __syncthreads();
     }
-    int64_t run = part[t] - sum;
+    int64_t run = nb[t] - sum;
     for (int64_t s = b; s < e; ++s) {
         a.geom[s].bin_lo = run;
         run += int64_t(a.geom[s].nbin[0]) * a.geom[s].nbin[1] * a.geom[s].nbin[2];
     }
+    if (t == 0 && nb[1023] > a.max_bins) bad = 1;
     __syncthreads();
+    bool ok = bad == 0;
     if (t == 0) {
-        if (part[1023] > a.max_bins) bad = 1;
-        *a.ok = bad ? 0 : 1;
-        if (bad) put_status(a.status, SOAP_EINVAL);
+        *a.ok = ok ? 1 : 0;
+        if (!ok) put_status(a.status, SOAP_EINVAL);
     }
+    return ok;
 }
 
-__global__ void k_zero_i32(int32_t* p, int64_t n)
+// structure, wrap and bin of atom i
+__device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-__global__ void k_assign(NeighborArgs a)
-{
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms || !*a.ok) return;
-    // structure of atom i: first s with atom_hi > i
     int lo = 0, hi = a.n_structures - 1;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
@@ -157,9 +184,8 @@ __global__ void k_assign(NeighborArgs a)
         if (!g.pbc[k]) { b[k] = 0; t[k] = 0; continue; }
         double f = r[0] * g.Hinv[0 * 3 + k] + r[1] * g.Hinv[1 * 3 + k] + r[2] * g.Hinv[2 * 3 + k];
         double fl = floor(f);
-        double fw = f - fl;
         t[k] = int(fl);
-        int bk = int(fw * g.nbin[k]);
+        int bk = int((f - fl) * g.nbin[k]);
         b[k] = bk < 0 ? 0 : (bk >= g.nbin[k] ? g.nbin[k] - 1 : bk);
     }
     int32_t bin = int32_t(g.bin_lo + (int64_t(b[0]) * g.nbin[1] + b[1]) * g.nbin[2] + b[2]);
@@ -170,39 +196,50 @@ __global__ void k_assign(NeighborArgs a)
     a.atom_wrap[3 * i + 2] = t[2];
     int sp = a.species[i];
     if (sp < 0 || sp >= a.n_species) put_status(a.status, SOAP_ESPECIES);
-    atomicAdd(&a.bin_count[bin], 1);
+    return bin;
 }
 
-// Exclusive scan of n values into out[0..n], out[n] = total, by one block
-// of 1024 threads (each thread owns a contiguous chunk).
-template <typename Tin, typename Tout>
-__global__ void __launch_bounds__(1024) k_scan(const Tin* in, Tout* out, Tout* out2, int64_t n,
-                                               int64_t capacity, int32_t* status)
+// Whole bin build in one work-group (systems with at most kSmallBins bins).
+__global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
 {
-    __shared__ Tout part[1024];
-    int t = threadIdx.x;
-    int64_t chunk = (n + 1023) / 1024;
-    int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
-    Tout s = 0;
-    for (int64_t k = b; k < e; ++k) s += Tout(in[k]);
-    part[t] = s;
+    __shared__ int cnt[kSmallBins + 1];
+    const int t = threadIdx.x;
+    if (!geometry_block(a)) return;
+    const int B = int(a.max_bins);
+    for (int b = t; b <= B; b += 1024) cnt[b] = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        Tout v = t >= off ? part[t - off] : Tout(0);
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    for (int64_t i = t; i < a.n_atoms; i += 1024) atomicAdd(&cnt[assign_atom(a, i)], 1);
+    __syncthreads();
+    block_scan<int, int>(cnt, a.bin_start, (int*)nullptr, B);
+    for (int b = t; b < B; b += 1024) cnt[b] = a.bin_start[b];
+    __syncthreads();
+    for (int64_t i = t; i < a.n_atoms; i += 1024) {
+        int pos = atomicAdd(&cnt[a.atom_bin[i]], 1);
+        a.bin_atoms[pos] = int32_t(i);
     }
-    Tout run = part[t] - s;
-    for (int64_t k = b; k < e; ++k) {
-        out[k] = run;
-        if (out2) out2[k] = run;
-        run += Tout(in[k]);
-    }
-    if (t == 1023) {
-        out[n] = part[1023];
-        if (capacity >= 0 && int64_t(part[1023]) > capacity) put_status(status, SOAP_ECAPACITY);
-    }
+}
+
+__global__ void __launch_bounds__(1024) k_geometry(NeighborArgs a) { geometry_block(a); }
+
+__global__ void k_zero_i32(int32_t* p, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_assign(NeighborArgs a)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n_atoms || !*a.ok) return;
+    atomicAdd(&a.bin_count[assign_atom(a, i)], 1);
+}
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(1024) k_scan(const Tin* in, Tout* out, Tout* out2, int64_t n, int64_t capacity,
+                                               int32_t* status)
+{
+    Tout total = block_scan<Tin, Tout>(in, out, out2, n);
+    if (threadIdx.x == 0 && capacity >= 0 && int64_t(total) > capacity) put_status(status, SOAP_ECAPACITY);
 }
 
 __global__ void k_bins(NeighborArgs a)
@@ -213,71 +250,109 @@ __global__ void k_bins(NeighborArgs a)
     a.bin_atoms[pos] = int32_t(i);
 }
 
-// Visit every (j, s) of centre i with 0 < |r_ji| < rcut.
-template <class F>
-__device__ void visit(const NeighborArgs& a, int64_t i, F&& emit)
+// ------------------------------------------------------- pair enumeration
+struct WaveScratch {
+    int prefix[65];     // exclusive prefix of the stencil-bin sizes of this round
+    int start[64];      // first slot in bin_atoms of each stencil bin
+    int cshift[64];     // cell shift of each stencil bin, 3 x 10 bits
+};
+
+__device__ __forceinline__ int wave_incl_scan(int v)
 {
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// All candidates of centre i, 64 per round: emit(hit, j, s0, s1, s2) is
+// called by every lane in every round (hit false for lanes with nothing).
+template <class F>
+__device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&& emit)
+{
+    const int lane = threadIdx.x & 63;
     const StructGeom& g = a.geom[a.atom_struct[i]];
-    int local = a.atom_bin[i] - int32_t(g.bin_lo);
-    int b2 = local % g.nbin[2];
-    int b1 = (local / g.nbin[2]) % g.nbin[1];
-    int b0 = local / (g.nbin[2] * g.nbin[1]);
-    int ti[3] = {a.atom_wrap[3 * i], a.atom_wrap[3 * i + 1], a.atom_wrap[3 * i + 2]};
-    double ri[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
-    double rc2 = a.rcut * a.rcut;
-    for (int d0 = -g.reach[0]; d0 <= g.reach[0]; ++d0) {
-        int u0 = b0 + d0, n0 = g.nbin[0];
-        int bb0 = u0 - floordiv(u0, n0) * n0, c0 = floordiv(u0, n0);
-        for (int d1 = -g.reach[1]; d1 <= g.reach[1]; ++d1) {
-            int u1 = b1 + d1, n1 = g.nbin[1];
-            int bb1 = u1 - floordiv(u1, n1) * n1, c1 = floordiv(u1, n1);
-            for (int d2 = -g.reach[2]; d2 <= g.reach[2]; ++d2) {
-                int u2 = b2 + d2, n2 = g.nbin[2];
-                int bb2 = u2 - floordiv(u2, n2) * n2, c2 = floordiv(u2, n2);
-                int64_t bin = g.bin_lo + (int64_t(bb0) * n1 + bb1) * n2 + bb2;
-                int q0 = a.bin_start[bin], q1 = a.bin_start[bin + 1];
-                for (int q = q0; q < q1; ++q) {
-                    int j = a.bin_atoms[q];
-                    int s0 = g.pbc[0] ? c0 + ti[0] - a.atom_wrap[3 * j + 0] : 0;
-                    int s1 = g.pbc[1] ? c1 + ti[1] - a.atom_wrap[3 * j + 1] : 0;
-                    int s2 = g.pbc[2] ? c2 + ti[2] - a.atom_wrap[3 * j + 2] : 0;
-                    if (j == i && s0 == 0 && s1 == 0 && s2 == 0) continue;
-                    double v[3];
-                    for (int x = 0; x < 3; ++x)
-                        v[x] = (a.positions[3 * j + x] - ri[x]) + s0 * g.H[0 * 3 + x] + s1 * g.H[1 * 3 + x] +
-                               s2 * g.H[2 * 3 + x];
-                    double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-                    if (r2 >= rc2) continue;
-                    if (r2 == 0.0) { put_status(a.status, SOAP_EGEOMETRY); continue; }
-                    emit(j, s0, s1, s2);
+    const int local = a.atom_bin[i] - int32_t(g.bin_lo);
+    const int bz = local % g.nbin[2];
+    const int by = (local / g.nbin[2]) % g.nbin[1];
+    const int bx = local / (g.nbin[2] * g.nbin[1]);
+    const int ti0 = a.atom_wrap[3 * i], ti1 = a.atom_wrap[3 * i + 1], ti2 = a.atom_wrap[3 * i + 2];
+    const double rx = a.positions[3 * i], ry = a.positions[3 * i + 1], rz = a.positions[3 * i + 2];
+    const double rc2 = a.rcut * a.rcut;
+    const int n0 = 2 * g.reach[0] + 1, n1 = 2 * g.reach[1] + 1, n2 = 2 * g.reach[2] + 1;
+    const int nst = n0 * n1 * n2;
+    for (int base = 0; base < nst; base += 64) {
+        int sb = base + lane;
+        int size = 0, start = 0, cs = 0;
+        if (sb < nst) {
+            int d2 = sb % n2 - g.reach[2], d1 = (sb / n2) % n1 - g.reach[1], d0 = sb / (n1 * n2) - g.reach[0];
+            int u0 = bx + d0, u1 = by + d1, u2 = bz + d2;
+            int c0 = floordiv(u0, g.nbin[0]), c1 = floordiv(u1, g.nbin[1]), c2 = floordiv(u2, g.nbin[2]);
+            int64_t bin = g.bin_lo + (int64_t(u0 - c0 * g.nbin[0]) * g.nbin[1] + (u1 - c1 * g.nbin[1])) * g.nbin[2] +
+                          (u2 - c2 * g.nbin[2]);
+            start = a.bin_start[bin];
+            size = a.bin_start[bin + 1] - start;
+            cs = ((c0 + 512) & 1023) | (((c1 + 512) & 1023) << 10) | (((c2 + 512) & 1023) << 20);
+        }
+        int incl = wave_incl_scan(size);
+        w.prefix[lane] = incl - size;
+        w.start[lane] = start;
+        w.cshift[lane] = cs;
+        const int total = __shfl(incl, 63, 64);
+        wave_fence();
+        const int nb = nst - base < 64 ? nst - base : 64;
+        for (int t0 = 0; t0 < total; t0 += 64) {
+            const int t = t0 + lane;
+            bool hit = false;
+            int j = 0, s0 = 0, s1 = 0, s2 = 0;
+            if (t < total) {
+                // last stencil bin whose prefix is <= t
+                int lo = 0, hi = nb - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (w.prefix[mid] <= t) lo = mid; else hi = mid - 1;
+                }
+                j = a.bin_atoms[w.start[lo] + (t - w.prefix[lo])];
+                int cs2 = w.cshift[lo];
+                int c0 = (cs2 & 1023) - 512, c1 = ((cs2 >> 10) & 1023) - 512, c2 = ((cs2 >> 20) & 1023) - 512;
+                s0 = g.pbc[0] ? c0 + ti0 - a.atom_wrap[3 * j + 0] : 0;
+                s1 = g.pbc[1] ? c1 + ti1 - a.atom_wrap[3 * j + 1] : 0;
+                s2 = g.pbc[2] ? c2 + ti2 - a.atom_wrap[3 * j + 2] : 0;
+                if (!(j == i && s0 == 0 && s1 == 0 && s2 == 0)) {
+                    double vx = (a.positions[3 * j] - rx) + s0 * g.H[0] + s1 * g.H[3] + s2 * g.H[6];
+                    double vy = (a.positions[3 * j + 1] - ry) + s0 * g.H[1] + s1 * g.H[4] + s2 * g.H[7];
+                    double vz = (a.positions[3 * j + 2] - rz) + s0 * g.H[2] + s1 * g.H[5] + s2 * g.H[8];
+                    double r2 = vx * vx + vy * vy + vz * vz;
+                    if (r2 < rc2) {
+                        if (r2 == 0.0) put_status(a.status, SOAP_EGEOMETRY);
+                        else hit = true;
+                    }
                 }
             }
+            emit(hit, j, s0, s1, s2);
         }
+        wave_fence();
     }
 }
 
-__global__ void k_count(NeighborArgs a)
+// one wave (block of 64) per centre
+__global__ void __launch_bounds__(64) k_count(NeighborArgs a)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms) return;
-    int64_t n = 0;
-    if (*a.ok) visit(a, i, [&](int, int, int, int) { ++n; });
-    a.centre_count[i] = n;
-}
-
-__global__ void k_fill(NeighborArgs a)
-{
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms || !*a.ok) return;
-    if (a.pair_offsets[a.n_atoms] > a.capacity) return;
-    int64_t o = a.pair_offsets[i];
-    visit(a, i, [&](int j, int s0, int s1, int s2) {
-        a.pair_j[o] = j;
-        a.pair_shift[3 * o + 0] = s0;
-        a.pair_shift[3 * o + 1] = s1;
-        a.pair_shift[3 * o + 2] = s2;
-        ++o;
-    });
+    __shared__ WaveScratch w;
+    const int64_t i = blockIdx.x;
+    int n = 0;
+    if (*a.ok) wave_visit(a, i, w, [&](bool hit, int, int, int, int) { n += hit ? 1 : 0; });
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+    if (threadIdx.x == 0) a.centre_count[i] = n;
 }
 
 // sort key: (species_j, j) in the high word, the three shifts (offset by
@@ -293,14 +368,14 @@ __device__ __forceinline__ bool key_less(int64_t ah, int64_t al, int64_t bh, int
     return ah < bh || (ah == bh && al < bl);
 }
 
-constexpr int kSortCap = 1024;
-
 template <bool F64>
-__device__ void write_vec(const NeighborArgs& a, int64_t i, int64_t q)
+__device__ __forceinline__ void write_pair(const NeighborArgs& a, const StructGeom& g, int64_t i, int64_t q, int j,
+                                           int s0, int s1, int s2)
 {
-    const StructGeom& g = a.geom[a.atom_struct[i]];
-    int j = a.pair_j[q];
-    int s0 = a.pair_shift[3 * q], s1 = a.pair_shift[3 * q + 1], s2 = a.pair_shift[3 * q + 2];
+    a.pair_j[q] = j;
+    a.pair_shift[3 * q] = s0;
+    a.pair_shift[3 * q + 1] = s1;
+    a.pair_shift[3 * q + 2] = s2;
     for (int x = 0; x < 3; ++x) {
         double v = (a.positions[3 * j + x] - a.positions[3 * i + x]) + s0 * g.H[0 * 3 + x] + s1 * g.H[1 * 3 + x] +
                    s2 * g.H[2 * 3 + x];
@@ -309,40 +384,51 @@ __device__ void write_vec(const NeighborArgs& a, int64_t i, int64_t q)
     }
 }
 
-// One wave per centre.
+// one wave per centre: enumerate again, rank by key in LDS, write sorted
 template <bool F64>
-__global__ void __launch_bounds__(64) k_sort(NeighborArgs a)
+__global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
 {
+    __shared__ WaveScratch w;
     __shared__ int64_t khi[kSortCap], klo[kSortCap];
     __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
-    int64_t i = blockIdx.x;
-    if (a.pair_offsets[a.n_atoms] > a.capacity) return;
-    int64_t o0 = a.pair_offsets[i], o1 = a.pair_offsets[i + 1];
-    int n = int(o1 - o0);
-    int t = threadIdx.x;
-    if (n <= kSortCap) {
-        for (int p = t; p < n; p += 64) {
-            int64_t q = o0 + p;
-            int j = a.pair_j[q];
-            int s0 = a.pair_shift[3 * q], s1 = a.pair_shift[3 * q + 1], s2 = a.pair_shift[3 * q + 2];
-            make_key(a.species[j], j, s0, s1, s2, khi[p], klo[p]);
-            kj[p] = j;
-            ks[3 * p] = s0; ks[3 * p + 1] = s1; ks[3 * p + 2] = s2;
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (!*a.ok || a.pair_offsets[a.n_atoms] > a.capacity) return;
+    const int64_t o0 = a.pair_offsets[i];
+    const int n = int(a.pair_offsets[i + 1] - o0);
+    const bool in_lds = n <= kSortCap;
+    int count = 0;
+    wave_visit(a, i, w, [&](bool hit, int j, int s0, int s1, int s2) {
+        uint64_t mask = __ballot(hit);
+        int idx = count + __popcll(mask & ((uint64_t(1) << lane) - 1));
+        if (hit && idx < n) {
+            if (in_lds) {
+                make_key(a.species[j], j, s0, s1, s2, khi[idx], klo[idx]);
+                kj[idx] = j;
+                ks[3 * idx] = s0; ks[3 * idx + 1] = s1; ks[3 * idx + 2] = s2;
+            } else {
+                a.pair_j[o0 + idx] = j;
+                a.pair_shift[3 * (o0 + idx)] = s0;
+                a.pair_shift[3 * (o0 + idx) + 1] = s1;
+                a.pair_shift[3 * (o0 + idx) + 2] = s2;
+            }
         }
-        __syncthreads();
-        for (int p = t; p < n; p += 64) {
-            int rank = 0;
+        count += __popcll(mask);
+    });
+    __syncthreads();
+    const StructGeom& g = a.geom[a.atom_struct[i]];
+    if (in_lds) {
+        for (int p = lane; p < n; p += 64) {
             int64_t h = khi[p], l = klo[p];
+            int rank = 0;
             for (int q = 0; q < n; ++q) rank += key_less(khi[q], klo[q], h, l) ? 1 : 0;
-            int64_t dst = o0 + rank;
-            a.pair_j[dst] = kj[p];
-            a.pair_shift[3 * dst] = ks[3 * p];
-            a.pair_shift[3 * dst + 1] = ks[3 * p + 1];
-            a.pair_shift[3 * dst + 2] = ks[3 * p + 2];
+            write_pair<F64>(a, g, i, o0 + rank, kj[p], ks[3 * p], ks[3 * p + 1], ks[3 * p + 2]);
         }
-    } else if (t == 0) {
-        // long environments: insertion sort in place in global memory
-        for (int64_t p = o0 + 1; p < o1; ++p) {
+        return;
+    }
+    // long environments: insertion sort in place in global memory
+    if (lane == 0) {
+        for (int64_t p = o0 + 1; p < o0 + n; ++p) {
             int j = a.pair_j[p];
             int s0 = a.pair_shift[3 * p], s1 = a.pair_shift[3 * p + 1], s2 = a.pair_shift[3 * p + 2];
             int64_t h, l;
@@ -362,7 +448,10 @@ __global__ void __launch_bounds__(64) k_sort(NeighborArgs a)
         }
     }
     __syncthreads();
-    for (int p = t; p < n; p += 64) write_vec<F64>(a, i, o0 + p);
+    for (int p = lane; p < n; p += 64) {
+        int64_t q = o0 + p;
+        write_pair<F64>(a, g, i, q, a.pair_j[q], a.pair_shift[3 * q], a.pair_shift[3 * q + 1], a.pair_shift[3 * q + 2]);
+    }
 }
 
 __global__ void k_transpose(NeighborArgs a)
@@ -406,28 +495,31 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
 {
     const int T = 256;
-    int64_t N = a.n_atoms;
-    hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
+    const int64_t N = a.n_atoms, B = a.max_bins;
     if (N == 0) {
+        hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream,
                            a.centre_count, a.pair_offsets, (int64_t*)nullptr, int64_t(0), a.capacity, a.status);
         return hipGetLastError();
     }
-    int64_t B = a.max_bins;
-    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(B + 1, T)), dim3(T), 0, stream, a.bin_count, B + 1);
-    hipLaunchKernelGGL(k_assign, dim3(blocks(N, T)), dim3(T), 0, stream, a);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int32_t, int32_t>), dim3(1), dim3(1024), 0, stream, a.bin_count,
-                       a.bin_start, a.bin_cursor, B, int64_t(-1), a.status);
-    hipLaunchKernelGGL(k_bins, dim3(blocks(N, T)), dim3(T), 0, stream, a);
-    hipLaunchKernelGGL(k_count, dim3(blocks(N, T)), dim3(T), 0, stream, a);
+    if (B <= kSmallBins) {
+        hipLaunchKernelGGL(k_bins_small, dim3(1), dim3(1024), 0, stream, a);
+    } else {
+        hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
+        hipLaunchKernelGGL(k_zero_i32, dim3(blocks(B + 1, T)), dim3(T), 0, stream, a.bin_count, B + 1);
+        hipLaunchKernelGGL(k_assign, dim3(blocks(N, T)), dim3(T), 0, stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int32_t, int32_t>), dim3(1), dim3(1024), 0, stream, a.bin_count,
+                           a.bin_start, a.bin_cursor, B, int64_t(-1), a.status);
+        hipLaunchKernelGGL(k_bins, dim3(blocks(N, T)), dim3(T), 0, stream, a);
+    }
+    hipLaunchKernelGGL(k_count, dim3(unsigned(N)), dim3(64), 0, stream, a);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream, a.centre_count,
                        a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.status);
     if (a.capacity > 0) {
-        hipLaunchKernelGGL(k_fill, dim3(blocks(N, T)), dim3(T), 0, stream, a);
         if (a.vec_f64)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_sort<true>), dim3(unsigned(N)), dim3(64), 0, stream, a);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<true>), dim3(unsigned(N)), dim3(64), 0, stream, a);
         else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_sort<false>), dim3(unsigned(N)), dim3(64), 0, stream, a);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<false>), dim3(unsigned(N)), dim3(64), 0, stream, a);
         if (a.pair_transpose)
             hipLaunchKernelGGL(k_transpose, dim3(blocks(a.capacity, T)), dim3(T), 0, stream, a);
     }

@@ -18,7 +18,7 @@ struct DeviceTables {
     bool ready = false;
     double* coef64 = nullptr;    // [M][nmax][lmax+1][4] local-t cubic coefficients
     float* coef32 = nullptr;
-    double* center64 = nullptr;  // [nmax]  I~_n0(0) * Y_00
+    double* center64 = nullptr;  // [nmax] I~_n0(0) Y_00, then [L2] harmonic normalisations K_lm
     float* center32 = nullptr;
 };
 
@@ -46,7 +46,7 @@ struct soap_calculator {
     double delta = 0.0, inv_delta = 0.0;
     std::vector<double> coef64;       // host copy of the FP64 table
     std::vector<float> coef32;
-    std::vector<double> center;       // [nmax]
+    std::vector<double> center;       // [nmax] centre terms, then [L2] K_lm
     std::vector<double> orth;         // S^{-1/2}, [nmax][nmax]
     soap_table_info info{};
     mutable std::mutex mu;
@@ -78,7 +78,7 @@ struct FeatureArgs {
     const void* pair_vec;
     int64_t pair_capacity;
     const void* coef;       // table of the working precision
-    const void* center;     // [nmax]
+    const void* center;     // [nmax] centre terms, then [L2] harmonic normalisations
     void* coeffs;
     void* p;
     void* dcoeffs;
@@ -89,6 +89,7 @@ struct FeatureArgs {
 };
 
 hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream);
+hipError_t launch_gradient_rows(const FeatureArgs& a, bool f64, hipStream_t stream);
 hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipStream_t stream);
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream);
 hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const void* grad_p,

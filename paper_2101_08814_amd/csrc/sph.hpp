@@ -50,15 +50,6 @@ __host__ __device__ __forceinline__ int l_of(int lm)
     return l;
 }
 
-// K_lm = sqrt((2 - delta_m0) (2l+1) / 4pi (l-m)! / (l+m)!)
-template <typename T>
-__device__ __forceinline__ T ylm_norm(int l, int am)
-{
-    double ratio = 1.0;
-    for (int k = l - am + 1; k <= l + am; ++k) ratio /= double(k);
-    return T(sqrt((am == 0 ? 1.0 : 2.0) * (2 * l + 1) / (4.0 * kPi) * ratio));
-}
-
 // Column m of the Qt table (l = m..lmax) at the unit vector with z
 // component z, and T_m = (x + i y)^m, written into the per-pair arrays.
 template <typename T>
@@ -89,15 +80,14 @@ __device__ __forceinline__ void q_column(int m, int lmax, T x, T y, T z, T* qt, 
 }
 
 // Y_lm and d Y_lm / d r_ji (3 components) of one pair, from its Qt table and
-// (x+iy)^m values; u is the unit vector, rinv = 1/r.
+// (x+iy)^m values; l is the degree of lm, K its normalisation, u the unit
+// vector and rinv = 1/r.
 template <typename T>
-__device__ __forceinline__ void ylm_and_grad(int lm, const T* qt, const T* cre, const T* cim, T ux, T uy, T uz,
-                                             T rinv, T& Y, T& gx, T& gy, T& gz)
+__device__ __forceinline__ void ylm_and_grad(int lm, int l, T K, const T* qt, const T* cre, const T* cim, T ux, T uy,
+                                             T uz, T rinv, T& Y, T& gx, T& gy, T& gz)
 {
-    int l = l_of(lm);
     int m = lm - l * l - l;
     int am = m < 0 ? -m : m;
-    T K = ylm_norm<T>(l, am);
     T Q = qt[qidx(l, am)];
     T Qa = (l >= 1 && am <= l - 1) ? qt[qidx(l - 1, am)] : T(0);          // Qt_{l-1}^m
     T Qb = (l >= 1 && am + 1 <= l - 1) ? qt[qidx(l - 1, am + 1)] : T(0);  // Qt_{l-1}^{m+1}

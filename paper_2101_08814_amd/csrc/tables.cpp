@@ -340,8 +340,16 @@ soap_status build_tables(soap_calculator* calc)
     RadialExact ex(h, calc->orth);
     std::vector<double> I0(nl), dI0(nl);
     ex.orth(0.0, I0.data(), dI0.data());
-    calc->center.resize(nmax);
+    // device constants: [nmax] centre terms I~_n0(0) Y_00, then [(lmax+1)^2]
+    // harmonic normalisations K_lm = sqrt((2 - delta_m0)(2l+1)/4pi (l-|m|)!/(l+|m|)!)
+    calc->center.resize(nmax + (lmax + 1) * (lmax + 1));
     for (int n = 0; n < nmax; ++n) calc->center[n] = I0[n * (lmax + 1)] / std::sqrt(4.0 * kPi);
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double lr = std::lgamma(l - am + 1.0) - std::lgamma(l + am + 1.0);
+            calc->center[nmax + l * l + l + m] = std::sqrt((am == 0 ? 1.0 : 2.0) * (2 * l + 1) / (4.0 * kPi) * std::exp(lr));
+        }
 
     double acc = h.spline_accuracy;
     for (int64_t M = 1024; M <= (int64_t(1) << 16); M *= 2) {

@@ -226,8 +226,10 @@ class Calculator:
                                           _ptr(dc), _ptr(dcs), _ptr(dp), _ptr(dps)))
         return (p, dp, dps) if rows is not None else p
 
-    def features(self, nl: Neighbors, species: torch.Tensor, dtype=torch.float32, gradients=False, out=None):
-        """soap_features: c and p (and all four gradient row arrays) in one launch."""
+    def features(self, nl: Neighbors, species: torch.Tensor, dtype=torch.float32, gradients=False, out=None,
+                 rows: bool = True):
+        """soap_features: c and p, with gradients also the self rows and (if
+        rows) the pair rows.  out = (c, p[, dc, dcs, dp, dps]) reuses buffers."""
         prec = _precision(dtype)
         td = _torch_dtype(prec)
         N = nl.pair_offsets.shape[0] - 1
@@ -236,12 +238,32 @@ class Calculator:
             out = self.allocate_features(N, nl.capacity, td, dev, gradients)
         c, p = out[0], out[1]
         dc, dcs, dp, dps = (out[2:] if gradients else (None,) * 4)
+        if not rows:
+            dc = dp = None
         vec = _vec_as(nl, td)
         e = self._exec()
         check(self._L.soap_features(self.handle, ctypes.byref(e), prec, N, _ptr(species), _ptr(nl.pair_offsets),
                                     _ptr(nl.pair_j), _ptr(vec), nl.capacity, _ptr(c), _ptr(p), _ptr(dc),
                                     _ptr(dcs), _ptr(dp), _ptr(dps)))
         return out
+
+    def gradient_rows(self, nl: Neighbors, species: torch.Tensor, coeffs: torch.Tensor, dc=None, dp=None,
+                      want_dc=True, want_dp=True):
+        """soap_gradient_rows: the pair rows d c / d r_ji and d p / d r_ji."""
+        prec = _precision(coeffs.dtype)
+        td = coeffs.dtype
+        N = nl.pair_offsets.shape[0] - 1
+        dev = coeffs.device
+        if want_dc and dc is None:
+            dc = torch.empty((max(nl.capacity, 1), 3, self.nmax, self.L2), dtype=td, device=dev)
+        if want_dp and dp is None:
+            dp = torch.empty((max(nl.capacity, 1), 3, self.lmax + 1, self.KK), dtype=td, device=dev)
+        vec = _vec_as(nl, td)
+        e = self._exec()
+        check(self._L.soap_gradient_rows(self.handle, ctypes.byref(e), prec, N, _ptr(species), _ptr(nl.pair_offsets),
+                                         _ptr(nl.pair_j), _ptr(vec), nl.capacity, _ptr(coeffs),
+                                         _ptr(dc) if want_dc else None, _ptr(dp) if want_dp else None))
+        return dc, dp
 
     def allocate_features(self, N, capacity, td, dev, gradients):
         c = torch.empty((N, self.S, self.nmax, self.L2), dtype=td, device=dev)

@@ -189,6 +189,30 @@ def test_separate_entry_points_match_fused():
             assert rel(a.double().cpu().numpy(), f.double().cpu().numpy()) <= (1e-12 if dt == torch.float64 else 1e-6)
 
 
+def test_gradient_rows_entry_point():
+    """soap_gradient_rows (dc and dp rows from c) gives the rows of
+    soap_features, together or one at a time."""
+    hyp = dict(n_species=2, nmax=6, lmax=5, rcut=4.5, sigma=0.45, cutoff_width=0.5, include_center=1)
+    b = synthetic.random_cell_structure(31, 48, np.array([[10.0, 0, 0], [0.8, 9.5, 0], [0.3, -0.6, 10.5]]), 2,
+                                        min_sep=1.3, hypers=hyp)
+    calc = P.Calculator.from_hypers(hyp)
+    nl, pos, spc = gpu_neighbors(calc, b, torch.float32)
+    c, p, dc, dcs, dp, dps = calc.features(nl, spc, torch.float32, gradients=True)
+    c2, p2, _, dcs2, _, dps2 = calc.features(nl, spc, torch.float32, gradients=True, rows=False)
+    r_dc, r_dp = calc.gradient_rows(nl, spc, c2)
+    o_dc, _ = calc.gradient_rows(nl, spc, c2, want_dp=False)
+    _, o_dp = calc.gradient_rows(nl, spc, c2, want_dc=False)
+    assert calc.device_status() == 0
+    Pn = nl.count()
+    for x, y in [(c, c2), (p, p2), (dcs, dcs2), (dps, dps2), (dc[:Pn], r_dc[:Pn]), (dp[:Pn], r_dp[:Pn]),
+                 (dc[:Pn], o_dc[:Pn]), (dp[:Pn], o_dp[:Pn])]:
+        assert torch.equal(x, y)
+    ref_nl = oracle.neighbors(b)
+    rdc, rdcs, rdp, rdps = oracle.gradients(hyp, b.species, ref_nl)
+    assert rel(r_dc[:Pn].double().cpu().numpy(), rdc) <= 1e-5
+    assert rel(r_dp[:Pn].double().cpu().numpy(), rdp) <= 1e-5
+
+
 def test_molecules_bf16_mfma_power_spectrum():
     """256 molecules of 20-200 atoms, 4 species, one launch: p from the
     bfloat16 hi/lo MFMA contraction against the FP64 oracle (bound 2e-3)."""
