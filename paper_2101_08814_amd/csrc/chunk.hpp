@@ -85,10 +85,12 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     L.dR = o; o += grad ? ch * d.nl : 0;
     L.Y = o; o += ch * d.L2;
     L.dY = o; o += grad ? 3 * ch * d.L2 : 0;
-    // the Legendre table is dead once the harmonics are staged; the y/z
-    // contractions of the gradient rows reuse its space
+    // the Legendre table is dead once the harmonics are staged; the
+    // per-(pair, l, k) operands of the gradient rows ({y, z_x, z_y, z_z} and
+    // {A, B}, 6 values) reuse its space, 4-element aligned for vector loads
+    o = (o + 3) & ~3;
     int scratch = ch * (d.nq + 2 * d.lm1);
-    int yz = (grad && rows_p) ? L.sub * 4 * d.lm1 * d.K : 0;
+    int yz = (grad && rows_p) ? L.sub * 6 * d.lm1 * d.K : 0;
     L.qt = o;
     L.cre = o + ch * d.nq;
     L.cim = L.cre + ch * d.lm1;
@@ -117,6 +119,16 @@ inline Layout choose_layout(const Dims& d, bool grad, bool rows_p, bool self_row
     if (size_t(L.total) * sizeof(T) > 160 * 1024) L.total = 0;
     return L;
 }
+
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+    T x, y, z, w;
+};
+
+template <typename T>
+struct alignas(2 * sizeof(T)) V2 {
+    T x, y;
+};
 
 template <typename T>
 struct Smem {

@@ -185,9 +185,13 @@ __global__ void __launch_bounds__(kThreads) k_rows(FeatureArgs a, Layout L)
     const int share = (n_pairs + G - 1) / G;
     const int p_lo = g * share, p_hi = (g + 1) * share < n_pairs ? (g + 1) * share : n_pairs;
     if (p_lo >= p_hi) return;
-    init_tables<T>(a, d, L, s);
     const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
     const int KK = d.KK, PL = lm1 * KK;
+    if (WANT_DP && L.tri + PL > L.total) {   // the launcher reserves the position table
+        if (tid == 0) put_status(a.status, SOAP_EUNSUPPORTED);
+        return;
+    }
+    init_tables<T>(a, d, L, s);
     if (WANT_DP) {
         const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
         for (int e = tid; e < KL2; e += kThreads) s.c[e] = c_in[e];
@@ -216,12 +220,16 @@ __global__ void __launch_bounds__(kThreads) k_rows(FeatureArgs a, Layout L)
                 const T beta = s.dY[(p * 3 + x) * d.L2 + lm];
                 const T* dRp = s.dR + p * d.nl + l;
                 const T* Rp = s.R + p * d.nl + l;
-                T* out = dc_base + int64_t(p) * EDC + x * nL2 + lm;
+                T* out = dc_base + (uint32_t(p * EDC) + uint32_t(x * nL2 + lm));
+#pragma unroll 4
                 for (int n = 0; n < d.nmax; ++n) out[n * d.L2] = dRp[n * lm1] * alpha + Rp[n * lm1] * beta;
             }
         }
         if (WANT_DP) {
-            // y_{l,k} = sum_m Y_lm c_{k,lm},  z_{x,l,k} = sum_m dY_{x,lm} c_{k,lm}
+            // per pair and (l, k): {y, z_x, z_y, z_z}_{l,k} with
+            //   y = sum_m Y_lm c_{k,lm},  z_x = sum_m dY_{x,lm} c_{k,lm},
+            // and {A, B}_{l,k} = {(f I~)', f I~}_{n l} for k = a_j nmax + n,
+            // zero outside the neighbour's species block
             for (int t = tid; t < nc * yzn; t += kThreads) {
                 int p = t / yzn, rem = t - p * yzn, l = rem / d.K, k = rem - l * d.K;
                 const T* ck_ = s.c + k * d.L2 + l * l;
@@ -237,33 +245,29 @@ __global__ void __launch_bounds__(kThreads) k_rows(FeatureArgs a, Layout L)
                     z1 += Dy[m] * cv;
                     z2 += Dz[m] * cv;
                 }
-                T* out = s.yz + p * 4 * yzn + l * d.K + k;
-                out[0] = y;
-                out[yzn] = z0;
-                out[2 * yzn] = z1;
-                out[3 * yzn] = z2;
+                reinterpret_cast<V4<T>*>(s.yz)[t] = V4<T>{y, z0, z1, z2};
+                const int n = k - s.spc[p] * d.nmax;
+                const bool in = n >= 0 && n < d.nmax;
+                reinterpret_cast<V2<T>*>(s.yz + 4 * nc * yzn)[t] =
+                    V2<T>{in ? s.dR[p * d.nl + n * lm1 + l] : T(0), in ? s.R[p * d.nl + n * lm1 + l] : T(0)};
             }
             __syncthreads();
             T* dp_base = static_cast<T*>(a.dp) + q0 * int64_t(3 * PL);
             for (int p = 0; p < nc; ++p) {
-                const int blk = s.spc[p] * d.nmax;
                 const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
-                const T* Rp = s.R + p * d.nl;
-                const T* dRp = s.dR + p * d.nl;
-                const T* ybase = s.yz + p * 4 * yzn;
-                T* row = dp_base + int64_t(p) * (3 * PL);
+                const V4<T>* yzp = reinterpret_cast<const V4<T>*>(s.yz) + p * yzn;
+                const V2<T>* abp = reinterpret_cast<const V2<T>*>(s.yz + 4 * nc * yzn) + p * yzn;
+                T* row = dp_base + uint32_t(p * 3 * PL);
                 for (int o = tid; o < PL; o += kThreads) {
                     const int v = s.tri[o];
                     const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
-                    const int n1 = k1 - blk, n2 = k2 - blk;
-                    const bool in1 = n1 >= 0 && n1 < d.nmax, in2 = n2 >= 0 && n2 < d.nmax;
-                    const T* yb = ybase + l * d.K;
-                    const T A1 = in1 ? dRp[n1 * lm1 + l] : T(0), B1 = in1 ? Rp[n1 * lm1 + l] : T(0);
-                    const T A2 = in2 ? dRp[n2 * lm1 + l] : T(0), B2 = in2 ? Rp[n2 * lm1 + l] : T(0);
-                    const T a0 = A1 * yb[k2] + A2 * yb[k1];
-                    row[o] = ux * a0 + B1 * yb[yzn + k2] + B2 * yb[yzn + k1];
-                    row[PL + o] = uy * a0 + B1 * yb[2 * yzn + k2] + B2 * yb[2 * yzn + k1];
-                    row[2 * PL + o] = uz * a0 + B1 * yb[3 * yzn + k2] + B2 * yb[3 * yzn + k1];
+                    const int i1 = l * d.K + k1, i2 = l * d.K + k2;
+                    const V4<T> q1 = yzp[i1], q2 = yzp[i2];
+                    const V2<T> ab1 = abp[i1], ab2 = abp[i2];
+                    const T a0 = ab1.x * q2.x + ab2.x * q1.x;
+                    row[o] = ux * a0 + ab1.y * q2.y + ab2.y * q1.y;
+                    row[PL + o] = uy * a0 + ab1.y * q2.z + ab2.y * q1.z;
+                    row[2 * PL + o] = uz * a0 + ab1.y * q2.w + ab2.y * q1.w;
                 }
             }
         }
@@ -435,7 +439,9 @@ hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, hip
 template <typename T, template <typename, int> class Fn, typename... Args>
 hipError_t by_lmax(int lmax, Args&&... args)
 {
-    if (!std::is_same<T, float>::value) return Fn<T, -1>::run(args...);
+    if constexpr (!std::is_same<T, float>::value) {
+        return Fn<T, -1>::run(args...);
+    } else {
     switch (lmax) {
     case 0: return Fn<T, 0>::run(args...);
     case 1: return Fn<T, 1>::run(args...);
@@ -451,6 +457,7 @@ hipError_t by_lmax(int lmax, Args&&... args)
     case 11: return Fn<T, 11>::run(args...);
     case 12: return Fn<T, 12>::run(args...);
     default: return Fn<T, -1>::run(args...);
+    }
     }
 }
 
@@ -480,9 +487,11 @@ hipError_t rows_t(const FeatureArgs& a, hipStream_t stream)
     if (a.pair_capacity == 0 || a.n_atoms == 0 || (!want_dc && !want_dp)) return hipSuccess;
     Layout R = make_layout(d, kRowChunk, true, want_dp, false, false);
     R.sub = kRowChunk;
-    // the dp-row position table replaces the triangle table
-    R.tri = R.total;
-    R.total += want_dp ? (d.lmax + 1) * d.KK : 0;
+    if (want_dp) {
+        // table of the (l, k1, k2) of every position of a dp row
+        R.tri = R.total;
+        R.total += (d.lmax + 1) * d.KK;
+    }
     size_t lds = size_t(R.total) * sizeof(T);
     if (lds > kMaxLds || (want_dp && d.K > 1023)) return hipErrorInvalidValue;
     // row groups of about kRowChunk pairs at the mean neighbour count
