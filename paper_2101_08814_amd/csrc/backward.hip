@@ -142,7 +142,7 @@ hipError_t ps_backward_t(const FeatureArgs& a, const void* grad_p, void* grad_c,
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
     size_t lds = (size_t(d.K) * d.L2 + size_t(d.KK)) * sizeof(T);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 160 * 1024) return hipErrorNotSupported;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ps_backward<T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -159,7 +159,7 @@ hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const 
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
     Layout L = choose_layout<T>(d, true, false, false, false);
-    if (L.total == 0) return hipErrorInvalidValue;
+    if (L.total == 0) return hipErrorNotSupported;
     size_t lds = size_t(L.total) * sizeof(T);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_exp_backward_pairs<T>),

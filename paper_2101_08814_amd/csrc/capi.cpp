@@ -47,6 +47,19 @@ soap_status device_tables(const soap_calculator* calc, const DeviceTables** out)
             hipMemcpy(t.center64, calc->center.data(), c64, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(t.center32, cf.data(), c32, hipMemcpyHostToDevice) != hipSuccess)
             return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
+        // (l, k1, k2) of every position of a packed dp row, for the row kernels
+        const int K = calc->K, lm1 = calc->h.lmax + 1;
+        if (K <= 1023 && int64_t(lm1) * calc->KK <= (int64_t(1) << 22)) {
+            std::vector<int32_t> pos;
+            pos.reserve(size_t(lm1) * calc->KK);
+            for (int l = 0; l < lm1; ++l)
+                for (int k1 = 0; k1 < K; ++k1)
+                    for (int k2 = k1; k2 < K; ++k2) pos.push_back(l | (k1 << 4) | (k2 << 14));
+            if (hipMalloc(&t.dp_pos, pos.size() * sizeof(int32_t)) != hipSuccess)
+                return fail(SOAP_ENOMEM, "allocation of the spline tables failed on device %d", dev);
+            if (hipMemcpy(t.dp_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+                return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
+        }
         t.ready = true;
     }
     *out = &t;
@@ -86,6 +99,8 @@ size_t elem_size(soap_precision p) { return p == SOAP_F64 ? 8 : 4; }
 
 soap_status launched(hipError_t e, const char* what)
 {
+    if (e == hipErrorNotSupported)
+        return fail(SOAP_EUNSUPPORTED, "%s: these sizes exceed what the kernels support (LDS per work-group or index packing)", what);
     if (e != hipSuccess) return fail(SOAP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     hipError_t last = hipGetLastError();
     if (last != hipSuccess) return fail(SOAP_EDEVICE, "%s: %s", what, hipGetErrorString(last));
@@ -111,12 +126,14 @@ FeatureArgs base_args(const soap_calculator* calc, const soap_exec* exec, bool f
     a.inv_delta = calc->inv_delta;
     a.coef = f64 ? static_cast<const void*>(t->coef64) : static_cast<const void*>(t->coef32);
     a.center = f64 ? static_cast<const void*>(t->center64) : static_cast<const void*>(t->center32);
+    a.dp_pos = t->dp_pos;
     a.status = status_of(exec);
     return a;
 }
 
 struct NbLayout {
-    size_t geom, ok, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, centre_count, total;
+    size_t geom, ok, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, slots, centre_count,
+        total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -138,6 +155,7 @@ NbLayout nb_layout(int32_t n_struct, int64_t N)
     L.bin_start = o; o = up256(o + 4 * size_t(B + 1));
     L.bin_cursor = o; o = up256(o + 4 * size_t(B + 1));
     L.bin_atoms = o; o = up256(o + 4 * size_t(N));
+    L.slots = o; o = up256(o + 32 * size_t(N));
     L.centre_count = o; o = up256(o + 8 * size_t(N + 1));
     L.total = o;
     return L;
@@ -196,6 +214,7 @@ soap_status soap_calculator_destroy(soap_calculator* calc)
         (void)hipFree(t.coef32);
         (void)hipFree(t.center64);
         (void)hipFree(t.center32);
+        (void)hipFree(t.dp_pos);
     }
     if (have) (void)hipSetDevice(cur);
     delete calc;
@@ -306,6 +325,7 @@ soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec*
     a.bin_start = reinterpret_cast<int32_t*>(ws + L.bin_start);
     a.bin_cursor = reinterpret_cast<int32_t*>(ws + L.bin_cursor);
     a.bin_atoms = reinterpret_cast<int32_t*>(ws + L.bin_atoms);
+    a.slots = reinterpret_cast<double4*>(ws + L.slots);
     a.centre_count = reinterpret_cast<int64_t*>(ws + L.centre_count);
     a.capacity = capacity;
     a.pair_offsets = pair_offsets;

@@ -17,6 +17,8 @@
 // an index.
 #pragma once
 
+#include <type_traits>
+
 #include "soap_internal.hpp"
 #include "sph.hpp"
 
@@ -26,6 +28,10 @@ namespace dev {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kTriMax = 8192;    // largest K (K+1)/2 kept as an LDS table
+
+// Kernels are instantiated with the degree lmax as a template parameter LM
+// (0..12) for float; LM = -1 takes lmax at run time.
+__device__ __forceinline__ int lmax_of(const FeatureArgs& a, int LM) { return LM >= 0 ? LM : a.lmax; }
 
 __device__ __forceinline__ void put_status(int32_t* st, int v)
 {
@@ -244,6 +250,34 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
         }
     }
     __syncthreads();
+}
+
+// Dispatch on lmax: float kernels are specialised on it (LM = 0..12, so
+// index decoding and strides fold to constants), everything else takes
+// LM = -1 (lmax at run time).
+template <typename T, template <typename, int> class Fn, typename... Args>
+hipError_t by_lmax(int lmax, Args&&... args)
+{
+    if constexpr (!std::is_same<T, float>::value) {
+        return Fn<T, -1>::run(args...);
+    } else {
+    switch (lmax) {
+    case 0: return Fn<T, 0>::run(args...);
+    case 1: return Fn<T, 1>::run(args...);
+    case 2: return Fn<T, 2>::run(args...);
+    case 3: return Fn<T, 3>::run(args...);
+    case 4: return Fn<T, 4>::run(args...);
+    case 5: return Fn<T, 5>::run(args...);
+    case 6: return Fn<T, 6>::run(args...);
+    case 7: return Fn<T, 7>::run(args...);
+    case 8: return Fn<T, 8>::run(args...);
+    case 9: return Fn<T, 9>::run(args...);
+    case 10: return Fn<T, 10>::run(args...);
+    case 11: return Fn<T, 11>::run(args...);
+    case 12: return Fn<T, 12>::run(args...);
+    default: return Fn<T, -1>::run(args...);
+    }
+    }
 }
 
 }  // namespace dev

@@ -17,13 +17,8 @@
 // (App. B: d r_ji / d r_i = -1).  After the last chunk c, p and the self
 // rows are written with consecutive lanes on consecutive addresses.
 //
-// Gradient rows (Sec. 4.G) then take one wave per pair.  The product rule
-//   dp_{x,l,k1 k2} = sum_m dc_{x,k1,lm} c_{k2,lm} + c_{k1,lm} dc_{x,k2,lm}
-// is summed in the reordered form
-//   sum_m dc_{x,(a_j,n),lm} c_{k,lm} = (f I~)'_nl u_x y_{l,k} + f I~_nl z_{x,l,k},
-//   y_{l,k} = sum_m Y_lm c_{k,lm},  z_{x,l,k} = sum_m dY_{x,lm} c_{k,lm},
-// so a row costs O(K L2) instead of O(K^2 L2) and the dc row is written to
-// memory but never read back.
+// The pair rows d c / d r_ji and d p / d r_ji are written by a second
+// kernel (gradient_rows.hip) once c of every centre is in memory.
 #include <type_traits>
 
 #include "chunk.hpp"
@@ -32,11 +27,6 @@ namespace soap {
 namespace {
 
 using namespace dev;
-
-// Kernels are instantiated with the degree lmax as a template parameter LM
-// (0..12) for float, so index decoding and strides fold to constants; LM = -1
-// takes lmax at run time (the double path and anything else).
-__device__ __forceinline__ int lmax_of(const FeatureArgs& a, int LM) { return LM >= 0 ? LM : a.lmax; }
 
 // ---------------------------------------------------------------------------
 // Per-centre pass: c, p and (with gradients) the self rows of c and p.
@@ -157,120 +147,6 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
         }
         kk += kThreads;
         while (kk >= KK) { kk -= KK; ++l; }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Gradient rows of every pair: grid (centres, groups); group g of centre i
-// takes a contiguous share of its pairs, restages them and streams out
-//   dc_{x,n,lm} = (f I~)'_nl u_x Y_lm + f I~_nl dY_{x,lm}
-// (one thread per (pair, x, lm) writes the nmax values of that (x, lm)) and,
-// with WANT_DP, the dp row in the reordered product-rule form (one thread
-// per packed position (l, k1, k2) of a pair writes its three components).
-// c of the centre (written by k_centres) is read back into LDS for dp.
-// ---------------------------------------------------------------------------
-template <typename T, int LM, bool WANT_DC, bool WANT_DP>
-__global__ void __launch_bounds__(kThreads) k_rows(FeatureArgs a, Layout L)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* base = reinterpret_cast<T*>(smem_raw);
-    Smem<T> s(base, L);
-    const Dims d = make_dims(a.S, a.nmax, lmax_of(a, LM));
-    const int tid = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    if (a.pair_offsets[a.n_atoms] > a.pair_capacity) return;
-    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
-    const int n_pairs = int(q_end - q_begin);
-    const int G = gridDim.y, g = blockIdx.y;
-    const int share = (n_pairs + G - 1) / G;
-    const int p_lo = g * share, p_hi = (g + 1) * share < n_pairs ? (g + 1) * share : n_pairs;
-    if (p_lo >= p_hi) return;
-    const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
-    const int KK = d.KK, PL = lm1 * KK;
-    if (WANT_DP && L.tri + PL > L.total) {   // the launcher reserves the position table
-        if (tid == 0) put_status(a.status, SOAP_EUNSUPPORTED);
-        return;
-    }
-    init_tables<T>(a, d, L, s);
-    if (WANT_DP) {
-        const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
-        for (int e = tid; e < KL2; e += kThreads) s.c[e] = c_in[e];
-        // packed positions of a dp row: l | k1 << 4 | k2 << 14
-        for (int o = tid; o < PL; o += kThreads) {
-            int l = o / KK, kk = o - l * KK, k1, k2;
-            tri_decode(d.K, kk, k1, k2);
-            s.tri[o] = l | (k1 << 4) | (k2 << 14);
-        }
-    }
-    const int EDC = 3 * nL2;
-    const int yzn = lm1 * d.K;
-    for (int c0 = p_lo; c0 < p_hi; c0 += L.chunk) {
-        const int nc = p_hi - c0 < L.chunk ? p_hi - c0 : L.chunk;
-        const int64_t q0 = q_begin + c0;
-        if (c0 != p_lo) __syncthreads();
-        stage_chunk<T, true>(a, d, s, q0, nc);
-        if (WANT_DC) {
-            T* dc_base = static_cast<T*>(a.dcoeffs) + q0 * EDC;
-            const int per_pair = 3 * d.L2;
-            for (int t = tid; t < nc * per_pair; t += kThreads) {
-                const int p = t / per_pair, rem = t - p * per_pair, x = rem / d.L2, lm = rem - x * d.L2;
-                const int l = s.lof[lm];
-                const T u = x == 0 ? s.ux[p] : (x == 1 ? s.uy[p] : s.uz[p]);
-                const T alpha = u * s.Y[p * d.L2 + lm];
-                const T beta = s.dY[(p * 3 + x) * d.L2 + lm];
-                const T* dRp = s.dR + p * d.nl + l;
-                const T* Rp = s.R + p * d.nl + l;
-                T* out = dc_base + (uint32_t(p * EDC) + uint32_t(x * nL2 + lm));
-#pragma unroll 4
-                for (int n = 0; n < d.nmax; ++n) out[n * d.L2] = dRp[n * lm1] * alpha + Rp[n * lm1] * beta;
-            }
-        }
-        if (WANT_DP) {
-            // per pair and (l, k): {y, z_x, z_y, z_z}_{l,k} with
-            //   y = sum_m Y_lm c_{k,lm},  z_x = sum_m dY_{x,lm} c_{k,lm},
-            // and {A, B}_{l,k} = {(f I~)', f I~}_{n l} for k = a_j nmax + n,
-            // zero outside the neighbour's species block
-            for (int t = tid; t < nc * yzn; t += kThreads) {
-                int p = t / yzn, rem = t - p * yzn, l = rem / d.K, k = rem - l * d.K;
-                const T* ck_ = s.c + k * d.L2 + l * l;
-                const T* Yp = s.Y + p * d.L2 + l * l;
-                const T* Dx = s.dY + (p * 3 + 0) * d.L2 + l * l;
-                const T* Dy = Dx + d.L2;
-                const T* Dz = Dy + d.L2;
-                T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
-                for (int m = 0; m < 2 * l + 1; ++m) {
-                    T cv = ck_[m];
-                    y += Yp[m] * cv;
-                    z0 += Dx[m] * cv;
-                    z1 += Dy[m] * cv;
-                    z2 += Dz[m] * cv;
-                }
-                reinterpret_cast<V4<T>*>(s.yz)[t] = V4<T>{y, z0, z1, z2};
-                const int n = k - s.spc[p] * d.nmax;
-                const bool in = n >= 0 && n < d.nmax;
-                reinterpret_cast<V2<T>*>(s.yz + 4 * nc * yzn)[t] =
-                    V2<T>{in ? s.dR[p * d.nl + n * lm1 + l] : T(0), in ? s.R[p * d.nl + n * lm1 + l] : T(0)};
-            }
-            __syncthreads();
-            T* dp_base = static_cast<T*>(a.dp) + q0 * int64_t(3 * PL);
-            for (int p = 0; p < nc; ++p) {
-                const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
-                const V4<T>* yzp = reinterpret_cast<const V4<T>*>(s.yz) + p * yzn;
-                const V2<T>* abp = reinterpret_cast<const V2<T>*>(s.yz + 4 * nc * yzn) + p * yzn;
-                T* row = dp_base + uint32_t(p * 3 * PL);
-                for (int o = tid; o < PL; o += kThreads) {
-                    const int v = s.tri[o];
-                    const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
-                    const int i1 = l * d.K + k1, i2 = l * d.K + k2;
-                    const V4<T> q1 = yzp[i1], q2 = yzp[i2];
-                    const V2<T> ab1 = abp[i1], ab2 = abp[i2];
-                    const T a0 = ab1.x * q2.x + ab2.x * q1.x;
-                    row[o] = ux * a0 + ab1.y * q2.y + ab2.y * q1.y;
-                    row[PL + o] = uy * a0 + ab1.y * q2.z + ab2.y * q1.z;
-                    row[2 * PL + o] = uz * a0 + ab1.y * q2.w + ab2.y * q1.w;
-                }
-            }
-        }
     }
 }
 
@@ -402,28 +278,6 @@ hipError_t launch_feat(K kernel, size_t lds, hipStream_t stream, const FeatureAr
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-template <typename K>
-hipError_t launch_rows(K kernel, size_t lds, hipStream_t stream, const FeatureArgs& a, const Layout& L, int groups)
-{
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kernel, dim3(unsigned(a.n_atoms), unsigned(groups)), dim3(kThreads), lds, stream, a, L);
-    return hipGetLastError();
-}
-
-
-template <typename T, int LM>
-hipError_t rows_launch(const FeatureArgs& a, const Layout& R, size_t lds, int groups, hipStream_t stream)
-{
-    const bool want_dc = a.dcoeffs != nullptr, want_dp = a.dp != nullptr;
-    if (want_dc && want_dp) return launch_rows(k_rows<T, LM, true, true>, lds, stream, a, R, groups);
-    if (want_dc) return launch_rows(k_rows<T, LM, true, false>, lds, stream, a, R, groups);
-    return launch_rows(k_rows<T, LM, false, true>, lds, stream, a, R, groups);
-}
-
 template <typename T, int LM>
 hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, hipStream_t stream)
 {
@@ -435,40 +289,6 @@ hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, hip
                   : launch_feat(k_centres<T, LM, false, false>, lds, stream, a, L);
 }
 
-// float kernels specialised on lmax, everything else generic
-template <typename T, template <typename, int> class Fn, typename... Args>
-hipError_t by_lmax(int lmax, Args&&... args)
-{
-    if constexpr (!std::is_same<T, float>::value) {
-        return Fn<T, -1>::run(args...);
-    } else {
-    switch (lmax) {
-    case 0: return Fn<T, 0>::run(args...);
-    case 1: return Fn<T, 1>::run(args...);
-    case 2: return Fn<T, 2>::run(args...);
-    case 3: return Fn<T, 3>::run(args...);
-    case 4: return Fn<T, 4>::run(args...);
-    case 5: return Fn<T, 5>::run(args...);
-    case 6: return Fn<T, 6>::run(args...);
-    case 7: return Fn<T, 7>::run(args...);
-    case 8: return Fn<T, 8>::run(args...);
-    case 9: return Fn<T, 9>::run(args...);
-    case 10: return Fn<T, 10>::run(args...);
-    case 11: return Fn<T, 11>::run(args...);
-    case 12: return Fn<T, 12>::run(args...);
-    default: return Fn<T, -1>::run(args...);
-    }
-    }
-}
-
-template <typename T, int LM>
-struct RowsFn {
-    static hipError_t run(const FeatureArgs& a, const Layout& R, size_t lds, int groups, hipStream_t st)
-    {
-        return rows_launch<T, LM>(a, R, lds, groups, st);
-    }
-};
-
 template <typename T, int LM>
 struct CentresFn {
     static hipError_t run(const FeatureArgs& a, const Layout& L, size_t lds, hipStream_t st)
@@ -476,30 +296,6 @@ struct CentresFn {
         return centres_launch<T, LM>(a, L, lds, st);
     }
 };
-
-constexpr int kRowChunk = 8;   // pairs a row group stages at a time
-
-template <typename T>
-hipError_t rows_t(const FeatureArgs& a, hipStream_t stream)
-{
-    Dims d = make_dims(a.S, a.nmax, a.lmax);
-    const bool want_dc = a.dcoeffs != nullptr, want_dp = a.dp != nullptr;
-    if (a.pair_capacity == 0 || a.n_atoms == 0 || (!want_dc && !want_dp)) return hipSuccess;
-    Layout R = make_layout(d, kRowChunk, true, want_dp, false, false);
-    R.sub = kRowChunk;
-    if (want_dp) {
-        // table of the (l, k1, k2) of every position of a dp row
-        R.tri = R.total;
-        R.total += (d.lmax + 1) * d.KK;
-    }
-    size_t lds = size_t(R.total) * sizeof(T);
-    if (lds > kMaxLds || (want_dp && d.K > 1023)) return hipErrorInvalidValue;
-    // row groups of about kRowChunk pairs at the mean neighbour count
-    int64_t mean = (a.pair_capacity + a.n_atoms - 1) / a.n_atoms;
-    int groups = int((mean + kRowChunk - 1) / kRowChunk);
-    groups = groups < 1 ? 1 : (groups > 64 ? 64 : groups);
-    return by_lmax<T, RowsFn>(a.lmax, a, R, lds, groups, stream);
-}
 
 // per-centre pass (c, p, self rows) then, if asked for, the pair rows
 template <typename T>
@@ -509,13 +305,13 @@ hipError_t features_t(const FeatureArgs& a, hipStream_t stream)
     bool grad = a.dcoeffs_self != nullptr;
     bool want_p = a.p != nullptr;
     Layout L = choose_layout<T>(d, grad, false, true, want_p);
-    if (L.total == 0) return hipErrorInvalidValue;
+    if (L.total == 0) return hipErrorNotSupported;
     size_t lds = size_t(L.total) * sizeof(T);
     FeatureArgs c = a;
     c.dp_self = want_p ? a.dp_self : nullptr;
     hipError_t e = by_lmax<T, CentresFn>(a.lmax, c, L, lds, stream);
     if (e != hipSuccess) return e;
-    return rows_t<T>(a, stream);
+    return launch_gradient_rows(a, std::is_same<T, double>::value, stream);
 }
 
 template <typename T>
@@ -528,7 +324,7 @@ hipError_t power_spectrum_t(const FeatureArgs& a, hipStream_t stream)
     size_t row_bufs = size_t(kWaves) * (3 * d.nmax * d.L2 + 3 * (d.lmax + 1) * d.nmax * d.K);
     if (grad) n += self_row > row_bufs ? self_row : row_bufs;
     size_t lds = n * sizeof(T);
-    if (lds > kMaxLds) return hipErrorInvalidValue;
+    if (lds > kMaxLds) return hipErrorNotSupported;
     dim3 grid(unsigned(a.n_atoms)), block(kThreads);
     if (grad) return launch_dyn(k_power_spectrum<T, true>, grid, block, lds, stream, a);
     return launch_dyn(k_power_spectrum<T, false>, grid, block, lds, stream, a);
@@ -539,11 +335,6 @@ hipError_t power_spectrum_t(const FeatureArgs& a, hipStream_t stream)
 hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream)
 {
     return f64 ? features_t<double>(a, stream) : features_t<float>(a, stream);
-}
-
-hipError_t launch_gradient_rows(const FeatureArgs& a, bool f64, hipStream_t stream)
-{
-    return f64 ? rows_t<double>(a, stream) : rows_t<float>(a, stream);
 }
 
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream)

@@ -95,35 +95,55 @@ __device__ bool make_geometry(const NeighborArgs& a, int s, StructGeom& g)
     return valid;
 }
 
+// Exclusive prefix of v over the 1024 threads of a block (shuffle scan in
+// each wave, then over the 16 wave totals); total receives the sum.
+template <typename T>
+__device__ T block_prefix(T v, T& total)
+{
+    __shared__ T wsum[17];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    T incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        T u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (t < 64) {
+        T x = t < 16 ? wsum[t] : T(0), y = x;
+        for (int off = 1; off < 16; off <<= 1) {
+            T u = __shfl_up(y, off, 64);
+            if (lane >= off) y += u;
+        }
+        if (t < 16) wsum[t] = y - x;
+        if (t == 15) wsum[16] = y;
+    }
+    __syncthreads();
+    const T r = wsum[wv] + incl - v;
+    total = wsum[16];
+    __syncthreads();   // wsum may be reused by the next call
+    return r;
+}
+
 // Exclusive scan of n values by one block of 1024 threads (each owns a
 // contiguous chunk); out[n] = total.  Returns the total in every thread.
 template <typename Tin, typename Tout>
 __device__ Tout block_scan(const Tin* in, Tout* out, Tout* out2, int64_t n)
 {
-    __shared__ Tout part[1024];
     const int t = threadIdx.x;
     const int64_t chunk = (n + 1023) / 1024;
     const int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
     Tout s = 0;
     for (int64_t k = b; k < e; ++k) s += Tout(in[k]);
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        Tout v = t >= off ? part[t - off] : Tout(0);
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    Tout run = part[t] - s;
+    Tout total;
+    Tout run = block_prefix<Tout>(s, total);
     for (int64_t k = b; k < e; ++k) {
         Tout v = Tout(in[k]);
         out[k] = run;
         if (out2) out2[k] = run;
         run += v;
     }
-    Tout total = part[1023];
     if (t == 1023) out[n] = total;
-    __syncthreads();
     return total;
 }
 
@@ -132,7 +152,6 @@ __device__ Tout block_scan(const Tin* in, Tout* out, Tout* out2, int64_t n)
 __device__ bool geometry_block(const NeighborArgs& a)
 {
     __shared__ int bad;
-    __shared__ int64_t nb[1024];
     const int t = threadIdx.x;
     if (t == 0) bad = (a.atom_offsets[0] != 0 || a.atom_offsets[a.n_structures] != a.n_atoms) ? 1 : 0;
     __syncthreads();
@@ -146,20 +165,13 @@ __device__ bool geometry_block(const NeighborArgs& a)
         sum += int64_t(g.nbin[0]) * g.nbin[1] * g.nbin[2];
         a.geom[s] = g;
     }
-    nb[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int64_t v = t >= off ? nb[t - off] : 0;
-        __syncthreads();
-        nb[t] += v;
-        __syncthreads();
-    }
-    int64_t run = nb[t] - sum;
+    int64_t total;
+    int64_t run = block_prefix<int64_t>(sum, total);
     for (int64_t s = b; s < e; ++s) {
         a.geom[s].bin_lo = run;
         run += int64_t(a.geom[s].nbin[0]) * a.geom[s].nbin[1] * a.geom[s].nbin[2];
     }
-    if (t == 0 && nb[1023] > a.max_bins) bad = 1;
+    if (t == 0 && total > a.max_bins) bad = 1;
     __syncthreads();
     bool ok = bad == 0;
     if (t == 0) {
@@ -199,6 +211,22 @@ __device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
     return bin;
 }
 
+// Record of atom i for its bin slot: the position wrapped into the cell,
+// w = r - t.H (t the integer wrap), and the atom index in the fourth word.
+// A candidate j seen through a stencil bin of cell shift c then has the
+// pair vector (w_j - w_i) + c.H and the image shift c + t_i - t_j.
+__device__ __forceinline__ double4 make_slot(const NeighborArgs& a, int64_t i)
+{
+    const StructGeom& g = a.geom[a.atom_struct[i]];
+    const int t0 = a.atom_wrap[3 * i], t1 = a.atom_wrap[3 * i + 1], t2 = a.atom_wrap[3 * i + 2];
+    double4 r;
+    r.x = a.positions[3 * i] - (t0 * g.H[0] + t1 * g.H[3] + t2 * g.H[6]);
+    r.y = a.positions[3 * i + 1] - (t0 * g.H[1] + t1 * g.H[4] + t2 * g.H[7]);
+    r.z = a.positions[3 * i + 2] - (t0 * g.H[2] + t1 * g.H[5] + t2 * g.H[8]);
+    r.w = __longlong_as_double((long long)i);
+    return r;
+}
+
 // Whole bin build in one work-group (systems with at most kSmallBins bins).
 __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
 {
@@ -210,12 +238,25 @@ __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
     __syncthreads();
     for (int64_t i = t; i < a.n_atoms; i += 1024) atomicAdd(&cnt[assign_atom(a, i)], 1);
     __syncthreads();
-    block_scan<int, int>(cnt, a.bin_start, (int*)nullptr, B);
-    for (int b = t; b < B; b += 1024) cnt[b] = a.bin_start[b];
+    // bin starts: each thread scans a contiguous chunk of bins in LDS
+    const int chunk = (B + 1023) / 1024;
+    const int b0 = t * chunk, b1 = b0 + chunk < B ? b0 + chunk : B;
+    int sum = 0;
+    for (int b = b0; b < b1; ++b) sum += cnt[b];
+    int total;
+    int run = block_prefix<int>(sum, total);
+    for (int b = b0; b < b1; ++b) {
+        const int v = cnt[b];
+        cnt[b] = run;
+        a.bin_start[b] = run;
+        run += v;
+    }
+    if (t == 1023) a.bin_start[B] = total;
     __syncthreads();
     for (int64_t i = t; i < a.n_atoms; i += 1024) {
         int pos = atomicAdd(&cnt[a.atom_bin[i]], 1);
         a.bin_atoms[pos] = int32_t(i);
+        a.slots[pos] = make_slot(a, i);
     }
 }
 
@@ -248,6 +289,7 @@ __global__ void k_bins(NeighborArgs a)
     if (i >= a.n_atoms || !*a.ok) return;
     int pos = atomicAdd(&a.bin_cursor[a.atom_bin[i]], 1);
     a.bin_atoms[pos] = int32_t(i);
+    a.slots[pos] = make_slot(a, i);
 }
 
 // ------------------------------------------------------- pair enumeration
@@ -274,8 +316,12 @@ __device__ __forceinline__ void wave_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// All candidates of centre i, 64 per round: emit(hit, j, s0, s1, s2) is
-// called by every lane in every round (hit false for lanes with nothing).
+// All candidates of centre i, 64 per round, kRounds rounds at a time with
+// their slot loads issued together: emit(hit, j, c0, c1, c2) is called by
+// every lane for every round (hit false for lanes with nothing), with the
+// cell shift c of the stencil bin the candidate was found in.
+constexpr int kRounds = 4;
+
 template <class F>
 __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&& emit)
 {
@@ -285,8 +331,7 @@ __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&&
     const int bz = local % g.nbin[2];
     const int by = (local / g.nbin[2]) % g.nbin[1];
     const int bx = local / (g.nbin[2] * g.nbin[1]);
-    const int ti0 = a.atom_wrap[3 * i], ti1 = a.atom_wrap[3 * i + 1], ti2 = a.atom_wrap[3 * i + 2];
-    const double rx = a.positions[3 * i], ry = a.positions[3 * i + 1], rz = a.positions[3 * i + 2];
+    const double4 wi = make_slot(a, i);
     const double rc2 = a.rcut * a.rcut;
     const int n0 = 2 * g.reach[0] + 1, n1 = 2 * g.reach[1] + 1, n2 = 2 * g.reach[2] + 1;
     const int nst = n0 * n1 * n2;
@@ -310,35 +355,46 @@ __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&&
         const int total = __shfl(incl, 63, 64);
         wave_fence();
         const int nb = nst - base < 64 ? nst - base : 64;
-        for (int t0 = 0; t0 < total; t0 += 64) {
-            const int t = t0 + lane;
-            bool hit = false;
-            int j = 0, s0 = 0, s1 = 0, s2 = 0;
-            if (t < total) {
-                // last stencil bin whose prefix is <= t
+        for (int t0 = 0; t0 < total; t0 += 64 * kRounds) {
+            double4 rec[kRounds];
+            int bin_of[kRounds];
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+                const int t = t0 + 64 * r + lane;
+                const int tt = t < total ? t : 0;    // total > 0: slot of candidate 0 is valid
+                // last stencil bin whose prefix is <= tt
                 int lo = 0, hi = nb - 1;
                 while (lo < hi) {
                     int mid = (lo + hi + 1) >> 1;
-                    if (w.prefix[mid] <= t) lo = mid; else hi = mid - 1;
+                    if (w.prefix[mid] <= tt) lo = mid; else hi = mid - 1;
                 }
-                j = a.bin_atoms[w.start[lo] + (t - w.prefix[lo])];
-                int cs2 = w.cshift[lo];
-                int c0 = (cs2 & 1023) - 512, c1 = ((cs2 >> 10) & 1023) - 512, c2 = ((cs2 >> 20) & 1023) - 512;
-                s0 = g.pbc[0] ? c0 + ti0 - a.atom_wrap[3 * j + 0] : 0;
-                s1 = g.pbc[1] ? c1 + ti1 - a.atom_wrap[3 * j + 1] : 0;
-                s2 = g.pbc[2] ? c2 + ti2 - a.atom_wrap[3 * j + 2] : 0;
-                if (!(j == i && s0 == 0 && s1 == 0 && s2 == 0)) {
-                    double vx = (a.positions[3 * j] - rx) + s0 * g.H[0] + s1 * g.H[3] + s2 * g.H[6];
-                    double vy = (a.positions[3 * j + 1] - ry) + s0 * g.H[1] + s1 * g.H[4] + s2 * g.H[7];
-                    double vz = (a.positions[3 * j + 2] - rz) + s0 * g.H[2] + s1 * g.H[5] + s2 * g.H[8];
-                    double r2 = vx * vx + vy * vy + vz * vz;
-                    if (r2 < rc2) {
-                        if (r2 == 0.0) put_status(a.status, SOAP_EGEOMETRY);
-                        else hit = true;
+                bin_of[r] = lo;
+                rec[r] = a.slots[w.start[lo] + (tt - w.prefix[lo])];
+            }
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+                const int t = t0 + 64 * r + lane;
+                bool hit = false;
+                int j = 0, c0 = 0, c1 = 0, c2 = 0;
+                if (t < total) {
+                    j = int(__double_as_longlong(rec[r].w));
+                    const int cs2 = w.cshift[bin_of[r]];
+                    c0 = (cs2 & 1023) - 512;
+                    c1 = ((cs2 >> 10) & 1023) - 512;
+                    c2 = ((cs2 >> 20) & 1023) - 512;
+                    if (!(j == i && c0 == 0 && c1 == 0 && c2 == 0)) {
+                        double vx = (rec[r].x - wi.x) + c0 * g.H[0] + c1 * g.H[3] + c2 * g.H[6];
+                        double vy = (rec[r].y - wi.y) + c0 * g.H[1] + c1 * g.H[4] + c2 * g.H[7];
+                        double vz = (rec[r].z - wi.z) + c0 * g.H[2] + c1 * g.H[5] + c2 * g.H[8];
+                        double r2 = vx * vx + vy * vy + vz * vz;
+                        if (r2 < rc2) {
+                            if (r2 == 0.0) put_status(a.status, SOAP_EGEOMETRY);
+                            else hit = true;
+                        }
                     }
                 }
+                emit(hit, j, c0, c1, c2);
             }
-            emit(hit, j, s0, s1, s2);
         }
         wave_fence();
     }
@@ -384,7 +440,18 @@ __device__ __forceinline__ void write_pair(const NeighborArgs& a, const StructGe
     }
 }
 
-// one wave per centre: enumerate again, rank by key in LDS, write sorted
+// image shift of a candidate j of centre i seen with cell shift c
+__device__ __forceinline__ void image_shift(const NeighborArgs& a, const StructGeom& g, int64_t i, int j, int c0,
+                                            int c1, int c2, int& s0, int& s1, int& s2)
+{
+    s0 = g.pbc[0] ? c0 + a.atom_wrap[3 * i] - a.atom_wrap[3 * j] : 0;
+    s1 = g.pbc[1] ? c1 + a.atom_wrap[3 * i + 1] - a.atom_wrap[3 * j + 1] : 0;
+    s2 = g.pbc[2] ? c2 + a.atom_wrap[3 * i + 2] - a.atom_wrap[3 * j + 2] : 0;
+}
+
+// one wave per centre: enumerate again (hits compacted in LDS), form the
+// image shifts and sort keys of all hits at once, rank them by key in LDS
+// and write them sorted
 template <bool F64>
 __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
 {
@@ -397,16 +464,18 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
     const int64_t o0 = a.pair_offsets[i];
     const int n = int(a.pair_offsets[i + 1] - o0);
     const bool in_lds = n <= kSortCap;
+    const StructGeom& g = a.geom[a.atom_struct[i]];
     int count = 0;
-    wave_visit(a, i, w, [&](bool hit, int j, int s0, int s1, int s2) {
+    wave_visit(a, i, w, [&](bool hit, int j, int c0, int c1, int c2) {
         uint64_t mask = __ballot(hit);
         int idx = count + __popcll(mask & ((uint64_t(1) << lane) - 1));
         if (hit && idx < n) {
             if (in_lds) {
-                make_key(a.species[j], j, s0, s1, s2, khi[idx], klo[idx]);
                 kj[idx] = j;
-                ks[3 * idx] = s0; ks[3 * idx + 1] = s1; ks[3 * idx + 2] = s2;
+                ks[3 * idx] = c0; ks[3 * idx + 1] = c1; ks[3 * idx + 2] = c2;
             } else {
+                int s0, s1, s2;
+                image_shift(a, g, i, j, c0, c1, c2, s0, s1, s2);
                 a.pair_j[o0 + idx] = j;
                 a.pair_shift[3 * (o0 + idx)] = s0;
                 a.pair_shift[3 * (o0 + idx) + 1] = s1;
@@ -416,8 +485,15 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
         count += __popcll(mask);
     });
     __syncthreads();
-    const StructGeom& g = a.geom[a.atom_struct[i]];
     if (in_lds) {
+        for (int p = lane; p < n; p += 64) {
+            const int j = kj[p];
+            int s0, s1, s2;
+            image_shift(a, g, i, j, ks[3 * p], ks[3 * p + 1], ks[3 * p + 2], s0, s1, s2);
+            ks[3 * p] = s0; ks[3 * p + 1] = s1; ks[3 * p + 2] = s2;
+            make_key(a.species[j], j, s0, s1, s2, khi[p], klo[p]);
+        }
+        __syncthreads();
         for (int p = lane; p < n; p += 64) {
             int64_t h = khi[p], l = klo[p];
             int rank = 0;

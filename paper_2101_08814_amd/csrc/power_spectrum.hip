@@ -115,7 +115,7 @@ hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipS
 {
     if (prec != SOAP_BF16_F32ACC) return launch_power_spectrum_valu(a, prec == SOAP_F64, stream);
     size_t lds = power_spectrum_bf16_lds(a.S, a.nmax, a.lmax);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 160 * 1024) return hipErrorNotSupported;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_power_spectrum_bf16),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));

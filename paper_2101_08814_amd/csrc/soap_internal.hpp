@@ -20,6 +20,7 @@ struct DeviceTables {
     float* coef32 = nullptr;
     double* center64 = nullptr;  // [nmax] I~_n0(0) Y_00, then [L2] harmonic normalisations K_lm
     float* center32 = nullptr;
+    int32_t* dp_pos = nullptr;   // [lmax+1][K(K+1)/2]: l | k1 << 4 | k2 << 14 of each dp row position
 };
 
 // Geometry of one structure for the neighbour search (built on the device
@@ -79,6 +80,7 @@ struct FeatureArgs {
     int64_t pair_capacity;
     const void* coef;       // table of the working precision
     const void* center;     // [nmax] centre terms, then [L2] harmonic normalisations
+    const int32_t* dp_pos;  // (l, k1, k2) of each position of a dp row, packed; NULL if K > 1023
     void* coeffs;
     void* p;
     void* dcoeffs;
@@ -118,6 +120,7 @@ struct NeighborArgs {
     int32_t* bin_start;           // [max_bins + 1]
     int32_t* bin_cursor;          // [max_bins + 1]
     int32_t* bin_atoms;           // [N]
+    double4* slots;               // [N] atoms in bin order: position x, y, z and (j, packed wrap)
     int64_t* centre_count;        // [N + 1]
     int32_t* ok;                  // set by the geometry phase: 1 if the input is valid
     int64_t capacity;

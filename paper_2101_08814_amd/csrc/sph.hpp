@@ -27,15 +27,20 @@ namespace dev {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
+__device__ __forceinline__ void sin_cos_pi(float x, float& s, float& c) { sincospif(x, &s, &c); }
+__device__ __forceinline__ void sin_cos_pi(double x, double& s, double& c) { sincospi(x, &s, &c); }
+
 template <typename T>
 __device__ __forceinline__ T fcut(T r, T rcut, T width, T& df)
 {
     if (r >= rcut) { df = T(0); return T(0); }
     T r0 = rcut - width;
     if (r <= r0) { df = T(0); return T(1); }
-    T t = T(kPi) * (r - r0) / width;
-    df = T(-0.5) * sin(t) * T(kPi) / width;
-    return T(0.5) * (T(1) + cos(t));
+    // sin and cos of pi x for x in (0, 1): no large-argument reduction
+    T x = (r - r0) / width, s, c;
+    sin_cos_pi(x, s, c);
+    df = T(-0.5) * s * T(kPi) / width;
+    return T(0.5) * (T(1) + c);
 }
 
 // Index of (l, m >= 0) in the lower-triangular Qt table.
