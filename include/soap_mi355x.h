@@ -268,6 +268,81 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
                                               const void* grad_coeffs, void* grad_pair_vec,
                                               void* grad_positions);
 
+/* ------------------------------------------------------------------
+ * Learned channel compression (a learned counterpart of the reduction of
+ * the feature space of Sec. 4.H and the lossy strategy of Sec. 7, keeping
+ * the symmetry of the features).  For every degree l one two-layer network
+ * acts on the channel index k = a nmax + n of each m-column of c, shared
+ * over m (so it commutes with rotations):
+ *   h_l = W1_l c_l,   g_{l,q} = h_{l,q} 2 sigmoid(alpha_{l,q} |h_{l,q}| + beta_{l,q}),
+ *   c~_l = W2_l g_l,  p~_{l,q1<=q2} = sum_m c~_{q1,lm} c~_{q2,lm},
+ * |.| the norm over m.  K = n_species nmax channels in, n_out out, hidden
+ * units.  weights: one float array, per l = 0..lmax in order W1_l
+ * [hidden][K], W2_l [n_out][hidden], alpha_l [hidden], beta_l [hidden].
+ * All arrays are float and on the device unless stated.
+ * Limits: 1 <= n_out <= 64, 1 <= hidden <= 256.
+ * ------------------------------------------------------------------ */
+
+/* Number of weights for (n_out, hidden): (lmax+1) (hidden K + n_out hidden + 2 hidden). */
+soap_status soap_compress_n_params(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t* n_params);
+
+/* Bytes of device workspace that soap_compress_init_pca and
+ * soap_compress_backward need.                                          */
+soap_status soap_compress_workspace_size(const soap_calculator* calc, int32_t n_out, int32_t hidden,
+                                         size_t* bytes);
+
+/* Closed-form start (and baseline): per l the top n_out eigenvectors U_l of
+ * the channel covariance sum_{i,m} c_{i,:,lm} c_{i,:,lm}^T over the n_atoms
+ * centres of coeffs [N][K][L2]: W1_l = [U_l^T; e R1], W2_l = [I e R2],
+ * alpha = beta = 0, where R1, R2 are standard normal draws of a splitmix64
+ * stream seeded with seed (hidden units beyond n_out) and e = noise.
+ * Synchronises exec->stream (the eigen-decomposition runs on the host).
+ * Writes weights (device, n_params floats).                            */
+soap_status soap_compress_init_pca(const soap_calculator* calc, const soap_exec* exec, int32_t n_out,
+                                   int32_t hidden, int64_t n_atoms, const float* coeffs, uint64_t seed,
+                                   float noise, void* workspace, size_t workspace_bytes, float* weights);
+
+/* Forward pass: coeffs [N][K][L2] -> coeffs_out [N][n_out][L2] and/or
+ * p_out [N][lmax+1][n_out (n_out+1)/2] (either may be NULL, not both).
+ * precision SOAP_F32: float arithmetic throughout.  SOAP_BF16_F32ACC: the
+ * two layers run on MFMA with bfloat16 operands (c and the weights rounded
+ * to bfloat16) and float accumulation; the gate and p~ in float.       */
+soap_status soap_compress_forward(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                  int32_t n_out, int32_t hidden, int64_t n_atoms, const float* weights,
+                                  const float* coeffs, float* coeffs_out, float* p_out);
+
+/* Reverse mode for training: given grad_p = dL/dp~ [N][lmax+1][n_out
+ * (n_out+1)/2] of the forward pass at (weights, coeffs), writes
+ * grad_weights (n_params floats, overwritten) = sum over the N centres of
+ * dL/dweights.  Float arithmetic; deterministic (fixed summation order). */
+soap_status soap_compress_backward(const soap_calculator* calc, const soap_exec* exec, int32_t n_out,
+                                   int32_t hidden, int64_t n_atoms, const float* weights, const float* coeffs,
+                                   const float* grad_p, void* workspace, size_t workspace_bytes,
+                                   float* grad_weights);
+
+/* Linear kernel of power spectra stored packed, X [n][lmax+1][Q(Q+1)/2]:
+ *   K_ij = sum_{l,q1,q2} p_{l q1 q2}(i) p_{l q1 q2}(j)
+ * over the full symmetric spectrum (packed off-diagonal entries weighted
+ * 2; this kernel does not depend on the orthonormal basis of the channel
+ * space).  out K [n][n].  n_channels = Q: the calculator's K for the plain
+ * spectrum, n_out for the compressed one.                              */
+soap_status soap_spectrum_gram(const soap_exec* exec, int32_t n, int32_t n_channels, int32_t lmax,
+                               const float* X, float* K);
+
+/* Training loss of the compression over a batch and its gradient:
+ *   L = |K~ - Kref|_F^2 / |Kref|_F^2,  K~ = soap_spectrum_gram(X),
+ *   grad_X = dL/dX [n][lmax+1][Q(Q+1)/2].
+ * work: n*n + 1 floats of device scratch; loss: device float.           */
+soap_status soap_spectrum_kernel_loss(const soap_exec* exec, int32_t n, int32_t n_channels, int32_t lmax,
+                                      const float* X, const float* Kref, float* work, float* loss,
+                                      float* grad_X);
+
+/* One Adam step (Kingma & Ba, bias-corrected; step counts from 1) on n
+ * parameters: m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+ * params <- params - lr mhat / (sqrt(vhat) + eps).                     */
+soap_status soap_adam_step(const soap_exec* exec, int64_t n, float* params, const float* grads, float* m,
+                           float* v, float lr, float beta1, float beta2, float eps, int32_t step);
+
 /* Synchronises exec->stream and returns *exec->dev_status (SOAP_OK if
  * dev_status is NULL), or SOAP_EDEVICE on a runtime error.             */
 soap_status soap_read_device_status(const soap_exec* exec);

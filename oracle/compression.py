@@ -176,3 +176,13 @@ def pca_weights(c, Q, H):
         W2 = np.zeros((Q, H)); W2[:, :Q] = np.eye(Q)
         parts.append((W1, W2, np.zeros(H), np.zeros(H)))
     return pack(parts)
+
+
+def adam_step(p, g, m, v, lr, b1, b2, eps, step):
+    """Adam (Kingma & Ba 2015, Algorithm 1) with bias correction; returns
+    (p, m, v) after one step (step counts from 1)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -24,7 +24,9 @@ EXPORTS = [
     "soap_calculator_info", "soap_calculator_upload", "soap_radial_integral_host",
     "soap_neighbors_workspace_size", "soap_compute_neighbors", "soap_spherical_expansion",
     "soap_power_spectrum", "soap_features", "soap_gradient_rows", "soap_power_spectrum_backward",
-    "soap_spherical_expansion_backward", "soap_read_device_status",
+    "soap_spherical_expansion_backward", "soap_compress_n_params", "soap_compress_workspace_size",
+    "soap_compress_init_pca", "soap_compress_forward", "soap_compress_backward", "soap_spectrum_gram",
+    "soap_spectrum_kernel_loss", "soap_adam_step", "soap_read_device_status",
 ]
 
 
@@ -92,6 +94,23 @@ def lib():
     L.soap_power_spectrum_backward.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp]
     L.soap_spherical_expansion_backward.restype = st
     L.soap_spherical_expansion_backward.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+    u64, f32, sz = ctypes.c_uint64, ctypes.c_float, ctypes.c_size_t
+    L.soap_compress_n_params.restype = st
+    L.soap_compress_n_params.argtypes = [vp, i32, i32, P(i64)]
+    L.soap_compress_workspace_size.restype = st
+    L.soap_compress_workspace_size.argtypes = [vp, i32, i32, P(sz)]
+    L.soap_compress_init_pca.restype = st
+    L.soap_compress_init_pca.argtypes = [vp, P(soap_exec), i32, i32, i64, vp, u64, f32, vp, sz, vp]
+    L.soap_compress_forward.restype = st
+    L.soap_compress_forward.argtypes = [vp, P(soap_exec), st, i32, i32, i64, vp, vp, vp, vp]
+    L.soap_compress_backward.restype = st
+    L.soap_compress_backward.argtypes = [vp, P(soap_exec), i32, i32, i64, vp, vp, vp, vp, sz, vp]
+    L.soap_spectrum_gram.restype = st
+    L.soap_spectrum_gram.argtypes = [P(soap_exec), i32, i32, i32, vp, vp]
+    L.soap_spectrum_kernel_loss.restype = st
+    L.soap_spectrum_kernel_loss.argtypes = [P(soap_exec), i32, i32, i32, vp, vp, vp, vp, vp]
+    L.soap_adam_step.restype = st
+    L.soap_adam_step.argtypes = [P(soap_exec), i64, vp, vp, vp, vp, f32, f32, f32, f32, i32]
     L.soap_read_device_status.restype = st
     L.soap_read_device_status.argtypes = [P(soap_exec)]
     _lib = L

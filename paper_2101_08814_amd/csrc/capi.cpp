@@ -163,6 +163,68 @@ NbLayout nb_layout(int32_t n_struct, int64_t N)
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ compression
+
+constexpr int kCompressSlices = 64;   // partial sums of the backward pass
+constexpr int kCovSlices = 32;        // partial sums of the channel covariance
+
+int64_t compress_params(const soap_calculator* calc, int Q, int H)
+{
+    const int K = calc->K, lm1 = calc->h.lmax + 1;
+    return int64_t(lm1) * (int64_t(H) * K + int64_t(Q) * H + 2 * int64_t(H));
+}
+
+soap_status check_compress(const soap_calculator* calc, int32_t Q, int32_t H)
+{
+    CHECK(check_calc(calc));
+    REQUIRE(Q >= 1 && Q <= 64, "n_out must be in [1, 64] (got %d)", Q);
+    REQUIRE(H >= 1 && H <= 256, "hidden must be in [1, 256] (got %d)", H);
+    return SOAP_OK;
+}
+
+CompressArgs compress_args(const soap_calculator* calc, const soap_exec* exec, int Q, int H, int64_t n)
+{
+    CompressArgs a{};
+    a.K = calc->K;
+    a.Q = Q;
+    a.H = H;
+    a.lmax = calc->h.lmax;
+    a.n = n;
+    a.n_params = compress_params(calc, Q, H);
+    a.slices = kCompressSlices;
+    a.status = status_of(exec);
+    return a;
+}
+
+size_t compress_workspace(const soap_calculator* calc, int Q, int H)
+{
+    const size_t grads = size_t(kCompressSlices) * size_t(compress_params(calc, Q, H)) * sizeof(float);
+    const size_t cov = size_t(kCovSlices) * (calc->h.lmax + 1) * size_t(calc->K) * calc->K * sizeof(float);
+    return std::max(grads, cov);
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) and Box-Muller normals
+struct SplitMix {
+    uint64_t s;
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double(next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+    double normal()
+    {
+        const double u1 = uniform(), u2 = uniform();
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    }
+};
+
+}  // namespace
+
 extern "C" {
 
 int32_t soap_abi_version(void) { return SOAP_ABI_VERSION; }
@@ -546,6 +608,172 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
     return launched(launch_expansion_backward(a, precision == SOAP_F64, pair_transpose, grad_coeffs, grad_pair_vec,
                                               grad_positions, stream_of(exec)),
                     "expansion backward");
+}
+
+
+soap_status soap_compress_n_params(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t* n_params)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(n_params != nullptr, "n_params must not be NULL");
+    *n_params = compress_params(calc, n_out, hidden);
+    return SOAP_OK;
+}
+
+soap_status soap_compress_workspace_size(const soap_calculator* calc, int32_t n_out, int32_t hidden, size_t* bytes)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(bytes != nullptr, "bytes must not be NULL");
+    *bytes = compress_workspace(calc, n_out, hidden);
+    return SOAP_OK;
+}
+
+soap_status soap_compress_init_pca(const soap_calculator* calc, const soap_exec* exec, int32_t n_out, int32_t hidden,
+                                   int64_t n_atoms, const float* coeffs, uint64_t seed, float noise, void* workspace,
+                                   size_t workspace_bytes, float* weights)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(n_atoms >= 1 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [1, 2^31)");
+    REQUIRE(n_out <= calc->K, "n_out (%d) must not exceed the %d input channels", n_out, calc->K);
+    REQUIRE(n_out <= hidden, "n_out (%d) must not exceed hidden (%d)", n_out, hidden);
+    REQUIRE(std::isfinite(noise) && noise >= 0.0f, "noise must be finite and >= 0");
+    CHECK(check_ptr(coeffs, 4, "coeffs"));
+    CHECK(check_ptr(weights, 4, "weights"));
+    CHECK(check_ptr(workspace, 256, "workspace"));
+    REQUIRE(workspace_bytes >= compress_workspace(calc, n_out, hidden), "workspace too small");
+    CompressArgs a = compress_args(calc, exec, n_out, hidden, n_atoms);
+    a.c = coeffs;
+    float* part = static_cast<float*>(workspace);
+    CHECK(launched(launch_channel_cov(a, part, kCovSlices, stream_of(exec)), "channel covariance"));
+    const int K = calc->K, lm1 = calc->h.lmax + 1, Q = n_out, H = hidden;
+    std::vector<float> hp(size_t(kCovSlices) * lm1 * K * K);
+    hipStream_t st = stream_of(exec);
+    if (hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(SOAP_EDEVICE, "copy of the channel covariance failed");
+    SplitMix rng{seed};
+    std::vector<float> w(size_t(compress_params(calc, Q, H)));
+    size_t o = 0;
+    for (int l = 0; l < lm1; ++l) {
+        std::vector<double> C(size_t(K) * K, 0.0), ev, U;
+        for (int s = 0; s < kCovSlices; ++s)
+            for (int e = 0; e < K * K; ++e) C[e] += hp[(size_t(s) * lm1 + l) * K * K + e];
+        for (int r = 0; r < K; ++r)   // symmetrise the float partial sums
+            for (int q = r + 1; q < K; ++q) C[r * K + q] = C[q * K + r] = 0.5 * (C[r * K + q] + C[q * K + r]);
+        sym_eigen(K, C, ev, U);
+        std::vector<int> order(K);
+        for (int k = 0; k < K; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ev[x] > ev[y]; });
+        for (int q = 0; q < H; ++q)           // W1_l [H][K]
+            for (int k = 0; k < K; ++k)
+                w[o + size_t(q) * K + k] =
+                    q < Q ? float(U[size_t(k) * K + order[q]]) : float(noise * rng.normal() / std::sqrt(double(K)));
+        o += size_t(H) * K;
+        for (int p = 0; p < Q; ++p)           // W2_l [Q][H]
+            for (int q = 0; q < H; ++q)
+                w[o + size_t(p) * H + q] =
+                    q < Q ? (p == q ? 1.0f : 0.0f) : float(noise * rng.normal() / std::sqrt(double(H)));
+        o += size_t(Q) * H;
+        for (int q = 0; q < 2 * H; ++q) w[o + q] = 0.0f;   // alpha_l, beta_l
+        o += 2 * size_t(H);
+    }
+    if (hipMemcpyAsync(weights, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(SOAP_EDEVICE, "upload of the initial weights failed");
+    return SOAP_OK;
+}
+
+soap_status soap_compress_forward(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                  int32_t n_out, int32_t hidden, int64_t n_atoms, const float* weights,
+                                  const float* coeffs, float* coeffs_out, float* p_out)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(precision == SOAP_F32 || precision == SOAP_BF16_F32ACC, "precision must be SOAP_F32 or SOAP_BF16_F32ACC");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(coeffs_out != nullptr || p_out != nullptr, "coeffs_out and p_out must not both be NULL");
+    if (n_atoms == 0) return SOAP_OK;
+    CHECK(check_ptr(weights, 4, "weights"));
+    CHECK(check_ptr(coeffs, 4, "coeffs"));
+    CHECK(check_ptr(coeffs_out, 4, "coeffs_out", true));
+    CHECK(check_ptr(p_out, 4, "p_out", true));
+    CompressArgs a = compress_args(calc, exec, n_out, hidden, n_atoms);
+    a.w = weights;
+    a.c = coeffs;
+    a.ct = coeffs_out;
+    a.pt = p_out;
+    if (precision == SOAP_BF16_F32ACC)
+        return launched(launch_compress_forward_bf16(a, stream_of(exec)), "compression (bf16)");
+    return launched(launch_compress_forward(a, stream_of(exec)), "compression");
+}
+
+soap_status soap_compress_backward(const soap_calculator* calc, const soap_exec* exec, int32_t n_out, int32_t hidden,
+                                   int64_t n_atoms, const float* weights, const float* coeffs, const float* grad_p,
+                                   void* workspace, size_t workspace_bytes, float* grad_weights)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    CHECK(check_ptr(weights, 4, "weights"));
+    CHECK(check_ptr(coeffs, 4, "coeffs", n_atoms == 0));
+    CHECK(check_ptr(grad_p, 4, "grad_p", n_atoms == 0));
+    CHECK(check_ptr(grad_weights, 4, "grad_weights"));
+    CHECK(check_ptr(workspace, 256, "workspace"));
+    REQUIRE(workspace_bytes >= compress_workspace(calc, n_out, hidden), "workspace too small");
+    CompressArgs a = compress_args(calc, exec, n_out, hidden, n_atoms);
+    a.w = weights;
+    a.c = coeffs;
+    a.gpt = grad_p;
+    a.gpart = static_cast<float*>(workspace);
+    return launched(launch_compress_backward(a, grad_weights, stream_of(exec)), "compression backward");
+}
+
+soap_status soap_spectrum_gram(const soap_exec* exec, int32_t n, int32_t n_channels, int32_t lmax, const float* X,
+                               float* K)
+{
+    clear_error();
+    REQUIRE(n >= 0 && n <= 65536, "n must be in [0, 65536]");
+    REQUIRE(n_channels >= 1 && n_channels <= 4096, "n_channels must be in [1, 4096]");
+    REQUIRE(lmax >= 0 && lmax <= 12, "lmax must be in [0, 12]");
+    if (n == 0) return SOAP_OK;
+    CHECK(check_ptr(X, 4, "X"));
+    CHECK(check_ptr(K, 4, "K"));
+    return launched(launch_spectrum_gram(n, n_channels, lmax, X, K, stream_of(exec)), "spectrum gram");
+}
+
+soap_status soap_spectrum_kernel_loss(const soap_exec* exec, int32_t n, int32_t n_channels, int32_t lmax,
+                                      const float* X, const float* Kref, float* work, float* loss, float* grad_X)
+{
+    clear_error();
+    REQUIRE(n >= 1 && n <= 65536, "n must be in [1, 65536]");
+    REQUIRE(n_channels >= 1 && n_channels <= 4096, "n_channels must be in [1, 4096]");
+    REQUIRE(lmax >= 0 && lmax <= 12, "lmax must be in [0, 12]");
+    CHECK(check_ptr(X, 4, "X"));
+    CHECK(check_ptr(Kref, 4, "Kref"));
+    CHECK(check_ptr(work, 4, "work"));
+    CHECK(check_ptr(loss, 4, "loss"));
+    CHECK(check_ptr(grad_X, 4, "grad_X"));
+    return launched(launch_spectrum_kernel_loss(n, n_channels, lmax, X, Kref, work, loss, work + int64_t(n) * n,
+                                                grad_X, stream_of(exec)),
+                    "kernel loss");
+}
+
+soap_status soap_adam_step(const soap_exec* exec, int64_t n, float* params, const float* grads, float* m, float* v,
+                           float lr, float beta1, float beta2, float eps, int32_t step)
+{
+    clear_error();
+    REQUIRE(n >= 0, "n must be >= 0");
+    REQUIRE(step >= 1, "step counts from 1");
+    REQUIRE(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f, "betas must be in [0, 1)");
+    REQUIRE(std::isfinite(lr) && std::isfinite(eps) && eps > 0.0f, "lr and eps must be finite, eps > 0");
+    if (n == 0) return SOAP_OK;
+    CHECK(check_ptr(params, 4, "params"));
+    CHECK(check_ptr(grads, 4, "grads"));
+    CHECK(check_ptr(m, 4, "m"));
+    CHECK(check_ptr(v, 4, "v"));
+    return launched(launch_adam(n, params, grads, m, v, lr, beta1, beta2, eps, step, stream_of(exec)), "adam");
 }
 
 soap_status soap_read_device_status(const soap_exec* exec)

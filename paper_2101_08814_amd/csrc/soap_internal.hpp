@@ -65,6 +65,9 @@ soap_status build_tables(soap_calculator* calc);
 void radial_exact(const soap_calculator* calc, int64_t n, const double* r, double* I, double* dI);
 void radial_spline_host(const soap_calculator* calc, double r, double* I, double* dI);
 soap_status device_tables(const soap_calculator* calc, const DeviceTables** out);
+// symmetric eigen-decomposition A = Q diag(w) Q^T of a small dense matrix
+// (row-major n x n; column k of Q is the eigenvector of w[k])
+void sym_eigen(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& Q);
 
 // launchers (kernels in the .hip files); each returns a hipError_t
 struct FeatureArgs {
@@ -99,6 +102,32 @@ hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const 
 hipError_t launch_expansion_backward(const FeatureArgs& a, bool f64, const int32_t* pair_transpose,
                                      const void* grad_coeffs, void* grad_pair_vec,
                                      void* grad_positions, hipStream_t stream);
+
+struct CompressArgs {
+    int K, Q, H, lmax;         // channels in, out, hidden; degree
+    int64_t n;                 // centres
+    int64_t n_params;          // (lmax+1) (H K + Q H + 2 H)
+    const float* w;            // weights: per l W1 [H][K], W2 [Q][H], alpha [H], beta [H]
+    const float* c;            // [n][K][L2]
+    float* ct;                 // [n][Q][L2] or NULL
+    float* pt;                 // [n][lmax+1][Q(Q+1)/2] or NULL
+    const float* gpt;          // backward: dL/dpt, same layout as pt
+    float* gpart;              // backward: per-slice partial gradients [slices][n_params]
+    int slices;
+    int32_t* status;
+};
+
+size_t compress_fwd_lds(const CompressArgs& a);
+size_t compress_bwd_lds(const CompressArgs& a);
+hipError_t launch_compress_forward(const CompressArgs& a, hipStream_t stream);
+hipError_t launch_compress_forward_bf16(const CompressArgs& a, hipStream_t stream);
+hipError_t launch_compress_backward(const CompressArgs& a, float* grad, hipStream_t stream);
+hipError_t launch_channel_cov(const CompressArgs& a, float* part, int slices, hipStream_t stream);
+hipError_t launch_spectrum_gram(int n, int Q, int lmax, const float* X, float* C, hipStream_t stream);
+hipError_t launch_spectrum_kernel_loss(int n, int Q, int lmax, const float* X, const float* Kref, float* Kt,
+                                       float* loss, float* scale, float* dX, hipStream_t stream);
+hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t stream);
 
 struct NeighborArgs {
     int32_t n_structures;

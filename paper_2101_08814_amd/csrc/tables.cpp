@@ -56,93 +56,6 @@ std::vector<double> gto_overlap(const Gto& g, int nmax)
     return S;
 }
 
-// Symmetric eigen-decomposition A = Q diag(w) Q^T of a small dense matrix.
-// Householder reflections bring A to tridiagonal form; implicit QR sweeps
-// with a Wilkinson shift (Golub & Van Loan, Sec. 8.3) diagonalise it.  The
-// rotations are applied to the dense matrix: n <= 16 here, so simplicity
-// wins over the O(n) tridiagonal update.
-void sym_eigen(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& Q)
-{
-    auto at = [n](std::vector<double>& M, int i, int j) -> double& { return M[i * n + j]; };
-    Q.assign(n * n, 0.0);
-    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
-    // Householder: zero column k below the subdiagonal.
-    for (int k = 0; k + 2 < n; ++k) {
-        std::vector<double> v(n, 0.0);
-        double norm = 0.0;
-        for (int i = k + 1; i < n; ++i) { v[i] = at(A, i, k); norm += v[i] * v[i]; }
-        norm = std::sqrt(norm);
-        if (norm == 0.0) continue;
-        double alpha = v[k + 1] > 0 ? -norm : norm;
-        v[k + 1] -= alpha;
-        double vn = 0.0;
-        for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
-        if (vn == 0.0) continue;
-        vn = std::sqrt(vn);
-        for (int i = k + 1; i < n; ++i) v[i] /= vn;
-        // A <- (I - 2vv^T) A (I - 2vv^T);  Q <- Q (I - 2vv^T)
-        for (int j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int i = k + 1; i < n; ++i) s += v[i] * at(A, i, j);
-            for (int i = k + 1; i < n; ++i) at(A, i, j) -= 2.0 * v[i] * s;
-        }
-        for (int i = 0; i < n; ++i) {
-            double s = 0.0;
-            for (int j = k + 1; j < n; ++j) s += at(A, i, j) * v[j];
-            for (int j = k + 1; j < n; ++j) at(A, i, j) -= 2.0 * s * v[j];
-        }
-        for (int i = 0; i < n; ++i) {
-            double s = 0.0;
-            for (int j = k + 1; j < n; ++j) s += at(Q, i, j) * v[j];
-            for (int j = k + 1; j < n; ++j) at(Q, i, j) -= 2.0 * s * v[j];
-        }
-    }
-    // rotation in the (p, p+1) plane applied as A <- G A G^T, Q <- Q G^T
-    auto rotate = [&](int p, double c, double s) {
-        for (int j = 0; j < n; ++j) {
-            double x = at(A, p, j), y = at(A, p + 1, j);
-            at(A, p, j) = c * x + s * y;
-            at(A, p + 1, j) = -s * x + c * y;
-        }
-        for (int i = 0; i < n; ++i) {
-            double x = at(A, i, p), y = at(A, i, p + 1);
-            at(A, i, p) = c * x + s * y;
-            at(A, i, p + 1) = -s * x + c * y;
-        }
-        for (int i = 0; i < n; ++i) {
-            double x = at(Q, i, p), y = at(Q, i, p + 1);
-            at(Q, i, p) = c * x + s * y;
-            at(Q, i, p + 1) = -s * x + c * y;
-        }
-    };
-    const double eps = 2.220446049250313e-16;
-    int hi = n - 1;
-    for (int iter = 0; hi > 0 && iter < 100 * n; ++iter) {
-        // deflate negligible subdiagonal entries
-        for (int i = 0; i < hi; ++i)
-            if (std::fabs(at(A, i + 1, i)) <= eps * (std::fabs(at(A, i, i)) + std::fabs(at(A, i + 1, i + 1)))) {
-                at(A, i + 1, i) = at(A, i, i + 1) = 0.0;
-            }
-        while (hi > 0 && at(A, hi, hi - 1) == 0.0) --hi;
-        if (hi == 0) break;
-        int lo = hi - 1;
-        while (lo > 0 && at(A, lo, lo - 1) != 0.0) --lo;
-        // Wilkinson shift from the trailing 2x2 block
-        double a = at(A, hi - 1, hi - 1), b = at(A, hi, hi - 1), cc = at(A, hi, hi);
-        double delta = 0.5 * (a - cc);
-        double sgn = delta >= 0 ? 1.0 : -1.0;
-        double mu = cc - b * b / (delta + sgn * std::sqrt(delta * delta + b * b));
-        double x = at(A, lo, lo) - mu, z = at(A, lo + 1, lo);
-        for (int k = lo; k < hi; ++k) {
-            double r = std::hypot(x, z);
-            double c = r == 0 ? 1.0 : x / r, s = r == 0 ? 0.0 : z / r;
-            rotate(k, c, s);
-            if (k + 1 < hi) { x = at(A, k + 1, k); z = at(A, k + 2, k); }
-        }
-    }
-    w.resize(n);
-    for (int i = 0; i < n; ++i) w[i] = at(A, i, i);
-}
 
 // ------------------------------------------------------- restricted 1F1
 // G(a, b, r) = Gamma(a)/Gamma(b) exp(-c r^2) 1F1(a; b; alpha r^2).
@@ -318,6 +231,94 @@ std::vector<double> clamped_second_derivatives(const std::vector<double>& y, dou
 }
 
 }  // namespace
+
+// Symmetric eigen-decomposition A = Q diag(w) Q^T of a small dense matrix.
+// Householder reflections bring A to tridiagonal form; implicit QR sweeps
+// with a Wilkinson shift (Golub & Van Loan, Sec. 8.3) diagonalise it.  The
+// rotations are applied to the dense matrix (n is at most a few hundred
+// here), which keeps the code short at O(n^3) cost.
+void sym_eigen(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& Q)
+{
+    auto at = [n](std::vector<double>& M, int i, int j) -> double& { return M[i * n + j]; };
+    Q.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+    // Householder: zero column k below the subdiagonal.
+    for (int k = 0; k + 2 < n; ++k) {
+        std::vector<double> v(n, 0.0);
+        double norm = 0.0;
+        for (int i = k + 1; i < n; ++i) { v[i] = at(A, i, k); norm += v[i] * v[i]; }
+        norm = std::sqrt(norm);
+        if (norm == 0.0) continue;
+        double alpha = v[k + 1] > 0 ? -norm : norm;
+        v[k + 1] -= alpha;
+        double vn = 0.0;
+        for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
+        if (vn == 0.0) continue;
+        vn = std::sqrt(vn);
+        for (int i = k + 1; i < n; ++i) v[i] /= vn;
+        // A <- (I - 2vv^T) A (I - 2vv^T);  Q <- Q (I - 2vv^T)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int i = k + 1; i < n; ++i) s += v[i] * at(A, i, j);
+            for (int i = k + 1; i < n; ++i) at(A, i, j) -= 2.0 * v[i] * s;
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += at(A, i, j) * v[j];
+            for (int j = k + 1; j < n; ++j) at(A, i, j) -= 2.0 * s * v[j];
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += at(Q, i, j) * v[j];
+            for (int j = k + 1; j < n; ++j) at(Q, i, j) -= 2.0 * s * v[j];
+        }
+    }
+    // rotation in the (p, p+1) plane applied as A <- G A G^T, Q <- Q G^T
+    auto rotate = [&](int p, double c, double s) {
+        for (int j = 0; j < n; ++j) {
+            double x = at(A, p, j), y = at(A, p + 1, j);
+            at(A, p, j) = c * x + s * y;
+            at(A, p + 1, j) = -s * x + c * y;
+        }
+        for (int i = 0; i < n; ++i) {
+            double x = at(A, i, p), y = at(A, i, p + 1);
+            at(A, i, p) = c * x + s * y;
+            at(A, i, p + 1) = -s * x + c * y;
+        }
+        for (int i = 0; i < n; ++i) {
+            double x = at(Q, i, p), y = at(Q, i, p + 1);
+            at(Q, i, p) = c * x + s * y;
+            at(Q, i, p + 1) = -s * x + c * y;
+        }
+    };
+    const double eps = 2.220446049250313e-16;
+    int hi = n - 1;
+    for (int iter = 0; hi > 0 && iter < 100 * n; ++iter) {
+        // deflate negligible subdiagonal entries
+        for (int i = 0; i < hi; ++i)
+            if (std::fabs(at(A, i + 1, i)) <= eps * (std::fabs(at(A, i, i)) + std::fabs(at(A, i + 1, i + 1)))) {
+                at(A, i + 1, i) = at(A, i, i + 1) = 0.0;
+            }
+        while (hi > 0 && at(A, hi, hi - 1) == 0.0) --hi;
+        if (hi == 0) break;
+        int lo = hi - 1;
+        while (lo > 0 && at(A, lo, lo - 1) != 0.0) --lo;
+        // Wilkinson shift from the trailing 2x2 block
+        double a = at(A, hi - 1, hi - 1), b = at(A, hi, hi - 1), cc = at(A, hi, hi);
+        double delta = 0.5 * (a - cc);
+        double sgn = delta >= 0 ? 1.0 : -1.0;
+        double mu = cc - b * b / (delta + sgn * std::sqrt(delta * delta + b * b));
+        double x = at(A, lo, lo) - mu, z = at(A, lo + 1, lo);
+        for (int k = lo; k < hi; ++k) {
+            double r = std::hypot(x, z);
+            double c = r == 0 ? 1.0 : x / r, s = r == 0 ? 0.0 : z / r;
+            rotate(k, c, s);
+            if (k + 1 < hi) { x = at(A, k + 1, k); z = at(A, k + 2, k); }
+        }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = at(A, i, i);
+}
 
 soap_status build_tables(soap_calculator* calc)
 {

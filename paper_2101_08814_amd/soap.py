@@ -346,3 +346,115 @@ class SOAPFunction(torch.autograd.Function):
 
 def soap_power_spectrum_of_positions(positions, calc, species, atom_offsets, cells, pbc, dtype=torch.float32):
     return SOAPFunction.apply(positions, calc, species, atom_offsets, cells, pbc, dtype)
+
+
+class Compressor:
+    """The learned equivariant channel compression of a calculator's
+    coefficients (soap_compress_*, soap_spectrum_*, soap_adam_step): per l a
+    two-layer network on the (species, n) channels, shared over m, with a
+    norm gate.  Holds the weights and the Adam moments on the device."""
+
+    def __init__(self, calc: Calculator, n_out: int = 16, hidden: int = 128, device=None):
+        self.calc, self.Q, self.H = calc, int(n_out), int(hidden)
+        L = calc._L
+        n = ctypes.c_int64()
+        check(L.soap_compress_n_params(calc.handle, self.Q, self.H, ctypes.byref(n)))
+        ws = ctypes.c_size_t()
+        check(L.soap_compress_workspace_size(calc.handle, self.Q, self.H, ctypes.byref(ws)))
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.n_params = int(n.value)
+        self.weights = torch.zeros(self.n_params, dtype=torch.float32, device=dev)
+        self._ws = torch.empty(max(int(ws.value), 256), dtype=torch.uint8, device=dev)
+        self._m = torch.zeros_like(self.weights)
+        self._v = torch.zeros_like(self.weights)
+        self._grad = torch.zeros_like(self.weights)
+        self._loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.step = 0
+
+    @property
+    def lmax(self) -> int:
+        return self.calc.lmax
+
+    def init_pca(self, coeffs: torch.Tensor, seed: int = 0, noise: float = 0.1):
+        """soap_compress_init_pca over the centres of coeffs [N, S, nmax, L2] (float)."""
+        assert coeffs.dtype == torch.float32 and coeffs.is_contiguous()
+        e = self.calc._exec()
+        check(self.calc._L.soap_compress_init_pca(self.calc.handle, ctypes.byref(e), self.Q, self.H,
+                                                  int(coeffs.shape[0]), _ptr(coeffs), ctypes.c_uint64(seed),
+                                                  float(noise), _ptr(self._ws), self._ws.numel(),
+                                                  _ptr(self.weights)))
+        self._m.zero_()
+        self._v.zero_()
+        self.step = 0
+
+    def forward(self, coeffs: torch.Tensor, precision=torch.float32, want_coeffs: bool = False, want_p: bool = True):
+        """soap_compress_forward: (c~ [N, Q, L2] or None, p~ [N, lmax+1, Q(Q+1)/2] or None)."""
+        assert coeffs.dtype == torch.float32 and coeffs.is_contiguous()
+        N, dev = int(coeffs.shape[0]), coeffs.device
+        prec = SOAP_BF16_F32ACC if precision in ("bf16", torch.bfloat16, SOAP_BF16_F32ACC) else SOAP_F32
+        ct = torch.empty((N, self.Q, self.calc.L2), dtype=torch.float32, device=dev) if want_coeffs else None
+        pt = (torch.empty((N, self.lmax + 1, self.Q * (self.Q + 1) // 2), dtype=torch.float32, device=dev)
+              if want_p else None)
+        e = self.calc._exec()
+        check(self.calc._L.soap_compress_forward(self.calc.handle, ctypes.byref(e), prec, self.Q, self.H, N,
+                                                 _ptr(self.weights), _ptr(coeffs), _ptr(ct), _ptr(pt)))
+        return ct, pt
+
+    def backward(self, coeffs: torch.Tensor, grad_p: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """soap_compress_backward: dL/dweights for dL/dp~ = grad_p."""
+        assert grad_p.dtype == torch.float32 and grad_p.is_contiguous()
+        out = self._grad if out is None else out
+        e = self.calc._exec()
+        check(self.calc._L.soap_compress_backward(self.calc.handle, ctypes.byref(e), self.Q, self.H,
+                                                  int(coeffs.shape[0]), _ptr(self.weights), _ptr(coeffs),
+                                                  _ptr(grad_p), _ptr(self._ws), self._ws.numel(), _ptr(out)))
+        return out
+
+    def gram(self, X: torch.Tensor, n_channels: int) -> torch.Tensor:
+        """soap_spectrum_gram of packed spectra X [n, lmax+1, Q(Q+1)/2]."""
+        assert X.dtype == torch.float32 and X.is_contiguous()
+        n = int(X.shape[0])
+        K = torch.empty((n, n), dtype=torch.float32, device=X.device)
+        e = self.calc._exec()
+        check(self.calc._L.soap_spectrum_gram(ctypes.byref(e), n, int(n_channels), self.lmax, _ptr(X), _ptr(K)))
+        return K
+
+    def kernel_loss(self, X: torch.Tensor, Kref: torch.Tensor):
+        """soap_spectrum_kernel_loss for compressed spectra X: (loss as a
+        device tensor [1], dL/dX)."""
+        n = int(X.shape[0])
+        work = torch.empty(n * n + 1, dtype=torch.float32, device=X.device)
+        gX = torch.empty_like(X)
+        e = self.calc._exec()
+        check(self.calc._L.soap_spectrum_kernel_loss(ctypes.byref(e), n, self.Q, self.lmax, _ptr(X), _ptr(Kref),
+                                                     _ptr(work), _ptr(self._loss), _ptr(gX)))
+        return self._loss, gX
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        """soap_adam_step on the weights with the last gradient."""
+        self.step += 1
+        e = self.calc._exec()
+        check(self.calc._L.soap_adam_step(ctypes.byref(e), self.n_params, _ptr(self.weights), _ptr(self._grad),
+                                          _ptr(self._m), _ptr(self._v), float(lr), float(beta1), float(beta2),
+                                          float(eps), self.step))
+
+    def train_step(self, coeffs: torch.Tensor, lr: float) -> torch.Tensor:
+        """One Adam step on a batch of centres: full spectrum and its kernel
+        (the reference), compressed spectrum, loss, gradients.  Returns the
+        loss before the step (device tensor)."""
+        pf = self.calc.power_spectrum(coeffs, precision=torch.float32)
+        Kref = self.gram(pf.reshape(pf.shape[0], self.lmax + 1, -1), self.calc.K)
+        _, pt = self.forward(coeffs)
+        loss, gX = self.kernel_loss(pt, Kref)
+        loss = loss.clone()
+        self.backward(coeffs, gX)
+        self.adam(lr)
+        return loss
+
+    def kernel_error(self, coeffs: torch.Tensor, precision=torch.float32) -> float:
+        """eps_K = |K~ - K|_F / |K|_F over the centres of coeffs (synchronises)."""
+        pf = self.calc.power_spectrum(coeffs, precision=torch.float32)
+        Kref = self.gram(pf.reshape(pf.shape[0], self.lmax + 1, -1), self.calc.K)
+        _, pt = self.forward(coeffs, precision=precision)
+        loss, _ = self.kernel_loss(pt, Kref)
+        return float(loss.item()) ** 0.5

@@ -108,3 +108,12 @@ def test_pca_baseline_is_exact_at_full_rank_and_monotone(coeffs):
         errs.append(C.kernel_error(p, C.power_spectrum(C.compress(c, w, Q, max(Q, 16)))))
     assert errs[-1] <= 1e-12
     assert all(a >= b - 1e-12 for a, b in zip(errs, errs[1:])), errs
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    """After bias correction the first Adam step is lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(2)
+    p, g = rng.normal(size=50), rng.normal(size=50)
+    p1, m, v = C.adam_step(p, g, np.zeros(50), np.zeros(50), 1e-2, 0.9, 0.999, 1e-8, 1)
+    assert np.allclose(p - p1, 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
