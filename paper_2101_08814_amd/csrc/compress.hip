@@ -382,6 +382,202 @@ __global__ void k_adam(int64_t n, float* p, const float* g, float* m, float* v, 
     p[e] -= lr * (mv / c1) / (sqrtf(vv / c2) + eps);
 }
 
+// ---------------------------------------------------- forward on MFMA
+// Inference with bfloat16 operands and float accumulation
+// (v_mfma_f32_16x16x32_bf16; lane (r = lane & 15, g = lane >> 4) holds
+// A[r][8g + j], B[8g + j][r] and D[4g + v][r]).  A work-group of four
+// waves owns 16 centres, the 16 columns of every product.  Per l:
+//   X_l     c_{k, l^2 + m} of the 16 centres -> LDS, bfloat16, [m][centre][k];
+//   pass 1  H_m = W1_l X_m (16-row tiles of hidden units spread over the
+//           waves, W1 fragments held in registers for the whole l), summing
+//           |h|^2 over m in registers; the gate factor per (q, centre);
+//   pass 2  H_m again, times the gate, -> LDS bfloat16 [centre][q]; the
+//           waves that own a 16-row tile of outputs form c~_m = W2_l G_m;
+//   then    p~_{q1 q2} = sum_m c~ c~ per centre, written packed.
+constexpr int kCC = 16;        // centres per work-group
+constexpr int kMT = 4;         // hidden tiles per wave (H <= 256)
+constexpr int kKS1 = 4;        // k-steps of the first layer (K <= 128)
+constexpr int kKS2 = 8;        // k-steps of the second layer (H <= 256)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float f)
+{
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+struct Bf16Dims {
+    int Kp, XS, Hp, HS, QT, HT, KS1, KS2;
+};
+
+__host__ __device__ inline Bf16Dims bf16_dims(int K, int Q, int H)
+{
+    Bf16Dims d;
+    d.Kp = (K + 31) / 32 * 32;
+    d.XS = d.Kp + 8;            // row stride of X (bf16), padded against bank conflicts
+    d.Hp = (H + 31) / 32 * 32;
+    d.HS = d.Hp + 8;
+    d.QT = (Q + 15) / 16;
+    d.HT = (H + 15) / 16;
+    d.KS1 = d.Kp / 32;
+    d.KS2 = d.Hp / 32;
+    return d;
+}
+
+template <bool WANT_CT, bool WANT_PT>
+__global__ void __launch_bounds__(kThreads) k_cmp_fwd_bf16(CompressArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int K = a.K, Q = a.Q, H = a.H, lmax = a.lmax, L2 = (lmax + 1) * (lmax + 1), MX = 2 * lmax + 1;
+    const int QQ = Q * (Q + 1) / 2;
+    const Bf16Dims D = bf16_dims(K, Q, H);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+    const int64_t i0 = int64_t(blockIdx.x) * kCC;
+    const int nc = a.n - i0 < kCC ? int(a.n - i0) : kCC;
+    unsigned short* Xs = reinterpret_cast<unsigned short*>(smem_raw);      // [MX][kCC][XS]
+    unsigned short* Hs = Xs + MX * kCC * D.XS;                              // [kCC][HS]
+    float* CT = reinterpret_cast<float*>(smem_raw + ((2 * size_t(MX * kCC * D.XS + kCC * D.HS) + 15) & ~size_t(15)));
+    const float* w = a.w;
+    for (int l = 0; l <= lmax; ++l) {
+        const int M = 2 * l + 1, b = l * l;
+        const float* W1 = w;
+        const float* W2 = W1 + H * K;
+        const float* al = W2 + Q * H;
+        const float* be = al + H;
+        w = be + H;
+        // X_l of the 16 centres, bfloat16, zero beyond K and beyond the last centre
+        for (int e = tid; e < kCC * D.Kp * M; e += kThreads) {
+            const int m = e % M, k = (e / M) % D.Kp, c = e / (M * D.Kp);
+            float v = 0.0f;
+            if (k < K && c < nc) v = a.c[((i0 + c) * K + k) * L2 + b + m];
+            Xs[(m * kCC + c) * D.XS + k] = to_bf16(v);
+        }
+        // first-layer fragments of this wave's hidden tiles (tile = wave + 4 t)
+        u16x8 A1[kMT][kKS1];
+#pragma unroll
+        for (int t = 0; t < kMT; ++t)
+#pragma unroll
+            for (int ks = 0; ks < kKS1; ++ks) {
+                const int q = (wave + 4 * t) * 16 + r;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = ks * 32 + 8 * g + j;
+                    A1[t][ks][j] = (q < H && k < K && ks < D.KS1) ? to_bf16(W1[q * K + k]) : (unsigned short)0;
+                }
+            }
+        __syncthreads();
+        // pass 1: |h_q|^2 over m for the (q, centre) this lane holds
+        float n2[kMT][4] = {};
+        for (int m = 0; m < M; ++m) {
+            u16x8 B[kKS1];
+#pragma unroll
+            for (int ks = 0; ks < kKS1; ++ks)
+                if (ks < D.KS1) B[ks] = *reinterpret_cast<const u16x8*>(&Xs[(m * kCC + r) * D.XS + ks * 32 + 8 * g]);
+#pragma unroll
+            for (int t = 0; t < kMT; ++t) {
+                if (wave + 4 * t >= D.HT) break;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kKS1; ++ks)
+                    if (ks < D.KS1)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A1[t][ks]),
+                                                                      __builtin_bit_cast(bf16x8, B[ks]), acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) n2[t][v] += acc[v] * acc[v];
+            }
+        }
+        // gate factor 2 sigma(alpha |h| + beta) of (q = tile 16 + 4g + v, centre r)
+        float G[kMT][4];
+#pragma unroll
+        for (int t = 0; t < kMT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int q = (wave + 4 * t) * 16 + 4 * g + v;
+                G[t][v] = q < H ? 2.0f * sigm(al[q] * sqrtf(n2[t][v]) + be[q]) : 0.0f;
+            }
+        // second-layer fragments: wave w owns output tile w
+        u16x8 A2[kKS2];
+#pragma unroll
+        for (int ks = 0; ks < kKS2; ++ks) {
+            const int p = wave * 16 + r;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int q = ks * 32 + 8 * g + j;
+                A2[ks][j] = (wave < D.QT && p < Q && q < H && ks < D.KS2) ? to_bf16(W2[p * H + q]) : (unsigned short)0;
+            }
+        }
+        // pass 2: gated hidden layer -> LDS, then c~_m
+        for (int m = 0; m < M; ++m) {
+            u16x8 B[kKS1];
+#pragma unroll
+            for (int ks = 0; ks < kKS1; ++ks)
+                if (ks < D.KS1) B[ks] = *reinterpret_cast<const u16x8*>(&Xs[(m * kCC + r) * D.XS + ks * 32 + 8 * g]);
+#pragma unroll
+            for (int t = 0; t < kMT; ++t) {
+                if (wave + 4 * t >= D.HT) break;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kKS1; ++ks)
+                    if (ks < D.KS1)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A1[t][ks]),
+                                                                      __builtin_bit_cast(bf16x8, B[ks]), acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = (wave + 4 * t) * 16 + 4 * g + v;
+                    Hs[r * D.HS + q] = to_bf16(acc[v] * G[t][v]);
+                }
+            }
+            // hidden units in [HT 16, Hp) stay zero
+            for (int e = tid; e < kCC * (D.Hp - D.HT * 16); e += kThreads) {
+                const int c = e / (D.Hp - D.HT * 16), q = D.HT * 16 + e % (D.Hp - D.HT * 16);
+                Hs[c * D.HS + q] = 0;
+            }
+            __syncthreads();
+            if (wave < D.QT) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kKS2; ++ks)
+                    if (ks < D.KS2) {
+                        const u16x8 Bv = *reinterpret_cast<const u16x8*>(&Hs[r * D.HS + ks * 32 + 8 * g]);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A2[ks]),
+                                                                      __builtin_bit_cast(bf16x8, Bv), acc, 0, 0, 0);
+                    }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) CT[(m * (D.QT * 16) + wave * 16 + 4 * g + v) * kCC + r] = acc[v];
+            }
+            __syncthreads();
+        }
+        // p~ of the 16 centres; c~ if asked for
+        if (WANT_PT)
+            for (int e = tid; e < nc * QQ; e += kThreads) {
+                const int c = e / QQ, t = e - c * QQ;
+                int q1, q2;
+                tri_decode(Q, t, q1, q2);
+                float acc = 0.0f;
+                for (int m = 0; m < M; ++m)
+                    acc += CT[(m * (D.QT * 16) + q1) * kCC + c] * CT[(m * (D.QT * 16) + q2) * kCC + c];
+                a.pt[((i0 + c) * (lmax + 1) + l) * int64_t(QQ) + t] = acc;
+            }
+        if (WANT_CT)
+            for (int e = tid; e < nc * Q * M; e += kThreads) {
+                const int m = e % M, q = (e / M) % Q, c = e / (M * Q);
+                a.ct[((i0 + c) * Q + q) * L2 + b + m] = CT[(m * (D.QT * 16) + q) * kCC + c];
+            }
+        __syncthreads();
+    }
+}
+
+size_t compress_bf16_lds(const CompressArgs& a)
+{
+    const Bf16Dims D = bf16_dims(a.K, a.Q, a.H);
+    const int MX = 2 * a.lmax + 1;
+    return ((2 * size_t(MX * kCC * D.XS + kCC * D.HS) + 15) & ~size_t(15)) + 4 * size_t(MX) * D.QT * 16 * kCC;
+}
+
 inline unsigned blocks_of(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 }  // namespace
@@ -415,11 +611,22 @@ hipError_t launch_compress_forward(const CompressArgs& a, hipStream_t stream)
     return hipGetLastError();
 }
 
+
 hipError_t launch_compress_forward_bf16(const CompressArgs& a, hipStream_t stream)
 {
-    (void)a;
-    (void)stream;
-    return hipErrorNotSupported;
+    if (a.n == 0) return hipSuccess;
+    if (a.K > 32 * kKS1 || a.H > 16 * 4 * kMT || a.Q > 64) return hipErrorNotSupported;
+    const size_t lds = compress_bf16_lds(a);
+    if (lds > 160 * 1024) return hipErrorNotSupported;
+    auto kernel = a.ct ? (a.pt ? k_cmp_fwd_bf16<true, true> : k_cmp_fwd_bf16<true, false>)
+                       : k_cmp_fwd_bf16<false, true>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, dim3(blocks_of(a.n, kCC)), dim3(kThreads), lds, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_compress_backward(const CompressArgs& a, float* grad, hipStream_t stream)

@@ -55,6 +55,25 @@ def test_forward_fp32(cells):
     assert e1 <= 1e-5 and e2 <= 1e-5
 
 
+@pytest.mark.parametrize("n_centres", [512, 37])
+def test_forward_bf16_mfma(cells, n_centres):
+    """bfloat16 operands, float accumulation: each product carries a
+    relative rounding of about 2^-8 on each operand, so c~ and p~ agree with
+    the FP64 result to about 1e-2 (Frobenius); 37 centres leave a partial
+    tile of 16."""
+    calc, c32, cd = cells
+    cmp_ = P.Compressor(calc, 16, 128)
+    w = random_weights(1, calc.K, 16, 128, calc.lmax)
+    cmp_.weights.copy_(torch.tensor(w))
+    cb = cd[:n_centres].contiguous()
+    ct, pt = cmp_.forward(cb, precision="bf16", want_coeffs=True)
+    ref_ct = C.compress(c32[:n_centres].astype(np.float64), w.astype(np.float64), 16, 128)
+    ref_pt = C.power_spectrum(ref_ct)
+    e1, e2 = rel(ct, ref_ct), rel(pt, ref_pt)
+    print(f"[compress bf16] c~ {e1:.2e}  p~ {e2:.2e}")
+    assert e1 <= 1e-2 and e2 <= 2e-2
+
+
 def test_identity_network_on_gpu():
     """K = 8 channels, W1 = W2 = I, gate off: p~ is the plain spectrum."""
     b = synthetic.clusters_2species().subset([0])
