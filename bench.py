@@ -101,6 +101,100 @@ def cpu_baseline(batch, seconds: float):
                       f"all gradient rows) in FP64, {el:.1f} s"}
 
 
+def run_compression(args) -> int:
+    """The learned-compression workload: 512 periodic cells x 256 atoms, 8
+    species (equal counts), rcut 5 A, sigma 0.5 A, nmax 12, lmax 8 (96
+    channels).  Trains the per-l network (16 outputs, 128 hidden, float) on
+    the coefficients of cells 0-409 (80%), scores the linear-kernel error of
+    the full symmetric spectrum on held-out centres of cells 410-511, and
+    times the plain path (expansion + full power spectrum) against the
+    compressed one (expansion + bfloat16 MFMA compression and spectrum)."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    import paper_2101_08814_amd as P
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    batch = synthetic.multi_species_cells()
+    h = batch.hypers
+    calc = P.Calculator.from_hypers(h)
+    pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
+    spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
+    ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
+    nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32, transpose=False)
+    N = batch.n_atoms
+    c = calc.spherical_expansion(nl, spc, dtype=torch.float32)
+    torch.cuda.synchronize()
+    log(f"[compression] {N} centres, {nl.count()} pairs, coefficients {c.numel() * 4 / 1e9:.2f} GB "
+        f"({time.perf_counter() - t0:.1f} s)")
+    n_train = int(batch.atom_offsets[410])
+    held = torch.arange(n_train, N, max(1, (N - n_train) // 2048), device=dev)[:2048]
+    c_held = c[held].contiguous()
+    Q, H = 16, 128
+    cmp_ = P.Compressor(calc, Q, H)
+    cmp_.init_pca(c[:n_train], seed=0, noise=0.0)
+    eps_pca = cmp_.kernel_error(c_held)
+    cmp_.init_pca(c[:n_train], seed=1005, noise=0.05)
+    gen = torch.Generator(device="cpu").manual_seed(1005)
+    t1 = time.perf_counter()
+    steps = args.train_steps
+    for k in range(steps):
+        idx = torch.randint(0, n_train, (512,), generator=gen).to(dev)
+        lr = 2e-3 * (0.05 ** (k / max(1, steps - 1)))
+        cmp_.train_step(c[idx].contiguous(), lr=lr)
+        if (k + 1) % 100 == 0:
+            log(f"[compression] step {k + 1}/{steps}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    eps32 = cmp_.kernel_error(c_held)
+    eps16 = cmp_.kernel_error(c_held, precision="bf16")
+    log(f"[compression] eps_K pca {eps_pca:.4f}  trained fp32 {eps32:.4f}  bf16 {eps16:.4f}  ({t_train:.1f} s)")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(1, args.steps)
+    t_exp = timed(lambda: calc.spherical_expansion(nl, spc, dtype=torch.float32), reps)
+    t_plain32 = timed(lambda: calc.power_spectrum(c, precision=torch.float32), reps)
+    t_plain16 = timed(lambda: calc.power_spectrum(c, precision="bf16"), reps)
+    t_comp = timed(lambda: cmp_.forward(c, precision="bf16"), reps)
+    t_plain = t_exp + min(t_plain32, t_plain16)
+    t_cpath = t_exp + t_comp
+    log(f"[compression] expansion {t_exp:.3f} ms  full p fp32 {t_plain32:.3f} ms  bf16 {t_plain16:.3f} ms  "
+        f"compressed p {t_comp:.3f} ms")
+    line = {
+        "metric": "atom-centres/s, expansion + compressed power spectrum (16 learned channels, bf16 MFMA) "
+                  "vs expansion + full power spectrum",
+        "value": N / (t_cpath * 1e-3),
+        "unit": "atom-centres/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t_cpath,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {
+            "workload": "512 periodic cells x 256 atoms (side 16.22 A), 8 species x 32, rcut 5 A, sigma 0.5 A, "
+                        "nmax 12, lmax 8; network 96 -> 128 -> 16 channels per l, trained on cells 0-409",
+            "centres": N, "plain_ms_per_step": t_plain, "speedup": t_plain / t_cpath,
+            "expansion_ms": t_exp, "full_spectrum_ms_fp32": t_plain32, "full_spectrum_ms_bf16": t_plain16,
+            "compressed_spectrum_ms": t_comp,
+            "eps_K_held_out": {"pca_16": eps_pca, "trained_fp32": eps32, "trained_bf16": eps16},
+            "held_out_centres": int(held.numel()), "train_steps": steps, "train_batch": 512,
+            "train_seconds": t_train,
+        },
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +206,10 @@ def main() -> int:
                     "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["diamond", "compression"], default="diamond",
+                    help="diamond: the headline step (default); compression: the learned channel compression "
+                         "of the 8-species cells, trained and timed against the full power spectrum")
+    ap.add_argument("--train-steps", type=int, default=600)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding over several GPUs is not "
@@ -125,6 +223,8 @@ def main() -> int:
     import paper_2101_08814_amd as P
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.workload == "compression":
+        return run_compression(args)
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
