@@ -111,17 +111,19 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     return L;
 }
 
-// Largest chunk (<= 32 pairs) whose layout fits 64 KB of LDS, else 160 KB;
+// Largest chunk (<= 32 pairs, at least 4) whose layout fits 40 KB of LDS
+// (four work-groups of 256 lanes per CU), else 64 KB, else 160 KB;
 // total = 0 if nothing fits.
 template <typename T>
 inline Layout choose_layout(const Dims& d, bool grad, bool rows_p, bool self_rows, bool want_tri)
 {
-    int ch = 32;
-    Layout L = make_layout(d, ch, grad, rows_p, self_rows, want_tri);
-    while (ch > 2 && size_t(L.total) * sizeof(T) > 65536) {
-        ch /= 2;
-        L = make_layout(d, ch, grad, rows_p, self_rows, want_tri);
-    }
+    const size_t limits[3] = {40 * 1024, 64 * 1024, 160 * 1024};
+    for (size_t lim : limits)
+        for (int ch = 32; ch >= 4; ch /= 2) {
+            Layout L = make_layout(d, ch, grad, rows_p, self_rows, want_tri);
+            if (size_t(L.total) * sizeof(T) <= lim) return L;
+        }
+    Layout L = make_layout(d, 2, grad, rows_p, self_rows, want_tri);
     if (size_t(L.total) * sizeof(T) > 160 * 1024) L.total = 0;
     return L;
 }
