@@ -186,7 +186,8 @@ soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec*
  *       d c_{i, a_j, n, lm} / d r_ji  (the only nonzero species block);
  *     dcoeffs_self [N][3][n_species][nmax][L2] or NULL: d c_i / d r_i
  *       = - sum of the rows of i (images of i included, App. B).
- *     dcoeffs and dcoeffs_self are both NULL or both given.
+ *     dcoeffs and dcoeffs_self are both NULL or both given; rows P to
+ *     pair_capacity - 1 of dcoeffs are not written.
  * precision: SOAP_F64 or SOAP_F32.                                      */
 soap_status soap_spherical_expansion(const soap_calculator* calc, const soap_exec* exec,
                                      soap_precision precision, int64_t n_atoms,

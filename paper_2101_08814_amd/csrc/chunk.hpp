@@ -67,8 +67,8 @@ __host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
 
 // LDS layout in elements of T (ints occupy T-sized slots).
 struct Layout {
-    int chunk, sub;                     // pairs per staged chunk, pairs per y/z batch
-    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, total;
+    int chunk;                          // pairs per staged chunk
+    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, pos, total;
 };
 
 __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, bool rows_p, bool self_rows = true,
@@ -76,7 +76,6 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
 {
     Layout L;
     L.chunk = ch;
-    L.sub = ch < 8 ? ch : 8;
     int o = 0;
     L.c = o; o += d.K * d.L2;
     L.dcs = o; o += (grad && self_rows) ? 3 * d.K * d.L2 : 0;
@@ -96,7 +95,7 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     // {A, B}, 6 values) reuse its space, 4-element aligned for vector loads
     o = (o + 3) & ~3;
     int scratch = ch * (d.nq + 2 * d.lm1);
-    int yz = (grad && rows_p) ? L.sub * 6 * d.lm1 * d.K : 0;
+    int yz = (grad && rows_p) ? ch * 6 * d.lm1 * d.K : 0;   // every pair of a chunk
     L.qt = o;
     L.cre = o + ch * d.nq;
     L.cim = L.cre + ch * d.lm1;
@@ -107,6 +106,7 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     L.ynorm = o; o += d.L2;
     L.lof = o; o += d.L2;
     L.tri = o; o += (want_tri && d.KK <= kTriMax) ? d.KK : 0;
+    L.pos = o;   // dp row positions: sized by the row kernel's launcher
     L.total = o;
     return L;
 }
@@ -141,14 +141,14 @@ struct alignas(2 * sizeof(T)) V2 {
 template <typename T>
 struct Smem {
     T *c, *dcs, *ux, *uy, *uz, *r, *rinv, *f, *df, *R, *dR, *Y, *dY, *qt, *cre, *cim, *yz, *ynorm;
-    int *spc, *seg, *lof, *tri;
+    int *spc, *seg, *lof, *tri, *pos;
     __device__ Smem(T* base, const Layout& L)
         : c(base + L.c), dcs(base + L.dcs), ux(base + L.ux), uy(base + L.uy), uz(base + L.uz), r(base + L.r),
           rinv(base + L.rinv), f(base + L.f), df(base + L.df), R(base + L.R), dR(base + L.dR), Y(base + L.Y),
           dY(base + L.dY), qt(base + L.qt), cre(base + L.cre), cim(base + L.cim), yz(base + L.yz),
           ynorm(base + L.ynorm), spc(reinterpret_cast<int*>(base + L.spc)),
           seg(reinterpret_cast<int*>(base + L.seg)), lof(reinterpret_cast<int*>(base + L.lof)),
-          tri(reinterpret_cast<int*>(base + L.tri))
+          tri(reinterpret_cast<int*>(base + L.tri)), pos(reinterpret_cast<int*>(base + L.pos))
     {
     }
 };
@@ -164,7 +164,7 @@ __device__ void init_tables(const FeatureArgs& a, const Dims& d, const Layout& L
         s.lof[lm] = l_of(lm);
         s.ynorm[lm] = knorm[lm];
     }
-    if (L.tri != L.total)
+    if (L.pos != L.tri)
         for (int k1 = tid; k1 < d.K; k1 += kThreads) {
             int start = k1 * d.K - k1 * (k1 - 1) / 2;
             for (int k2 = k1; k2 < d.K; ++k2) s.tri[start + k2 - k1] = k1 | (k2 << 16);

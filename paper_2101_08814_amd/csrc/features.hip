@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
     }
     if (!WANT_P) return;
     const int KK = d.KK, PL = lm1 * KK;
-    const bool tri_tab = L.tri != L.total;
+    const bool tri_tab = L.pos != L.tri;
     T* p_out = static_cast<T*>(a.p) + i * int64_t(PL);
     T* dps_out = GRAD ? static_cast<T*>(a.dp_self) + i * int64_t(3 * PL) : nullptr;
     int l = tid / KK, kk = tid - (tid / KK) * KK;

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_rows(FeatureArgs a, Layout L)
         const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
         for (int e = tid; e < KL2; e += kThreads) s.c[e] = c_in[e];
         // packed positions of a dp row: l | k1 << 4 | k2 << 14
-        for (int o = tid; o < PL; o += kThreads) s.tri[o] = a.dp_pos[o];
+        for (int o = tid; o < PL; o += kThreads) s.pos[o] = a.dp_pos[o];
     }
     const int EDC = 3 * nL2;
     const int yzn = lm1 * d.K;
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_rows(FeatureArgs a, Layout L)
                 const V2<T>* abp = reinterpret_cast<const V2<T>*>(s.yz + 4 * nc * yzn) + p * yzn;
                 T* row = dp_base + uint32_t(p * 3 * PL);
                 for (int o = tid; o < PL; o += kThreads) {
-                    const int v = s.tri[o];
+                    const int v = s.pos[o];
                     const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
                     const int i1 = l * d.K + k1, i2 = l * d.K + k2;
                     const V4<T> q1 = yzp[i1], q2 = yzp[i2];
@@ -158,10 +158,9 @@ hipError_t rows_t(const FeatureArgs& a, hipStream_t stream)
     if (a.pair_capacity == 0 || a.n_atoms == 0 || (!want_dc && !want_dp)) return hipSuccess;
     if (want_dp && a.dp_pos == nullptr) return hipErrorNotSupported;   // K > 1023: no position table
     Layout R = make_layout(d, kRowChunk, true, want_dp, false, false);
-    R.sub = kRowChunk;
     if (want_dp) {
         // table of the (l, k1, k2) of every position of a dp row
-        R.tri = R.total;
+        R.pos = R.total;
         R.total += (d.lmax + 1) * d.KK;
     }
     const size_t lds = size_t(R.total) * sizeof(T);

@@ -11,8 +11,8 @@
 // distinct (bin, cell shift) pair, so each image is seen exactly once even
 // in cells thinner than rcut.
 //
-// Bin build: one work-group when the system has at most kSmallBins bins
-// (occupancy counted in LDS), otherwise five small launches (geometry,
+// Bin build: one work-group when the system has at most kSmallBins bins and
+// kSmallAtoms atoms (occupancy counted in LDS), otherwise five small launches (geometry,
 // clear, assign with integer atomics, scan, scatter).
 // Pair list: one wave per centre.  The wave reads the sizes of its stencil
 // bins in one round, scans them across lanes, and then tests 64 candidates
@@ -28,6 +28,7 @@ namespace soap {
 namespace {
 
 constexpr int kSmallBins = 8192;   // single-work-group bin build up to this many bins
+constexpr int kSmallAtoms = 8192;  // ... and this many atoms
 constexpr int kSortCap = 512;      // pairs per centre ranked in LDS
 
 __device__ __forceinline__ void put_status(int32_t* st, int v)
@@ -70,15 +71,16 @@ __device__ bool make_geometry(const NeighborArgs& a, int s, StructGeom& g)
                  H[2] * (H[3] * H[7] - H[4] * H[6]);
     if (!(fabs(det) > 1e-10 * scale * scale * scale) || !(scale > 0.0) || !isfinite(det)) return false;
     double* Hi = g.Hinv;
-    Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
-    Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
-    Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
-    Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
-    Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
-    Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
-    Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
-    Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
-    Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    const double idet = 1.0 / det;
+    Hi[0] = (H[4] * H[8] - H[5] * H[7]) * idet;
+    Hi[1] = (H[2] * H[7] - H[1] * H[8]) * idet;
+    Hi[2] = (H[1] * H[5] - H[2] * H[4]) * idet;
+    Hi[3] = (H[5] * H[6] - H[3] * H[8]) * idet;
+    Hi[4] = (H[0] * H[8] - H[2] * H[6]) * idet;
+    Hi[5] = (H[2] * H[3] - H[0] * H[5]) * idet;
+    Hi[6] = (H[3] * H[7] - H[4] * H[6]) * idet;
+    Hi[7] = (H[1] * H[6] - H[0] * H[7]) * idet;
+    Hi[8] = (H[0] * H[4] - H[1] * H[3]) * idet;
     int cap = 1;
     while (int64_t(cap + 1) * (cap + 1) * (cap + 1) <= ns && cap < 128) ++cap;
     for (int k = 0; k < 3; ++k) {
@@ -181,15 +183,10 @@ __device__ bool geometry_block(const NeighborArgs& a)
     return ok;
 }
 
-// structure, wrap and bin of atom i
-__device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
+// wrap t and bin of atom i in structure s with geometry g (written to the
+// workspace), and its position wrapped into the cell, w = r - t.H
+__device__ int32_t place_atom(const NeighborArgs& a, int64_t i, int s, const StructGeom& g, double4& w)
 {
-    int lo = 0, hi = a.n_structures - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a.geom[mid].atom_hi > i) hi = mid; else lo = mid + 1;
-    }
-    const StructGeom& g = a.geom[lo];
     double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
     int b[3], t[3];
     for (int k = 0; k < 3; ++k) {
@@ -201,14 +198,37 @@ __device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
         b[k] = bk < 0 ? 0 : (bk >= g.nbin[k] ? g.nbin[k] - 1 : bk);
     }
     int32_t bin = int32_t(g.bin_lo + (int64_t(b[0]) * g.nbin[1] + b[1]) * g.nbin[2] + b[2]);
-    a.atom_struct[i] = lo;
+    a.atom_struct[i] = s;
     a.atom_bin[i] = bin;
     a.atom_wrap[3 * i + 0] = t[0];
     a.atom_wrap[3 * i + 1] = t[1];
     a.atom_wrap[3 * i + 2] = t[2];
     int sp = a.species[i];
     if (sp < 0 || sp >= a.n_species) put_status(a.status, SOAP_ESPECIES);
+    w.x = r[0] - (t[0] * g.H[0] + t[1] * g.H[3] + t[2] * g.H[6]);
+    w.y = r[1] - (t[0] * g.H[1] + t[1] * g.H[4] + t[2] * g.H[7]);
+    w.z = r[2] - (t[0] * g.H[2] + t[1] * g.H[5] + t[2] * g.H[8]);
+    w.w = __longlong_as_double((long long)i);
     return bin;
+}
+
+// structure of atom i: last s with atom_lo <= i (geom holds n structures)
+__device__ __forceinline__ int structure_of(const StructGeom* geom, int n, int64_t i)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (geom[mid].atom_hi > i) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// structure, wrap and bin of atom i
+__device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
+{
+    const int s = structure_of(a.geom, a.n_structures, i);
+    double4 w;
+    return place_atom(a, i, s, a.geom[s], w);
 }
 
 // Record of atom i for its bin slot: the position wrapped into the cell,
@@ -227,16 +247,38 @@ __device__ __forceinline__ double4 make_slot(const NeighborArgs& a, int64_t i)
     return r;
 }
 
-// Whole bin build in one work-group (systems with at most kSmallBins bins).
+// Whole bin build in one work-group (systems with at most kSmallBins bins
+// and kSmallAtoms atoms: at most kAtomsPerLane atoms per lane).  The
+// geometry of the first kGeomCache structures is kept in LDS, and each
+// lane keeps the bin and wrapped position of its atoms in registers from
+// the counting pass to the placing pass.
+constexpr int kAtomsPerLane = kSmallAtoms / 1024;
+constexpr int kGeomCache = 16;
+
 __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
 {
     __shared__ int cnt[kSmallBins + 1];
+    __shared__ StructGeom gc[kGeomCache];
     const int t = threadIdx.x;
     if (!geometry_block(a)) return;
+    const int ns = a.n_structures;
+    const bool cached = ns <= kGeomCache;
+    if (cached && t < ns) gc[t] = a.geom[t];
     const int B = int(a.max_bins);
     for (int b = t; b <= B; b += 1024) cnt[b] = 0;
     __syncthreads();
-    for (int64_t i = t; i < a.n_atoms; i += 1024) atomicAdd(&cnt[assign_atom(a, i)], 1);
+    const StructGeom* geom = cached ? gc : a.geom;
+    int bin_of[kAtomsPerLane];
+    double4 w_of[kAtomsPerLane];
+#pragma unroll
+    for (int u = 0; u < kAtomsPerLane; ++u) {
+        const int64_t i = t + 1024 * int64_t(u);
+        if (i < a.n_atoms) {
+            const int s = structure_of(geom, ns, i);
+            bin_of[u] = place_atom(a, i, s, geom[s], w_of[u]);
+            atomicAdd(&cnt[bin_of[u]], 1);
+        }
+    }
     __syncthreads();
     // bin starts: each thread scans a contiguous chunk of bins in LDS
     const int chunk = (B + 1023) / 1024;
@@ -253,10 +295,14 @@ __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
     }
     if (t == 1023) a.bin_start[B] = total;
     __syncthreads();
-    for (int64_t i = t; i < a.n_atoms; i += 1024) {
-        int pos = atomicAdd(&cnt[a.atom_bin[i]], 1);
-        a.bin_atoms[pos] = int32_t(i);
-        a.slots[pos] = make_slot(a, i);
+#pragma unroll
+    for (int u = 0; u < kAtomsPerLane; ++u) {
+        const int64_t i = t + 1024 * int64_t(u);
+        if (i < a.n_atoms) {
+            const int pos = atomicAdd(&cnt[bin_of[u]], 1);
+            a.bin_atoms[pos] = int32_t(i);
+            a.slots[pos] = w_of[u];
+        }
     }
 }
 
@@ -578,7 +624,7 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
                            a.centre_count, a.pair_offsets, (int64_t*)nullptr, int64_t(0), a.capacity, a.status);
         return hipGetLastError();
     }
-    if (B <= kSmallBins) {
+    if (B <= kSmallBins && N <= kSmallAtoms) {
         hipLaunchKernelGGL(k_bins_small, dim3(1), dim3(1024), 0, stream, a);
     } else {
         hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
