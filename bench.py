@@ -7,9 +7,10 @@ Workload (one step): a periodic perturbed-diamond cell of 1024 atoms
 full neighbour list with periodic images, FP32 spherical expansion, power
 spectrum and forward-mode position gradients of both (every pair row and
 every self row).  Inputs are resident in HBM when the timed region starts;
-each step launches three phases on one stream: the neighbour list, the
-per-centre pass (c, p and the self rows, soap_features) and the pair rows
-(soap_gradient_rows, the kernel that writes ~97% of the bytes).
+each step launches two phases on one stream: the neighbour list and
+soap_features, whose one kernel writes c, p, the self rows and the pair
+rows (~97% of the bytes).  --two-pass times the older split instead: the
+per-centre pass, then the pair rows from soap_gradient_rows.
 
 Prints ONE JSON line on stdout; diagnostics go to stderr.
 """
@@ -26,9 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-DOMINANT_KERNEL = "k_pair_rows<float, 6, true, true>"
+DOMINANT_KERNEL = "k_centres<float, 6, true, true, true>"
+TWO_PASS_KERNEL = "k_pair_rows<float, 6, true, true>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "features_diamond1024_traffic.txt")
-KERNEL_SOURCES = ["gradient_rows.hip", "chunk.hpp", "sph.hpp"]
+KERNEL_SOURCES = ["features.hip", "chunk.hpp", "sph.hpp"]
 
 
 def log(*a):
@@ -68,14 +70,19 @@ def algorithmic_bytes(N: int, P: int, S: int, nmax: int, lmax: int, es: int = 4)
     Per-centre pass: pair vectors, neighbour indices and species, CSR
     offsets, centre species in; c, p and both self rows out.
     Row pass: pair vectors, neighbour indices and species, CSR offsets and c
-    of each centre in; the dc and dp rows of every pair out."""
+    of each centre in; the dc and dp rows of every pair out.
+    Fused pass (soap_features with rows): the inputs of the per-centre pass
+    in; c, p, both self rows and both pair rows out."""
     L2 = (lmax + 1) ** 2
     K = S * nmax
     KK = K * (K + 1) // 2
     pair_in = 12 + 4 + 4
-    centres = N * (es * (K * L2 + (lmax + 1) * KK + 3 * K * L2 + 3 * (lmax + 1) * KK) + 8 + 4) + P * pair_in
-    rows = N * (es * K * L2 + 8) + P * (es * (3 * nmax * L2 + 3 * (lmax + 1) * KK) + pair_in)
-    return centres, rows
+    centre_out = es * (K * L2 + (lmax + 1) * KK + 3 * K * L2 + 3 * (lmax + 1) * KK)
+    pair_out = es * (3 * nmax * L2 + 3 * (lmax + 1) * KK)
+    centres = N * (centre_out + 8 + 4) + P * pair_in
+    rows = N * (es * K * L2 + 8) + P * (pair_out + pair_in)
+    fused = N * (centre_out + 8 + 4) + P * (pair_in + pair_out)
+    return centres, rows, fused
 
 
 def cpu_baseline(batch, seconds: float):
@@ -206,8 +213,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--graph", action="store_true", help="replay the three phases as HIP graphs instead of "
+    ap.add_argument("--graph", action="store_true", help="replay the phases as HIP graphs instead of "
                     "launching them eagerly (measured slower: each graph launch adds a gap)")
+    ap.add_argument("--two-pass", action="store_true", help="per-centre pass and pair rows as two kernels "
+                    "(soap_features without rows, then soap_gradient_rows) instead of the one fused kernel")
     ap.add_argument("--calibrate-copy", action="store_true", help="only copy 256 MiB device-to-device five times "
                     "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -257,12 +266,12 @@ def main() -> int:
         calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32, out=nl)
 
     def step_centres():
-        calc.features(nl, spc, torch.float32, gradients=True, out=out, rows=False)
+        calc.features(nl, spc, torch.float32, gradients=True, out=out, rows=not args.two_pass)
 
     def step_rows():
         calc.gradient_rows(nl, spc, out[0], dc=out[2], dp=out[4])
 
-    steps = [step_neighbors, step_centres, step_rows]
+    steps = [step_neighbors, step_centres] + ([step_rows] if args.two_pass else [])
     # eager warm-up (also sets LDS attributes before any capture)
     for _ in range(3):
         for f in steps:
@@ -280,14 +289,14 @@ def main() -> int:
         for g, f in zip(graphs, steps):
             with torch.cuda.graph(g):
                 f()
-        run_nl, run_centres, run_rows = [g.replay for g in graphs]
+        runs = [g.replay for g in graphs]
     else:
-        run_nl, run_centres, run_rows = steps
+        runs = steps
+    n_ph = len(runs)
 
     for _ in range(args.warmup):
-        run_nl()
-        run_centres()
-        run_rows()
+        for f in runs:
+            f()
     torch.cuda.synchronize()
     for a, b in zip(out, ref):
         if not torch.equal(a, b):
@@ -295,25 +304,23 @@ def main() -> int:
             return 3
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    # ev[k][j] is recorded after phase j of step k (same stream as the kernels)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ph)] for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
     end_all = torch.cuda.Event(enable_timing=True)
     start_all.record()
     for k in range(K):
-        run_nl()
-        ev[k][0].record()
-        run_centres()
-        ev[k][1].record()
-        run_rows()
-        ev[k][2].record()
+        for j, f in enumerate(runs):
+            f()
+            ev[k][j].record()
     end_all.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = start_all.elapsed_time(end_all)
     centres_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    rows_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    rows_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev])) if args.two_pass else 0.0
     status = calc.device_status()
     if status != 0:
         log(f"device status {status}")
@@ -325,13 +332,22 @@ def main() -> int:
 
     ms_per_step = total_ms / K
     value = N / (ms_per_step * 1e-3)
-    alg_centres, alg = algorithmic_bytes(N, Pn, h["n_species"], h["nmax"], h["lmax"])
-    achieved = alg / (rows_ms * 1e-3) / 1e9
-    traffic = measured_traffic(alg)
-    log(f"[bench] N={N} P={Pn} steps={K} total={total_ms:.2f} ms (host wall {wall * 1e3:.1f} ms) "
-        f"step={ms_per_step * 1e3:.1f} us  centres={centres_ms * 1e3:.1f} us "
-        f"({alg_centres / (centres_ms * 1e-3) / 1e9:.0f} GB/s)  rows={rows_ms * 1e3:.1f} us ({achieved:.0f} GB/s)  "
-        f"neighbours+gaps={(ms_per_step - rows_ms - centres_ms) * 1e3:.1f} us  row bytes/launch={alg / 1e6:.1f} MB")
+    alg_centres, alg_rows, alg_fused = algorithmic_bytes(N, Pn, h["n_species"], h["nmax"], h["lmax"])
+    if args.two_pass:
+        kernel, alg, kernel_ms = TWO_PASS_KERNEL, alg_rows, rows_ms
+        log(f"[bench] two-pass N={N} P={Pn} steps={K} total={total_ms:.2f} ms (host wall {wall * 1e3:.1f} ms) "
+            f"step={ms_per_step * 1e3:.1f} us  centres={centres_ms * 1e3:.1f} us "
+            f"({alg_centres / (centres_ms * 1e-3) / 1e9:.0f} GB/s)  rows={rows_ms * 1e3:.1f} us "
+            f"({alg_rows / (rows_ms * 1e-3) / 1e9:.0f} GB/s)  "
+            f"neighbours+gaps={(ms_per_step - rows_ms - centres_ms) * 1e3:.1f} us")
+    else:
+        kernel, alg, kernel_ms = DOMINANT_KERNEL, alg_fused, centres_ms
+        log(f"[bench] N={N} P={Pn} steps={K} total={total_ms:.2f} ms (host wall {wall * 1e3:.1f} ms) "
+            f"step={ms_per_step * 1e3:.1f} us  features={centres_ms * 1e3:.1f} us "
+            f"({alg_fused / (centres_ms * 1e-3) / 1e9:.0f} GB/s)  "
+            f"neighbours+gaps={(ms_per_step - centres_ms) * 1e3:.1f} us  bytes/launch={alg_fused / 1e6:.1f} MB")
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(alg) if not args.two_pass else None
 
     line = {
         "metric": "atom-centres/s (expansion+power spectrum+grads) at stated error vs FP64 oracle",
@@ -347,6 +363,7 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
+            "two_pass": bool(args.two_pass),
             "workload": "periodic perturbed diamond, 1024 atoms (4x4x8 cells, a=5.43 A, 0.1 A displacements), "
                         "1 species, rcut 5 A, sigma 0.5 A, nmax 8, lmax 6; neighbour list with images + FP32 "
                         "expansion + power spectrum + forward-mode position gradients",
@@ -356,13 +373,13 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": DOMINANT_KERNEL,
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel_ms": rows_ms,
+            "kernel_ms": kernel_ms,
             "algorithmic_bytes_per_launch": alg,
         },
     }

@@ -158,7 +158,7 @@ hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const 
                           void* grad_pos, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
-    Layout L = choose_layout<T>(d, true, false, false, false);
+    Layout L = choose_layout<T>(d, true, false, false);
     if (L.total == 0) return hipErrorNotSupported;
     size_t lds = size_t(L.total) * sizeof(T);
     if (lds > 65536) {

@@ -68,14 +68,19 @@ __host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
 // LDS layout in elements of T (ints occupy T-sized slots).
 struct Layout {
     int chunk;                          // pairs per staged chunk
+    int yzb;                            // pairs per batch of gradient-row operands
     int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, pos, total;
 };
 
-__host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, bool rows_p, bool self_rows = true,
-                                              bool want_tri = false)
+// yz: elements of the region for the per-(pair, l, k) operands of the
+// gradient rows (it reuses the Legendre table's space); pos: entries of the
+// table of dp row positions.
+__host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, int yz = 0, bool self_rows = true,
+                                              bool want_tri = false, int pos = 0)
 {
     Layout L;
     L.chunk = ch;
+    L.yzb = 0;
     int o = 0;
     L.c = o; o += d.K * d.L2;
     L.dcs = o; o += (grad && self_rows) ? 3 * d.K * d.L2 : 0;
@@ -91,11 +96,10 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     L.Y = o; o += ch * d.L2;
     L.dY = o; o += grad ? 3 * ch * d.L2 : 0;
     // the Legendre table is dead once the harmonics are staged; the
-    // per-(pair, l, k) operands of the gradient rows ({y, z_x, z_y, z_z} and
-    // {A, B}, 6 values) reuse its space, 4-element aligned for vector loads
+    // operands of the gradient rows reuse its space, 4-element aligned for
+    // vector loads
     o = (o + 3) & ~3;
     int scratch = ch * (d.nq + 2 * d.lm1);
-    int yz = (grad && rows_p) ? ch * 6 * d.lm1 * d.K : 0;   // every pair of a chunk
     L.qt = o;
     L.cre = o + ch * d.nq;
     L.cim = L.cre + ch * d.lm1;
@@ -106,7 +110,7 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     L.ynorm = o; o += d.L2;
     L.lof = o; o += d.L2;
     L.tri = o; o += (want_tri && d.KK <= kTriMax) ? d.KK : 0;
-    L.pos = o;   // dp row positions: sized by the row kernel's launcher
+    L.pos = o; o += pos;
     L.total = o;
     return L;
 }
@@ -115,16 +119,36 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
 // (four work-groups of 256 lanes per CU), else 64 KB, else 160 KB;
 // total = 0 if nothing fits.
 template <typename T>
-inline Layout choose_layout(const Dims& d, bool grad, bool rows_p, bool self_rows, bool want_tri)
+inline Layout choose_layout(const Dims& d, bool grad, bool self_rows, bool want_tri)
 {
     const size_t limits[3] = {40 * 1024, 64 * 1024, 160 * 1024};
     for (size_t lim : limits)
         for (int ch = 32; ch >= 4; ch /= 2) {
-            Layout L = make_layout(d, ch, grad, rows_p, self_rows, want_tri);
+            Layout L = make_layout(d, ch, grad, 0, self_rows, want_tri);
             if (size_t(L.total) * sizeof(T) <= lim) return L;
         }
-    Layout L = make_layout(d, 2, grad, rows_p, self_rows, want_tri);
+    Layout L = make_layout(d, 2, grad, 0, self_rows, want_tri);
     if (size_t(L.total) * sizeof(T) > 160 * 1024) L.total = 0;
+    return L;
+}
+
+// Layout of the expansion kernel that also writes the pair rows: the
+// {y, z_x, z_y, z_z} operands of yzb pairs at a time (yzb <= 8) and the dp
+// position table.  Largest chunk first, then largest batch, under the same
+// LDS limits; total = 0 if nothing fits.
+template <typename T>
+inline Layout choose_rows_layout(const Dims& d)
+{
+    const size_t limits[3] = {40 * 1024, 64 * 1024, 160 * 1024};
+    for (size_t lim : limits)
+        for (int ch = 32; ch >= 4; ch /= 2)
+            for (int yzb = ch < 8 ? ch : 8; yzb >= 1; yzb /= 2) {
+                Layout L = make_layout(d, ch, true, yzb * 4 * d.lm1 * d.K, true, false, d.lm1 * d.KK);
+                L.yzb = yzb;
+                if (size_t(L.total) * sizeof(T) <= lim) return L;
+            }
+    Layout L = make_layout(d, 2, true, 0, true, false, 0);
+    L.total = 0;
     return L;
 }
 

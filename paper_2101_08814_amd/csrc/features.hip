@@ -29,13 +29,15 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------------------
-// Per-centre pass: c, p and (with gradients) the self rows of c and p.
+// Per-centre pass: c, p and (with gradients) the self rows of c and p; with
+// ROWS also the pair rows of c and p.
 // One thread owns a species channel and an lm and accumulates every n of it
 // over the centre's pairs of that species.
 // ---------------------------------------------------------------------------
-template <typename T, int LM, bool GRAD, bool WANT_P>
+template <typename T, int LM, bool GRAD, bool WANT_P, bool ROWS>
 __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
 {
+    static_assert(!ROWS || (GRAD && WANT_P), "pair rows come with the self rows and p");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* base = reinterpret_cast<T*>(smem_raw);
     Smem<T> s(base, L);
@@ -51,10 +53,14 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
     const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
     const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
     const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
+    const int KK = d.KK, PL = lm1 * KK;
     for (int e = tid; e < KL2; e += kThreads) {
         s.c[e] = T(0);
         if (GRAD) { s.dcs[e] = T(0); s.dcs[KL2 + e] = T(0); s.dcs[2 * KL2 + e] = T(0); }
     }
+    // packed (l, k1, k2) of every position of a dp row: l | k1 << 4 | k2 << 14
+    if (ROWS)
+        for (int o = tid; o < PL; o += kThreads) s.pos[o] = a.dp_pos[o];
     // items (species, n pair, lm): two n per thread share the Y and dY loads
     const int ng = (d.nmax + 1) / 2;
     const int items = d.S * ng * d.L2;
@@ -78,18 +84,32 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
                 c0 += R0 * Yv;
                 c1 += R1 * Yv;
                 if (GRAD) {
-                    // d c_i / d r_i = -sum over pairs of [(f I~)' Y u + f I~ grad Y]
+                    // pair row d c / d r_ji = (f I~)' u Y + f I~ grad Y; the
+                    // self row is minus the sum of the rows (App. B)
                     const T* dRp = s.dR + p * d.nl + n0 * lm1 + l;
                     const T* D = s.dY + p * 3 * d.L2 + lm;
+                    const T dR0 = dRp[0], dR1 = two ? dRp[lm1] : T(0);
+                    const T al0 = s.ux[p] * Yv, al1 = s.uy[p] * Yv, al2 = s.uz[p] * Yv;
                     const T D0 = D[0], D1 = D[d.L2], D2 = D[2 * d.L2];
-                    const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
-                    const T t0 = dRp[0] * Yv, t1 = (two ? dRp[lm1] : T(0)) * Yv;
-                    a0 += t0 * ux + R0 * D0;
-                    a1 += t0 * uy + R0 * D1;
-                    a2 += t0 * uz + R0 * D2;
-                    b0 += t1 * ux + R1 * D0;
-                    b1 += t1 * uy + R1 * D1;
-                    b2 += t1 * uz + R1 * D2;
+                    const T r00 = dR0 * al0 + R0 * D0, r01 = dR0 * al1 + R0 * D1, r02 = dR0 * al2 + R0 * D2;
+                    const T r10 = dR1 * al0 + R1 * D0, r11 = dR1 * al1 + R1 * D1, r12 = dR1 * al2 + R1 * D2;
+                    a0 += r00;
+                    a1 += r01;
+                    a2 += r02;
+                    b0 += r10;
+                    b1 += r11;
+                    b2 += r12;
+                    if (ROWS) {
+                        T* dq = static_cast<T*>(a.dcoeffs) + (q0 + p) * int64_t(3 * nL2) + (n0 * d.L2 + lm);
+                        dq[0] = r00;
+                        dq[nL2] = r01;
+                        dq[2 * nL2] = r02;
+                        if (two) {
+                            dq[d.L2] = r10;
+                            dq[nL2 + d.L2] = r11;
+                            dq[2 * nL2 + d.L2] = r12;
+                        }
+                    }
                 }
             }
             s.c[e0] += c0;
@@ -121,14 +141,20 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
         for (int e = tid; e < 3 * KL2; e += kThreads) dcs_out[e] = s.dcs[e];
     }
     if (!WANT_P) return;
-    const int KK = d.KK, PL = lm1 * KK;
     const bool tri_tab = L.pos != L.tri;
     T* p_out = static_cast<T*>(a.p) + i * int64_t(PL);
     T* dps_out = GRAD ? static_cast<T*>(a.dp_self) + i * int64_t(3 * PL) : nullptr;
     int l = tid / KK, kk = tid - (tid / KK) * KK;
     for (int o = tid; o < PL; o += kThreads) {
         int k1, k2;
-        tri_pair(d, s, tri_tab, kk, k1, k2);
+        if (ROWS) {
+            const int v = s.pos[o];
+            l = v & 15;
+            k1 = (v >> 4) & 1023;
+            k2 = v >> 14;
+        } else {
+            tri_pair(d, s, tri_tab, kk, k1, k2);
+        }
         const T* c1 = s.c + k1 * d.L2 + l * l;
         const T* c2 = s.c + k2 * d.L2 + l * l;
         T acc = T(0);
@@ -145,8 +171,75 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
                 dps_out[x * PL + o] = acc2;
             }
         }
-        kk += kThreads;
-        while (kk >= KK) { kk -= KK; ++l; }
+        if (!ROWS) {
+            kk += kThreads;
+            while (kk >= KK) { kk -= KK; ++l; }
+        }
+    }
+    if (!ROWS) return;
+    // Pair rows of p (Sec. 4.G) in the reordered product rule
+    //   dp_{x,l,k1 k2} = u_x (A_{l,k1} y_{l,k2} + A_{l,k2} y_{l,k1})
+    //                    + B_{l,k1} z_{x,l,k2} + B_{l,k2} z_{x,l,k1},
+    //   y_{l,k} = sum_m Y_lm c_{k,lm},  z_{x,l,k} = sum_m dY_{x,lm} c_{k,lm},
+    //   {A, B}_{l,k} = {(f I~)'_nl, f I~_nl} for k = a_j nmax + n, else 0.
+    // The last chunk is still staged; earlier chunks are staged again.  The
+    // {y, z} operands of yzb pairs at a time go to LDS (one lane per
+    // (l, pair, k), l slowest so a wave mostly shares the length of its m
+    // loop); then one lane per dp position writes its three components.
+    V4<T>* yz4 = reinterpret_cast<V4<T>*>(s.yz);
+    const int yzb = L.yzb;
+    for (int ck = n_chunks - 1; ck >= 0; --ck) {
+        const int64_t q0 = q_begin + int64_t(ck) * chunk;
+        const int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
+        __syncthreads();
+        if (ck != n_chunks - 1) stage_chunk<T, true>(a, d, s, q0, nc);
+        for (int b0 = 0; b0 < nc; b0 += yzb) {
+            const int nb = nc - b0 < yzb ? nc - b0 : yzb;
+            if (b0 != 0) __syncthreads();
+            const int per_l = nb * d.K;
+            for (int t = tid; t < lm1 * per_l; t += kThreads) {
+                const int l2 = t / per_l, rem = t - l2 * per_l, p = rem / d.K, k = rem - p * d.K;
+                const int pp = b0 + p;
+                const T* ck_ = s.c + k * d.L2 + l2 * l2;
+                const T* Yp = s.Y + pp * d.L2 + l2 * l2;
+                const T* Dx = s.dY + (pp * 3 + 0) * d.L2 + l2 * l2;
+                const T* Dy = Dx + d.L2;
+                const T* Dz = Dy + d.L2;
+                T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
+                for (int m = 0; m < 2 * l2 + 1; ++m) {
+                    T cv = ck_[m];
+                    y += Yp[m] * cv;
+                    z0 += Dx[m] * cv;
+                    z1 += Dy[m] * cv;
+                    z2 += Dz[m] * cv;
+                }
+                yz4[(p * lm1 + l2) * d.K + k] = V4<T>{y, z0, z1, z2};
+            }
+            __syncthreads();
+            T* dp_base = static_cast<T*>(a.dp) + (q0 + b0) * int64_t(3 * PL);
+            for (int p = 0; p < nb; ++p) {
+                const int pp = b0 + p;
+                const T ux = s.ux[pp], uy = s.uy[pp], uz = s.uz[pp];
+                const int blk = s.spc[pp] * d.nmax;
+                const V4<T>* yzp = yz4 + p * lm1 * d.K;
+                const T* Rp = s.R + pp * d.nl;
+                const T* dRp = s.dR + pp * d.nl;
+                T* row = dp_base + uint32_t(p * 3 * PL);
+                for (int o = tid; o < PL; o += kThreads) {
+                    const int v = s.pos[o];
+                    const int l2 = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
+                    const V4<T> q1 = yzp[l2 * d.K + k1], q2 = yzp[l2 * d.K + k2];
+                    const int n1 = k1 - blk, n2 = k2 - blk;
+                    const bool in1 = n1 >= 0 && n1 < d.nmax, in2 = n2 >= 0 && n2 < d.nmax;
+                    const T A1 = in1 ? dRp[n1 * lm1 + l2] : T(0), B1 = in1 ? Rp[n1 * lm1 + l2] : T(0);
+                    const T A2 = in2 ? dRp[n2 * lm1 + l2] : T(0), B2 = in2 ? Rp[n2 * lm1 + l2] : T(0);
+                    const T a0 = A1 * q2.x + A2 * q1.x;
+                    row[o] = ux * a0 + B1 * q2.y + B2 * q1.y;
+                    row[PL + o] = uy * a0 + B1 * q2.z + B2 * q1.z;
+                    row[2 * PL + o] = uz * a0 + B1 * q2.w + B2 * q1.w;
+                }
+            }
+        }
     }
 }
 
@@ -279,37 +372,45 @@ hipError_t launch_feat(K kernel, size_t lds, hipStream_t stream, const FeatureAr
 constexpr size_t kMaxLds = 160 * 1024;
 
 template <typename T, int LM>
-hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, hipStream_t stream)
+hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, bool rows, hipStream_t stream)
 {
     const bool grad = a.dcoeffs_self != nullptr, want_p = a.p != nullptr;
+    if (rows) return launch_feat(k_centres<T, LM, true, true, true>, lds, stream, a, L);
     if (grad)
-        return want_p ? launch_feat(k_centres<T, LM, true, true>, lds, stream, a, L)
-                      : launch_feat(k_centres<T, LM, true, false>, lds, stream, a, L);
-    return want_p ? launch_feat(k_centres<T, LM, false, true>, lds, stream, a, L)
-                  : launch_feat(k_centres<T, LM, false, false>, lds, stream, a, L);
+        return want_p ? launch_feat(k_centres<T, LM, true, true, false>, lds, stream, a, L)
+                      : launch_feat(k_centres<T, LM, true, false, false>, lds, stream, a, L);
+    return want_p ? launch_feat(k_centres<T, LM, false, true, false>, lds, stream, a, L)
+                  : launch_feat(k_centres<T, LM, false, false, false>, lds, stream, a, L);
 }
 
 template <typename T, int LM>
 struct CentresFn {
-    static hipError_t run(const FeatureArgs& a, const Layout& L, size_t lds, hipStream_t st)
+    static hipError_t run(const FeatureArgs& a, const Layout& L, size_t lds, bool rows, hipStream_t st)
     {
-        return centres_launch<T, LM>(a, L, lds, st);
+        return centres_launch<T, LM>(a, L, lds, rows, st);
     }
 };
 
-// per-centre pass (c, p, self rows) then, if asked for, the pair rows
+// Per-centre pass (c, p, self rows).  The pair rows come from the same
+// kernel when both are asked for, the position table exists and its layout
+// fits; otherwise from the row kernel once c is in memory.
 template <typename T>
 hipError_t features_t(const FeatureArgs& a, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
     bool grad = a.dcoeffs_self != nullptr;
     bool want_p = a.p != nullptr;
-    Layout L = choose_layout<T>(d, grad, false, true, want_p);
-    if (L.total == 0) return hipErrorNotSupported;
-    size_t lds = size_t(L.total) * sizeof(T);
     FeatureArgs c = a;
     c.dp_self = want_p ? a.dp_self : nullptr;
-    hipError_t e = by_lmax<T, CentresFn>(a.lmax, c, L, lds, stream);
+    if (grad && want_p && a.dcoeffs && a.dp && a.dp_pos && a.pair_capacity > 0) {
+        Layout L = choose_rows_layout<T>(d);
+        if (L.total != 0)
+            return by_lmax<T, CentresFn>(a.lmax, c, L, size_t(L.total) * sizeof(T), true, stream);
+    }
+    Layout L = choose_layout<T>(d, grad, true, want_p);
+    if (L.total == 0) return hipErrorNotSupported;
+    size_t lds = size_t(L.total) * sizeof(T);
+    hipError_t e = by_lmax<T, CentresFn>(a.lmax, c, L, lds, false, stream);
     if (e != hipSuccess) return e;
     return launch_gradient_rows(a, std::is_same<T, double>::value, stream);
 }

@@ -157,12 +157,10 @@ hipError_t rows_t(const FeatureArgs& a, hipStream_t stream)
     const bool want_dc = a.dcoeffs != nullptr, want_dp = a.dp != nullptr;
     if (a.pair_capacity == 0 || a.n_atoms == 0 || (!want_dc && !want_dp)) return hipSuccess;
     if (want_dp && a.dp_pos == nullptr) return hipErrorNotSupported;   // K > 1023: no position table
-    Layout R = make_layout(d, kRowChunk, true, want_dp, false, false);
-    if (want_dp) {
-        // table of the (l, k1, k2) of every position of a dp row
-        R.pos = R.total;
-        R.total += (d.lmax + 1) * d.KK;
-    }
+    // {y, z} and {A, B} of every (pair, l, k) of a chunk, and the table of
+    // the (l, k1, k2) of every position of a dp row
+    Layout R = make_layout(d, kRowChunk, true, want_dp ? kRowChunk * 6 * d.lm1 * d.K : 0, false, false,
+                           want_dp ? d.lm1 * d.KK : 0);
     const size_t lds = size_t(R.total) * sizeof(T);
     if (lds > kMaxRowLds) return hipErrorNotSupported;
     // about one chunk of pairs per work-group at the mean neighbour count

@@ -206,13 +206,21 @@ def test_gradient_rows_entry_point():
     _, o_dp = calc.gradient_rows(nl, spc, c2, want_dc=False)
     assert calc.device_status() == 0
     Pn = nl.count()
-    for x, y in [(c, c2), (p, p2), (dcs, dcs2), (dps, dps2), (dc[:Pn], r_dc[:Pn]), (dp[:Pn], r_dp[:Pn]),
-                 (dc[:Pn], o_dc[:Pn]), (dp[:Pn], o_dp[:Pn])]:
-        assert torch.equal(x, y)
+    # the row kernel is the one behind soap_gradient_rows, alone or for both
+    # rows: same arithmetic, same bits
+    for name, x, y in [("dc", r_dc[:Pn], o_dc[:Pn]), ("dp", r_dp[:Pn], o_dp[:Pn])]:
+        assert torch.equal(x, y), name
+    # soap_features may write the rows from the expansion kernel, whose LDS
+    # layout stages fewer pairs at a time (partial sums rounded in another
+    # grouping) and where the compiler contracts the same products into other
+    # fused multiply-adds: equal to rounding
+    for name, x, y in [("c", c, c2), ("p", p, p2), ("dcs", dcs, dcs2), ("dps", dps, dps2), ("dc", dc[:Pn], r_dc[:Pn]),
+                       ("dp", dp[:Pn], r_dp[:Pn])]:
+        assert rel(x.double().cpu().numpy(), y.double().cpu().numpy()) <= 1e-6, name
     ref_nl = oracle.neighbors(b)
     rdc, rdcs, rdp, rdps = oracle.gradients(hyp, b.species, ref_nl)
-    assert rel(r_dc[:Pn].double().cpu().numpy(), rdc) <= 1e-5
-    assert rel(r_dp[:Pn].double().cpu().numpy(), rdp) <= 1e-5
+    for x, y in [(r_dc[:Pn], rdc), (r_dp[:Pn], rdp), (dc[:Pn], rdc), (dp[:Pn], rdp), (dcs, rdcs), (dps, rdps)]:
+        assert rel(x.double().cpu().numpy(), y) <= 1e-5
 
 
 def test_molecules_bf16_mfma_power_spectrum():
