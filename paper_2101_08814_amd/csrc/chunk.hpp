@@ -28,6 +28,7 @@ namespace dev {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kTriMax = 8192;    // largest K (K+1)/2 kept as an LDS table
+constexpr int kSplineBatch = 4;  // spline coefficient loads a lane keeps in flight
 
 // Kernels are instantiated with the degree lmax as a template parameter LM
 // (0..12) for float; LM = -1 takes lmax at run time.
@@ -68,7 +69,6 @@ __host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
 // LDS layout in elements of T (ints occupy T-sized slots).
 struct Layout {
     int chunk;                          // pairs per staged chunk
-    int yzb;                            // pairs per batch of gradient-row operands
     int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, pos, total;
 };
 
@@ -80,7 +80,6 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
 {
     Layout L;
     L.chunk = ch;
-    L.yzb = 0;
     int o = 0;
     L.c = o; o += d.K * d.L2;
     L.dcs = o; o += (grad && self_rows) ? 3 * d.K * d.L2 : 0;
@@ -132,21 +131,19 @@ inline Layout choose_layout(const Dims& d, bool grad, bool self_rows, bool want_
     return L;
 }
 
-// Layout of the expansion kernel that also writes the pair rows: the
-// {y, z_x, z_y, z_z} operands of yzb pairs at a time (yzb <= 8) and the dp
-// position table.  Largest chunk first, then largest batch, under the same
-// LDS limits; total = 0 if nothing fits.
+// Layout of the expansion kernel that also writes the pair rows: one
+// buffer of {y, z_x, z_y, z_z} operands per wave and the dp position table.
+// Largest chunk first under the same LDS limits; total = 0 if nothing fits.
 template <typename T>
 inline Layout choose_rows_layout(const Dims& d)
 {
     const size_t limits[3] = {40 * 1024, 64 * 1024, 160 * 1024};
+    const int yz = kWaves * 4 * d.lm1 * d.K;
     for (size_t lim : limits)
-        for (int ch = 32; ch >= 4; ch /= 2)
-            for (int yzb = ch < 8 ? ch : 8; yzb >= 1; yzb /= 2) {
-                Layout L = make_layout(d, ch, true, yzb * 4 * d.lm1 * d.K, true, false, d.lm1 * d.KK);
-                L.yzb = yzb;
-                if (size_t(L.total) * sizeof(T) <= lim) return L;
-            }
+        for (int ch = 32; ch >= 4; ch /= 2) {
+            Layout L = make_layout(d, ch, true, yz, true, false, d.lm1 * d.KK);
+            if (size_t(L.total) * sizeof(T) <= lim) return L;
+        }
     Layout L = make_layout(d, 2, true, 0, true, false, 0);
     L.total = 0;
     return L;
@@ -252,14 +249,35 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
         s.seg[2 * sp] = lo;
         s.seg[2 * sp + 1] = hi;
     }
-    // radial spline: one lane per (pair, n, l)
-    const T* coef = static_cast<const T*>(a.coef);
-    for (int t = tid; t < nc * d.nl; t += kThreads) {
-        int p = t / d.nl, j = t - p * d.nl;
-        T v, dv;
-        spline_eval<T>(coef, a.M, T(a.inv_delta), d.nl, j, s.r[p], v, dv);
-        s.R[p * d.nl + j] = s.f[p] * v;
-        if (GRAD) s.dR[p * d.nl + j] = s.df[p] * v + s.f[p] * dv;
+    // radial spline: one lane per (pair, n, l); a lane issues the
+    // coefficient loads of up to kSplineBatch of its items before using any
+    const V4<T>* coef = static_cast<const V4<T>*>(a.coef);
+    const T inv_delta = T(a.inv_delta);
+    const int n_items = nc * d.nl;
+    for (int t0 = tid; t0 < n_items; t0 += kSplineBatch * kThreads) {
+        V4<T> cf[kSplineBatch];
+        T tt[kSplineBatch];
+#pragma unroll
+        for (int u = 0; u < kSplineBatch; ++u) {
+            const int t = t0 + u * kThreads;
+            if (t < n_items) {
+                const int p = t / d.nl, j = t - p * d.nl;
+                int64_t k;
+                spline_locate<T>(a.M, inv_delta, s.r[p], k, tt[u]);
+                cf[u] = coef[k * d.nl + j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSplineBatch; ++u) {
+            const int t = t0 + u * kThreads;
+            if (t < n_items) {
+                const int p = t / d.nl;
+                T v, dv;
+                spline_poly<T>(cf[u].x, cf[u].y, cf[u].z, cf[u].w, tt[u], inv_delta, v, dv);
+                s.R[t] = s.f[p] * v;
+                if (GRAD) s.dR[t] = s.df[p] * v + s.f[p] * dv;
+            }
+        }
     }
     __syncthreads();
     // harmonics and gradients: one lane per (pair, lm)

@@ -44,13 +44,14 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
     const Dims d = make_dims(a.S, a.nmax, lmax_of(a, LM));
     const int tid = threadIdx.x;
     const int64_t i = blockIdx.x;
-    if (a.pair_offsets[a.n_atoms] > a.pair_capacity) {
+    const int64_t q_total = a.pair_offsets[a.n_atoms];
+    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
+    if (q_total > a.pair_capacity) {
         if (tid == 0) put_status(a.status, SOAP_ECAPACITY);
         return;
     }
     const int chunk = L.chunk;
     init_tables<T>(a, d, L, s);
-    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
     const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
     const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
     const int KK = d.KK, PL = lm1 * KK;
@@ -182,63 +183,57 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
     //                    + B_{l,k1} z_{x,l,k2} + B_{l,k2} z_{x,l,k1},
     //   y_{l,k} = sum_m Y_lm c_{k,lm},  z_{x,l,k} = sum_m dY_{x,lm} c_{k,lm},
     //   {A, B}_{l,k} = {(f I~)'_nl, f I~_nl} for k = a_j nmax + n, else 0.
-    // The last chunk is still staged; earlier chunks are staged again.  The
-    // {y, z} operands of yzb pairs at a time go to LDS (one lane per
-    // (l, pair, k), l slowest so a wave mostly shares the length of its m
-    // loop); then one lane per dp position writes its three components.
-    V4<T>* yz4 = reinterpret_cast<V4<T>*>(s.yz);
-    const int yzb = L.yzb;
+    // The last chunk is still staged; earlier chunks are staged again.  Each
+    // wave takes whole pairs: its lanes put the {y, z} of every (l, k) of the
+    // pair in the wave's own LDS buffer, then one lane per dp position writes
+    // its three components; waves synchronise only with themselves.
+    const int wave = tid >> 6, lane = tid & 63;
+    const int nlk = lm1 * d.K;
+    V4<T>* yzw = reinterpret_cast<V4<T>*>(s.yz) + wave * nlk;
     for (int ck = n_chunks - 1; ck >= 0; --ck) {
         const int64_t q0 = q_begin + int64_t(ck) * chunk;
         const int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
         __syncthreads();
         if (ck != n_chunks - 1) stage_chunk<T, true>(a, d, s, q0, nc);
-        for (int b0 = 0; b0 < nc; b0 += yzb) {
-            const int nb = nc - b0 < yzb ? nc - b0 : yzb;
-            if (b0 != 0) __syncthreads();
-            const int per_l = nb * d.K;
-            for (int t = tid; t < lm1 * per_l; t += kThreads) {
-                const int l2 = t / per_l, rem = t - l2 * per_l, p = rem / d.K, k = rem - p * d.K;
-                const int pp = b0 + p;
-                const T* ck_ = s.c + k * d.L2 + l2 * l2;
-                const T* Yp = s.Y + pp * d.L2 + l2 * l2;
-                const T* Dx = s.dY + (pp * 3 + 0) * d.L2 + l2 * l2;
-                const T* Dy = Dx + d.L2;
-                const T* Dz = Dy + d.L2;
+        for (int p = wave; p < nc; p += kWaves) {
+            const T* Yp = s.Y + p * d.L2;
+            const T* Dx = s.dY + (p * 3 + 0) * d.L2;
+            const T* Dy = Dx + d.L2;
+            const T* Dz = Dy + d.L2;
+            for (int t = lane; t < nlk; t += 64) {
+                const int l2 = t / d.K, k = t - l2 * d.K;
+                const int m0 = l2 * l2;
+                const T* ck_ = s.c + k * d.L2;
                 T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
-                for (int m = 0; m < 2 * l2 + 1; ++m) {
+                for (int m = m0; m < m0 + 2 * l2 + 1; ++m) {
                     T cv = ck_[m];
                     y += Yp[m] * cv;
                     z0 += Dx[m] * cv;
                     z1 += Dy[m] * cv;
                     z2 += Dz[m] * cv;
                 }
-                yz4[(p * lm1 + l2) * d.K + k] = V4<T>{y, z0, z1, z2};
+                yzw[t] = V4<T>{y, z0, z1, z2};
             }
-            __syncthreads();
-            T* dp_base = static_cast<T*>(a.dp) + (q0 + b0) * int64_t(3 * PL);
-            for (int p = 0; p < nb; ++p) {
-                const int pp = b0 + p;
-                const T ux = s.ux[pp], uy = s.uy[pp], uz = s.uz[pp];
-                const int blk = s.spc[pp] * d.nmax;
-                const V4<T>* yzp = yz4 + p * lm1 * d.K;
-                const T* Rp = s.R + pp * d.nl;
-                const T* dRp = s.dR + pp * d.nl;
-                T* row = dp_base + uint32_t(p * 3 * PL);
-                for (int o = tid; o < PL; o += kThreads) {
-                    const int v = s.pos[o];
-                    const int l2 = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
-                    const V4<T> q1 = yzp[l2 * d.K + k1], q2 = yzp[l2 * d.K + k2];
-                    const int n1 = k1 - blk, n2 = k2 - blk;
-                    const bool in1 = n1 >= 0 && n1 < d.nmax, in2 = n2 >= 0 && n2 < d.nmax;
-                    const T A1 = in1 ? dRp[n1 * lm1 + l2] : T(0), B1 = in1 ? Rp[n1 * lm1 + l2] : T(0);
-                    const T A2 = in2 ? dRp[n2 * lm1 + l2] : T(0), B2 = in2 ? Rp[n2 * lm1 + l2] : T(0);
-                    const T a0 = A1 * q2.x + A2 * q1.x;
-                    row[o] = ux * a0 + B1 * q2.y + B2 * q1.y;
-                    row[PL + o] = uy * a0 + B1 * q2.z + B2 * q1.z;
-                    row[2 * PL + o] = uz * a0 + B1 * q2.w + B2 * q1.w;
-                }
+            wave_sync();
+            const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
+            const int blk = s.spc[p] * d.nmax;
+            const T* Rp = s.R + p * d.nl;
+            const T* dRp = s.dR + p * d.nl;
+            T* row = static_cast<T*>(a.dp) + (q0 + p) * int64_t(3 * PL);
+            for (int o = lane; o < PL; o += 64) {
+                const int v = s.pos[o];
+                const int l2 = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
+                const V4<T> q1 = yzw[l2 * d.K + k1], q2 = yzw[l2 * d.K + k2];
+                const int n1 = k1 - blk, n2 = k2 - blk;
+                const bool in1 = n1 >= 0 && n1 < d.nmax, in2 = n2 >= 0 && n2 < d.nmax;
+                const T A1 = in1 ? dRp[n1 * lm1 + l2] : T(0), B1 = in1 ? Rp[n1 * lm1 + l2] : T(0);
+                const T A2 = in2 ? dRp[n2 * lm1 + l2] : T(0), B2 = in2 ? Rp[n2 * lm1 + l2] : T(0);
+                const T a0 = A1 * q2.x + A2 * q1.x;
+                row[o] = ux * a0 + B1 * q2.y + B2 * q1.y;
+                row[PL + o] = uy * a0 + B1 * q2.z + B2 * q1.z;
+                row[2 * PL + o] = uz * a0 + B1 * q2.w + B2 * q1.w;
             }
+            wave_sync();
         }
     }
 }

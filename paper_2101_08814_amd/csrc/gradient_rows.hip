@@ -42,11 +42,12 @@ __global__ void __launch_bounds__(kThreads) k_pair_rows(FeatureArgs a, Layout L)
     const Dims d = make_dims(a.S, a.nmax, lmax_of(a, LM));
     const int tid = threadIdx.x;
     const int64_t i = blockIdx.x;
-    if (a.pair_offsets[a.n_atoms] > a.pair_capacity) {
+    const int64_t q_total = a.pair_offsets[a.n_atoms];
+    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
+    if (q_total > a.pair_capacity) {
         if (tid == 0) put_status(a.status, SOAP_ECAPACITY);
         return;
     }
-    const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
     const int n_pairs = int(q_end - q_begin);
     const int G = gridDim.y, g = blockIdx.y;
     const int share = (n_pairs + G - 1) / G;

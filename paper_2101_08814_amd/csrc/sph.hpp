@@ -121,21 +121,37 @@ __device__ __forceinline__ void ylm_and_grad(int lm, int l, T K, const T* qt, co
     gz = (zz - lz * uz) * rinv;
 }
 
-// Splined orthogonalised radial integral and its r-derivative for one
-// (n, l) channel: the interval's cubic a0 + t (a1 + t (a2 + t a3)).
+// Interval k of the radial spline that holds r and the local coordinate
+// t = r / delta - k in [0, 1] (clamped to the table).
 template <typename T>
-__device__ __forceinline__ void spline_eval(const T* coef, int64_t M, T inv_delta, int nl, int j, T r, T& v, T& dv)
+__device__ __forceinline__ void spline_locate(int64_t M, T inv_delta, T r, int64_t& k, T& t)
 {
     T x = r * inv_delta;
     T xmax = T(M) - T(0.5);
-    int64_t k = int64_t(x < xmax ? x : xmax);
+    k = int64_t(x < xmax ? x : xmax);
     if (k < 0) k = 0;
     if (k > M - 1) k = M - 1;
-    T t = x - T(k);
-    const T* cf = coef + (k * nl + j) * 4;
-    T a0 = cf[0], a1 = cf[1], a2 = cf[2], a3 = cf[3];
+    t = x - T(k);
+}
+
+// Value and r-derivative of the interval's cubic a0 + t (a1 + t (a2 + t a3)).
+template <typename T>
+__device__ __forceinline__ void spline_poly(T a0, T a1, T a2, T a3, T t, T inv_delta, T& v, T& dv)
+{
     v = a0 + t * (a1 + t * (a2 + t * a3));
     dv = (a1 + t * (T(2) * a2 + T(3) * t * a3)) * inv_delta;
+}
+
+// Splined orthogonalised radial integral and its r-derivative for one
+// (n, l) channel j (table [M][nl][4]).
+template <typename T>
+__device__ __forceinline__ void spline_eval(const T* coef, int64_t M, T inv_delta, int nl, int j, T r, T& v, T& dv)
+{
+    int64_t k;
+    T t;
+    spline_locate<T>(M, inv_delta, r, k, t);
+    const T* cf = coef + (k * nl + j) * 4;
+    spline_poly<T>(cf[0], cf[1], cf[2], cf[3], t, inv_delta, v, dv);
 }
 
 // Packed upper-triangle index -> (k1, k2), k1 <= k2 < K.
