@@ -22,6 +22,8 @@
 // pair vectors formed in double from the positions.  Optionally the index
 // of the reverse pair (j, i, -s).  The bin contents may be in any order; the
 // sorted output does not depend on it, so the list is deterministic.
+#include <type_traits>
+
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -183,11 +185,12 @@ __device__ bool geometry_block(const NeighborArgs& a)
     return ok;
 }
 
-// wrap t and bin of atom i in structure s with geometry g (written to the
-// workspace), and its position wrapped into the cell, w = r - t.H
-__device__ int32_t place_atom(const NeighborArgs& a, int64_t i, int s, const StructGeom& g, double4& w)
+// wrap t and bin of atom i (position r, species sp) in structure s with
+// geometry g (written to the workspace), and its position wrapped into the
+// cell, w = r - t.H
+__device__ int32_t place_atom(const NeighborArgs& a, int64_t i, int s, const StructGeom& g, const double* r, int sp,
+                              double4& w)
 {
-    double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
     int b[3], t[3];
     for (int k = 0; k < 3; ++k) {
         if (!g.pbc[k]) { b[k] = 0; t[k] = 0; continue; }
@@ -203,7 +206,6 @@ __device__ int32_t place_atom(const NeighborArgs& a, int64_t i, int s, const Str
     a.atom_wrap[3 * i + 0] = t[0];
     a.atom_wrap[3 * i + 1] = t[1];
     a.atom_wrap[3 * i + 2] = t[2];
-    int sp = a.species[i];
     if (sp < 0 || sp >= a.n_species) put_status(a.status, SOAP_ESPECIES);
     w.x = r[0] - (t[0] * g.H[0] + t[1] * g.H[3] + t[2] * g.H[6]);
     w.y = r[1] - (t[0] * g.H[1] + t[1] * g.H[4] + t[2] * g.H[7]);
@@ -227,8 +229,9 @@ __device__ __forceinline__ int structure_of(const StructGeom* geom, int n, int64
 __device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
 {
     const int s = structure_of(a.geom, a.n_structures, i);
+    const double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
     double4 w;
-    return place_atom(a, i, s, a.geom[s], w);
+    return place_atom(a, i, s, a.geom[s], r, a.species[i], w);
 }
 
 // Record of atom i for its bin slot: the position wrapped into the cell,
@@ -275,7 +278,8 @@ __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
         const int64_t i = t + 1024 * int64_t(u);
         if (i < a.n_atoms) {
             const int s = structure_of(geom, ns, i);
-            bin_of[u] = place_atom(a, i, s, geom[s], w_of[u]);
+            const double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
+            bin_of[u] = place_atom(a, i, s, geom[s], r, a.species[i], w_of[u]);
             atomicAdd(&cnt[bin_of[u]], 1);
         }
     }
@@ -363,24 +367,56 @@ __device__ __forceinline__ void wave_fence()
 }
 
 // All candidates of centre i, 64 per round, kRounds rounds at a time with
-// their slot loads issued together: emit(hit, j, c0, c1, c2) is called by
-// every lane for every round (hit false for lanes with nothing), with the
-// cell shift c of the stencil bin the candidate was found in.
+// their slot loads issued together: emit(hit, j, c0, c1, c2, v) is called
+// by every lane for every round (hit false for lanes with nothing), with
+// the cell shift c of the stencil bin the candidate was found in and, for a
+// hit, the pair vector v = (w_j - w_i) + c.H (= r_j - r_i + s.H for the
+// image shift s = c + t_i - t_j).
 constexpr int kRounds = 4;
 
+// Centre i as the enumeration sees it, loaded before the validity flag is
+// looked at: every address read here is in bounds whatever the flag says
+// (with one structure the geometry is structure 0; otherwise it is read
+// only once the flag is known), so the loads go out together.
+struct Centre {
+    int ok;
+    int32_t bin;
+    double4 wi;          // position wrapped into the cell, w = r - t.H
+    int t[3];            // integer wrap
+    const StructGeom* g;
+};
+
+template <bool ONE>
+__device__ __forceinline__ Centre load_centre(const NeighborArgs& a, int64_t i)
+{
+    Centre c;
+    c.ok = *a.ok;
+    const int32_t s = ONE ? 0 : a.atom_struct[i];
+    c.bin = a.atom_bin[i];
+    for (int k = 0; k < 3; ++k) c.t[k] = a.atom_wrap[3 * i + k];
+    const double r0 = a.positions[3 * i], r1 = a.positions[3 * i + 1], r2 = a.positions[3 * i + 2];
+    c.g = a.geom + (ONE ? 0 : (c.ok ? s : 0));
+    const StructGeom& g = *c.g;
+    c.wi.x = r0 - (c.t[0] * g.H[0] + c.t[1] * g.H[3] + c.t[2] * g.H[6]);
+    c.wi.y = r1 - (c.t[0] * g.H[1] + c.t[1] * g.H[4] + c.t[2] * g.H[7]);
+    c.wi.z = r2 - (c.t[0] * g.H[2] + c.t[1] * g.H[5] + c.t[2] * g.H[8]);
+    c.wi.w = __longlong_as_double((long long)i);
+    return c;
+}
+
 template <class F>
-__device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&& emit)
+__device__ void wave_visit(const NeighborArgs& a, int64_t i, const Centre& ce, WaveScratch& w, F&& emit)
 {
     const int lane = threadIdx.x & 63;
-    const StructGeom& g = a.geom[a.atom_struct[i]];
-    const int local = a.atom_bin[i] - int32_t(g.bin_lo);
+    const StructGeom& g = *ce.g;
+    const int local = ce.bin - int32_t(g.bin_lo);
     const int bz = local % g.nbin[2];
     const int by = (local / g.nbin[2]) % g.nbin[1];
     const int bx = local / (g.nbin[2] * g.nbin[1]);
-    const double4 wi = make_slot(a, i);
+    const double4 wi = ce.wi;
     const double rc2 = a.rcut * a.rcut;
     const int n0 = 2 * g.reach[0] + 1, n1 = 2 * g.reach[1] + 1, n2 = 2 * g.reach[2] + 1;
-    const int nst = n0 * n1 * n2;
+    const int nst = ce.ok ? n0 * n1 * n2 : 0;   // nothing is visited on invalid input
     for (int base = 0; base < nst; base += 64) {
         int sb = base + lane;
         int size = 0, start = 0, cs = 0;
@@ -422,6 +458,7 @@ __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&&
                 const int t = t0 + 64 * r + lane;
                 bool hit = false;
                 int j = 0, c0 = 0, c1 = 0, c2 = 0;
+                double vx = 0.0, vy = 0.0, vz = 0.0;
                 if (t < total) {
                     j = int(__double_as_longlong(rec[r].w));
                     const int cs2 = w.cshift[bin_of[r]];
@@ -429,9 +466,9 @@ __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&&
                     c1 = ((cs2 >> 10) & 1023) - 512;
                     c2 = ((cs2 >> 20) & 1023) - 512;
                     if (!(j == i && c0 == 0 && c1 == 0 && c2 == 0)) {
-                        double vx = (rec[r].x - wi.x) + c0 * g.H[0] + c1 * g.H[3] + c2 * g.H[6];
-                        double vy = (rec[r].y - wi.y) + c0 * g.H[1] + c1 * g.H[4] + c2 * g.H[7];
-                        double vz = (rec[r].z - wi.z) + c0 * g.H[2] + c1 * g.H[5] + c2 * g.H[8];
+                        vx = (rec[r].x - wi.x) + c0 * g.H[0] + c1 * g.H[3] + c2 * g.H[6];
+                        vy = (rec[r].y - wi.y) + c0 * g.H[1] + c1 * g.H[4] + c2 * g.H[7];
+                        vz = (rec[r].z - wi.z) + c0 * g.H[2] + c1 * g.H[5] + c2 * g.H[8];
                         double r2 = vx * vx + vy * vy + vz * vz;
                         if (r2 < rc2) {
                             if (r2 == 0.0) put_status(a.status, SOAP_EGEOMETRY);
@@ -439,7 +476,7 @@ __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&&
                         }
                     }
                 }
-                emit(hit, j, c0, c1, c2);
+                emit(hit, j, c0, c1, c2, vx, vy, vz);
             }
         }
         wave_fence();
@@ -447,12 +484,14 @@ __device__ void wave_visit(const NeighborArgs& a, int64_t i, WaveScratch& w, F&&
 }
 
 // one wave (block of 64) per centre
+template <bool ONE>
 __global__ void __launch_bounds__(64) k_count(NeighborArgs a)
 {
     __shared__ WaveScratch w;
     const int64_t i = blockIdx.x;
+    const Centre ce = load_centre<ONE>(a, i);
     int n = 0;
-    if (*a.ok) wave_visit(a, i, w, [&](bool hit, int, int, int, int) { n += hit ? 1 : 0; });
+    wave_visit(a, i, ce, w, [&](bool hit, int, int, int, int, double, double, double) { n += hit ? 1 : 0; });
     for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
     if (threadIdx.x == 0) a.centre_count[i] = n;
 }
@@ -486,42 +525,47 @@ __device__ __forceinline__ void write_pair(const NeighborArgs& a, const StructGe
     }
 }
 
-// image shift of a candidate j of centre i seen with cell shift c
-__device__ __forceinline__ void image_shift(const NeighborArgs& a, const StructGeom& g, int64_t i, int j, int c0,
+// image shift of a candidate j of centre i (wrap ti) seen with cell shift c
+__device__ __forceinline__ void image_shift(const NeighborArgs& a, const StructGeom& g, const int* ti, int j, int c0,
                                             int c1, int c2, int& s0, int& s1, int& s2)
 {
-    s0 = g.pbc[0] ? c0 + a.atom_wrap[3 * i] - a.atom_wrap[3 * j] : 0;
-    s1 = g.pbc[1] ? c1 + a.atom_wrap[3 * i + 1] - a.atom_wrap[3 * j + 1] : 0;
-    s2 = g.pbc[2] ? c2 + a.atom_wrap[3 * i + 2] - a.atom_wrap[3 * j + 2] : 0;
+    s0 = g.pbc[0] ? c0 + ti[0] - a.atom_wrap[3 * j] : 0;
+    s1 = g.pbc[1] ? c1 + ti[1] - a.atom_wrap[3 * j + 1] : 0;
+    s2 = g.pbc[2] ? c2 + ti[2] - a.atom_wrap[3 * j + 2] : 0;
 }
 
-// one wave per centre: enumerate again (hits compacted in LDS), form the
-// image shifts and sort keys of all hits at once, rank them by key in LDS
-// and write them sorted
-template <bool F64>
+// one wave per centre: enumerate again (hits compacted in LDS with their
+// pair vectors), form the image shifts and sort keys of all hits at once,
+// rank them by key in LDS and write them sorted
+template <bool ONE, bool F64>
 __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
 {
+    using VT = typename std::conditional<F64, double, float>::type;
     __shared__ WaveScratch w;
     __shared__ int64_t khi[kSortCap], klo[kSortCap];
     __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
+    __shared__ VT kv[3 * kSortCap];
     const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
-    if (!*a.ok || a.pair_offsets[a.n_atoms] > a.capacity) return;
+    const int64_t total = a.pair_offsets[a.n_atoms];
     const int64_t o0 = a.pair_offsets[i];
     const int n = int(a.pair_offsets[i + 1] - o0);
+    const Centre ce = load_centre<ONE>(a, i);
+    if (!ce.ok || total > a.capacity) return;
     const bool in_lds = n <= kSortCap;
-    const StructGeom& g = a.geom[a.atom_struct[i]];
+    const StructGeom& g = *ce.g;
     int count = 0;
-    wave_visit(a, i, w, [&](bool hit, int j, int c0, int c1, int c2) {
+    wave_visit(a, i, ce, w, [&](bool hit, int j, int c0, int c1, int c2, double vx, double vy, double vz) {
         uint64_t mask = __ballot(hit);
         int idx = count + __popcll(mask & ((uint64_t(1) << lane) - 1));
         if (hit && idx < n) {
             if (in_lds) {
                 kj[idx] = j;
                 ks[3 * idx] = c0; ks[3 * idx + 1] = c1; ks[3 * idx + 2] = c2;
+                kv[3 * idx] = VT(vx); kv[3 * idx + 1] = VT(vy); kv[3 * idx + 2] = VT(vz);
             } else {
                 int s0, s1, s2;
-                image_shift(a, g, i, j, c0, c1, c2, s0, s1, s2);
+                image_shift(a, g, ce.t, j, c0, c1, c2, s0, s1, s2);
                 a.pair_j[o0 + idx] = j;
                 a.pair_shift[3 * (o0 + idx)] = s0;
                 a.pair_shift[3 * (o0 + idx) + 1] = s1;
@@ -535,16 +579,24 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
         for (int p = lane; p < n; p += 64) {
             const int j = kj[p];
             int s0, s1, s2;
-            image_shift(a, g, i, j, ks[3 * p], ks[3 * p + 1], ks[3 * p + 2], s0, s1, s2);
+            image_shift(a, g, ce.t, j, ks[3 * p], ks[3 * p + 1], ks[3 * p + 2], s0, s1, s2);
             ks[3 * p] = s0; ks[3 * p + 1] = s1; ks[3 * p + 2] = s2;
             make_key(a.species[j], j, s0, s1, s2, khi[p], klo[p]);
         }
         __syncthreads();
+        VT* vec = static_cast<VT*>(a.pair_vec);
         for (int p = lane; p < n; p += 64) {
             int64_t h = khi[p], l = klo[p];
             int rank = 0;
             for (int q = 0; q < n; ++q) rank += key_less(khi[q], klo[q], h, l) ? 1 : 0;
-            write_pair<F64>(a, g, i, o0 + rank, kj[p], ks[3 * p], ks[3 * p + 1], ks[3 * p + 2]);
+            const int64_t q = o0 + rank;
+            a.pair_j[q] = kj[p];
+            a.pair_shift[3 * q] = ks[3 * p];
+            a.pair_shift[3 * q + 1] = ks[3 * p + 1];
+            a.pair_shift[3 * q + 2] = ks[3 * p + 2];
+            vec[3 * q] = kv[3 * p];
+            vec[3 * q + 1] = kv[3 * p + 1];
+            vec[3 * q + 2] = kv[3 * p + 2];
         }
         return;
     }
@@ -624,7 +676,8 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
                            a.centre_count, a.pair_offsets, (int64_t*)nullptr, int64_t(0), a.capacity, a.status);
         return hipGetLastError();
     }
-    if (B <= kSmallBins && N <= kSmallAtoms) {
+    const bool small = B <= kSmallBins && N <= kSmallAtoms;
+    if (small) {
         hipLaunchKernelGGL(k_bins_small, dim3(1), dim3(1024), 0, stream, a);
     } else {
         hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
@@ -634,14 +687,20 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
                            a.bin_start, a.bin_cursor, B, int64_t(-1), a.status);
         hipLaunchKernelGGL(k_bins, dim3(blocks(N, T)), dim3(T), 0, stream, a);
     }
-    hipLaunchKernelGGL(k_count, dim3(unsigned(N)), dim3(64), 0, stream, a);
+    const bool one = a.n_structures == 1;
+    const dim3 grid{unsigned(N)}, wave{64};
+    if (one) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count<true>), grid, wave, 0, stream, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count<false>), grid, wave, 0, stream, a);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream, a.centre_count,
                        a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.status);
     if (a.capacity > 0) {
-        if (a.vec_f64)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<true>), dim3(unsigned(N)), dim3(64), 0, stream, a);
-        else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<false>), dim3(unsigned(N)), dim3(64), 0, stream, a);
+        if (a.vec_f64) {
+            if (one) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<true, true>), grid, wave, 0, stream, a);
+            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<false, true>), grid, wave, 0, stream, a);
+        } else {
+            if (one) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<true, false>), grid, wave, 0, stream, a);
+            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<false, false>), grid, wave, 0, stream, a);
+        }
         if (a.pair_transpose)
             hipLaunchKernelGGL(k_transpose, dim3(blocks(a.capacity, T)), dim3(T), 0, stream, a);
     }
