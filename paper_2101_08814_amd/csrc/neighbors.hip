@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kSmallBins = 8192;   // single-work-group bin build up to this many bins
 constexpr int kSmallAtoms = 8192;  // ... and this many atoms
+constexpr int kPrefixAtoms = 2048; // fill kernel sums the counts itself up to this many atoms
 constexpr int kSortCap = 512;      // pairs per centre ranked in LDS
 
 __device__ __forceinline__ void put_status(int32_t* st, int v)
@@ -536,8 +537,10 @@ __device__ __forceinline__ void image_shift(const NeighborArgs& a, const StructG
 
 // one wave per centre: enumerate again (hits compacted in LDS with their
 // pair vectors), form the image shifts and sort keys of all hits at once,
-// rank them by key in LDS and write them sorted
-template <bool ONE, bool F64>
+// rank them by key in LDS and write them sorted.  With PREFIX (small
+// systems) the wave also sums the counts before its centre and all counts
+// itself and writes its pair_offsets entry, in place of a separate scan.
+template <bool ONE, bool F64, bool PREFIX>
 __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
 {
     using VT = typename std::conditional<F64, double, float>::type;
@@ -547,9 +550,42 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
     __shared__ VT kv[3 * kSortCap];
     const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
-    const int64_t total = a.pair_offsets[a.n_atoms];
-    const int64_t o0 = a.pair_offsets[i];
-    const int n = int(a.pair_offsets[i + 1] - o0);
+    int64_t total, o0;
+    int n;
+    if (PREFIX) {
+        // all loads in flight at once (N <= kPrefixAtoms)
+        constexpr int R = kPrefixAtoms / 64;
+        int64_t c[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t k = lane + 64 * r;
+            c[r] = k < a.n_atoms ? a.centre_count[k] : 0;
+        }
+        n = int(a.centre_count[i]);
+        int64_t before = 0, all = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            all += c[r];
+            before += lane + 64 * r < i ? c[r] : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            before += __shfl_xor(before, off, 64);
+            all += __shfl_xor(all, off, 64);
+        }
+        o0 = before;
+        total = all;
+        if (lane == 0) {
+            a.pair_offsets[i] = o0;
+            if (i == a.n_atoms - 1) {
+                a.pair_offsets[a.n_atoms] = total;
+                if (total > a.capacity) put_status(a.status, SOAP_ECAPACITY);
+            }
+        }
+    } else {
+        total = a.pair_offsets[a.n_atoms];
+        o0 = a.pair_offsets[i];
+        n = int(a.pair_offsets[i + 1] - o0);
+    }
     const Centre ce = load_centre<ONE>(a, i);
     if (!ce.ok || total > a.capacity) return;
     const bool in_lds = n <= kSortCap;
@@ -691,16 +727,23 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
     const dim3 grid{unsigned(N)}, wave{64};
     if (one) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count<true>), grid, wave, 0, stream, a);
     else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count<false>), grid, wave, 0, stream, a);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream, a.centre_count,
-                       a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.status);
+    // small systems with pairs to write: the fill kernel forms the offsets;
+    // otherwise a scan (which also reports the count when capacity is 0)
+    const bool prefix = N <= kPrefixAtoms && a.capacity > 0;
+    if (!prefix)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream, a.centre_count,
+                           a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.status);
     if (a.capacity > 0) {
-        if (a.vec_f64) {
-            if (one) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<true, true>), grid, wave, 0, stream, a);
-            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<false, true>), grid, wave, 0, stream, a);
+#define SOAP_FILL(ONE_, F64_, PRE_) \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<ONE_, F64_, PRE_>), grid, wave, 0, stream, a)
+        if (prefix) {
+            if (a.vec_f64) { if (one) SOAP_FILL(true, true, true); else SOAP_FILL(false, true, true); }
+            else { if (one) SOAP_FILL(true, false, true); else SOAP_FILL(false, false, true); }
         } else {
-            if (one) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<true, false>), grid, wave, 0, stream, a);
-            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<false, false>), grid, wave, 0, stream, a);
+            if (a.vec_f64) { if (one) SOAP_FILL(true, true, false); else SOAP_FILL(false, true, false); }
+            else { if (one) SOAP_FILL(true, false, false); else SOAP_FILL(false, false, false); }
         }
+#undef SOAP_FILL
         if (a.pair_transpose)
             hipLaunchKernelGGL(k_transpose, dim3(blocks(a.capacity, T)), dim3(T), 0, stream, a);
     }
