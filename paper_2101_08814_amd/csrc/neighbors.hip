@@ -153,28 +153,37 @@ __device__ Tout block_scan(const Tin* in, Tout* out, Tout* out2, int64_t n)
 }
 
 // Geometry of every structure (one block of 1024 threads).  Returns true in
-// every thread when the input is valid; writes *a.ok.
-__device__ bool geometry_block(const NeighborArgs& a)
+// every thread when the input is valid; writes *a.ok.  The first cache_n
+// structures are also written to the LDS array cache (bin_lo included).
+__device__ bool geometry_block(const NeighborArgs& a, StructGeom* cache = nullptr, int cache_n = 0)
 {
     __shared__ int bad;
     const int t = threadIdx.x;
-    if (t == 0) bad = (a.atom_offsets[0] != 0 || a.atom_offsets[a.n_structures] != a.n_atoms) ? 1 : 0;
+    if (t == 0) bad = 0;
     __syncthreads();
     const int64_t n = a.n_structures;
     const int64_t chunk = (n + 1023) / 1024;
     const int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
     int64_t sum = 0;
+    bool mine_bad = false;
     for (int64_t s = b; s < e; ++s) {
         StructGeom g;
-        if (!make_geometry(a, int(s), g)) bad = 1;
+        if (!make_geometry(a, int(s), g)) mine_bad = true;
+        // the structures must tile the atoms from 0 to N
+        if (s == 0 && g.atom_lo != 0) mine_bad = true;
+        if (s == n - 1 && g.atom_hi != a.n_atoms) mine_bad = true;
         sum += int64_t(g.nbin[0]) * g.nbin[1] * g.nbin[2];
-        a.geom[s] = g;
+        if (s < cache_n) cache[s] = g;
+        else a.geom[s] = g;
     }
+    if (mine_bad) bad = 1;
     int64_t total;
     int64_t run = block_prefix<int64_t>(sum, total);
     for (int64_t s = b; s < e; ++s) {
-        a.geom[s].bin_lo = run;
-        run += int64_t(a.geom[s].nbin[0]) * a.geom[s].nbin[1] * a.geom[s].nbin[2];
+        StructGeom* gp = s < cache_n ? &cache[s] : &a.geom[s];
+        gp->bin_lo = run;
+        run += int64_t(gp->nbin[0]) * gp->nbin[1] * gp->nbin[2];
+        if (s < cache_n) a.geom[s] = *gp;
     }
     if (t == 0 && total > a.max_bins) bad = 1;
     __syncthreads();
@@ -264,10 +273,18 @@ __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
     __shared__ int cnt[kSmallBins + 1];
     __shared__ StructGeom gc[kGeomCache];
     const int t = threadIdx.x;
-    if (!geometry_block(a)) return;
+    // the first atom of each lane is read before the geometry is built
+    double r_first[3] = {0.0, 0.0, 0.0};
+    int sp_first = 0;
+    if (t < a.n_atoms) {
+        r_first[0] = a.positions[3 * t];
+        r_first[1] = a.positions[3 * t + 1];
+        r_first[2] = a.positions[3 * t + 2];
+        sp_first = a.species[t];
+    }
     const int ns = a.n_structures;
     const bool cached = ns <= kGeomCache;
-    if (cached && t < ns) gc[t] = a.geom[t];
+    if (!geometry_block(a, gc, cached ? ns : 0)) return;
     const int B = int(a.max_bins);
     for (int b = t; b <= B; b += 1024) cnt[b] = 0;
     __syncthreads();
@@ -279,8 +296,12 @@ __global__ void __launch_bounds__(1024) k_bins_small(NeighborArgs a)
         const int64_t i = t + 1024 * int64_t(u);
         if (i < a.n_atoms) {
             const int s = structure_of(geom, ns, i);
-            const double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
-            bin_of[u] = place_atom(a, i, s, geom[s], r, a.species[i], w_of[u]);
+            if (u == 0) {
+                bin_of[u] = place_atom(a, i, s, geom[s], r_first, sp_first, w_of[u]);
+            } else {
+                const double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
+                bin_of[u] = place_atom(a, i, s, geom[s], r, a.species[i], w_of[u]);
+            }
             atomicAdd(&cnt[bin_of[u]], 1);
         }
     }
