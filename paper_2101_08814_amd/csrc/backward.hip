@@ -97,11 +97,12 @@ __global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, 
                 int n = e / d.L2, lm = e - n * d.L2;
                 int rl = n * lm1 + s.lof[lm];
                 T Gv = G[e];
-                T t = Gv * s.dR[p * d.nl + rl] * s.Y[p * d.L2 + lm];
+                const V4<T> yd = s.YD[p * d.L2 + lm];
+                T t = Gv * s.dR[p * d.nl + rl] * yd.x;
                 T r = Gv * s.R[p * d.nl + rl];
-                gx += t * s.ux[p] + r * s.dY[(p * 3 + 0) * d.L2 + lm];
-                gy += t * s.uy[p] + r * s.dY[(p * 3 + 1) * d.L2 + lm];
-                gz += t * s.uz[p] + r * s.dY[(p * 3 + 2) * d.L2 + lm];
+                gx += t * s.ux[p] + r * yd.y;
+                gy += t * s.uy[p] + r * yd.z;
+                gz += t * s.uz[p] + r * yd.w;
             }
             gx = wave_sum(gx);
             gy = wave_sum(gy);

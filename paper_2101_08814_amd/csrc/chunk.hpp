@@ -69,7 +69,7 @@ __host__ __device__ inline Dims make_dims(int S, int nmax, int lmax)
 // LDS layout in elements of T (ints occupy T-sized slots).
 struct Layout {
     int chunk;                          // pairs per staged chunk
-    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, dY, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, pos, total;
+    int c, dcs, ux, uy, uz, r, rinv, f, df, R, dR, Y, qt, cre, cim, yz, spc, seg, ynorm, lof, tri, pos, total;
 };
 
 // yz: elements of the region for the per-(pair, l, k) operands of the
@@ -92,8 +92,10 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
     L.df = o; o += ch;
     L.R = o; o += ch * d.nl;
     L.dR = o; o += grad ? ch * d.nl : 0;
-    L.Y = o; o += ch * d.L2;
-    L.dY = o; o += grad ? 3 * ch * d.L2 : 0;
+    // harmonics: Y alone, or {Y, dY_x, dY_y, dY_z} records (4-element
+    // aligned) with gradients
+    o = (o + 3) & ~3;
+    L.Y = o; o += (grad ? 4 : 1) * ch * d.L2;
     // the Legendre table is dead once the harmonics are staged; the
     // operands of the gradient rows reuse its space, 4-element aligned for
     // vector loads
@@ -161,12 +163,14 @@ struct alignas(2 * sizeof(T)) V2 {
 
 template <typename T>
 struct Smem {
-    T *c, *dcs, *ux, *uy, *uz, *r, *rinv, *f, *df, *R, *dR, *Y, *dY, *qt, *cre, *cim, *yz, *ynorm;
+    T *c, *dcs, *ux, *uy, *uz, *r, *rinv, *f, *df, *R, *dR, *Y, *qt, *cre, *cim, *yz, *ynorm;
+    V4<T>* YD;   // {Y, dY_x, dY_y, dY_z} of each (pair, lm) when staged with gradients
     int *spc, *seg, *lof, *tri, *pos;
     __device__ Smem(T* base, const Layout& L)
         : c(base + L.c), dcs(base + L.dcs), ux(base + L.ux), uy(base + L.uy), uz(base + L.uz), r(base + L.r),
           rinv(base + L.rinv), f(base + L.f), df(base + L.df), R(base + L.R), dR(base + L.dR), Y(base + L.Y),
-          dY(base + L.dY), qt(base + L.qt), cre(base + L.cre), cim(base + L.cim), yz(base + L.yz),
+          qt(base + L.qt), cre(base + L.cre), cim(base + L.cim), yz(base + L.yz),
+          YD(reinterpret_cast<V4<T>*>(base + L.Y)),
           ynorm(base + L.ynorm), spc(reinterpret_cast<int*>(base + L.spc)),
           seg(reinterpret_cast<int*>(base + L.seg)), lof(reinterpret_cast<int*>(base + L.lof)),
           tri(reinterpret_cast<int*>(base + L.tri)), pos(reinterpret_cast<int*>(base + L.pos))
@@ -286,12 +290,8 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
         T Y, gx, gy, gz;
         ylm_and_grad<T>(lm, s.lof[lm], s.ynorm[lm], s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1, s.ux[p],
                         s.uy[p], s.uz[p], s.rinv[p], Y, gx, gy, gz);
-        s.Y[p * d.L2 + lm] = Y;
-        if (GRAD) {
-            s.dY[(p * 3 + 0) * d.L2 + lm] = gx;
-            s.dY[(p * 3 + 1) * d.L2 + lm] = gy;
-            s.dY[(p * 3 + 2) * d.L2 + lm] = gz;
-        }
+        if (GRAD) s.YD[p * d.L2 + lm] = V4<T>{Y, gx, gy, gz};
+        else s.Y[p * d.L2 + lm] = Y;
     }
     __syncthreads();
 }

@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
             const int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
             for (int p = p0; p < p1; ++p) {
                 if (s.spc[p] != sp) continue;
-                const T Yv = s.Y[p * d.L2 + lm];
+                V4<T> yd;
+                if (GRAD) yd = s.YD[p * d.L2 + lm];
+                const T Yv = GRAD ? yd.x : s.Y[p * d.L2 + lm];
                 const T* Rp = s.R + p * d.nl + n0 * lm1 + l;
                 const T R0 = Rp[0], R1 = two ? Rp[lm1] : T(0);
                 c0 += R0 * Yv;
@@ -88,10 +90,9 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
                     // pair row d c / d r_ji = (f I~)' u Y + f I~ grad Y; the
                     // self row is minus the sum of the rows (App. B)
                     const T* dRp = s.dR + p * d.nl + n0 * lm1 + l;
-                    const T* D = s.dY + p * 3 * d.L2 + lm;
                     const T dR0 = dRp[0], dR1 = two ? dRp[lm1] : T(0);
                     const T al0 = s.ux[p] * Yv, al1 = s.uy[p] * Yv, al2 = s.uz[p] * Yv;
-                    const T D0 = D[0], D1 = D[d.L2], D2 = D[2 * d.L2];
+                    const T D0 = yd.y, D1 = yd.z, D2 = yd.w;
                     const T r00 = dR0 * al0 + R0 * D0, r01 = dR0 * al1 + R0 * D1, r02 = dR0 * al2 + R0 * D2;
                     const T r10 = dR1 * al0 + R1 * D0, r11 = dR1 * al1 + R1 * D1, r12 = dR1 * al2 + R1 * D2;
                     a0 += r00;
@@ -196,21 +197,19 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
         __syncthreads();
         if (ck != n_chunks - 1) stage_chunk<T, true>(a, d, s, q0, nc);
         for (int p = wave; p < nc; p += kWaves) {
-            const T* Yp = s.Y + p * d.L2;
-            const T* Dx = s.dY + (p * 3 + 0) * d.L2;
-            const T* Dy = Dx + d.L2;
-            const T* Dz = Dy + d.L2;
+            const V4<T>* YDp = s.YD + p * d.L2;
             for (int t = lane; t < nlk; t += 64) {
                 const int l2 = t / d.K, k = t - l2 * d.K;
                 const int m0 = l2 * l2;
                 const T* ck_ = s.c + k * d.L2;
                 T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
                 for (int m = m0; m < m0 + 2 * l2 + 1; ++m) {
-                    T cv = ck_[m];
-                    y += Yp[m] * cv;
-                    z0 += Dx[m] * cv;
-                    z1 += Dy[m] * cv;
-                    z2 += Dz[m] * cv;
+                    const T cv = ck_[m];
+                    const V4<T> yd = YDp[m];
+                    y += yd.x * cv;
+                    z0 += yd.y * cv;
+                    z1 += yd.z * cv;
+                    z2 += yd.w * cv;
                 }
                 yzw[t] = V4<T>{y, z0, z1, z2};
             }

@@ -76,8 +76,9 @@ __global__ void __launch_bounds__(kThreads) k_pair_rows(FeatureArgs a, Layout L)
                 const int p = t / per_pair, rem = t - p * per_pair, x = rem / d.L2, lm = rem - x * d.L2;
                 const int l = s.lof[lm];
                 const T u = x == 0 ? s.ux[p] : (x == 1 ? s.uy[p] : s.uz[p]);
-                const T alpha = u * s.Y[p * d.L2 + lm];
-                const T beta = s.dY[(p * 3 + x) * d.L2 + lm];
+                const V4<T> yd = s.YD[p * d.L2 + lm];
+                const T alpha = u * yd.x;
+                const T beta = x == 0 ? yd.y : (x == 1 ? yd.z : yd.w);
                 const T* dRp = s.dR + p * d.nl + l;
                 const T* Rp = s.R + p * d.nl + l;
                 T* out = dc_base + (uint32_t(p * EDC) + uint32_t(x * nL2 + lm));
@@ -93,17 +94,15 @@ __global__ void __launch_bounds__(kThreads) k_pair_rows(FeatureArgs a, Layout L)
             for (int t = tid; t < nc * yzn; t += kThreads) {
                 int p = t / yzn, rem = t - p * yzn, l = rem / d.K, k = rem - l * d.K;
                 const T* ck_ = s.c + k * d.L2 + l * l;
-                const T* Yp = s.Y + p * d.L2 + l * l;
-                const T* Dx = s.dY + (p * 3 + 0) * d.L2 + l * l;
-                const T* Dy = Dx + d.L2;
-                const T* Dz = Dy + d.L2;
+                const V4<T>* YDp = s.YD + p * d.L2 + l * l;
                 T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
                 for (int m = 0; m < 2 * l + 1; ++m) {
-                    T cv = ck_[m];
-                    y += Yp[m] * cv;
-                    z0 += Dx[m] * cv;
-                    z1 += Dy[m] * cv;
-                    z2 += Dz[m] * cv;
+                    const T cv = ck_[m];
+                    const V4<T> yd = YDp[m];
+                    y += yd.x * cv;
+                    z0 += yd.y * cv;
+                    z1 += yd.z * cv;
+                    z2 += yd.w * cv;
                 }
                 reinterpret_cast<V4<T>*>(s.yz)[t] = V4<T>{y, z0, z1, z2};
                 const int n = k - s.spc[p] * d.nmax;
