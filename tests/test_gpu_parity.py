@@ -191,6 +191,37 @@ def test_separate_entry_points_match_fused():
             assert rel(a.double().cpu().numpy(), f.double().cpu().numpy()) <= (1e-12 if dt == torch.float64 else 1e-6)
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_fused_rows_over_many_chunks(dt):
+    """A dense small periodic cell (about 100 neighbours per centre, several
+    LDS chunks per centre, the last one partial): the pair rows written by
+    soap_features, whose kernel loads each chunk ahead while the previous
+    one is in use, against the oracle and against soap_gradient_rows."""
+    hyp = dict(n_species=2, nmax=4, lmax=4, rcut=6.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+    b = synthetic.random_cell_structure(41, 40, np.array([[7.0, 0, 0], [0.4, 6.8, 0], [-0.3, 0.5, 7.2]]), 2,
+                                        min_sep=1.2, hypers=hyp)
+    calc = P.Calculator.from_hypers(hyp)
+    nl, pos, spc = gpu_neighbors(calc, b, dt)
+    c, p, dc, dcs, dp, dps = calc.features(nl, spc, dt, gradients=True)
+    r_dc, r_dp = calc.gradient_rows(nl, spc, c)
+    assert calc.device_status() == 0
+    Pn = nl.count()
+    assert Pn / b.n_atoms > 80
+    ref_nl = oracle.neighbors(b)
+    ref_c = oracle.expansion(hyp, b.species, ref_nl)
+    ref_p = oracle.power_spectrum(hyp, ref_c)
+    rdc, rdcs, rdp, rdps = oracle.gradients(hyp, b.species, ref_nl)
+    tol = 1e-7 if dt == torch.float64 else 1e-5
+    for name, x, y in [("c", c, ref_c), ("p", p, ref_p), ("dc", dc[:Pn], rdc), ("dcs", dcs, rdcs),
+                       ("dp", dp[:Pn], rdp), ("dps", dps, rdps)]:
+        e = rel(x.double().cpu().numpy(), y)
+        print(f"[many chunks {dt}] {name} {e:.3e}")
+        assert e <= tol, name
+    same = 1e-12 if dt == torch.float64 else 1e-6
+    for name, x, y in [("dc", dc[:Pn], r_dc[:Pn]), ("dp", dp[:Pn], r_dp[:Pn])]:
+        assert rel(x.double().cpu().numpy(), y.double().cpu().numpy()) <= same, name
+
+
 def test_gradient_rows_entry_point():
     """soap_gradient_rows (dc and dp rows from c) gives the rows of
     soap_features, together or one at a time."""
