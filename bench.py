@@ -208,6 +208,172 @@ def run_compression(args) -> int:
     return 0
 
 
+def config_bytes(kind: str, N: int, P: int, S: int, nmax: int, lmax: int, es: int):
+    """Algorithmic bytes of one launch of a phase of the parity workloads
+    (inputs read once, outputs written once; the L2-resident spline table
+    not counted).  es: bytes per element of c and p."""
+    L2 = (lmax + 1) ** 2
+    K = S * nmax
+    KK = K * (K + 1) // 2
+    c, p = es * K * L2, es * (lmax + 1) * KK
+    pair_in = 3 * es + 4 + 4
+    if kind == "expansion":          # c from the pairs
+        return N * (c + 12) + P * pair_in
+    if kind == "features":           # c and p from the pairs
+        return N * (c + p + 12) + P * pair_in
+    if kind == "spectrum":           # p from c
+        return N * (c + p)
+    if kind == "spectrum_backward":  # grad_c from c and grad_p
+        return N * (2 * c + p)
+    if kind == "expansion_backward":  # per-pair g and grad_r from grad_c and the pairs
+        return N * (c + 8 + 3 * es) + P * (pair_in + 4 + 3 * es)
+    raise ValueError(kind)
+
+
+def run_config(args) -> int:
+    """The parity workloads as timed steps (neighbours included, as in the
+    headline step); each phase is timed with HIP events on the launch stream.
+    clusters: 8 x 64-atom clusters, FP64 c and p.
+    molecules: 256 molecules of 20-200 atoms, 4 species, FP32 c then p from
+      the bfloat16 hi/lo MFMA contraction (one launch for all structures).
+    liquid: 4096-atom periodic liquid, 2 species, FP32 c and p, then the
+      adjoint for an upstream gradient drawn N(0, 1) (seed 2004)."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    import paper_2101_08814_amd as P
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    wl = args.workload
+    batch = {"clusters": synthetic.clusters_2species, "molecules": synthetic.molecule_batch,
+             "liquid": synthetic.liquid_bulk}[wl]()
+    h = batch.hypers
+    calc = P.Calculator.from_hypers(h)
+    td = torch.float64 if wl == "clusters" else torch.float32
+    es = 8 if td == torch.float64 else 4
+    pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
+    spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
+    ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
+    adjoint = wl == "liquid"
+    nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=td, transpose=adjoint)
+    N, Pn = batch.n_atoms, nl.count()
+    S, nmax, lmax = h["n_species"], h["nmax"], h["lmax"]
+    state = {}
+
+    def ph_neighbors():
+        calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=td, out=nl)
+
+    phases = [("neighbours", ph_neighbors, None)]
+    if wl == "molecules":
+        out_c = torch.empty((N, S, nmax, (lmax + 1) ** 2), dtype=td, device=dev)
+
+        def ph_expansion():
+            state["c"] = calc.spherical_expansion(nl, spc, td)
+
+        def ph_spectrum():
+            state["p"] = calc.power_spectrum(state["c"], "bf16")
+
+        phases += [("expansion", ph_expansion, ("k_centres<float, 6, false, false, false>", "expansion")),
+                   ("spectrum_bf16_mfma", ph_spectrum, ("k_power_spectrum_bf16", "spectrum"))]
+    else:
+        out = calc.allocate_features(N, nl.capacity, td, dev, False)
+
+        def ph_features():
+            calc.features(nl, spc, td, out=out)
+
+        kname = "k_centres<double, -1, false, true, false>" if td == torch.float64 else \
+            f"k_centres<float, {lmax}, false, true, false>"
+        phases.append(("features", ph_features, (kname, "features")))
+        if adjoint:
+            g = torch.Generator(device="cpu").manual_seed(2004)
+            grad_p = torch.randn(out[1].shape, generator=g, dtype=torch.float64).to(dev, td)
+
+            def ph_ps_backward():
+                state["gc"] = calc.power_spectrum_backward(out[0], grad_p)
+
+            def ph_exp_backward():
+                state["gpos"] = calc.spherical_expansion_backward(nl, spc, state["gc"])[0]
+
+            phases += [("spectrum_backward", ph_ps_backward, ("k_ps_backward<float>", "spectrum_backward")),
+                       ("expansion_backward", ph_exp_backward,
+                        ("k_exp_backward_pairs + k_exp_backward_gather", "expansion_backward"))]
+    for _ in range(max(3, args.warmup)):
+        for _, f, _ in phases:
+            f()
+    torch.cuda.synchronize()
+    calc.reset_status()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(K)]
+    t_all0, t_all1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record()
+    for k in range(K):
+        ev[k][0].record()
+        for j, (_, f, _) in enumerate(phases):
+            f()
+            ev[k][j + 1].record()
+    t_all1.record()
+    torch.cuda.synchronize()
+    status = calc.device_status()
+    if status != 0:
+        log(f"device status {status}")
+        return 4
+    total_ms = t_all0.elapsed_time(t_all1)
+    ph_ms = {name: float(np.median([e[j].elapsed_time(e[j + 1]) for e in ev])) for j, (name, _, _) in
+             enumerate(phases)}
+    ms_per_step = total_ms / K
+    rows = {}
+    for name, _, info in phases:
+        if info is None:
+            continue
+        kern, kind = info
+        b = config_bytes(kind, N, Pn, S, nmax, lmax, es)
+        rows[name] = {"kernel": kern, "ms": ph_ms[name], "algorithmic_bytes": b,
+                      "GB_s": b / (ph_ms[name] * 1e-3) / 1e9}
+    dom = max(rows, key=lambda k: rows[k]["ms"])
+    d = rows[dom]
+    roof = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["GB_s"] / HBM_PEAK_GBS, "traffic": None, "kernel_ms": d["ms"],
+            "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
+    if wl == "molecules":
+        KK = (S * nmax) * (S * nmax + 1) // 2
+        flops = 2.0 * N * KK * (lmax + 1) ** 2                 # packed p: K(K+1)/2 dot products of L2 terms
+        tf = flops / (rows["spectrum_bf16_mfma"]["ms"] * 1e-3) / 1e12
+        rows["spectrum_bf16_mfma"].update({"algorithmic_tflops": tf, "frac_of_bf16_peak": tf / 2500.0,
+                                           "attainable_tflops_at_hbm": flops / rows["spectrum_bf16_mfma"][
+                                               "algorithmic_bytes"] * HBM_PEAK_GBS / 1e3})
+    if adjoint:
+        # VALU work of the adjoint's pair pass: per pair and (n, lm) the three
+        # components of G * grad(f I Y), about 12 flops (2 FMA x 3 + the product)
+        fl = 12.0 * Pn * nmax * (lmax + 1) ** 2
+        tf = fl / (rows["expansion_backward"]["ms"] * 1e-3) / 1e12
+        rows["expansion_backward"].update({"algorithmic_tflops": tf, "frac_of_fp32_valu_peak": tf / 157.3})
+    log(f"[bench:{wl}] N={N} P={Pn} step={ms_per_step * 1e3:.1f} us  " +
+        "  ".join(f"{k}={v * 1e3:.1f} us" for k, v in ph_ms.items()))
+    names = {"clusters": "8 clusters x 64 atoms (cube 8.618 A), 2 species 32/32, rcut 4 A, sigma 0.5 A, nmax 6, "
+                         "lmax 4; neighbours + FP64 expansion and power spectrum",
+             "molecules": "256 molecules of 20-200 atoms at 0.08 A^-3, 4 species, rcut 5 A, sigma 0.4 A, nmax 8, "
+                          "lmax 6; neighbours + FP32 expansion + bfloat16 hi/lo MFMA power spectrum, one launch",
+             "liquid": "4096-atom periodic liquid (side 43.44 A), 2 species 2867/1229, rcut 6 A, sigma 0.5 A, "
+                       "nmax 10, lmax 8; neighbours with reverse-pair index + FP32 expansion and power spectrum + "
+                       "adjoint (vector-Jacobian product for an N(0,1) upstream gradient)"}
+    line = {
+        "metric": "atom-centres/s (neighbours + " + {"clusters": "FP64 expansion + power spectrum)",
+                                                    "molecules": "expansion + bf16 MFMA power spectrum)",
+                                                    "liquid": "expansion + power spectrum + adjoint)"}[wl],
+        "value": N / (ms_per_step * 1e-3), "unit": "atom-centres/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if es == 8 else ("bf16" if wl == "molecules" else "f32"),
+        "data": "synthetic",
+        "config": {"workload": names[wl], "centres": N, "pairs": Pn, "phases_ms": ph_ms, "phases": rows},
+        "roofline": roof,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,8 +387,10 @@ def main() -> int:
                     "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["diamond", "compression"], default="diamond",
-                    help="diamond: the headline step (default); compression: the learned channel compression "
+    ap.add_argument("--workload", choices=["diamond", "clusters", "molecules", "liquid", "compression"],
+                    default="diamond",
+                    help="diamond: the headline step (default); clusters, molecules, liquid: the FP64, MFMA and "
+                         "adjoint parity workloads as timed steps; compression: the learned channel compression "
                          "of the 8-species cells, trained and timed against the full power spectrum")
     ap.add_argument("--train-steps", type=int, default=600)
     args = ap.parse_args()
@@ -240,6 +408,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.workload == "compression":
         return run_compression(args)
+    if args.workload in ("clusters", "molecules", "liquid"):
+        return run_config(args)
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
