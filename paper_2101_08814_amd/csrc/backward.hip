@@ -24,24 +24,42 @@ namespace {
 using namespace dev;
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_ps_backward(FeatureArgs a, const T* grad_p, T* grad_c)
+__global__ void __launch_bounds__(kThreads) k_ps_backward(FeatureArgs a, const T* grad_p, T* grad_c, bool all)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const Dims d = make_dims(a.S, a.nmax, a.lmax);
     const int KL2 = d.K * d.L2;
     T* c = sm;            // [K][L2]
-    T* w = c + KL2;       // [KK] packed W_l
+    T* w = c + KL2;       // packed W_l: of every l at once when `all`, else of one l at a time
     const int tid = threadIdx.x;
     const int64_t i = blockIdx.x;
-    const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
-    for (int e = tid; e < KL2; e += kThreads) c[e] = c_in[e];
+    const int PL = (d.lmax + 1) * d.KK;
+    const T* gp = grad_p + i * int64_t(PL);
+    copy_in(c, static_cast<const T*>(a.coeffs) + i * KL2, KL2);
     T* g_out = grad_c + i * KL2;
     const int K = d.K;
-    for (int l = 0; l <= d.lmax; ++l) {
-        const T* wl = grad_p + (i * (d.lmax + 1) + l) * d.KK;
+    if (all) {
+        copy_in(w, gp, PL);
         __syncthreads();
-        for (int64_t e = tid; e < d.KK; e += kThreads) w[e] = wl[e];
+        // one lane per (k, lm), lm over every l
+        for (int t = tid; t < K * d.L2; t += kThreads) {
+            const int k = t / d.L2, lm = t - k * d.L2;
+            const T* wl = w + l_of(lm) * d.KK;
+            T acc = T(0);
+            for (int kp = 0; kp < K; ++kp) {
+                int lo = k < kp ? k : kp, hi = k < kp ? kp : k;
+                T wv = wl[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
+                if (kp == k) wv += wv;
+                acc += wv * c[kp * d.L2 + lm];
+            }
+            g_out[t] = acc;
+        }
+        return;
+    }
+    for (int l = 0; l <= d.lmax; ++l) {
+        __syncthreads();
+        copy_in(w, gp + l * d.KK, d.KK);
         __syncthreads();
         const int nm = 2 * l + 1;
         for (int t = tid; t < K * nm; t += kThreads) {
@@ -83,7 +101,7 @@ __global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, 
     const int chunk = L.chunk;
     init_tables<T>(a, d, L, s);
     const T* g_in = grad_c + i * KL2;
-    for (int e = tid; e < KL2; e += kThreads) s.c[e] = g_in[e];   // the c slot holds dL/dc here
+    copy_in(s.c, g_in, KL2);   // the c slot holds dL/dc here
     const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
     const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
     for (int ck = 0; ck < n_chunks; ++ck) {
@@ -142,7 +160,10 @@ template <typename T>
 hipError_t ps_backward_t(const FeatureArgs& a, const void* grad_p, void* grad_c, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
-    size_t lds = (size_t(d.K) * d.L2 + size_t(d.KK)) * sizeof(T);
+    // the upstream gradient of every l in LDS at once when that fits 64 KB
+    const size_t all_lds = (size_t(d.K) * d.L2 + size_t(d.lmax + 1) * d.KK) * sizeof(T);
+    const bool all = all_lds <= 64 * 1024;
+    size_t lds = all ? all_lds : (size_t(d.K) * d.L2 + size_t(d.KK)) * sizeof(T);
     if (lds > 160 * 1024) return hipErrorNotSupported;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ps_backward<T>),
@@ -150,7 +171,7 @@ hipError_t ps_backward_t(const FeatureArgs& a, const void* grad_p, void* grad_c,
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ps_backward<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads), lds, stream, a,
-                       static_cast<const T*>(grad_p), static_cast<T*>(grad_c));
+                       static_cast<const T*>(grad_p), static_cast<T*>(grad_c), all);
     return hipGetLastError();
 }
 

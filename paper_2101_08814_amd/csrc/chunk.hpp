@@ -29,6 +29,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kTriMax = 8192;    // largest K (K+1)/2 kept as an LDS table
 constexpr int kSplineBatch = 4;  // spline coefficient loads a lane keeps in flight
+constexpr int kCopyBatch = 8;    // loads a lane keeps in flight when copying to LDS
 
 // Kernels are instantiated with the degree lmax as a template parameter LM
 // (0..12) for float; LM = -1 takes lmax at run time.
@@ -177,6 +178,27 @@ struct Smem {
     {
     }
 };
+
+// Copy n elements from global memory to LDS with all lanes of the block,
+// each lane keeping up to kCopyBatch loads in flight before it stores any
+// (a plain strided loop waits for every load in turn).
+template <typename T>
+__device__ __forceinline__ void copy_in(T* dst, const T* src, int n)
+{
+    for (int e0 = threadIdx.x; e0 < n; e0 += kCopyBatch * kThreads) {
+        T v[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            const int e = e0 + u * kThreads;
+            v[u] = e < n ? src[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e < n) dst[e] = v[u];
+        }
+    }
+}
 
 // l of each lm, K_lm, and (when present) the packed-triangle decode table
 // tri[kk] = k1 | k2 << 16.  Caller synchronises afterwards.

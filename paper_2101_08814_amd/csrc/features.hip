@@ -253,11 +253,8 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum(FeatureArgs a)
     T* c = sm;                 // [K][L2]
     T* g = c + KL2;            // [3][K][L2] self row, then per-wave row buffers
     const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
-    for (int e = tid; e < KL2; e += kThreads) c[e] = c_in[e];
-    if (GRAD) {
-        const T* g_in = static_cast<const T*>(a.dcoeffs_self) + i * 3 * KL2;
-        for (int e = tid; e < 3 * KL2; e += kThreads) g[e] = g_in[e];
-    }
+    copy_in(c, c_in, KL2);
+    if (GRAD) copy_in(g, static_cast<const T*>(a.dcoeffs_self) + i * 3 * KL2, 3 * KL2);
     __syncthreads();
     T* p_out = static_cast<T*>(a.p) + i * PL;
     for (int64_t o = tid; o < PL; o += kThreads) {

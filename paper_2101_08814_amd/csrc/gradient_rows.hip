@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_rows(FeatureArgs a, Layout L)
     init_tables<T>(a, d, L, s);
     if (WANT_DP) {
         const T* c_in = static_cast<const T*>(a.coeffs) + i * KL2;
-        for (int e = tid; e < KL2; e += kThreads) s.c[e] = c_in[e];
+        copy_in(s.c, c_in, KL2);
         // packed positions of a dp row: l | k1 << 4 | k2 << 14
         for (int o = tid; o < PL; o += kThreads) s.pos[o] = a.dp_pos[o];
     }

@@ -11,11 +11,13 @@
 // one product whose inner dimension is 3(2l+1); the dropped L L^T term and
 // the rounding of L leave a relative error of order 2^-16.
 //
-// One work-group of four waves owns one centre.  C is split once into LDS;
-// for each l the 16 x 16 output tiles (I <= J) are spread over the waves,
-// each a chain of v_mfma_f32_16x16x32_bf16 over the padded inner dimension.
-// The tile lands in an LDS copy of the packed row p_{i,l,.}, which is then
-// written to memory with consecutive lanes on consecutive addresses.
+// W waves own one centre (W = 1, four centres per work-group, when C is
+// small; W = 4 otherwise), with no work-group barriers: the centre's waves
+// split C into their LDS region as {H, L} pairs, then for each l run the
+// 16 x 16 output tiles (I <= J), dealt round-robin, as chains of
+// v_mfma_f32_16x16x32_bf16 over the padded inner dimension (each lane
+// gathers its 8 operand values per step) and store the packed upper
+// triangle straight from the accumulators (16 consecutive k2 per store).
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -29,6 +31,7 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
+constexpr int kLoadBatch = 16;   // coefficient loads a lane keeps in flight
 
 // round to nearest even (finite inputs)
 __device__ __forceinline__ unsigned short to_bf16(float f)
@@ -40,89 +43,132 @@ __device__ __forceinline__ unsigned short to_bf16(float f)
 
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
+template <int W>
 __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
 {
+    constexpr int CPG = kThreads / 64 / W;   // centres per work-group
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int S = a.S, nmax = a.nmax, lmax = a.lmax;
     const int K = S * nmax, L2 = (lmax + 1) * (lmax + 1);
     const int KK = K * (K + 1) / 2;
     const int KL2 = K * L2;
-    unsigned short* hi = reinterpret_cast<unsigned short*>(smem_raw);
-    unsigned short* lo = hi + KL2;
-    float* prow = reinterpret_cast<float*>(smem_raw + ((4 * size_t(KL2) + 15) & ~size_t(15)));
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t i = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = wave / W, wc = wave - slot * W;   // centre slot in the work-group, wave within the centre
+    const int64_t i = int64_t(blockIdx.x) * CPG + slot;
+    if (i >= a.n_atoms) return;
+    // {H, L} of every element of C: H in the low half, L in the high half
+    unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * KL2;
     const float* c_in = static_cast<const float*>(a.coeffs) + i * KL2;
-    for (int e = tid; e < KL2; e += kThreads) {
-        float v = c_in[e];
-        unsigned short h = to_bf16(v);
-        hi[e] = h;
-        lo[e] = to_bf16(v - from_bf16(h));
+    // kLoadBatch loads in flight per lane before any is used
+    for (int e0 = wc * 64 + lane; e0 < KL2; e0 += kLoadBatch * W * 64) {
+        float v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int e = e0 + u * W * 64;
+            v[u] = e < KL2 ? c_in[e] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int e = e0 + u * W * 64;
+            if (e < KL2) {
+                const unsigned short h = to_bf16(v[u]);
+                hl[e] = (unsigned int)h | ((unsigned int)to_bf16(v[u] - from_bf16(h)) << 16);
+            }
+        }
     }
-    __syncthreads();
+    if (W == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();   // one centre per work-group
+    }
     const int T = (K + 15) / 16;
     const int n_tiles = T * (T + 1) / 2;
     const int row = lane & 15, kg = lane >> 4;
     float* p_out = static_cast<float*>(a.p) + i * int64_t(lmax + 1) * KK;
     for (int l = 0; l <= lmax; ++l) {
         const int w = 2 * l + 1, inner = 3 * w, steps = (inner + 31) / 32;
-        for (int t = wave; t < n_tiles; t += kThreads / 64) {
+        float* dst = p_out + int64_t(l) * KK;
+        for (int t = wc; t < n_tiles; t += W) {
             // tile t -> (I, J), I <= J, row-major over the upper triangle
             int I = 0, rem = t;
             while (rem >= T - I) { rem -= T - I; ++I; }
-            int J = I + rem;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int J = I + rem;
             const int ka = I * 16 + row, kb = J * 16 + row;
+            const unsigned int* ra = hl + (ka < K ? ka : 0) * L2 + l * l;
+            const unsigned int* rb = hl + (kb < K ? kb : 0) * L2 + l * l;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             for (int st = 0; st < steps; ++st) {
+                // inner index q = st*32 + kg*8 + j runs over [H | L | H] (A) and [H | H | L] (B)
+                const int q0 = st * 32 + kg * 8;
+                int seg = q0 / w, m = q0 - seg * w;
                 u16x8 av, bv;
+#pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    int q = st * 32 + kg * 8 + j;
-                    int seg = q / w, m = q - seg * w;
                     unsigned short va = 0, vb = 0;
                     if (seg < 3) {
-                        if (ka < K) va = (seg == 1 ? lo : hi)[ka * L2 + l * l + m];
-                        if (kb < K) vb = (seg == 2 ? lo : hi)[kb * L2 + l * l + m];
+                        const unsigned int xa = ra[m], xb = rb[m];
+                        va = (unsigned short)(seg == 1 ? xa >> 16 : xa & 0xFFFFu);
+                        vb = (unsigned short)(seg == 2 ? xb >> 16 : xb & 0xFFFFu);
+                        if (ka >= K) va = 0;
+                        if (kb >= K) vb = 0;
                     }
                     av[j] = va;
                     bv[j] = vb;
+                    if (++m == w) { m = 0; ++seg; }
                 }
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
                                                               __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
             }
-            // lane holds D[4*kg + v][row]
+            // lane holds D[4*kg + v][row] = P[k1][k2] with k1 = 16 I + 4 kg + v, k2 = 16 J + row
             const int k2 = J * 16 + row;
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int k1 = I * 16 + 4 * kg + v;
-                if (k1 <= k2 && k2 < K) prow[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
+                const int k1 = I * 16 + 4 * kg + v;
+                if (k1 <= k2 && k2 < K) dst[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
             }
         }
-        __syncthreads();
-        float* dst = p_out + int64_t(l) * KK;
-        for (int e = tid; e < KK; e += kThreads) dst[e] = prow[e];
-        __syncthreads();
     }
+}
+
+// waves per centre: one when four centres' C fit 40 KB of LDS
+int bf16_waves_per_centre(int S, int nmax, int lmax)
+{
+    const size_t KL2 = size_t(S) * nmax * (lmax + 1) * (lmax + 1);
+    return 4 * 4 * KL2 <= 40 * 1024 ? 1 : 4;
 }
 
 }  // namespace
 
 size_t power_spectrum_bf16_lds(int S, int nmax, int lmax)
 {
-    size_t K = size_t(S) * nmax, L2 = size_t(lmax + 1) * (lmax + 1);
-    return ((4 * K * L2 + 15) & ~size_t(15)) + 4 * (K * (K + 1) / 2);
+    const size_t K = size_t(S) * nmax, L2 = size_t(lmax + 1) * (lmax + 1);
+    return size_t(kThreads / 64 / bf16_waves_per_centre(S, nmax, lmax)) * 4 * K * L2;
+}
+
+template <int W>
+hipError_t launch_bf16(const FeatureArgs& a, size_t lds, hipStream_t stream)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_power_spectrum_bf16<W>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    constexpr int cpg = kThreads / 64 / W;
+    const unsigned groups = unsigned((a.n_atoms + cpg - 1) / cpg);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_power_spectrum_bf16<W>), dim3(groups), dim3(kThreads), lds, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipStream_t stream)
 {
     if (prec != SOAP_BF16_F32ACC) return launch_power_spectrum_valu(a, prec == SOAP_F64, stream);
-    size_t lds = power_spectrum_bf16_lds(a.S, a.nmax, a.lmax);
+    const size_t lds = power_spectrum_bf16_lds(a.S, a.nmax, a.lmax);
     if (lds > 160 * 1024) return hipErrorNotSupported;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_power_spectrum_bf16),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_power_spectrum_bf16, dim3(unsigned(a.n_atoms)), dim3(kThreads), lds, stream, a);
-    return hipGetLastError();
+    if (a.n_atoms == 0) return hipSuccess;
+    return bf16_waves_per_centre(a.S, a.nmax, a.lmax) == 1 ? launch_bf16<1>(a, lds, stream)
+                                                             : launch_bf16<4>(a, lds, stream);
 }
 
 }  // namespace soap

@@ -279,10 +279,15 @@ def test_multispecies_fp32_parity(n_cells):
     """8 species, nmax 12, lmax 8 (K = 96, 41904 features per centre)."""
     b = synthetic.multi_species_cells().subset(list(range(n_cells)))
     calc, nl, spc, (c, p) = run_features(b, torch.float32)
+    c_t = calc.spherical_expansion(nl, spc, torch.float32)
+    p16 = calc.power_spectrum(c_t, "bf16")   # K = 96: several waves per centre on the matrix cores
+    assert calc.device_status() == 0
     ref_nl, ref_c, ref_p = oracle.features(b)
-    ec, ep = rel(c, ref_c), rel(p, ref_p)
-    print(f"[multispecies {n_cells} cells] rel c={ec:.3e} p={ep:.3e}")
+    ec, ep, e16 = rel(c, ref_c), rel(p, ref_p), rel(p16.double().cpu().numpy(), ref_p)
+    w16 = worst_centre(p16.double().cpu().numpy(), ref_p)
+    print(f"[multispecies {n_cells} cells] rel c={ec:.3e} p={ep:.3e} p_bf16={e16:.3e} worst-centre bf16={w16:.3e}")
     assert ec <= 1e-6 and ep <= 1e-6
+    assert e16 <= 2e-3 and w16 <= 2e-3
 
 
 def test_rotation_invariance_on_gpu():
