@@ -132,8 +132,8 @@ FeatureArgs base_args(const soap_calculator* calc, const soap_exec* exec, bool f
 }
 
 struct NbLayout {
-    size_t geom, ok, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, slots, centre_count,
-        total;
+    size_t geom, ok, atom_struct, atom_bin, atom_wrap, bin_count, bin_start, bin_cursor, bin_atoms, slots, wrapped,
+        centre_count, scan_tmp, total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -156,7 +156,9 @@ NbLayout nb_layout(int32_t n_struct, int64_t N)
     L.bin_cursor = o; o = up256(o + 4 * size_t(B + 1));
     L.bin_atoms = o; o = up256(o + 4 * size_t(N));
     L.slots = o; o = up256(o + 32 * size_t(N));
+    L.wrapped = o; o = up256(o + 32 * size_t(N));
     L.centre_count = o; o = up256(o + 8 * size_t(N + 1));
+    L.scan_tmp = o; o = up256(o + 8 * size_t((B + 1) / 4096 + 2));   // one sum per 4096-value tile of the longer scan
     L.total = o;
     return L;
 }
@@ -388,7 +390,9 @@ soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec*
     a.bin_cursor = reinterpret_cast<int32_t*>(ws + L.bin_cursor);
     a.bin_atoms = reinterpret_cast<int32_t*>(ws + L.bin_atoms);
     a.slots = reinterpret_cast<double4*>(ws + L.slots);
+    a.wrapped = reinterpret_cast<double4*>(ws + L.wrapped);
     a.centre_count = reinterpret_cast<int64_t*>(ws + L.centre_count);
+    a.scan_tmp = reinterpret_cast<int64_t*>(ws + L.scan_tmp);
     a.capacity = capacity;
     a.pair_offsets = pair_offsets;
     a.pair_j = pair_j;

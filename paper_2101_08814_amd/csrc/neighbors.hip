@@ -32,7 +32,8 @@ namespace {
 constexpr int kSmallBins = 8192;   // single-work-group bin build up to this many bins
 constexpr int kSmallAtoms = 8192;  // ... and this many atoms
 constexpr int kPrefixAtoms = 2048; // fill kernel sums the counts itself up to this many atoms
-constexpr int kSortCap = 512;      // pairs per centre ranked in LDS
+constexpr int kSortCap = 512;      // sort records in LDS per fill work-group (shared by its waves)
+constexpr int kFillWaves = 4;      // centres (one wave each) per fill work-group
 
 __device__ __forceinline__ void put_status(int32_t* st, int v)
 {
@@ -132,21 +133,58 @@ __device__ T block_prefix(T v, T& total)
 
 // Exclusive scan of n values by one block of 1024 threads (each owns a
 // contiguous chunk); out[n] = total.  Returns the total in every thread.
+// Chunks of up to kScanRegs values stay in registers between the two passes
+// and all their loads are in flight together; longer chunks are read in
+// batches of kScanBatch, twice.
+constexpr int kScanRegs = 32;
+constexpr int kScanBatch = 8;
+
 template <typename Tin, typename Tout>
 __device__ Tout block_scan(const Tin* in, Tout* out, Tout* out2, int64_t n)
 {
     const int t = threadIdx.x;
     const int64_t chunk = (n + 1023) / 1024;
     const int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
-    Tout s = 0;
-    for (int64_t k = b; k < e; ++k) s += Tout(in[k]);
     Tout total;
-    Tout run = block_prefix<Tout>(s, total);
-    for (int64_t k = b; k < e; ++k) {
-        Tout v = Tout(in[k]);
-        out[k] = run;
-        if (out2) out2[k] = run;
-        run += v;
+    if (chunk <= kScanRegs) {
+        Tout v[kScanRegs];
+        Tout s = 0;
+#pragma unroll
+        for (int u = 0; u < kScanRegs; ++u) v[u] = b + u < e ? Tout(in[b + u]) : Tout(0);
+#pragma unroll
+        for (int u = 0; u < kScanRegs; ++u) s += v[u];
+        Tout run = block_prefix<Tout>(s, total);
+#pragma unroll
+        for (int u = 0; u < kScanRegs; ++u) {
+            if (b + u < e) {
+                out[b + u] = run;
+                if (out2) out2[b + u] = run;
+                run += v[u];
+            }
+        }
+    } else {
+        Tout s = 0;
+        for (int64_t k0 = b; k0 < e; k0 += kScanBatch) {
+            Tout v[kScanBatch];
+#pragma unroll
+            for (int u = 0; u < kScanBatch; ++u) v[u] = k0 + u < e ? Tout(in[k0 + u]) : Tout(0);
+#pragma unroll
+            for (int u = 0; u < kScanBatch; ++u) s += v[u];
+        }
+        Tout run = block_prefix<Tout>(s, total);
+        for (int64_t k0 = b; k0 < e; k0 += kScanBatch) {
+            Tout v[kScanBatch];
+#pragma unroll
+            for (int u = 0; u < kScanBatch; ++u) v[u] = k0 + u < e ? Tout(in[k0 + u]) : Tout(0);
+#pragma unroll
+            for (int u = 0; u < kScanBatch; ++u) {
+                if (k0 + u < e) {
+                    out[k0 + u] = run;
+                    if (out2) out2[k0 + u] = run;
+                    run += v[u];
+                }
+            }
+        }
     }
     if (t == 1023) out[n] = total;
     return total;
@@ -235,31 +273,6 @@ __device__ __forceinline__ int structure_of(const StructGeom* geom, int n, int64
     return lo;
 }
 
-// structure, wrap and bin of atom i
-__device__ int32_t assign_atom(const NeighborArgs& a, int64_t i)
-{
-    const int s = structure_of(a.geom, a.n_structures, i);
-    const double r[3] = {a.positions[3 * i], a.positions[3 * i + 1], a.positions[3 * i + 2]};
-    double4 w;
-    return place_atom(a, i, s, a.geom[s], r, a.species[i], w);
-}
-
-// Record of atom i for its bin slot: the position wrapped into the cell,
-// w = r - t.H (t the integer wrap), and the atom index in the fourth word.
-// A candidate j seen through a stencil bin of cell shift c then has the
-// pair vector (w_j - w_i) + c.H and the image shift c + t_i - t_j.
-__device__ __forceinline__ double4 make_slot(const NeighborArgs& a, int64_t i)
-{
-    const StructGeom& g = a.geom[a.atom_struct[i]];
-    const int t0 = a.atom_wrap[3 * i], t1 = a.atom_wrap[3 * i + 1], t2 = a.atom_wrap[3 * i + 2];
-    double4 r;
-    r.x = a.positions[3 * i] - (t0 * g.H[0] + t1 * g.H[3] + t2 * g.H[6]);
-    r.y = a.positions[3 * i + 1] - (t0 * g.H[1] + t1 * g.H[4] + t2 * g.H[7]);
-    r.z = a.positions[3 * i + 2] - (t0 * g.H[2] + t1 * g.H[5] + t2 * g.H[8]);
-    r.w = __longlong_as_double((long long)i);
-    return r;
-}
-
 // Whole bin build in one work-group (systems with at most kSmallBins bins
 // and kSmallAtoms atoms: at most kAtomsPerLane atoms per lane).  The
 // geometry of the first kGeomCache structures is kept in LDS, and each
@@ -340,11 +353,134 @@ __global__ void k_zero_i32(int32_t* p, int64_t n)
     if (i < n) p[i] = 0;
 }
 
-__global__ void k_assign(NeighborArgs a)
+// Multi-work-group exclusive scan for long arrays: per-tile sums, a
+// single-work-group scan of the sums (in place, total at the end), then
+// each tile scanned again from its offset through LDS (coalesced loads and
+// stores, each lane scanning a contiguous run of kTileRun values).
+constexpr int kTileRun = 16;
+constexpr int kScanTile = 256 * kTileRun;
+constexpr int64_t kMultiScan = 16384;   // arrays longer than this use the multi-work-group scan
+
+template <typename Tout>
+__device__ __forceinline__ Tout block256_excl(Tout v, Tout& total)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n_atoms || !*a.ok) return;
-    atomicAdd(&a.bin_count[assign_atom(a, i)], 1);
+    __shared__ Tout wsum[5];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    Tout incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        Tout u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (t == 0) {
+        Tout r = 0;
+        for (int k = 0; k < 4; ++k) { const Tout x = wsum[k]; wsum[k] = r; r += x; }
+        wsum[4] = r;
+    }
+    __syncthreads();
+    total = wsum[4];
+    return wsum[wv] + incl - v;
+}
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_tile_sums(const Tin* in, Tout* sums, int64_t n)
+{
+    const int64_t t0 = int64_t(blockIdx.x) * kScanTile + threadIdx.x;
+    Tout v[kTileRun];
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) v[u] = t0 + 256 * u < n ? Tout(in[t0 + 256 * u]) : Tout(0);
+    Tout s = 0;
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) s += v[u];
+    Tout total;
+    block256_excl<Tout>(s, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256) k_tile_scan(const Tin* in, Tout* out, Tout* out2, const Tout* offs,
+                                                   int64_t n, int64_t n_tiles)
+{
+    __shared__ Tout tile[kScanTile];
+    const int t = threadIdx.x;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    Tout v[kTileRun];
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) v[u] = base + t + 256 * u < n ? Tout(in[base + t + 256 * u]) : Tout(0);
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) tile[t + 256 * u] = v[u];
+    __syncthreads();
+    Tout run[kTileRun];
+    Tout s = 0;
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) { run[u] = tile[t * kTileRun + u]; s += run[u]; }
+    Tout total;
+    Tout r = offs[blockIdx.x] + block256_excl<Tout>(s, total);
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) { const Tout x = run[u]; tile[t * kTileRun + u] = r; r += x; }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kTileRun; ++u) {
+        const int64_t k = base + t + 256 * u;
+        if (k < n) {
+            out[k] = tile[t + 256 * u];
+            if (out2) out2[k] = tile[t + 256 * u];
+        }
+    }
+    if (blockIdx.x == 0 && t == 0) out[n] = offs[n_tiles];
+}
+
+// Large systems, one lane per atom: structure (binary search over the atom
+// offsets, kept in LDS for up to kOffsetCache structures), bin, wrap and
+// wrapped position (kept for the placing pass), bin occupancy by atomics.
+constexpr int kOffsetCache = 2048;
+
+__global__ void __launch_bounds__(256) k_assign(NeighborArgs a)
+{
+    __shared__ int64_t offs[kOffsetCache + 1];
+    const int ns = a.n_structures;
+    const bool cached = ns <= kOffsetCache;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool in = i < a.n_atoms;
+    // position and species first: they do not depend on the structure
+    double r[3] = {0.0, 0.0, 0.0};
+    int sp = 0;
+    if (in) {
+        r[0] = a.positions[3 * i];
+        r[1] = a.positions[3 * i + 1];
+        r[2] = a.positions[3 * i + 2];
+        sp = a.species[i];
+    }
+    const int ok = *a.ok;
+    if (cached) {
+        for (int k0 = threadIdx.x; k0 <= ns; k0 += 8 * 256) {
+            int64_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = k0 + u * 256 <= ns ? a.atom_offsets[k0 + u * 256] : 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u * 256 <= ns) offs[k0 + u * 256] = v[u];
+        }
+    }
+    __syncthreads();
+    if (!in || !ok) return;
+    int s;
+    if (cached) {
+        // first k in [1, ns] with offs[k] > i; the structures tile [0, N) (checked by the geometry pass)
+        int lo = 1, hi = ns;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (offs[mid] > i) hi = mid; else lo = mid + 1;
+        }
+        s = lo - 1;
+    } else {
+        s = structure_of(a.geom, ns, i);
+    }
+    double4 w;
+    const int32_t bin = place_atom(a, i, s, a.geom[s], r, sp, w);
+    a.wrapped[i] = w;
+    atomicAdd(&a.bin_count[bin], 1);
 }
 
 template <typename Tin, typename Tout>
@@ -359,9 +495,10 @@ __global__ void k_bins(NeighborArgs a)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_atoms || !*a.ok) return;
+    const double4 w = a.wrapped[i];
     int pos = atomicAdd(&a.bin_cursor[a.atom_bin[i]], 1);
     a.bin_atoms[pos] = int32_t(i);
-    a.slots[pos] = make_slot(a, i);
+    a.slots[pos] = w;
 }
 
 // ------------------------------------------------------- pair enumeration
@@ -562,15 +699,24 @@ __device__ __forceinline__ void image_shift(const NeighborArgs& a, const StructG
 // systems) the wave also sums the counts before its centre and all counts
 // itself and writes its pair_offsets entry, in place of a separate scan.
 template <bool ONE, bool F64, bool PREFIX>
-__global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
+__global__ void __launch_bounds__(kFillWaves * 64) k_fill(NeighborArgs a)
 {
     using VT = typename std::conditional<F64, double, float>::type;
-    __shared__ WaveScratch w;
+    // small systems (PREFIX): one centre per work-group, so that the few
+    // work-groups spread over every CU; otherwise kFillWaves
+    constexpr int W = PREFIX ? 1 : kFillWaves;
+    __shared__ WaveScratch ws[W];
+    // sort records of the work-group's waves, taken from one pool
     __shared__ int64_t khi[kSortCap], klo[kSortCap];
     __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
     __shared__ VT kv[3 * kSortCap];
-    const int64_t i = blockIdx.x;
-    const int lane = threadIdx.x;
+    __shared__ int pool_used;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) pool_used = 0;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * W + wave;
+    if (i >= a.n_atoms) return;
+    WaveScratch& w = ws[wave];
     int64_t total, o0;
     int n;
     if (PREFIX) {
@@ -609,7 +755,23 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
     }
     const Centre ce = load_centre<ONE>(a, i);
     if (!ce.ok || total > a.capacity) return;
-    const bool in_lds = n <= kSortCap;
+    // reserve n records of the pool (else sort in global memory)
+    int base = -1;
+    if (lane == 0) {
+        int cur = pool_used;
+        while (cur + n <= kSortCap) {
+            const int prev = atomicCAS(&pool_used, cur, cur + n);
+            if (prev == cur) { base = cur; break; }
+            cur = prev;
+        }
+    }
+    base = __shfl(base, 0, 64);
+    const bool in_lds = base >= 0;
+    int64_t* const hh = khi + (in_lds ? base : 0);
+    int64_t* const hl = klo + (in_lds ? base : 0);
+    int32_t* const jj = kj + (in_lds ? base : 0);
+    int32_t* const ss = ks + 3 * (in_lds ? base : 0);
+    VT* const vv = kv + 3 * (in_lds ? base : 0);
     const StructGeom& g = *ce.g;
     int count = 0;
     wave_visit(a, i, ce, w, [&](bool hit, int j, int c0, int c1, int c2, double vx, double vy, double vz) {
@@ -617,9 +779,9 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
         int idx = count + __popcll(mask & ((uint64_t(1) << lane) - 1));
         if (hit && idx < n) {
             if (in_lds) {
-                kj[idx] = j;
-                ks[3 * idx] = c0; ks[3 * idx + 1] = c1; ks[3 * idx + 2] = c2;
-                kv[3 * idx] = VT(vx); kv[3 * idx + 1] = VT(vy); kv[3 * idx + 2] = VT(vz);
+                jj[idx] = j;
+                ss[3 * idx] = c0; ss[3 * idx + 1] = c1; ss[3 * idx + 2] = c2;
+                vv[3 * idx] = VT(vx); vv[3 * idx + 1] = VT(vy); vv[3 * idx + 2] = VT(vz);
             } else {
                 int s0, s1, s2;
                 image_shift(a, g, ce.t, j, c0, c1, c2, s0, s1, s2);
@@ -631,33 +793,34 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
         }
         count += __popcll(mask);
     });
-    __syncthreads();
+    wave_fence();
     if (in_lds) {
         for (int p = lane; p < n; p += 64) {
-            const int j = kj[p];
+            const int j = jj[p];
             int s0, s1, s2;
-            image_shift(a, g, ce.t, j, ks[3 * p], ks[3 * p + 1], ks[3 * p + 2], s0, s1, s2);
-            ks[3 * p] = s0; ks[3 * p + 1] = s1; ks[3 * p + 2] = s2;
-            make_key(a.species[j], j, s0, s1, s2, khi[p], klo[p]);
+            image_shift(a, g, ce.t, j, ss[3 * p], ss[3 * p + 1], ss[3 * p + 2], s0, s1, s2);
+            ss[3 * p] = s0; ss[3 * p + 1] = s1; ss[3 * p + 2] = s2;
+            make_key(a.species[j], j, s0, s1, s2, hh[p], hl[p]);
         }
-        __syncthreads();
+        wave_fence();
         VT* vec = static_cast<VT*>(a.pair_vec);
         for (int p = lane; p < n; p += 64) {
-            int64_t h = khi[p], l = klo[p];
+            int64_t h = hh[p], l = hl[p];
             int rank = 0;
-            for (int q = 0; q < n; ++q) rank += key_less(khi[q], klo[q], h, l) ? 1 : 0;
+            for (int q = 0; q < n; ++q) rank += key_less(hh[q], hl[q], h, l) ? 1 : 0;
             const int64_t q = o0 + rank;
-            a.pair_j[q] = kj[p];
-            a.pair_shift[3 * q] = ks[3 * p];
-            a.pair_shift[3 * q + 1] = ks[3 * p + 1];
-            a.pair_shift[3 * q + 2] = ks[3 * p + 2];
-            vec[3 * q] = kv[3 * p];
-            vec[3 * q + 1] = kv[3 * p + 1];
-            vec[3 * q + 2] = kv[3 * p + 2];
+            a.pair_j[q] = jj[p];
+            a.pair_shift[3 * q] = ss[3 * p];
+            a.pair_shift[3 * q + 1] = ss[3 * p + 1];
+            a.pair_shift[3 * q + 2] = ss[3 * p + 2];
+            vec[3 * q] = vv[3 * p];
+            vec[3 * q + 1] = vv[3 * p + 1];
+            vec[3 * q + 2] = vv[3 * p + 2];
         }
         return;
     }
     // long environments: insertion sort in place in global memory
+    __threadfence_block();
     if (lane == 0) {
         for (int64_t p = o0 + 1; p < o0 + n; ++p) {
             int j = a.pair_j[p];
@@ -678,7 +841,8 @@ __global__ void __launch_bounds__(64) k_fill(NeighborArgs a)
             a.pair_shift[3 * (q + 1)] = s0; a.pair_shift[3 * (q + 1) + 1] = s1; a.pair_shift[3 * (q + 1) + 2] = s2;
         }
     }
-    __syncthreads();
+    __threadfence_block();
+    wave_fence();
     for (int p = lane; p < n; p += 64) {
         int64_t q = o0 + p;
         write_pair<F64>(a, g, i, q, a.pair_j[q], a.pair_shift[3 * q], a.pair_shift[3 * q + 1], a.pair_shift[3 * q + 2]);
@@ -721,6 +885,25 @@ __global__ void k_transpose(NeighborArgs a)
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
+// exclusive scan of n values (out[n] = total; capacity < 0: no check)
+template <typename Tin, typename Tout>
+void scan(const Tin* in, Tout* out, Tout* out2, int64_t n, int64_t capacity, int64_t* tmp, int32_t* status,
+          hipStream_t stream)
+{
+    if (n <= kMultiScan) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<Tin, Tout>), dim3(1), dim3(1024), 0, stream, in, out, out2, n,
+                           capacity, status);
+        return;
+    }
+    const int64_t nt = (n + kScanTile - 1) / kScanTile;
+    Tout* sums = reinterpret_cast<Tout*>(tmp);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tile_sums<Tin, Tout>), dim3(unsigned(nt)), dim3(256), 0, stream, in, sums, n);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<Tout, Tout>), dim3(1), dim3(1024), 0, stream, sums, sums,
+                       (Tout*)nullptr, nt, capacity, status);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tile_scan<Tin, Tout>), dim3(unsigned(nt)), dim3(256), 0, stream, in, out, out2,
+                       sums, n, nt);
+}
+
 }  // namespace
 
 hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
@@ -739,9 +922,8 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
     } else {
         hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
         hipLaunchKernelGGL(k_zero_i32, dim3(blocks(B + 1, T)), dim3(T), 0, stream, a.bin_count, B + 1);
-        hipLaunchKernelGGL(k_assign, dim3(blocks(N, T)), dim3(T), 0, stream, a);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int32_t, int32_t>), dim3(1), dim3(1024), 0, stream, a.bin_count,
-                           a.bin_start, a.bin_cursor, B, int64_t(-1), a.status);
+        hipLaunchKernelGGL(k_assign, dim3(blocks(N, 256)), dim3(256), 0, stream, a);
+        scan<int32_t, int32_t>(a.bin_count, a.bin_start, a.bin_cursor, B, int64_t(-1), a.scan_tmp, a.status, stream);
         hipLaunchKernelGGL(k_bins, dim3(blocks(N, T)), dim3(T), 0, stream, a);
     }
     const bool one = a.n_structures == 1;
@@ -752,11 +934,12 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
     // otherwise a scan (which also reports the count when capacity is 0)
     const bool prefix = N <= kPrefixAtoms && a.capacity > 0;
     if (!prefix)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream, a.centre_count,
-                           a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.status);
+        scan<int64_t, int64_t>(a.centre_count, a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.scan_tmp, a.status,
+                               stream);
     if (a.capacity > 0) {
-#define SOAP_FILL(ONE_, F64_, PRE_) \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<ONE_, F64_, PRE_>), grid, wave, 0, stream, a)
+#define SOAP_FILL(ONE_, F64_, PRE_)                                                                       \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<ONE_, F64_, PRE_>), dim3(blocks(N, PRE_ ? 1 : kFillWaves)), \
+                       dim3(64 * (PRE_ ? 1 : kFillWaves)), 0, stream, a)
         if (prefix) {
             if (a.vec_f64) { if (one) SOAP_FILL(true, true, true); else SOAP_FILL(false, true, true); }
             else { if (one) SOAP_FILL(true, false, true); else SOAP_FILL(false, false, true); }

@@ -149,8 +149,10 @@ struct NeighborArgs {
     int32_t* bin_start;           // [max_bins + 1]
     int32_t* bin_cursor;          // [max_bins + 1]
     int32_t* bin_atoms;           // [N]
-    double4* slots;               // [N] atoms in bin order: position x, y, z and (j, packed wrap)
+    double4* slots;               // [N] atoms in bin order: wrapped position x, y, z and the atom index
+    double4* wrapped;             // [N] the same records in atom order (large systems)
     int64_t* centre_count;        // [N + 1]
+    int64_t* scan_tmp;            // per-tile sums of the multi-work-group scan
     int32_t* ok;                  // set by the geometry phase: 1 if the input is valid
     int64_t capacity;
     int64_t* pair_offsets;
