@@ -7,17 +7,18 @@
 // nu2-basis-coupled with real coefficients).  bfloat16 keeps 8 significant
 // bits, too few for a 2e-3 relative error on p, so C is split into
 // H = bf16(C) and L = bf16(C - H) and
-//   P_l ~= H H^T + H L^T + L H^T = [H | L | H] [H | H | L]^T,
-// one product whose inner dimension is 3(2l+1); the dropped L L^T term and
-// the rounding of L leave a relative error of order 2^-16.
+//   P_l ~= H H^T + H L^T + L H^T,
+// three products of inner dimension 2l+1 (one 32-wide MFMA step each for
+// lmax <= 12); the dropped L L^T term and the rounding of L leave a
+// relative error of order 2^-16.
 //
 // W waves own one centre (W = 1, four centres per work-group, when C is
 // small; W = 4 otherwise), with no work-group barriers: the centre's waves
 // split C into their LDS region as {H, L} pairs, then for each l run the
-// 16 x 16 output tiles (I <= J), dealt round-robin, as chains of
-// v_mfma_f32_16x16x32_bf16 over the padded inner dimension (each lane
-// gathers its 8 operand values per step) and store the packed upper
-// triangle straight from the accumulators (16 consecutive k2 per store).
+// 16 x 16 output tiles (I <= J), dealt round-robin, as three
+// v_mfma_f32_16x16x32_bf16 each (a lane reads 8 consecutive {H, L} words of
+// each of its two rows) and store the packed upper triangle straight from
+// the accumulators (16 consecutive k2 per store).
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     const int64_t i = int64_t(blockIdx.x) * CPG + slot;
     if (i >= a.n_atoms) return;
     // {H, L} of every element of C: H in the low half, L in the high half
-    unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * KL2;
+    unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * (KL2 + 32);
     const float* c_in = static_cast<const float*>(a.coeffs) + i * KL2;
     // kLoadBatch loads in flight per lane before any is used
     for (int e0 = wc * 64 + lane; e0 < KL2; e0 += kLoadBatch * W * 64) {
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     const int row = lane & 15, kg = lane >> 4;
     float* p_out = static_cast<float*>(a.p) + i * int64_t(lmax + 1) * KK;
     for (int l = 0; l <= lmax; ++l) {
-        const int w = 2 * l + 1, inner = 3 * w, steps = (inner + 31) / 32;
+        const int w = 2 * l + 1;   // <= 25 for lmax <= 12: one 32-wide step per product
         float* dst = p_out + int64_t(l) * KK;
         for (int t = wc; t < n_tiles; t += W) {
             // tile t -> (I, J), I <= J, row-major over the upper triangle
@@ -96,31 +97,32 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
             while (rem >= T - I) { rem -= T - I; ++I; }
             const int J = I + rem;
             const int ka = I * 16 + row, kb = J * 16 + row;
-            const unsigned int* ra = hl + (ka < K ? ka : 0) * L2 + l * l;
-            const unsigned int* rb = hl + (kb < K ? kb : 0) * L2 + l * l;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int st = 0; st < steps; ++st) {
-                // inner index q = st*32 + kg*8 + j runs over [H | L | H] (A) and [H | H | L] (B)
-                const int q0 = st * 32 + kg * 8;
-                int seg = q0 / w, m = q0 - seg * w;
-                u16x8 av, bv;
+            // this lane's operand values: m = 8 kg + j of rows ka and kb (zero past w or past K)
+            const unsigned int* ra = hl + (ka < K ? ka : 0) * L2 + l * l + kg * 8;
+            const unsigned int* rb = hl + (kb < K ? kb : 0) * L2 + l * l + kg * 8;
+            unsigned int xa[8], xb[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    unsigned short va = 0, vb = 0;
-                    if (seg < 3) {
-                        const unsigned int xa = ra[m], xb = rb[m];
-                        va = (unsigned short)(seg == 1 ? xa >> 16 : xa & 0xFFFFu);
-                        vb = (unsigned short)(seg == 2 ? xb >> 16 : xb & 0xFFFFu);
-                        if (ka >= K) va = 0;
-                        if (kb >= K) vb = 0;
-                    }
-                    av[j] = va;
-                    bv[j] = vb;
-                    if (++m == w) { m = 0; ++seg; }
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                              __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+            for (int j = 0; j < 8; ++j) {
+                const bool ok = kg * 8 + j < w;
+                xa[j] = ok && ka < K ? ra[j] : 0u;
+                xb[j] = ok && kb < K ? rb[j] : 0u;
             }
+            u16x8 ha, la, hb, lb;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                ha[j] = (unsigned short)(xa[j] & 0xFFFFu);
+                la[j] = (unsigned short)(xa[j] >> 16);
+                hb[j] = (unsigned short)(xb[j] & 0xFFFFu);
+                lb[j] = (unsigned short)(xb[j] >> 16);
+            }
+            // P ~= H H^T + H L^T + L H^T
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, hb),
+                                                          acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, lb),
+                                                          acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, la), __builtin_bit_cast(bf16x8, hb),
+                                                          acc, 0, 0, 0);
             // lane holds D[4*kg + v][row] = P[k1][k2] with k1 = 16 I + 4 kg + v, k2 = 16 J + row
             const int k2 = J * 16 + row;
 #pragma unroll
@@ -144,7 +146,7 @@ int bf16_waves_per_centre(int S, int nmax, int lmax)
 size_t power_spectrum_bf16_lds(int S, int nmax, int lmax)
 {
     const size_t K = size_t(S) * nmax, L2 = size_t(lmax + 1) * (lmax + 1);
-    return size_t(kThreads / 64 / bf16_waves_per_centre(S, nmax, lmax)) * 4 * K * L2;
+    return size_t(kThreads / 64 / bf16_waves_per_centre(S, nmax, lmax)) * 4 * (K * L2 + 32);
 }
 
 template <int W>
