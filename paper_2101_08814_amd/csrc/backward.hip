@@ -136,24 +136,35 @@ __global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, 
     }
 }
 
+// one wave per atom k: lanes over its pairs, then a fixed reduction tree
+// (deterministic; no atomics)
 template <typename T>
-__global__ void k_exp_backward_gather(FeatureArgs a, const int32_t* transpose, const T* grad_pair, T* grad_pos)
+__global__ void __launch_bounds__(256) k_exp_backward_gather(FeatureArgs a, const int32_t* transpose,
+                                                             const T* grad_pair, T* grad_pos)
 {
-    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t k = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (k >= a.n_atoms) return;
     T gx = T(0), gy = T(0), gz = T(0);
     if (a.pair_offsets[a.n_atoms] <= a.pair_capacity) {
-        for (int64_t q = a.pair_offsets[k]; q < a.pair_offsets[k + 1]; ++q) {
-            int32_t t = transpose[q];
+        const int64_t q0 = a.pair_offsets[k], q1 = a.pair_offsets[k + 1];
+        for (int64_t q = q0 + lane; q < q1; q += 64) {
+            const int32_t t = transpose[q];
+            const T ox = grad_pair[3 * q], oy = grad_pair[3 * q + 1], oz = grad_pair[3 * q + 2];
             if (t < 0 || t >= a.pair_capacity) { put_status(a.status, SOAP_EGEOMETRY); continue; }
-            gx += grad_pair[3 * int64_t(t)] - grad_pair[3 * q];
-            gy += grad_pair[3 * int64_t(t) + 1] - grad_pair[3 * q + 1];
-            gz += grad_pair[3 * int64_t(t) + 2] - grad_pair[3 * q + 2];
+            gx += grad_pair[3 * int64_t(t)] - ox;
+            gy += grad_pair[3 * int64_t(t) + 1] - oy;
+            gz += grad_pair[3 * int64_t(t) + 2] - oz;
         }
     }
-    grad_pos[3 * k] = gx;
-    grad_pos[3 * k + 1] = gy;
-    grad_pos[3 * k + 2] = gz;
+    gx = wave_sum(gx);
+    gy = wave_sum(gy);
+    gz = wave_sum(gz);
+    if (lane == 0) {
+        grad_pos[3 * k] = gx;
+        grad_pos[3 * k + 1] = gy;
+        grad_pos[3 * k + 2] = gz;
+    }
 }
 
 template <typename T>
@@ -191,7 +202,7 @@ hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const 
     if (a.pair_capacity > 0)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_pairs<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads), lds,
                            stream, a, L, static_cast<const T*>(grad_c), static_cast<T*>(grad_pair));
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_gather<T>), dim3(unsigned((a.n_atoms + 255) / 256)), dim3(256),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_gather<T>), dim3(unsigned((a.n_atoms + 3) / 4)), dim3(256),
                        0, stream, a, transpose, static_cast<const T*>(grad_pair), static_cast<T*>(grad_pos));
     return hipGetLastError();
 }

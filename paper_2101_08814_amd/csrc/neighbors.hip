@@ -693,30 +693,24 @@ __device__ __forceinline__ void image_shift(const NeighborArgs& a, const StructG
     s2 = g.pbc[2] ? c2 + ti[2] - a.atom_wrap[3 * j + 2] : 0;
 }
 
-// one wave per centre: enumerate again (hits compacted in LDS with their
-// pair vectors), form the image shifts and sort keys of all hits at once,
-// rank them by key in LDS and write them sorted.  With PREFIX (small
-// systems) the wave also sums the counts before its centre and all counts
-// itself and writes its pair_offsets entry, in place of a separate scan.
+// Small systems: one wave per work-group and per centre, with its own
+// kSortCap sort records (the few work-groups spread over every CU); this
+// form measured faster than k_fill below at one wave per work-group.
+// Enumerate again (hits compacted in LDS with their pair vectors), form the
+// image shifts and sort keys of all hits at once, rank them by key in LDS
+// and write them sorted.  With PREFIX the wave also sums the counts before
+// its centre and all counts itself and writes its pair_offsets entry, in
+// place of a separate scan.
 template <bool ONE, bool F64, bool PREFIX>
-__global__ void __launch_bounds__(kFillWaves * 64) k_fill(NeighborArgs a)
+__global__ void __launch_bounds__(64) k_fill1(NeighborArgs a)
 {
     using VT = typename std::conditional<F64, double, float>::type;
-    // small systems (PREFIX): one centre per work-group, so that the few
-    // work-groups spread over every CU; otherwise kFillWaves
-    constexpr int W = PREFIX ? 1 : kFillWaves;
-    __shared__ WaveScratch ws[W];
-    // sort records of the work-group's waves, taken from one pool
+    __shared__ WaveScratch w;
     __shared__ int64_t khi[kSortCap], klo[kSortCap];
     __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
     __shared__ VT kv[3 * kSortCap];
-    __shared__ int pool_used;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) pool_used = 0;
-    __syncthreads();
-    const int64_t i = int64_t(blockIdx.x) * W + wave;
-    if (i >= a.n_atoms) return;
-    WaveScratch& w = ws[wave];
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
     int64_t total, o0;
     int n;
     if (PREFIX) {
@@ -755,6 +749,109 @@ __global__ void __launch_bounds__(kFillWaves * 64) k_fill(NeighborArgs a)
     }
     const Centre ce = load_centre<ONE>(a, i);
     if (!ce.ok || total > a.capacity) return;
+    const bool in_lds = n <= kSortCap;
+    const StructGeom& g = *ce.g;
+    int count = 0;
+    wave_visit(a, i, ce, w, [&](bool hit, int j, int c0, int c1, int c2, double vx, double vy, double vz) {
+        uint64_t mask = __ballot(hit);
+        int idx = count + __popcll(mask & ((uint64_t(1) << lane) - 1));
+        if (hit && idx < n) {
+            if (in_lds) {
+                kj[idx] = j;
+                ks[3 * idx] = c0; ks[3 * idx + 1] = c1; ks[3 * idx + 2] = c2;
+                kv[3 * idx] = VT(vx); kv[3 * idx + 1] = VT(vy); kv[3 * idx + 2] = VT(vz);
+            } else {
+                int s0, s1, s2;
+                image_shift(a, g, ce.t, j, c0, c1, c2, s0, s1, s2);
+                a.pair_j[o0 + idx] = j;
+                a.pair_shift[3 * (o0 + idx)] = s0;
+                a.pair_shift[3 * (o0 + idx) + 1] = s1;
+                a.pair_shift[3 * (o0 + idx) + 2] = s2;
+            }
+        }
+        count += __popcll(mask);
+    });
+    __syncthreads();
+    if (in_lds) {
+        for (int p = lane; p < n; p += 64) {
+            const int j = kj[p];
+            int s0, s1, s2;
+            image_shift(a, g, ce.t, j, ks[3 * p], ks[3 * p + 1], ks[3 * p + 2], s0, s1, s2);
+            ks[3 * p] = s0; ks[3 * p + 1] = s1; ks[3 * p + 2] = s2;
+            make_key(a.species[j], j, s0, s1, s2, khi[p], klo[p]);
+        }
+        __syncthreads();
+        VT* vec = static_cast<VT*>(a.pair_vec);
+        for (int p = lane; p < n; p += 64) {
+            int64_t h = khi[p], l = klo[p];
+            int rank = 0;
+            for (int q = 0; q < n; ++q) rank += key_less(khi[q], klo[q], h, l) ? 1 : 0;
+            const int64_t q = o0 + rank;
+            a.pair_j[q] = kj[p];
+            a.pair_shift[3 * q] = ks[3 * p];
+            a.pair_shift[3 * q + 1] = ks[3 * p + 1];
+            a.pair_shift[3 * q + 2] = ks[3 * p + 2];
+            vec[3 * q] = kv[3 * p];
+            vec[3 * q + 1] = kv[3 * p + 1];
+            vec[3 * q + 2] = kv[3 * p + 2];
+        }
+        return;
+    }
+    // long environments: insertion sort in place in global memory
+    if (lane == 0) {
+        for (int64_t p = o0 + 1; p < o0 + n; ++p) {
+            int j = a.pair_j[p];
+            int s0 = a.pair_shift[3 * p], s1 = a.pair_shift[3 * p + 1], s2 = a.pair_shift[3 * p + 2];
+            int64_t h, l;
+            make_key(a.species[j], j, s0, s1, s2, h, l);
+            int64_t q = p - 1;
+            while (q >= o0) {
+                int jq = a.pair_j[q];
+                int64_t hq, lq;
+                make_key(a.species[jq], jq, a.pair_shift[3 * q], a.pair_shift[3 * q + 1], a.pair_shift[3 * q + 2], hq, lq);
+                if (!key_less(h, l, hq, lq)) break;
+                a.pair_j[q + 1] = jq;
+                for (int x = 0; x < 3; ++x) a.pair_shift[3 * (q + 1) + x] = a.pair_shift[3 * q + x];
+                --q;
+            }
+            a.pair_j[q + 1] = j;
+            a.pair_shift[3 * (q + 1)] = s0; a.pair_shift[3 * (q + 1) + 1] = s1; a.pair_shift[3 * (q + 1) + 2] = s2;
+        }
+    }
+    __syncthreads();
+    for (int p = lane; p < n; p += 64) {
+        int64_t q = o0 + p;
+        write_pair<F64>(a, g, i, q, a.pair_j[q], a.pair_shift[3 * q], a.pair_shift[3 * q + 1], a.pair_shift[3 * q + 2]);
+    }
+}
+
+// Large systems: kFillWaves centres per work-group (one wave each) that
+// draw their sort records from one pool of kSortCap, so that four times as
+// many centres are resident as with a pool per wave; a centre whose records
+// do not fit sorts in global memory.  Otherwise as k_fill1 (offsets from
+// the scan).
+template <bool ONE, bool F64>
+__global__ void __launch_bounds__(kFillWaves * 64) k_fill(NeighborArgs a)
+{
+    using VT = typename std::conditional<F64, double, float>::type;
+    constexpr int W = kFillWaves;
+    __shared__ WaveScratch ws[W];
+    // sort records of the work-group's waves, taken from one pool
+    __shared__ int64_t khi[kSortCap], klo[kSortCap];
+    __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
+    __shared__ VT kv[3 * kSortCap];
+    __shared__ int pool_used;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) pool_used = 0;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * W + wave;
+    if (i >= a.n_atoms) return;
+    WaveScratch& w = ws[wave];
+    const int64_t total = a.pair_offsets[a.n_atoms];
+    const int64_t o0 = a.pair_offsets[i];
+    const int n = int(a.pair_offsets[i + 1] - o0);
+    const Centre ce = load_centre<ONE>(a, i);
+    if (!ce.ok || total > a.capacity) return;
     // reserve n records of the pool (else sort in global memory)
     int base = -1;
     if (lane == 0) {
@@ -767,11 +864,12 @@ __global__ void __launch_bounds__(kFillWaves * 64) k_fill(NeighborArgs a)
     }
     base = __shfl(base, 0, 64);
     const bool in_lds = base >= 0;
-    int64_t* const hh = khi + (in_lds ? base : 0);
-    int64_t* const hl = klo + (in_lds ? base : 0);
-    int32_t* const jj = kj + (in_lds ? base : 0);
-    int32_t* const ss = ks + 3 * (in_lds ? base : 0);
-    VT* const vv = kv + 3 * (in_lds ? base : 0);
+    const int off = in_lds ? base : 0;
+    int64_t* const hh = khi + off;
+    int64_t* const hl = klo + off;
+    int32_t* const jj = kj + off;
+    int32_t* const ss = ks + 3 * off;
+    VT* const vv = kv + 3 * off;
     const StructGeom& g = *ce.g;
     int count = 0;
     wave_visit(a, i, ce, w, [&](bool hit, int j, int c0, int c1, int c2, double vx, double vy, double vz) {
@@ -937,15 +1035,18 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
         scan<int64_t, int64_t>(a.centre_count, a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.scan_tmp, a.status,
                                stream);
     if (a.capacity > 0) {
-#define SOAP_FILL(ONE_, F64_, PRE_)                                                                       \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<ONE_, F64_, PRE_>), dim3(blocks(N, PRE_ ? 1 : kFillWaves)), \
-                       dim3(64 * (PRE_ ? 1 : kFillWaves)), 0, stream, a)
+#define SOAP_FILL(ONE_, F64_)                                                                             \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill<ONE_, F64_>), dim3(blocks(N, kFillWaves)), dim3(64 * kFillWaves), 0, \
+                       stream, a)
         if (prefix) {
-            if (a.vec_f64) { if (one) SOAP_FILL(true, true, true); else SOAP_FILL(false, true, true); }
-            else { if (one) SOAP_FILL(true, false, true); else SOAP_FILL(false, false, true); }
+#define SOAP_FILL1(ONE_, F64_) \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill1<ONE_, F64_, true>), grid, wave, 0, stream, a)
+            if (a.vec_f64) { if (one) SOAP_FILL1(true, true); else SOAP_FILL1(false, true); }
+            else { if (one) SOAP_FILL1(true, false); else SOAP_FILL1(false, false); }
+#undef SOAP_FILL1
         } else {
-            if (a.vec_f64) { if (one) SOAP_FILL(true, true, false); else SOAP_FILL(false, true, false); }
-            else { if (one) SOAP_FILL(true, false, false); else SOAP_FILL(false, false, false); }
+            if (a.vec_f64) { if (one) SOAP_FILL(true, true); else SOAP_FILL(false, true); }
+            else { if (one) SOAP_FILL(true, false); else SOAP_FILL(false, false); }
         }
 #undef SOAP_FILL
         if (a.pair_transpose)
