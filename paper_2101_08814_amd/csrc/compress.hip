@@ -575,7 +575,176 @@ size_t compress_bf16_lds(const CompressArgs& a)
 {
     const Bf16Dims D = bf16_dims(a.K, a.Q, a.H);
     const int MX = 2 * a.lmax + 1;
-    return ((2 * size_t(MX * kCC * D.XS + kCC * D.HS) + 15) & ~size_t(15)) + 4 * size_t(MX) * D.QT * 16 * kCC;
+    const size_t ct_slices = a.Q <= 32 ? 1 : size_t(MX);   // one m slice of c~ when p~ sums in registers
+    return ((2 * size_t(MX * kCC * D.XS + kCC * D.HS) + 15) & ~size_t(15)) + 4 * ct_slices * D.QT * 16 * kCC;
+}
+
+// The same product for Q <= 32 with the packed p~ of the 16 centres kept
+// in registers and summed over m as each c~_m appears (one m slice of c~
+// in LDS instead of all of them): about half the LDS of the form above, so
+// two work-groups share a CU.  Lane j < ceil(Q/2) of centre c (16 lanes
+// per centre) owns rows q1 = j and Q-1-j of its packed triangle, Q + 1
+// entries, so no index is decoded.  X_l is read row by row, the M values
+// of a (centre, k) row in flight together.
+constexpr int kMMax = 25;   // 2 lmax + 1 for lmax <= 12
+
+template <bool WANT_CT, bool WANT_PT, int QMAX>
+__global__ void __launch_bounds__(kThreads, 2) k_cmp_fwd_bf16_r(CompressArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int K = a.K, Q = a.Q, H = a.H, lmax = a.lmax, L2 = (lmax + 1) * (lmax + 1), MX = 2 * lmax + 1;
+    const int QQ = Q * (Q + 1) / 2;
+    const Bf16Dims D = bf16_dims(K, Q, H);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+    const int64_t i0 = int64_t(blockIdx.x) * kCC;
+    const int nc = a.n - i0 < kCC ? int(a.n - i0) : kCC;
+    unsigned short* Xs = reinterpret_cast<unsigned short*>(smem_raw);      // [MX][kCC][XS]
+    unsigned short* Hs = Xs + MX * kCC * D.XS;                              // [kCC][HS]
+    float* CTm = reinterpret_cast<float*>(smem_raw + ((2 * size_t(MX * kCC * D.XS + kCC * D.HS) + 15) & ~size_t(15)));
+    // p~ rows of this lane: centre pc, rows q1 = pj and Q-1-pj (once if equal)
+    const int pc = tid >> 4, pj = tid & 15;
+    const int rowA = pj, rowB = Q - 1 - pj;
+    const bool p_on = WANT_PT && pc < nc && rowA <= rowB;
+    const int nA = Q - rowA, nB = rowB > rowA ? Q - rowB : 0;   // entries of the two rows
+    float acc_p[QMAX + 1];
+#pragma unroll
+    for (int u = 0; u <= QMAX; ++u) acc_p[u] = 0.0f;
+    const float* w = a.w;
+    for (int l = 0; l <= lmax; ++l) {
+        const int M = 2 * l + 1, b = l * l;
+        const float* W1 = w;
+        const float* W2 = W1 + H * K;
+        const float* al = W2 + Q * H;
+        const float* be = al + H;
+        w = be + H;
+        // X_l of the 16 centres, bfloat16, zero beyond K and beyond the last centre
+        for (int row = tid; row < kCC * D.Kp; row += kThreads) {
+            const int c = row / D.Kp, k = row - c * D.Kp;
+            const bool ok = k < K && c < nc;
+            const float* src = a.c + ((i0 + (ok ? c : 0)) * K + (ok ? k : 0)) * L2 + b;
+            float v[kMMax];
+#pragma unroll
+            for (int m = 0; m < kMMax; ++m) v[m] = (ok && m < M) ? src[m] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < kMMax; ++m)
+                if (m < M) Xs[(m * kCC + c) * D.XS + k] = to_bf16(v[m]);
+        }
+        u16x8 A1[kMT][kKS1];
+#pragma unroll
+        for (int t = 0; t < kMT; ++t)
+#pragma unroll
+            for (int ks = 0; ks < kKS1; ++ks) {
+                const int q = (wave + 4 * t) * 16 + r;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = ks * 32 + 8 * g + j;
+                    A1[t][ks][j] = (q < H && k < K && ks < D.KS1) ? to_bf16(W1[q * K + k]) : (unsigned short)0;
+                }
+            }
+        __syncthreads();
+        float n2[kMT][4] = {};
+        for (int m = 0; m < M; ++m) {
+            u16x8 B[kKS1];
+#pragma unroll
+            for (int ks = 0; ks < kKS1; ++ks)
+                if (ks < D.KS1) B[ks] = *reinterpret_cast<const u16x8*>(&Xs[(m * kCC + r) * D.XS + ks * 32 + 8 * g]);
+#pragma unroll
+            for (int t = 0; t < kMT; ++t) {
+                if (wave + 4 * t >= D.HT) break;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kKS1; ++ks)
+                    if (ks < D.KS1)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A1[t][ks]),
+                                                                      __builtin_bit_cast(bf16x8, B[ks]), acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) n2[t][v] += acc[v] * acc[v];
+            }
+        }
+        float G[kMT][4];
+#pragma unroll
+        for (int t = 0; t < kMT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int q = (wave + 4 * t) * 16 + 4 * g + v;
+                G[t][v] = q < H ? 2.0f * sigm(al[q] * sqrtf(n2[t][v]) + be[q]) : 0.0f;
+            }
+        u16x8 A2[kKS2];
+#pragma unroll
+        for (int ks = 0; ks < kKS2; ++ks) {
+            const int p = wave * 16 + r;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int q = ks * 32 + 8 * g + j;
+                A2[ks][j] = (wave < D.QT && p < Q && q < H && ks < D.KS2) ? to_bf16(W2[p * H + q]) : (unsigned short)0;
+            }
+        }
+        for (int m = 0; m < M; ++m) {
+            u16x8 B[kKS1];
+#pragma unroll
+            for (int ks = 0; ks < kKS1; ++ks)
+                if (ks < D.KS1) B[ks] = *reinterpret_cast<const u16x8*>(&Xs[(m * kCC + r) * D.XS + ks * 32 + 8 * g]);
+#pragma unroll
+            for (int t = 0; t < kMT; ++t) {
+                if (wave + 4 * t >= D.HT) break;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kKS1; ++ks)
+                    if (ks < D.KS1)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A1[t][ks]),
+                                                                      __builtin_bit_cast(bf16x8, B[ks]), acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = (wave + 4 * t) * 16 + 4 * g + v;
+                    Hs[r * D.HS + q] = to_bf16(acc[v] * G[t][v]);
+                }
+            }
+            for (int e = tid; e < kCC * (D.Hp - D.HT * 16); e += kThreads) {
+                const int c = e / (D.Hp - D.HT * 16), q = D.HT * 16 + e % (D.Hp - D.HT * 16);
+                Hs[c * D.HS + q] = 0;
+            }
+            __syncthreads();
+            if (wave < D.QT) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < kKS2; ++ks)
+                    if (ks < D.KS2) {
+                        const u16x8 Bv = *reinterpret_cast<const u16x8*>(&Hs[r * D.HS + ks * 32 + 8 * g]);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A2[ks]),
+                                                                      __builtin_bit_cast(bf16x8, Bv), acc, 0, 0, 0);
+                    }
+                // c~_m[q][centre]
+#pragma unroll
+                for (int v = 0; v < 4; ++v) CTm[(wave * 16 + 4 * g + v) * kCC + r] = acc[v];
+            }
+            __syncthreads();
+            if (p_on) {
+                const float a1 = CTm[rowA * kCC + pc], b1 = CTm[rowB * kCC + pc];
+#pragma unroll
+                for (int u = 0; u <= QMAX; ++u) {
+                    // entry u: (rowA, rowA + u) for u < nA, then (rowB, rowB + u - nA)
+                    if (u < nA) acc_p[u] += a1 * CTm[(rowA + u) * kCC + pc];
+                    else if (u < nA + nB) acc_p[u] += b1 * CTm[(rowB + u - nA) * kCC + pc];
+                }
+            }
+            if (WANT_CT)
+                for (int e = tid; e < nc * Q; e += kThreads) {
+                    const int q = e % Q, c = e / Q;
+                    a.ct[((i0 + c) * Q + q) * L2 + b + m] = CTm[q * kCC + c];
+                }
+        }
+        if (p_on) {
+            float* dst = a.pt + ((i0 + pc) * (lmax + 1) + l) * int64_t(QQ);
+            const int sA = rowA * Q - rowA * (rowA - 1) / 2, sB = rowB * Q - rowB * (rowB - 1) / 2;
+#pragma unroll
+            for (int u = 0; u <= QMAX; ++u) {
+                if (u < nA) dst[sA + u] = acc_p[u];
+                else if (u < nA + nB) dst[sB + u - nA] = acc_p[u];
+                acc_p[u] = 0.0f;
+            }
+        }
+        __syncthreads();
+    }
 }
 
 inline unsigned blocks_of(int64_t n, int t) { return unsigned((n + t - 1) / t); }
@@ -618,8 +787,12 @@ hipError_t launch_compress_forward_bf16(const CompressArgs& a, hipStream_t strea
     if (a.K > 32 * kKS1 || a.H > 16 * 4 * kMT || a.Q > 64) return hipErrorNotSupported;
     const size_t lds = compress_bf16_lds(a);
     if (lds > 160 * 1024) return hipErrorNotSupported;
-    auto kernel = a.ct ? (a.pt ? k_cmp_fwd_bf16<true, true> : k_cmp_fwd_bf16<true, false>)
-                       : k_cmp_fwd_bf16<false, true>;
+    auto kernel = a.Q <= 16 ? (a.ct ? (a.pt ? k_cmp_fwd_bf16_r<true, true, 16> : k_cmp_fwd_bf16_r<true, false, 16>)
+                                    : k_cmp_fwd_bf16_r<false, true, 16>)
+                : a.Q <= 32 ? (a.ct ? (a.pt ? k_cmp_fwd_bf16_r<true, true, 32> : k_cmp_fwd_bf16_r<true, false, 32>)
+                                    : k_cmp_fwd_bf16_r<false, true, 32>)
+                            : (a.ct ? (a.pt ? k_cmp_fwd_bf16<true, true> : k_cmp_fwd_bf16<true, false>)
+                                    : k_cmp_fwd_bf16<false, true>);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
