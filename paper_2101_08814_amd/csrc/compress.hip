@@ -233,10 +233,10 @@ __global__ void k_reduce(const float* part, int slices, int64_t n, float* out)
     out[e] = acc;
 }
 
-// ---------------------------------------------------- channel covariance
-// cov[l][k1][k2] partial sums over slices of centres:
-// sum_{i in slice, m} c_{i,k1,lm} c_{i,k2,lm}; grid (lmax + 1, K, slices).
-__global__ void __launch_bounds__(kThreads) k_channel_cov(CompressArgs a, float* part)
+// Per-l channel covariance sum_{i, m} c_{i,k1,lm} c_{i,k2,lm}, partial sums
+// over slices of the centres.  Wide channel counts (K > 128): one
+// work-group per (l, k1, slice), lanes over k2, centres s, s + S, ...
+__global__ void __launch_bounds__(kThreads) k_channel_cov_wide(CompressArgs a, float* part)
 {
     const int K = a.K, lmax = a.lmax, L2 = (lmax + 1) * (lmax + 1);
     const int l = blockIdx.x, k1 = blockIdx.y, S = gridDim.z, s = blockIdx.z;
@@ -250,6 +250,76 @@ __global__ void __launch_bounds__(kThreads) k_channel_cov(CompressArgs a, float*
         part[((int64_t(s) * (lmax + 1) + l) * K + k1) * K + k2] = acc;
     }
 }
+
+constexpr int kCovBatch = 4;
+constexpr int kCovR = 8;
+
+// Per-l channel covariance sum_{i, m} c_{i,k1,lm} c_{i,k2,lm} over a
+// contiguous slice of the centres (grid (lmax + 1, slices)): kCovBatch
+// centres' X_l at a time go to LDS (loads in flight together), and lane
+// (a, b) of the 16 x 16 lanes accumulates the k1 = a + 16 u, k2 = b + 16 v
+// entries in registers (K <= 16 kCovR).
+__global__ void __launch_bounds__(kThreads) k_channel_cov(CompressArgs a, float* part)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* X = reinterpret_cast<float*>(smem_raw);   // [kCovBatch][K][M]
+    const int K = a.K, lmax = a.lmax, L2 = (lmax + 1) * (lmax + 1);
+    const int l = blockIdx.x, S = gridDim.y, s = blockIdx.y;
+    const int M = 2 * l + 1, b = l * l, KM = K * M;
+    const int64_t lo = a.n * s / S, hi = a.n * (s + 1) / S;
+    const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
+    float acc[kCovR][kCovR];
+#pragma unroll
+    for (int u = 0; u < kCovR; ++u)
+#pragma unroll
+        for (int v = 0; v < kCovR; ++v) acc[u][v] = 0.0f;
+    for (int64_t i0 = lo; i0 < hi; i0 += kCovBatch) {
+        const int nb = hi - i0 < kCovBatch ? int(hi - i0) : kCovBatch;
+        __syncthreads();
+        for (int e0 = threadIdx.x; e0 < nb * KM; e0 += 8 * kThreads) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kThreads;
+                if (e < nb * KM) {
+                    const int c = e / KM, r = e - c * KM, k = r / M, m = r - k * M;
+                    v[u] = a.c[((i0 + c) * K + k) * int64_t(L2) + b + m];
+                } else {
+                    v[u] = 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e0 + u * kThreads < nb * KM) X[e0 + u * kThreads] = v[u];
+        }
+        __syncthreads();
+        for (int c = 0; c < nb; ++c) {
+            const float* Xc = X + c * KM;
+            for (int m = 0; m < M; ++m) {
+                float xa[kCovR], xb[kCovR];
+#pragma unroll
+                for (int u = 0; u < kCovR; ++u) {
+                    const int k1 = ta + 16 * u, k2 = tb + 16 * u;
+                    xa[u] = k1 < K ? Xc[k1 * M + m] : 0.0f;
+                    xb[u] = k2 < K ? Xc[k2 * M + m] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kCovR; ++u)
+#pragma unroll
+                    for (int v = 0; v < kCovR; ++v) acc[u][v] += xa[u] * xb[v];
+            }
+        }
+    }
+    float* out = part + (int64_t(s) * (lmax + 1) + l) * K * K;
+#pragma unroll
+    for (int u = 0; u < kCovR; ++u)
+#pragma unroll
+        for (int v = 0; v < kCovR; ++v) {
+            const int k1 = ta + 16 * u, k2 = tb + 16 * v;
+            if (k1 < K && k2 < K) out[k1 * K + k2] = acc[u][v];
+        }
+}
+
 
 // ------------------------------------------------ kernel matrix and loss
 // Tiled products of the feature matrix X [n][F] (F = (lmax+1) Q(Q+1)/2):
@@ -819,8 +889,19 @@ hipError_t launch_compress_backward(const CompressArgs& a, float* grad, hipStrea
 
 hipError_t launch_channel_cov(const CompressArgs& a, float* part, int slices, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_channel_cov, dim3(unsigned(a.lmax + 1), unsigned(a.K), unsigned(slices)), dim3(kThreads), 0,
-                       stream, a, part);
+    if (a.K > 16 * kCovR) {
+        hipLaunchKernelGGL(k_channel_cov_wide, dim3(unsigned(a.lmax + 1), unsigned(a.K), unsigned(slices)),
+                           dim3(kThreads), 0, stream, a, part);
+        return hipGetLastError();
+    }
+    const size_t lds = sizeof(float) * kCovBatch * size_t(a.K) * (2 * a.lmax + 1);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_channel_cov),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_channel_cov, dim3(unsigned(a.lmax + 1), unsigned(slices)), dim3(kThreads), lds, stream, a,
+                       part);
     return hipGetLastError();
 }
 

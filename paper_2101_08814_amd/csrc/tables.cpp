@@ -292,11 +292,22 @@ void sym_eigen(int n, std::vector<double> A, std::vector<double>& w, std::vector
         }
     };
     const double eps = 2.220446049250313e-16;
+    // A subdiagonal entry is negligible next to its two diagonal neighbours
+    // or next to the whole matrix: the second test deflates blocks of
+    // (near-)zero eigenvalues, whose neighbours are themselves rounding
+    // noise, at a backward error of eps |A|.
+    double anorm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        anorm += at(A, i, i) * at(A, i, i);
+        if (i + 1 < n) anorm += 2.0 * at(A, i + 1, i) * at(A, i + 1, i);
+    }
+    anorm = std::sqrt(anorm);
     int hi = n - 1;
     for (int iter = 0; hi > 0 && iter < 100 * n; ++iter) {
         // deflate negligible subdiagonal entries
         for (int i = 0; i < hi; ++i)
-            if (std::fabs(at(A, i + 1, i)) <= eps * (std::fabs(at(A, i, i)) + std::fabs(at(A, i + 1, i + 1)))) {
+            if (std::fabs(at(A, i + 1, i)) <= eps * (std::fabs(at(A, i, i)) + std::fabs(at(A, i + 1, i + 1))) ||
+                std::fabs(at(A, i + 1, i)) <= eps * anorm) {
                 at(A, i + 1, i) = at(A, i, i + 1) = 0.0;
             }
         while (hi > 0 && at(A, hi, hi - 1) == 0.0) --hi;

@@ -140,11 +140,12 @@ def test_pca_start_matches_oracle_baseline(cells):
     w_ref = C.pca_weights(c64, 16, 128)
     eps_ref = C.kernel_error(pf, C.power_spectrum(C.compress(c64, w_ref, 16, 128)))
     print(f"[compress pca] eps_K gpu {eps_gpu:.5f} oracle {eps_ref:.5f}")
-    # the library sums the covariance in float; the leading subspace then
-    # turns slightly where eigenvalues near the 16th are close, which moves
-    # eps_K by a few parts in 1e3 (a wrong order or transpose moves it by
-    # far more)
-    assert abs(eps_gpu - eps_ref) <= 1e-2 * eps_ref
+    # the library sums the covariance in float (a relative error near 1e-7
+    # on each l block) and diagonalises it in double; the gap after the 16th
+    # eigenvalue is at least 6 % on every l here, so the kept subspace, and
+    # eps_K with it, follow to far better than 1e-3 (a solver that stops
+    # short, a wrong order or a transpose move eps_K by percent)
+    assert abs(eps_gpu - eps_ref) <= 1e-3 * eps_ref
 
 
 def test_training_lowers_the_kernel_error(cells):
