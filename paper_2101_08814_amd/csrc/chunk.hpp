@@ -76,13 +76,14 @@ struct Layout {
 // yz: elements of the region for the per-(pair, l, k) operands of the
 // gradient rows (it reuses the Legendre table's space); pos: entries of the
 // table of dp row positions.
+// with_c = false leaves out the c accumulator (kept in registers instead).
 __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, int yz = 0, bool self_rows = true,
-                                              bool want_tri = false, int pos = 0)
+                                              bool want_tri = false, int pos = 0, bool with_c = true)
 {
     Layout L;
     L.chunk = ch;
     int o = 0;
-    L.c = o; o += d.K * d.L2;
+    L.c = o; o += with_c ? d.K * d.L2 : 0;
     L.dcs = o; o += (grad && self_rows) ? 3 * d.K * d.L2 : 0;
     L.ux = o; o += ch;
     L.uy = o; o += ch;
@@ -121,15 +122,15 @@ __host__ __device__ inline Layout make_layout(const Dims& d, int ch, bool grad, 
 // (four work-groups of 256 lanes per CU), else 64 KB, else 160 KB;
 // total = 0 if nothing fits.
 template <typename T>
-inline Layout choose_layout(const Dims& d, bool grad, bool self_rows, bool want_tri)
+inline Layout choose_layout(const Dims& d, bool grad, bool self_rows, bool want_tri, bool with_c = true)
 {
     const size_t limits[3] = {40 * 1024, 64 * 1024, 160 * 1024};
     for (size_t lim : limits)
         for (int ch = 32; ch >= 4; ch /= 2) {
-            Layout L = make_layout(d, ch, grad, 0, self_rows, want_tri);
+            Layout L = make_layout(d, ch, grad, 0, self_rows, want_tri, 0, with_c);
             if (size_t(L.total) * sizeof(T) <= lim) return L;
         }
-    Layout L = make_layout(d, 2, grad, 0, self_rows, want_tri);
+    Layout L = make_layout(d, 2, grad, 0, self_rows, want_tri, 0, with_c);
     if (size_t(L.total) * sizeof(T) > 160 * 1024) L.total = 0;
     return L;
 }

@@ -32,12 +32,18 @@ using namespace dev;
 // Per-centre pass: c, p and (with gradients) the self rows of c and p; with
 // ROWS also the pair rows of c and p.
 // One thread owns a species channel and an lm and accumulates every n of it
-// over the centre's pairs of that species.
+// over the centre's pairs of that species.  REGC (c alone, at most
+// kRegItems items per lane): the sums stay in registers, the layout has no c
+// region, so the chunk can hold more pairs and a centre takes fewer
+// staging rounds.
 // ---------------------------------------------------------------------------
-template <typename T, int LM, bool GRAD, bool WANT_P, bool ROWS>
-__global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
+constexpr int kRegItems = 16;
+
+template <typename T, int LM, bool GRAD, bool WANT_P, bool ROWS, bool REGC>
+__device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout& L)
 {
     static_assert(!ROWS || (GRAD && WANT_P), "pair rows come with the self rows and p");
+    static_assert(!REGC || (!GRAD && !WANT_P), "register sums are for c alone");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* base = reinterpret_cast<T*>(smem_raw);
     Smem<T> s(base, L);
@@ -55,20 +61,50 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
     const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
     const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
     const int KK = d.KK, PL = lm1 * KK;
-    for (int e = tid; e < KL2; e += kThreads) {
-        s.c[e] = T(0);
-        if (GRAD) { s.dcs[e] = T(0); s.dcs[KL2 + e] = T(0); s.dcs[2 * KL2 + e] = T(0); }
-    }
+    if (!REGC)
+        for (int e = tid; e < KL2; e += kThreads) {
+            s.c[e] = T(0);
+            if (GRAD) { s.dcs[e] = T(0); s.dcs[KL2 + e] = T(0); s.dcs[2 * KL2 + e] = T(0); }
+        }
     // packed (l, k1, k2) of every position of a dp row: l | k1 << 4 | k2 << 14
     if (ROWS)
         for (int o = tid; o < PL; o += kThreads) s.pos[o] = a.dp_pos[o];
     // items (species, n pair, lm): two n per thread share the Y and dY loads
     const int ng = (d.nmax + 1) / 2;
     const int items = d.S * ng * d.L2;
+    T rc[REGC ? kRegItems : 1][2];
+#pragma unroll
+    for (int j = 0; j < (REGC ? kRegItems : 1); ++j) rc[j][0] = rc[j][1] = T(0);
     for (int ck = 0; ck < n_chunks; ++ck) {
         int64_t q0 = q_begin + int64_t(ck) * chunk;
         int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
         stage_chunk<T, GRAD>(a, d, s, q0, nc);
+        if constexpr (REGC) {
+#pragma unroll
+            for (int j = 0; j < kRegItems; ++j) {
+                int t = tid + j * kThreads;
+                if (t >= items) break;
+                // keep the item's decode inside the chunk loop: hoisted
+                // for every j it would hold ~100 registers across the staging
+                asm volatile("" : "+v"(t));
+                const int sp = t / (ng * d.L2), rem = t - sp * (ng * d.L2), g = rem / d.L2, lm = rem - g * d.L2;
+                const int n0 = 2 * g, two = n0 + 1 < d.nmax;
+                const int l = s.lof[lm];
+                T c0 = T(0), c1 = T(0);
+                const int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
+                for (int p = p0; p < p1; ++p) {
+                    if (s.spc[p] != sp) continue;
+                    const T Yv = s.Y[p * d.L2 + lm];
+                    const T* Rp = s.R + p * d.nl + n0 * lm1 + l;
+                    c0 += Rp[0] * Yv;
+                    c1 += (two ? Rp[lm1] : T(0)) * Yv;
+                }
+                rc[j][0] += c0;
+                rc[j][1] += c1;
+            }
+            if (ck + 1 < n_chunks) __syncthreads();
+            continue;
+        }
         for (int t = tid; t < items; t += kThreads) {
             const int sp = t / (ng * d.L2), rem = t - sp * (ng * d.L2), g = rem / d.L2, lm = rem - g * d.L2;
             const int n0 = 2 * g, two = n0 + 1 < d.nmax;
@@ -128,6 +164,30 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
             }
         }
         if (ck + 1 < n_chunks) __syncthreads();
+    }
+    if constexpr (REGC) {
+        // c straight from the registers, the central atom's term added to
+        // the lm = 0 entries of its own species
+        const int sp_i = a.include_center ? a.species[i] : -1;
+        if (a.include_center && tid == 0 && (sp_i < 0 || sp_i >= d.S)) put_status(a.status, SOAP_ESPECIES);
+        const T* centre_term = static_cast<const T*>(a.center);
+        T* c_out = static_cast<T*>(a.coeffs) + i * KL2;
+#pragma unroll
+        for (int j = 0; j < kRegItems; ++j) {
+            const int t = tid + j * kThreads;
+            if (t >= items) break;
+            const int sp = t / (ng * d.L2), rem = t - sp * (ng * d.L2), g = rem / d.L2, lm = rem - g * d.L2;
+            const int n0 = 2 * g, two = n0 + 1 < d.nmax;
+            T v0 = rc[j][0], v1 = rc[j][1];
+            if (lm == 0 && sp == sp_i) {
+                v0 += centre_term[n0];
+                if (two) v1 += centre_term[n0 + 1];
+            }
+            const int e0 = (sp * d.nmax + n0) * d.L2 + lm;
+            c_out[e0] = v0;
+            if (two) c_out[e0 + d.L2] = v1;
+        }
+        return;
     }
     __syncthreads();
     if (a.include_center && tid < d.nmax) {
@@ -235,6 +295,19 @@ __global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
             wave_sync();
         }
     }
+}
+
+template <typename T, int LM, bool GRAD, bool WANT_P, bool ROWS>
+__global__ void __launch_bounds__(kThreads) k_centres(FeatureArgs a, Layout L)
+{
+    centres_body<T, LM, GRAD, WANT_P, ROWS, false>(a, L);
+}
+
+// c alone with register sums: four work-groups per CU (at most 128 VGPRs)
+template <typename T, int LM>
+__global__ void __launch_bounds__(kThreads, 4) k_centres_c(FeatureArgs a, Layout L)
+{
+    centres_body<T, LM, false, false, false, true>(a, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,6 +440,9 @@ hipError_t centres_launch(const FeatureArgs& a, const Layout& L, size_t lds, boo
 {
     const bool grad = a.dcoeffs_self != nullptr, want_p = a.p != nullptr;
     if (rows) return launch_feat(k_centres<T, LM, true, true, true>, lds, stream, a, L);
+    if constexpr (std::is_same<T, float>::value)
+        if (L.c == L.dcs)   // no c region: register sums
+            return launch_feat(k_centres_c<T, LM>, lds, stream, a, L);
     if (grad)
         return want_p ? launch_feat(k_centres<T, LM, true, true, false>, lds, stream, a, L)
                       : launch_feat(k_centres<T, LM, true, false, false>, lds, stream, a, L);
@@ -399,6 +475,14 @@ hipError_t features_t(const FeatureArgs& a, hipStream_t stream)
             return by_lmax<T, CentresFn>(a.lmax, c, L, size_t(L.total) * sizeof(T), true, stream);
     }
     Layout L = choose_layout<T>(d, grad, true, want_p);
+    // c alone in float, when its LDS accumulator forces chunks below 32
+    // pairs: register sums instead (128 VGPRs, four work-groups per CU; in
+    // double they would spill).  When the chunk already holds 32 pairs the
+    // LDS form keeps more work-groups per CU.
+    const bool regc = std::is_same<T, float>::value && !grad && !want_p &&
+                      d.S * ((d.nmax + 1) / 2) * d.L2 <= kRegItems * kThreads &&
+                      (L.chunk < 32 || size_t(L.total) * sizeof(T) > 40 * 1024);
+    if (regc) L = choose_layout<T>(d, false, true, false, false);
     if (L.total == 0) return hipErrorNotSupported;
     size_t lds = size_t(L.total) * sizeof(T);
     hipError_t e = by_lmax<T, CentresFn>(a.lmax, c, L, lds, false, stream);

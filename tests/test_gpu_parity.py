@@ -220,6 +220,10 @@ def test_fused_rows_over_many_chunks(dt):
     same = 1e-12 if dt == torch.float64 else 1e-6
     for name, x, y in [("dc", dc[:Pn], r_dc[:Pn]), ("dp", dp[:Pn], r_dp[:Pn])]:
         assert rel(x.double().cpu().numpy(), y.double().cpu().numpy()) <= same, name
+    # c alone (in float the sums stay in registers across the chunks)
+    c_only = calc.spherical_expansion(nl, spc, dt)
+    assert rel(c_only.double().cpu().numpy(), ref_c) <= tol
+    assert rel(c_only.double().cpu().numpy(), c.double().cpu().numpy()) <= same
 
 
 def test_gradient_rows_entry_point():
@@ -284,9 +288,11 @@ def test_multispecies_fp32_parity(n_cells):
     assert calc.device_status() == 0
     ref_nl, ref_c, ref_p = oracle.features(b)
     ec, ep, e16 = rel(c, ref_c), rel(p, ref_p), rel(p16.double().cpu().numpy(), ref_p)
+    ect = rel(c_t.double().cpu().numpy(), ref_c)
     w16 = worst_centre(p16.double().cpu().numpy(), ref_p)
-    print(f"[multispecies {n_cells} cells] rel c={ec:.3e} p={ep:.3e} p_bf16={e16:.3e} worst-centre bf16={w16:.3e}")
-    assert ec <= 1e-6 and ep <= 1e-6
+    print(f"[multispecies {n_cells} cells] rel c={ec:.3e} c alone={ect:.3e} p={ep:.3e} p_bf16={e16:.3e} "
+          f"worst-centre bf16={w16:.3e}")
+    assert ec <= 1e-6 and ect <= 1e-6 and ep <= 1e-6
     assert e16 <= 2e-3 and w16 <= 2e-3
 
 
