@@ -817,6 +817,342 @@ __global__ void __launch_bounds__(kThreads, 2) k_cmp_fwd_bf16_r(CompressArgs a)
     }
 }
 
+// One wave per centre, cpw centres per work-group sharing the weights of
+// the current l in LDS.  The centre's c goes to LDS once, read as float4
+// with consecutive lanes on consecutive addresses, as bfloat16 rows
+// X[lm][k].  Per l the columns of every product are the m of the centre
+// (one 16-wide tile, two when 2l + 1 > 16):
+//   layer 1  h = W1_l X_m, 16-row tiles of hidden units, 32-wide k-steps;
+//            h stays in registers for the whole l;
+//   gate     |h_q|^2 over m, summed across the 16 column lanes of a row
+//            with DPP rotations;
+//   layer 2  c~ = W2_l (G h).  W1_l is staged in LDS with its rows in the
+//            order that makes a lane's layer-1 accumulators its operand of
+//            the layer-2 product: row 4g + v of tile t holds hidden unit
+//            32 (t >> 1) + 8 g + 4 (t & 1) + v, so the two tiles of k-step
+//            ks give lane g exactly units 32 ks + 8 g + j, j < 8;
+//   p~       the Gram matrix of c~ over m on the matrix cores, c~ split into
+//            bfloat16 high and low parts (H H^T + H L^T + L H^T, as for the
+//            full spectrum), from c~ staged in the wave's own LDS.
+// Two work-group barriers per l (the shared weights); none per m.
+constexpr int kWaveCentres = 8;   // most centres (waves) per work-group
+constexpr int kCB = 36;           // row stride of the c~ staging (floats, 16-byte rows)
+constexpr int kXLoads = 16;       // float4 loads of c a lane keeps in flight
+constexpr int kWQuads = 12;       // weight float4s a lane stages per l from kept offsets
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// two floats to packed bfloat16 (round to nearest even), low half first
+__device__ __forceinline__ unsigned int pack_bf16(float lo, float hi)
+{
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(unsigned int, __builtin_convertvector(v, bf16x2));
+}
+
+// sum over the 16 lanes of a DPP row (every lane receives the sum)
+__device__ __forceinline__ float row_sum16(float s)
+{
+    s += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), 0x128, 0xF, 0xF, false));
+    s += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), 0x124, 0xF, 0xF, false));
+    s += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), 0x122, 0xF, 0xF, false));
+    s += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), 0x121, 0xF, 0xF, false));
+    return s;
+}
+
+struct WaveLayout {
+    int Kp, XS, Hp, HS, HT, KS, KS2, QT, cpw;
+    int E1, E2, E;           // weight float4s per l: W1 rows, W2 rows, then {alpha, beta}
+    int x_bytes, cb_bytes;   // per centre
+    int w1, w2, ab, x, cb, total;   // byte offsets, 16-byte aligned
+};
+
+__host__ __device__ inline int up16(int b) { return (b + 15) & ~15; }
+
+__host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax, int cpw)
+{
+    WaveLayout W;
+    W.Kp = (K + 31) / 32 * 32;
+    W.XS = W.Kp + 8;   // row stride (bf16) of X and W1: 16 consecutive rows hit distinct banks
+    W.Hp = (H + 31) / 32 * 32;
+    W.HS = W.Hp + 8;
+    W.HT = W.Hp / 16;
+    W.KS = W.Kp / 32;
+    W.KS2 = W.Hp / 32;
+    W.QT = (Q + 15) / 16;
+    W.cpw = cpw;
+    W.E1 = W.HT * 16 * (W.Kp / 4);
+    W.E2 = W.QT * 16 * (W.Hp / 4);
+    W.E = W.E1 + W.E2 + W.Hp / 2;
+    const int L2 = (lmax + 1) * (lmax + 1);
+    W.x_bytes = up16(L2 * W.XS * 2);
+    W.cb_bytes = up16(W.QT * 16 * kCB * 4);
+    int o = 0;
+    W.w1 = o; o += up16(W.HT * 16 * W.XS * 2);
+    W.w2 = o; o += up16(W.QT * 16 * W.HS * 2);
+    W.ab = o; o += up16(2 * W.Hp * 4);
+    W.x = o; o += cpw * W.x_bytes;
+    W.cb = o; o += cpw * W.cb_bytes;
+    W.total = o;
+    return W;
+}
+
+// column of element (lm, k) in the LDS rows of X: 8-element groups swapped
+// within their 32-wide k-step by bits 4-5 of lm, so the stores of a wave
+// (consecutive lanes 4 lm apart) spread over the banks while the 16 rows of
+// an operand read keep one swizzle
+__device__ __forceinline__ int xcol(int lm, int k) { return k ^ (((lm >> 4) & 3) << 3); }
+
+// hidden unit held by LDS row `row` of the staged W1
+__device__ __forceinline__ int wave_unit(int row)
+{
+    const int t = row >> 4, rho = row & 15;
+    return 32 * (t >> 1) + 8 * (rho >> 2) + 4 * (t & 1) + (rho & 3);
+}
+
+// Weight float4 e of one l: its offset in the l's weights (-1: outside
+// them, staged as zeros) and its byte offset in LDS.  W1 rows (bfloat16, in
+// the unit order above), W2 rows (bfloat16), then {alpha_l, beta_l} (float).
+__device__ __forceinline__ void wave_weight_slot(const CompressArgs& a, const WaveLayout& W, int e, int& src, int& dst)
+{
+    const int K = a.K, H = a.H, Q = a.Q;
+    if (e < W.E1) {
+        const int kq = W.Kp / 4, row = e / kq, k = 4 * (e - row * kq), q = wave_unit(row);
+        src = (q < H && k < K) ? q * K + k : -1;
+        dst = W.w1 + 2 * (row * W.XS + k);
+    } else if (e < W.E1 + W.E2) {
+        const int hq = W.Hp / 4, f = e - W.E1, p = f / hq, q = 4 * (f - p * hq);
+        src = (p < Q && q < H) ? H * K + p * H + q : -1;
+        dst = W.w2 + 2 * (p * W.HS + q);
+    } else {
+        const int j = 4 * (e - W.E1 - W.E2), q = j < W.Hp ? j : j - W.Hp;
+        src = q < H ? H * K + Q * H + (j < W.Hp ? 0 : H) + q : -1;
+        dst = W.ab + 4 * j;
+    }
+}
+
+__device__ __forceinline__ void wave_weight_put(unsigned char* smem, const WaveLayout& W, int dst, float4 v)
+{
+    if (dst < W.ab) {
+        uint2 pk;
+        pk.x = pack_bf16(v.x, v.y);
+        pk.y = pack_bf16(v.z, v.w);
+        *reinterpret_cast<uint2*>(smem + dst) = pk;
+    } else {
+        *reinterpret_cast<float4*>(smem + dst) = v;
+    }
+}
+
+template <bool WANT_CT, bool WANT_PT, int QT>
+__global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs a, WaveLayout W)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int K = a.K, Q = a.Q, H = a.H, lmax = a.lmax, L2 = (lmax + 1) * (lmax + 1);
+    const int QQ = Q * (Q + 1) / 2;
+    const int tid = threadIdx.x, nthr = blockDim.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+    const int64_t i = int64_t(blockIdx.x) * W.cpw + wave;
+    const bool live = i < a.n;
+    const unsigned short* W1s = reinterpret_cast<const unsigned short*>(smem_raw + W.w1);
+    const unsigned short* W2s = reinterpret_cast<const unsigned short*>(smem_raw + W.w2);
+    const float* ab = reinterpret_cast<const float*>(smem_raw + W.ab);
+    unsigned short* X = reinterpret_cast<unsigned short*>(smem_raw + W.x + wave * W.x_bytes);
+    float* cb = reinterpret_cast<float*>(smem_raw + W.cb + wave * W.cb_bytes);
+    const int lsize = H * K + Q * H + 2 * H;
+
+    // this lane's weight float4s (the same offsets for every l)
+    int wsrc[kWQuads], wdst[kWQuads];
+#pragma unroll
+    for (int u = 0; u < kWQuads; ++u) {
+        const int e = tid + nthr * u;
+        wsrc[u] = -1;
+        wdst[u] = -1;
+        if (e < W.E) wave_weight_slot(a, W, e, wsrc[u], wdst[u]);
+    }
+
+    // X[lm][k] of this centre, bfloat16 (zero for k in [K, Kp))
+    if (live) {
+        const float4* src = reinterpret_cast<const float4*>(a.c + i * int64_t(K) * L2);
+        const int n4 = K * L2 / 4;
+        const int dk = 256 / L2, dlm = 256 - dk * L2;   // element-index advance per step of 64 float4s
+        int k = (4 * lane) / L2, lm = 4 * lane - k * L2;
+        for (int e0 = lane; e0 < n4; e0 += 64 * kXLoads) {
+            float4 v[kXLoads];
+#pragma unroll
+            for (int u = 0; u < kXLoads; ++u) {
+                const int e = e0 + 64 * u;
+                v[u] = src[e < n4 ? e : n4 - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kXLoads; ++u) {
+                if (e0 + 64 * u < n4) {
+                    const unsigned int p01 = pack_bf16(v[u].x, v[u].y), p23 = pack_bf16(v[u].z, v[u].w);
+                    const unsigned short hv[4] = {(unsigned short)p01, (unsigned short)(p01 >> 16),
+                                                  (unsigned short)p23, (unsigned short)(p23 >> 16)};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        int kj = k, lj = lm + j;
+                        if (lj >= L2) { lj -= L2; ++kj; }
+                        X[lj * W.XS + xcol(lj, kj)] = hv[j];
+                    }
+                }
+                k += dk;
+                lm += dlm;
+                if (lm >= L2) { lm -= L2; ++k; }
+            }
+        }
+        for (int e = lane; e < L2 * (W.Kp - K); e += 64) {
+            const int lr = e / (W.Kp - K);
+            X[lr * W.XS + xcol(lr, K + (e - lr * (W.Kp - K)))] = 0;
+        }
+    }
+
+    const float* wl = a.w;
+    for (int l = 0; l <= lmax; ++l, wl += lsize) {
+        __syncthreads();   // the weights of l - 1 are no longer read
+        {
+            float4 wv[kWQuads];
+#pragma unroll
+            for (int u = 0; u < kWQuads; ++u)   // every load issued before any is used
+                wv[u] = *reinterpret_cast<const float4*>(wl + (wsrc[u] >= 0 ? wsrc[u] : 0));
+#pragma unroll
+            for (int u = 0; u < kWQuads; ++u)
+                if (wdst[u] >= 0)
+                    wave_weight_put(smem_raw, W, wdst[u], wsrc[u] >= 0 ? wv[u] : make_float4(0.f, 0.f, 0.f, 0.f));
+            for (int e = tid + nthr * kWQuads; e < W.E; e += nthr) {   // beyond the kept offsets
+                int s0, d0;
+                wave_weight_slot(a, W, e, s0, d0);
+                wave_weight_put(smem_raw, W, d0,
+                                s0 >= 0 ? *reinterpret_cast<const float4*>(wl + s0) : make_float4(0.f, 0.f, 0.f, 0.f));
+            }
+        }
+        __syncthreads();
+        if (!live) continue;
+        const int M = 2 * l + 1, b = l * l, MT = (M + 15) >> 4;
+        // layer 1: k-steps outside, the hidden tiles' accumulators inside;
+        // each W1 fragment serves both column tiles as it is read
+        f32x4 h[2][8];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) h[ct][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            if (kk < W.KS) {
+                u16x8 B0 = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, B1 = B0;
+                if (r < M) B0 = *reinterpret_cast<const u16x8*>(&X[(b + r) * W.XS + xcol(b + r, 32 * kk + 8 * g)]);
+                if (16 + r < M)
+                    B1 = *reinterpret_cast<const u16x8*>(&X[(b + 16 + r) * W.XS + xcol(b + 16 + r, 32 * kk + 8 * g)]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    if (t < W.HT) {
+                        const u16x8 A = *reinterpret_cast<const u16x8*>(&W1s[(16 * t + r) * W.XS + 32 * kk + 8 * g]);
+                        h[0][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, A), __builtin_bit_cast(bf16x8, B0), h[0][t], 0, 0, 0);
+                        if (MT > 1)
+                            h[1][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, A), __builtin_bit_cast(bf16x8, B1), h[1][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // gate factor 2 sigma(alpha |h| + beta) of unit q (row 4g + v of
+        // tile t), |h_q|^2 summed over the m columns (zero where not
+        // computed); h is scaled in place
+        for (int t = 0; t < 8; ++t) {
+            const int q0 = 32 * (t >> 1) + 8 * g + 4 * (t & 1);
+            const float4 al = *reinterpret_cast<const float4*>(ab + q0);
+            const float4 be = *reinterpret_cast<const float4*>(ab + W.Hp + q0);
+            const float alv[4] = {al.x, al.y, al.z, al.w}, bev[4] = {be.x, be.y, be.z, be.w};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float s = row_sum16(h[0][t][v] * h[0][t][v] + h[1][t][v] * h[1][t][v]);
+                const float x = alv[v] * __builtin_amdgcn_sqrtf(s) + bev[v];
+                const float G = (t < W.HT && q0 + v < H)
+                                    ? 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x))
+                                    : 0.0f;
+                h[0][t][v] *= G;
+                h[1][t][v] *= G;
+            }
+        }
+        // layer 2: c~ of the m columns -> the wave's staging (and c~ out)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (ct >= MT) continue;
+            f32x4 acc2[QT];
+#pragma unroll
+            for (int pt = 0; pt < QT; ++pt) acc2[pt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                if (ks >= W.KS2) continue;
+                u32x4 Bw;
+                Bw[0] = pack_bf16(h[ct][2 * ks][0], h[ct][2 * ks][1]);
+                Bw[1] = pack_bf16(h[ct][2 * ks][2], h[ct][2 * ks][3]);
+                Bw[2] = pack_bf16(h[ct][2 * ks + 1][0], h[ct][2 * ks + 1][1]);
+                Bw[3] = pack_bf16(h[ct][2 * ks + 1][2], h[ct][2 * ks + 1][3]);
+#pragma unroll
+                for (int pt = 0; pt < QT; ++pt) {
+                    const u16x8 A2 = *reinterpret_cast<const u16x8*>(&W2s[(16 * pt + r) * W.HS + 32 * ks + 8 * g]);
+                    acc2[pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A2),
+                                                                       __builtin_bit_cast(bf16x8, Bw), acc2[pt], 0, 0, 0);
+                }
+            }
+            const int m = 16 * ct + r;
+#pragma unroll
+            for (int pt = 0; pt < QT; ++pt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int p = 16 * pt + 4 * g + v;
+                    cb[p * kCB + m] = acc2[pt][v];
+                    if (WANT_CT && p < Q && m < M) a.ct[(i * Q + p) * int64_t(L2) + b + m] = acc2[pt][v];
+                }
+        }
+        if (WANT_PT) {
+            wave_sync();
+            // rows 16 P + r of c~ as the lane's operand: m = 8 g + j, zero past
+            // the columns written for this l; high and low bfloat16 parts
+            u32x4 hi[QT], lo[QT];
+#pragma unroll
+            for (int P = 0; P < QT; ++P) {
+                float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (8 * g < 16 * MT) {
+                    const float4 x0 = *reinterpret_cast<const float4*>(cb + (16 * P + r) * kCB + 8 * g);
+                    const float4 x1 = *reinterpret_cast<const float4*>(cb + (16 * P + r) * kCB + 8 * g + 4);
+                    x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+                    x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const unsigned int hp = pack_bf16(x[2 * j], x[2 * j + 1]);
+                    hi[P][j] = hp;
+                    lo[P][j] = pack_bf16(x[2 * j] - __uint_as_float(hp << 16), x[2 * j + 1] - __uint_as_float(hp & 0xFFFF0000u));
+                }
+            }
+            float* dst = a.pt + (i * (lmax + 1) + l) * int64_t(QQ);
+#pragma unroll
+            for (int P1 = 0; P1 < QT; ++P1)
+#pragma unroll
+                for (int P2 = P1; P2 < QT; ++P2) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, hi[P1]),
+                                                                  __builtin_bit_cast(bf16x8, hi[P2]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, hi[P1]),
+                                                                  __builtin_bit_cast(bf16x8, lo[P2]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, lo[P1]),
+                                                                  __builtin_bit_cast(bf16x8, hi[P2]), acc, 0, 0, 0);
+                    // lane holds p~[p1][p2], p1 = 16 P1 + 4 g + v, p2 = 16 P2 + r
+                    const int p2 = 16 * P2 + r;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int p1 = 16 * P1 + 4 * g + v;
+                        if (p1 <= p2 && p2 < Q) dst[p1 * Q - p1 * (p1 - 1) / 2 + (p2 - p1)] = acc[v];
+                    }
+                }
+            wave_sync();
+        }
+    }
+}
+
 inline unsigned blocks_of(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 }  // namespace
@@ -851,9 +1187,41 @@ hipError_t launch_compress_forward(const CompressArgs& a, hipStream_t stream)
 }
 
 
+template <int QT>
+hipError_t launch_cmp_wave_q(const CompressArgs& a, const WaveLayout& W, hipStream_t stream)
+{
+    auto kernel = a.ct ? (a.pt ? k_cmp_fwd_wave<true, true, QT> : k_cmp_fwd_wave<true, false, QT>)
+                       : k_cmp_fwd_wave<false, true, QT>;
+    if (W.total > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, W.total);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, dim3(blocks_of(a.n, W.cpw)), dim3(64 * W.cpw), size_t(W.total), stream, a, W);
+    return hipGetLastError();
+}
+
+// the one-wave-per-centre form when the shapes fit it: K, H <= 128 and
+// multiples of 4 (weights and c read as float4), Q <= 32, 1 <= lmax <= 12
+// (a float4 of c then spans at most two lm rows), 16-byte aligned c and
+// weights, at least two centres per work-group
+bool cmp_wave_fits(const CompressArgs& a, WaveLayout& W)
+{
+    if (a.K > 128 || a.H > 128 || a.Q > 32 || a.lmax < 1 || a.lmax > 12) return false;
+    if (a.K % 4 != 0 || a.H % 4 != 0) return false;
+    if ((reinterpret_cast<uintptr_t>(a.c) & 15) != 0 || (reinterpret_cast<uintptr_t>(a.w) & 15) != 0) return false;
+    for (int cpw = kWaveCentres; cpw >= 2; --cpw) {
+        W = wave_layout(a.K, a.Q, a.H, a.lmax, cpw);
+        if (W.total <= 160 * 1024) return true;
+    }
+    return false;
+}
+
 hipError_t launch_compress_forward_bf16(const CompressArgs& a, hipStream_t stream)
 {
     if (a.n == 0) return hipSuccess;
+    WaveLayout W;
+    if (cmp_wave_fits(a, W)) return a.Q <= 16 ? launch_cmp_wave_q<1>(a, W, stream) : launch_cmp_wave_q<2>(a, W, stream);
     if (a.K > 32 * kKS1 || a.H > 16 * 4 * kMT || a.Q > 64) return hipErrorNotSupported;
     const size_t lds = compress_bf16_lds(a);
     if (lds > 160 * 1024) return hipErrorNotSupported;

@@ -55,23 +55,28 @@ def test_forward_fp32(cells):
     assert e1 <= 1e-5 and e2 <= 1e-5
 
 
-@pytest.mark.parametrize("n_centres", [512, 37])
-def test_forward_bf16_mfma(cells, n_centres):
+@pytest.mark.parametrize("n_centres,Q,H", [(512, 16, 128), (37, 16, 128), (301, 32, 128), (37, 32, 96),
+                                           (45, 12, 40)])
+def test_forward_bf16_mfma(cells, n_centres, Q, H):
     """bfloat16 operands, float accumulation: each product carries a
     relative rounding of about 2^-8 on each operand, so c~ and p~ agree with
-    the FP64 result to about 1e-2 (Frobenius); 37 centres leave a partial
-    tile of 16."""
+    the FP64 result to about 1e-2 (Frobenius).  Centre counts leave a
+    partial work-group; Q = 32 takes two output tiles, Q = 12 and H = 40,
+    96 padded ones; c~ alone and p~ alone agree with the pair."""
     calc, c32, cd = cells
-    cmp_ = P.Compressor(calc, 16, 128)
-    w = random_weights(1, calc.K, 16, 128, calc.lmax)
+    cmp_ = P.Compressor(calc, Q, H)
+    w = random_weights(1, calc.K, Q, H, calc.lmax)
     cmp_.weights.copy_(torch.tensor(w))
     cb = cd[:n_centres].contiguous()
     ct, pt = cmp_.forward(cb, precision="bf16", want_coeffs=True)
-    ref_ct = C.compress(c32[:n_centres].astype(np.float64), w.astype(np.float64), 16, 128)
+    ct_only, _ = cmp_.forward(cb, precision="bf16", want_coeffs=True, want_p=False)
+    _, pt_only = cmp_.forward(cb, precision="bf16")
+    ref_ct = C.compress(c32[:n_centres].astype(np.float64), w.astype(np.float64), Q, H)
     ref_pt = C.power_spectrum(ref_ct)
     e1, e2 = rel(ct, ref_ct), rel(pt, ref_pt)
-    print(f"[compress bf16] c~ {e1:.2e}  p~ {e2:.2e}")
+    print(f"[compress bf16 Q={Q} H={H} n={n_centres}] c~ {e1:.2e}  p~ {e2:.2e}")
     assert e1 <= 1e-2 and e2 <= 2e-2
+    assert torch.equal(ct_only, ct) and torch.equal(pt_only, pt)
 
 
 def test_identity_network_on_gpu():
