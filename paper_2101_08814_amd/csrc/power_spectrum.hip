@@ -44,6 +44,13 @@ __device__ __forceinline__ unsigned short to_bf16(float f)
 
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int W>
 __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
 {
@@ -57,8 +64,11 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     const int slot = wave / W, wc = wave - slot * W;   // centre slot in the work-group, wave within the centre
     const int64_t i = int64_t(blockIdx.x) * CPG + slot;
     if (i >= a.n_atoms) return;
-    // {H, L} of every element of C: H in the low half, L in the high half
-    unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * (KL2 + 32);
+    // {H, L} of every element of C: H in the low half, L in the high half;
+    // with one wave per centre, then the packed P_l of the current l
+    const int HLS = (KL2 + 32 + 3) & ~3, OBS = W == 1 ? (KK + 3) & ~3 : 0;   // 16-byte aligned regions
+    unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * (HLS + OBS);
+    float* ob = reinterpret_cast<float*>(hl + HLS);
     const float* c_in = static_cast<const float*>(a.coeffs) + i * KL2;
     // kLoadBatch loads in flight per lane before any is used
     for (int e0 = wc * 64 + lane; e0 < KL2; e0 += kLoadBatch * W * 64) {
@@ -128,25 +138,47 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int k1 = I * 16 + 4 * kg + v;
-                if (k1 <= k2 && k2 < K) dst[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
+                if (k1 <= k2 && k2 < K) {
+                    if (W == 1) ob[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
+                    else dst[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
+                }
             }
+        }
+        if (W == 1) {
+            // the packed P_l leaves as contiguous rows: float4 stores when
+            // aligned, else one float per lane
+            wave_sync();
+            if ((KK & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                for (int e = lane; e < KK / 4; e += 64)
+                    reinterpret_cast<float4*>(dst)[e] = reinterpret_cast<const float4*>(ob)[e];
+            } else {
+                for (int e = lane; e < KK; e += 64) dst[e] = ob[e];
+            }
+            wave_sync();
         }
     }
 }
 
-// waves per centre: one when four centres' C fit 40 KB of LDS
+// LDS words of one centre's slot: {H, L} of C, then (one wave per centre)
+// the packed P_l
+size_t bf16_slot_words(int S, int nmax, int lmax, int W)
+{
+    const size_t K = size_t(S) * nmax, KL2 = K * (lmax + 1) * (lmax + 1), KK = K * (K + 1) / 2;
+    return ((KL2 + 32 + 3) & ~size_t(3)) + (W == 1 ? (KK + 3) & ~size_t(3) : 0);
+}
+
+// waves per centre: one when four centres' slots fit 40 KB of LDS
 int bf16_waves_per_centre(int S, int nmax, int lmax)
 {
-    const size_t KL2 = size_t(S) * nmax * (lmax + 1) * (lmax + 1);
-    return 4 * 4 * KL2 <= 40 * 1024 ? 1 : 4;
+    return 4 * 4 * bf16_slot_words(S, nmax, lmax, 1) <= 40 * 1024 ? 1 : 4;
 }
 
 }  // namespace
 
 size_t power_spectrum_bf16_lds(int S, int nmax, int lmax)
 {
-    const size_t K = size_t(S) * nmax, L2 = size_t(lmax + 1) * (lmax + 1);
-    return size_t(kThreads / 64 / bf16_waves_per_centre(S, nmax, lmax)) * 4 * (K * L2 + 32);
+    const int W = bf16_waves_per_centre(S, nmax, lmax);
+    return size_t(kThreads / 64 / W) * 4 * bf16_slot_words(S, nmax, lmax, W);
 }
 
 template <int W>
