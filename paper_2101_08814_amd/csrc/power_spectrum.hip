@@ -13,12 +13,13 @@
 // relative error of order 2^-16.
 //
 // W waves own one centre (W = 1, four centres per work-group, when C is
-// small; W = 4 otherwise), with no work-group barriers: the centre's waves
+// small; W = 4, one centre per work-group, otherwise): the centre's waves
 // split C into their LDS region as {H, L} pairs, then for each l run the
 // 16 x 16 output tiles (I <= J), dealt round-robin, as three
 // v_mfma_f32_16x16x32_bf16 each (a lane reads 8 consecutive {H, L} words of
-// each of its two rows) and store the packed upper triangle straight from
-// the accumulators (16 consecutive k2 per store).
+// each of its two rows), put the packed upper triangle in LDS and store it
+// as contiguous float4 rows (the accumulators alone give 64-byte pieces).
+// One wave per centre needs no work-group barrier; four take two per l.
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -65,8 +66,8 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     const int64_t i = int64_t(blockIdx.x) * CPG + slot;
     if (i >= a.n_atoms) return;
     // {H, L} of every element of C: H in the low half, L in the high half;
-    // with one wave per centre, then the packed P_l of the current l
-    const int HLS = (KL2 + 32 + 3) & ~3, OBS = W == 1 ? (KK + 3) & ~3 : 0;   // 16-byte aligned regions
+    // then the packed P_l of the current l
+    const int HLS = (KL2 + 32 + 3) & ~3, OBS = (KK + 3) & ~3;   // 16-byte aligned regions
     unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * (HLS + OBS);
     float* ob = reinterpret_cast<float*>(hl + HLS);
     const float* c_in = static_cast<const float*>(a.coeffs) + i * KL2;
@@ -138,33 +139,29 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int k1 = I * 16 + 4 * kg + v;
-                if (k1 <= k2 && k2 < K) {
-                    if (W == 1) ob[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
-                    else dst[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
-                }
+                if (k1 <= k2 && k2 < K) ob[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
             }
         }
-        if (W == 1) {
+        {
             // the packed P_l leaves as contiguous rows: float4 stores when
             // aligned, else one float per lane
-            wave_sync();
+            if (W == 1) wave_sync(); else __syncthreads();
             if ((KK & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-                for (int e = lane; e < KK / 4; e += 64)
+                for (int e = wc * 64 + lane; e < KK / 4; e += W * 64)
                     reinterpret_cast<float4*>(dst)[e] = reinterpret_cast<const float4*>(ob)[e];
             } else {
-                for (int e = lane; e < KK; e += 64) dst[e] = ob[e];
+                for (int e = wc * 64 + lane; e < KK; e += W * 64) dst[e] = ob[e];
             }
-            wave_sync();
+            if (W == 1) wave_sync(); else __syncthreads();
         }
     }
 }
 
-// LDS words of one centre's slot: {H, L} of C, then (one wave per centre)
-// the packed P_l
+// LDS words of one centre's slot: {H, L} of C, then the packed P_l
 size_t bf16_slot_words(int S, int nmax, int lmax, int W)
 {
     const size_t K = size_t(S) * nmax, KL2 = K * (lmax + 1) * (lmax + 1), KK = K * (K + 1) / 2;
-    return ((KL2 + 32 + 3) & ~size_t(3)) + (W == 1 ? (KK + 3) & ~size_t(3) : 0);
+    return ((KL2 + 32 + 3) & ~size_t(3)) + ((KK + 3) & ~size_t(3));
 }
 
 // waves per centre: one when four centres' slots fit 40 KB of LDS
