@@ -451,6 +451,29 @@ class Compressor:
         self.adam(lr)
         return loss
 
+    def save(self, path: str) -> None:
+        """Writes the weights, the Adam moments and step, and the shape (n_out,
+        hidden, the calculator's channel count and lmax) to an .npz file
+        (plain arrays, no pickled objects)."""
+        np.savez(path, weights=self.weights.cpu().numpy(), m=self._m.cpu().numpy(), v=self._v.cpu().numpy(),
+                 step=np.int64(self.step), n_out=np.int64(self.Q), hidden=np.int64(self.H),
+                 channels=np.int64(self.calc.K), lmax=np.int64(self.lmax))
+
+    def load(self, path: str) -> None:
+        """Reads a file written by save(); its shape must match this
+        compressor's (ValueError otherwise)."""
+        with np.load(path, allow_pickle=False) as f:
+            shape = tuple(int(f[k]) for k in ("n_out", "hidden", "channels", "lmax"))
+            if shape != (self.Q, self.H, self.calc.K, self.lmax):
+                raise ValueError(f"saved compressor has (n_out, hidden, channels, lmax) = {shape}, this one "
+                                 f"{(self.Q, self.H, self.calc.K, self.lmax)}")
+            for name, t in (("weights", self.weights), ("m", self._m), ("v", self._v)):
+                a = f[name]
+                if a.shape != (self.n_params,) or a.dtype != np.float32:
+                    raise ValueError(f"saved {name} has shape {a.shape} and type {a.dtype}")
+                t.copy_(torch.from_numpy(a))
+            self.step = int(f["step"])
+
     def kernel_error(self, coeffs: torch.Tensor, precision=torch.float32) -> float:
         """eps_K = |K~ - K|_F / |K|_F over the centres of coeffs (synchronises)."""
         pf = self.calc.power_spectrum(coeffs, precision=torch.float32)

@@ -165,3 +165,23 @@ def test_training_lowers_the_kernel_error(cells):
     after = cmp_.kernel_error(cd[384:].contiguous())
     print(f"[compress train] held-out eps_K {before:.4f} -> {after:.4f}")
     assert after < before
+
+
+def test_save_and_load_round_trip(cells, tmp_path):
+    """Weights, Adam moments and step survive save/load; the loaded
+    compressor gives the same p~; a file of another shape is refused."""
+    calc, c32, cd = cells
+    a = P.Compressor(calc, 8, 32)
+    a.weights.copy_(torch.tensor(random_weights(3, calc.K, 8, 32, calc.lmax)))
+    a.train_step(cd[:64].contiguous(), lr=1e-3)
+    path = str(tmp_path / "compressor.npz")
+    a.save(path)
+    b = P.Compressor(calc, 8, 32)
+    b.load(path)
+    assert b.step == a.step == 1
+    for x, y in [(a.weights, b.weights), (a._m, b._m), (a._v, b._v)]:
+        assert torch.equal(x, y)
+    assert torch.equal(a.forward(cd[:64].contiguous())[1], b.forward(cd[:64].contiguous())[1])
+    with pytest.raises(ValueError):
+        P.Compressor(calc, 8, 40).load(path)
+
