@@ -36,6 +36,7 @@
  *   exceeded, coincident atoms, species out of range) are stored as a
  *   nonzero soap_status into *exec->dev_status (caller-zeroed device int32);
  *   soap_read_device_status() synchronises the stream and returns it.
+ *   The outputs of a call that stores such a status are not meaningful.
  *   Kernels that read a neighbour list whose total exceeds the capacity
  *   they are given store SOAP_ECAPACITY and write nothing else.
  * - Floating-point type: SOAP_F64 -> double, SOAP_F32 -> float for

@@ -238,16 +238,21 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
 {
     const int tid = threadIdx.x;
     const T* vec = static_cast<const T*>(a.pair_vec);
+    // Geometry of pair tid.  The species of j (a load that depends on j) is
+    // only needed for the segments, so its value is taken after the spline
+    // loads of the next phase are issued and its round trip overlaps theirs.
+    // A pair whose j or species is invalid stores a status and counts as
+    // species 0 (the outputs of such a call are not meaningful).
+    int sp_j = 0;
+    bool bad_j = false;
     if (tid < nc) {
         int64_t q = q0 + tid;
         T vx = vec[3 * q], vy = vec[3 * q + 1], vz = vec[3 * q + 2];
         T r = sqrt(vx * vx + vy * vy + vz * vz);
         int j = a.pair_j[q];
-        bool bad_j = j < 0 || j >= a.n_atoms;
+        bad_j = j < 0 || j >= a.n_atoms;
         if (bad_j) put_status(a.status, SOAP_EINVAL);
-        int sp = bad_j ? -1 : a.species[j];
-        bool bad_sp = sp < 0 || sp >= d.S;
-        if (bad_sp) { if (!bad_j) put_status(a.status, SOAP_ESPECIES); sp = 0; }
+        sp_j = a.species[bad_j ? 0 : j];
         T f = T(0), df = T(0);
         if (!(r > T(1e-8))) {
             put_status(a.status, SOAP_EGEOMETRY);
@@ -255,26 +260,18 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
         } else {
             T ri = T(1) / r;
             s.ux[tid] = vx * ri; s.uy[tid] = vy * ri; s.uz[tid] = vz * ri; s.rinv[tid] = ri;
-            if (!bad_sp) f = fcut<T>(r, T(a.rcut), T(a.width), df);
+            f = fcut<T>(r, T(a.rcut), T(a.width), df);
         }
         s.f[tid] = f;
         s.df[tid] = df;
-        s.spc[tid] = sp;
         s.r[tid] = r;
     }
     __syncthreads();
-    // Qt columns and (x + i y)^m: one lane per (pair, m); species segments
+    // Qt columns and (x + i y)^m: one lane per (pair, m)
     const int lm1 = d.lm1;
     for (int t = tid; t < nc * lm1; t += kThreads) {
         int p = t / lm1, m = t - p * lm1;
         q_column<T>(m, d.lmax, s.ux[p], s.uy[p], s.uz[p], s.qt + p * d.nq, s.cre + p * lm1, s.cim + p * lm1);
-    }
-    for (int sp = tid; sp < d.S; sp += kThreads) {
-        int lo = nc, hi = 0;
-        for (int p = 0; p < nc; ++p)
-            if (s.spc[p] == sp) { lo = p < lo ? p : lo; hi = p + 1; }
-        s.seg[2 * sp] = lo;
-        s.seg[2 * sp + 1] = hi;
     }
     // radial spline: one lane per (pair, n, l); a lane issues the
     // coefficient loads of up to kSplineBatch of its items before using any
@@ -306,7 +303,23 @@ __device__ void stage_chunk(const FeatureArgs& a, const Dims& d, Smem<T>& s, int
             }
         }
     }
+    if (tid < nc) {
+        int sp = bad_j ? -1 : sp_j;
+        if (sp < 0 || sp >= d.S) {
+            if (!bad_j) put_status(a.status, SOAP_ESPECIES);
+            sp = 0;
+        }
+        s.spc[tid] = sp;
+    }
     __syncthreads();
+    // species segments (pairs come sorted by species)
+    for (int sp = tid; sp < d.S; sp += kThreads) {
+        int lo = nc, hi = 0;
+        for (int p = 0; p < nc; ++p)
+            if (s.spc[p] == sp) { lo = p < lo ? p : lo; hi = p + 1; }
+        s.seg[2 * sp] = lo;
+        s.seg[2 * sp + 1] = hi;
+    }
     // harmonics and gradients: one lane per (pair, lm)
     for (int t = tid; t < nc * d.L2; t += kThreads) {
         int p = t / d.L2, lm = t - p * d.L2;

@@ -39,6 +39,43 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 constexpr int kRegItems = 16;
 
+// c of one (species, n pair, lm) item summed over the chunk's pairs
+// [p0, p1) of that species, in pair order; U pairs' LDS reads are issued
+// together (pairs of another species, possible when the list is not
+// sorted, are skipped)
+template <typename T, int U>
+__device__ __forceinline__ void species_sums(const Smem<T>& s, const Dims& d, int sp, int lm, int l, int n0, bool two,
+                                             int p0, int p1, T& c0, T& c1)
+{
+    const int lm1 = d.lm1;
+    int p = p0;
+    for (; p + U <= p1; p += U) {
+        int sc[U];
+        T Yv[U], R0[U], R1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sc[u] = s.spc[p + u];
+            Yv[u] = s.Y[(p + u) * d.L2 + lm];
+            const T* Rp = s.R + (p + u) * d.nl + n0 * lm1 + l;
+            R0[u] = Rp[0];
+            R1[u] = two ? Rp[lm1] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (sc[u] == sp) {
+                c0 += R0[u] * Yv[u];
+                c1 += R1[u] * Yv[u];
+            }
+    }
+    for (; p < p1; ++p) {
+        if (s.spc[p] != sp) continue;
+        const T Yv = s.Y[p * d.L2 + lm];
+        const T* Rp = s.R + p * d.nl + n0 * lm1 + l;
+        c0 += Rp[0] * Yv;
+        c1 += (two ? Rp[lm1] : T(0)) * Yv;
+    }
+}
+
 template <typename T, int LM, bool GRAD, bool WANT_P, bool ROWS, bool REGC>
 __device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout& L)
 {
@@ -89,16 +126,8 @@ __device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout&
                 asm volatile("" : "+v"(t));
                 const int sp = t / (ng * d.L2), rem = t - sp * (ng * d.L2), g = rem / d.L2, lm = rem - g * d.L2;
                 const int n0 = 2 * g, two = n0 + 1 < d.nmax;
-                const int l = s.lof[lm];
                 T c0 = T(0), c1 = T(0);
-                const int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
-                for (int p = p0; p < p1; ++p) {
-                    if (s.spc[p] != sp) continue;
-                    const T Yv = s.Y[p * d.L2 + lm];
-                    const T* Rp = s.R + p * d.nl + n0 * lm1 + l;
-                    c0 += Rp[0] * Yv;
-                    c1 += (two ? Rp[lm1] : T(0)) * Yv;
-                }
+                species_sums<T, 1>(s, d, sp, lm, s.lof[lm], n0, two, s.seg[2 * sp], s.seg[2 * sp + 1], c0, c1);
                 rc[j][0] += c0;
                 rc[j][1] += c1;
             }
@@ -113,7 +142,8 @@ __device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout&
             T c0 = T(0), c1 = T(0);
             T a0 = T(0), a1 = T(0), a2 = T(0), b0 = T(0), b1 = T(0), b2 = T(0);
             const int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
-            for (int p = p0; p < p1; ++p) {
+            if (!GRAD) species_sums<T, 4>(s, d, sp, lm, l, n0, two, p0, p1, c0, c1);
+            for (int p = p0; p < (GRAD ? p1 : p0); ++p) {
                 if (s.spc[p] != sp) continue;
                 V4<T> yd;
                 if (GRAD) yd = s.YD[p * d.L2 + lm];
