@@ -185,3 +185,35 @@ def test_save_and_load_round_trip(cells, tmp_path):
     with pytest.raises(ValueError):
         P.Compressor(calc, 8, 40).load(path)
 
+
+
+def test_full_workload_sampled_cells():
+    """The whole 512-cell workload (131,072 centres) in the launches the
+    compression benchmark times: c from the c-only expansion and p~ from
+    the bf16 compression, each compared with the oracle on three sampled
+    cells (first, middle, last: the last two centres form a partial
+    work-group of the compression kernel)."""
+    b = synthetic.multi_species_cells()
+    calc = P.Calculator.from_hypers(b.hypers)
+    dev = torch.device("cuda")
+    pos = torch.tensor(b.positions, dtype=torch.float64, device=dev)
+    spc = torch.tensor(b.species, dtype=torch.int32, device=dev)
+    nl = calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc, vec_dtype=torch.float32, transpose=False)
+    c = calc.spherical_expansion(nl, spc, dtype=torch.float32)
+    Q, H = 16, 128
+    cmp_ = P.Compressor(calc, Q, H)
+    w = random_weights(7, calc.K, Q, H, calc.lmax)
+    cmp_.weights.copy_(torch.tensor(w))
+    _, pt = cmp_.forward(c, precision="bf16")
+    assert calc.device_status() == 0
+    picked = [0, 255, 511]
+    rows = np.concatenate([np.arange(b.atom_offsets[s], b.atom_offsets[s + 1]) for s in picked])
+    rows_t = torch.tensor(rows, device=dev)
+    _, ref_c, _ = oracle.features(b.subset(picked))
+    K, L2 = calc.K, calc.L2
+    ref_c = ref_c.reshape(len(rows), K, L2)
+    ec = rel(c[rows_t].reshape(len(rows), K, L2), ref_c)
+    ref_pt = C.power_spectrum(C.compress(ref_c.astype(np.float32).astype(np.float64), w.astype(np.float64), Q, H))
+    ep = rel(pt[rows_t], ref_pt)
+    print(f"[compression full size] {c.shape[0]} centres; sampled c {ec:.2e}, p~ bf16 {ep:.2e}")
+    assert ec <= 1e-6 and ep <= 2e-2
