@@ -76,6 +76,58 @@ __global__ void __launch_bounds__(kThreads) k_ps_backward(FeatureArgs a, const T
     }
 }
 
+// The same product with W_l unpacked once into a full symmetric K x K
+// block per l (diagonal doubled) and each lane forming four channels
+// k..k+3 of one lm: per k' one 4-wide read of row k' of W_l (the rows are
+// the columns: W_l is symmetric) and one read of c, four FMAs.  K is a
+// multiple of 4; c, the packed gradient and the blocks fit 64 KB.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ps_backward_full(FeatureArgs a, const T* grad_p, T* grad_c)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Dims d = make_dims(a.S, a.nmax, a.lmax);
+    const int K = d.K, L2 = d.L2, lm1 = d.lm1, KK = d.KK, KL2 = K * L2, PL = lm1 * KK;
+    T* wf = reinterpret_cast<T*>(smem_raw);        // [lm1][K][K]
+    T* c = wf + lm1 * K * K;                        // [K][L2]
+    T* wp = c + KL2;                                // packed [lm1][KK]
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    copy_in(c, static_cast<const T*>(a.coeffs) + i * KL2, KL2);
+    copy_in(wp, grad_p + i * int64_t(PL), PL);
+    __syncthreads();
+    // one thread per row (l, k1) of the full blocks
+    for (int row = tid; row < lm1 * K; row += kThreads) {
+        const int l = row / K, k1 = row - l * K;
+        const T* src = wp + l * KK;
+        T* dst = wf + row * K;
+        for (int k2 = 0; k2 < K; ++k2) {
+            const int lo = k1 < k2 ? k1 : k2, hi = k1 < k2 ? k2 : k1;
+            const T v = src[lo * K - lo * (lo - 1) / 2 + (hi - lo)];
+            dst[k2] = k2 == k1 ? v + v : v;
+        }
+    }
+    __syncthreads();
+    T* g_out = grad_c + i * KL2;
+    const int KB = K / 4;
+    for (int t = tid; t < KB * L2; t += kThreads) {
+        const int kb = t / L2, lm = t - kb * L2, k = 4 * kb;
+        const T* Wl = wf + l_of(lm) * K * K + k;
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+        for (int kp = 0; kp < K; ++kp) {
+            const V4<T> w = *reinterpret_cast<const V4<T>*>(Wl + kp * K);
+            const T cv = c[kp * L2 + lm];
+            a0 += w.x * cv;
+            a1 += w.y * cv;
+            a2 += w.z * cv;
+            a3 += w.w * cv;
+        }
+        g_out[k * L2 + lm] = a0;
+        g_out[(k + 1) * L2 + lm] = a1;
+        g_out[(k + 2) * L2 + lm] = a2;
+        g_out[(k + 3) * L2 + lm] = a3;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -171,6 +223,13 @@ template <typename T>
 hipError_t ps_backward_t(const FeatureArgs& a, const void* grad_p, void* grad_c, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
+    const size_t full_lds =
+        (size_t(d.lm1) * d.K * d.K + size_t(d.K) * d.L2 + size_t(d.lm1) * d.KK) * sizeof(T);
+    if (d.K % 4 == 0 && full_lds <= 64 * 1024) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ps_backward_full<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads),
+                           full_lds, stream, a, static_cast<const T*>(grad_p), static_cast<T*>(grad_c));
+        return hipGetLastError();
+    }
     // the upstream gradient of every l in LDS at once when that fits 64 KB
     const size_t all_lds = (size_t(d.K) * d.L2 + size_t(d.lmax + 1) * d.KK) * sizeof(T);
     const bool all = all_lds <= 64 * 1024;
