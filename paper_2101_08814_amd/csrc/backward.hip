@@ -8,7 +8,8 @@
 // One work-group per centre; W_l is staged row by row through LDS.
 //
 // Expansion (App. B Eq. energy-derivative): for pair q = (i, j, s)
-//   g_q = dL/dr_ji = sum_{n,lm} G_{i,a_j,n,lm} [(f I~)'_nl Y_lm u + f I~_nl grad Y_lm]
+//   g_q = dL/dr_ji = sum_{n,lm} G_{i,a_j,n,lm} [(f I~)'_nl Y_lm u + f I~_nl grad Y_lm],
+// formed as a sum over lm after the sum over n,
 // with G = dL/dc.  The per-pair factors are recomputed (the same LDS staging
 // as the forward pass) instead of being stored: the model-side sum is
 // contracted first, as the paper recommends for forces.  Then
@@ -161,18 +162,25 @@ __global__ void __launch_bounds__(kThreads) k_exp_backward_pairs(FeatureArgs a, 
         int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
         stage_chunk<T, true>(a, d, s, q0, nc);
         for (int p = wave; p < nc; p += kWaves) {
+            // g = u sum_lm Y_lm A_lm + sum_lm grad Y_lm B_lm with
+            // {A, B}_lm = sum_n G_{n,lm} {(f I~)'_nl, f I~_nl}: one lane per lm
             const T* G = s.c + s.spc[p] * nL2;
+            const T* Rp = s.R + p * d.nl;
+            const T* dRp = s.dR + p * d.nl;
             T gx = T(0), gy = T(0), gz = T(0);
-            for (int e = lane; e < nL2; e += 64) {
-                int n = e / d.L2, lm = e - n * d.L2;
-                int rl = n * lm1 + s.lof[lm];
-                T Gv = G[e];
+            for (int lm = lane; lm < d.L2; lm += 64) {
+                const int l = s.lof[lm];
+                T A = T(0), B = T(0);
+                for (int n = 0; n < d.nmax; ++n) {
+                    const T Gv = G[n * d.L2 + lm];
+                    A += Gv * dRp[n * lm1 + l];
+                    B += Gv * Rp[n * lm1 + l];
+                }
                 const V4<T> yd = s.YD[p * d.L2 + lm];
-                T t = Gv * s.dR[p * d.nl + rl] * yd.x;
-                T r = Gv * s.R[p * d.nl + rl];
-                gx += t * s.ux[p] + r * yd.y;
-                gy += t * s.uy[p] + r * yd.z;
-                gz += t * s.uz[p] + r * yd.w;
+                const T t = A * yd.x;
+                gx += t * s.ux[p] + B * yd.y;
+                gy += t * s.uy[p] + B * yd.z;
+                gz += t * s.uz[p] + B * yd.w;
             }
             gx = wave_sum(gx);
             gy = wave_sum(gy);
