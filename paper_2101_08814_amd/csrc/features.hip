@@ -360,16 +360,18 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum(FeatureArgs a)
     if (GRAD) copy_in(g, static_cast<const T*>(a.dcoeffs_self) + i * 3 * KL2, 3 * KL2);
     __syncthreads();
     T* p_out = static_cast<T*>(a.p) + i * PL;
-    for (int64_t o = tid; o < PL; o += kThreads) {
-        int l = int(o / d.KK);
-        int kk = int(o - int64_t(l) * d.KK);
+    // one lane per packed (k1, k2), decoded once, every l of it (the lanes
+    // of one l store consecutive positions)
+    for (int kk = tid; kk < d.KK; kk += kThreads) {
         int k1, k2;
         dev::tri_decode(d.K, kk, k1, k2);
-        const T* c1 = c + k1 * d.L2 + l * l;
-        const T* c2 = c + k2 * d.L2 + l * l;
-        T acc = T(0);
-        for (int m = 0; m < 2 * l + 1; ++m) acc += c1[m] * c2[m];
-        p_out[o] = acc;
+        const T* c1 = c + k1 * d.L2;
+        const T* c2 = c + k2 * d.L2;
+        for (int l = 0; l < lm1; ++l) {
+            T acc = T(0);
+            for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) acc += c1[lm] * c2[lm];
+            p_out[int64_t(l) * d.KK + kk] = acc;
+        }
     }
     if (!GRAD) return;
     if (a.pair_offsets[a.n_atoms] > a.pair_capacity) {
