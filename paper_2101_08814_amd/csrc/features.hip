@@ -379,20 +379,21 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum(FeatureArgs a)
         return;
     }
     T* dps_out = static_cast<T*>(a.dp_self) + i * 3 * PL;
-    for (int64_t o = tid; o < 3 * PL; o += kThreads) {
-        int x = int(o / PL);
-        int64_t r0 = o - x * PL;
-        int l = int(r0 / d.KK);
-        int kk = int(r0 - int64_t(l) * d.KK);
+    // self rows of p: the product rule on the self rows of c, one lane per
+    // packed (k1, k2) over every (x, l)
+    for (int kk = tid; kk < d.KK; kk += kThreads) {
         int k1, k2;
         dev::tri_decode(d.K, kk, k1, k2);
-        const T* c1 = c + k1 * d.L2 + l * l;
-        const T* c2 = c + k2 * d.L2 + l * l;
-        const T* g1 = g + x * KL2 + k1 * d.L2 + l * l;
-        const T* g2 = g + x * KL2 + k2 * d.L2 + l * l;
-        T acc = T(0);
-        for (int m = 0; m < 2 * l + 1; ++m) acc += g1[m] * c2[m] + c1[m] * g2[m];
-        dps_out[o] = acc;
+        for (int x = 0; x < 3; ++x)
+            for (int l = 0; l < lm1; ++l) {
+                const T* c1 = c + k1 * d.L2 + l * l;
+                const T* c2 = c + k2 * d.L2 + l * l;
+                const T* g1 = g + x * KL2 + k1 * d.L2 + l * l;
+                const T* g2 = g + x * KL2 + k2 * d.L2 + l * l;
+                T acc = T(0);
+                for (int m = 0; m < 2 * l + 1; ++m) acc += g1[m] * c2[m] + c1[m] * g2[m];
+                dps_out[x * PL + int64_t(l) * d.KK + kk] = acc;
+            }
     }
     __syncthreads();
     // rows: one wave per pair; w[x][l][n][k] = sum_m dc_{x,n,lm} c_{k,lm}
