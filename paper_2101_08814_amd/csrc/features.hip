@@ -96,6 +96,10 @@ __device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout&
     const int chunk = L.chunk;
     init_tables<T>(a, d, L, s);
     const int n_chunks = int((q_end - q_begin + chunk - 1) / chunk);
+    // the partial chunk comes first, so the chunk left staged after the
+    // accumulation (the last) is a full one and the pair-row phase restages
+    // the fewest pairs
+    const int pad = int(int64_t(n_chunks) * chunk - (q_end - q_begin));
     const int KL2 = d.K * d.L2, nL2 = d.nmax * d.L2, lm1 = d.lm1;
     const int KK = d.KK, PL = lm1 * KK;
     if (!REGC)
@@ -113,8 +117,8 @@ __device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout&
 #pragma unroll
     for (int j = 0; j < (REGC ? kRegItems : 1); ++j) rc[j][0] = rc[j][1] = T(0);
     for (int ck = 0; ck < n_chunks; ++ck) {
-        int64_t q0 = q_begin + int64_t(ck) * chunk;
-        int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
+        const int64_t q0 = q_begin + (ck == 0 ? 0 : int64_t(ck) * chunk - pad);
+        const int nc = ck == 0 ? chunk - pad : chunk;
         stage_chunk<T, GRAD>(a, d, s, q0, nc);
         if constexpr (REGC) {
 #pragma unroll
@@ -282,8 +286,8 @@ __device__ __forceinline__ void centres_body(const FeatureArgs& a, const Layout&
     const int nlk = lm1 * d.K;
     V4<T>* yzw = reinterpret_cast<V4<T>*>(s.yz) + wave * nlk;
     for (int ck = n_chunks - 1; ck >= 0; --ck) {
-        const int64_t q0 = q_begin + int64_t(ck) * chunk;
-        const int nc = int(q_end - q0 < chunk ? q_end - q0 : chunk);
+        const int64_t q0 = q_begin + (ck == 0 ? 0 : int64_t(ck) * chunk - pad);
+        const int nc = ck == 0 ? chunk - pad : chunk;
         __syncthreads();
         if (ck != n_chunks - 1) stage_chunk<T, true>(a, d, s, q0, nc);
         for (int p = wave; p < nc; p += kWaves) {
