@@ -5,7 +5,8 @@
 // gradient of p_{i,l,.} unpacked into a symmetric K x K matrix whose
 // diagonal is doubled,
 //   dL/dc_{k,lm} = sum_k' W_{l,k k'} c_{k',lm}.
-// One work-group per centre; W_l is staged row by row through LDS.
+// One work-group per centre: W_l unpacked into full blocks in LDS when K is
+// a multiple of 4 and they fit, else read from the packed triangle.
 //
 // Expansion (App. B Eq. energy-derivative): for pair q = (i, j, s)
 //   g_q = dL/dr_ji = sum_{n,lm} G_{i,a_j,n,lm} [(f I~)'_nl Y_lm u + f I~_nl grad Y_lm],
