@@ -436,6 +436,38 @@ __global__ void __launch_bounds__(256) k_tile_scan(const Tin* in, Tout* out, Tou
 // wrapped position (kept for the placing pass), bin occupancy by atomics.
 constexpr int kOffsetCache = 2048;
 
+// atomicAdd(&ctr[key], 1) for every active lane of the wave, returning the
+// old value, with the lanes that share a key combined into one atomic (a
+// molecule's atoms all land in one bin, so plain per-lane atomics on the
+// same counter serialise); up to kAggRounds distinct keys per wave this
+// way, the rest one atomic per lane.  Lanes of one key take consecutive
+// values in lane order.
+constexpr int kAggRounds = 4;
+
+__device__ __forceinline__ int wave_counter_inc(int* ctr, int key)
+{
+    const int lane = threadIdx.x & 63;
+    bool pending = true;
+    int result = 0;
+    for (int round = 0; round < kAggRounds; ++round) {
+        const uint64_t pend = __ballot(pending);
+        if (pend == 0) break;
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const int lkey = __shfl(key, leader, 64);
+        const bool mine = pending && key == lkey;
+        const uint64_t m = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[lkey], int(__popcll(m)));
+        base = __shfl(base, leader, 64);
+        if (mine) {
+            result = base + int(__popcll(m & ((uint64_t(1) << lane) - 1)));
+            pending = false;
+        }
+    }
+    if (pending) result = atomicAdd(&ctr[key], 1);
+    return result;
+}
+
 __global__ void __launch_bounds__(256) k_assign(NeighborArgs a)
 {
     __shared__ int64_t offs[kOffsetCache + 1];
@@ -480,7 +512,7 @@ __global__ void __launch_bounds__(256) k_assign(NeighborArgs a)
     double4 w;
     const int32_t bin = place_atom(a, i, s, a.geom[s], r, sp, w);
     a.wrapped[i] = w;
-    atomicAdd(&a.bin_count[bin], 1);
+    wave_counter_inc(a.bin_count, bin);
 }
 
 template <typename Tin, typename Tout>
@@ -496,7 +528,7 @@ __global__ void k_bins(NeighborArgs a)
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_atoms || !*a.ok) return;
     const double4 w = a.wrapped[i];
-    int pos = atomicAdd(&a.bin_cursor[a.atom_bin[i]], 1);
+    int pos = wave_counter_inc(a.bin_cursor, a.atom_bin[i]);
     a.bin_atoms[pos] = int32_t(i);
     a.slots[pos] = w;
 }
