@@ -979,18 +979,8 @@ __global__ void __launch_bounds__(kFillWaves * 64) k_fill(NeighborArgs a)
     }
 }
 
-__global__ void k_transpose(NeighborArgs a)
+__device__ void transpose_pair(const NeighborArgs& a, int64_t i, int64_t q)
 {
-    int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t P = a.pair_offsets[a.n_atoms];
-    if (P > a.capacity || q >= P) return;
-    // centre of pair q: last i with pair_offsets[i] <= q
-    int64_t lo = 0, hi = a.n_atoms - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (a.pair_offsets[mid] <= q) lo = mid; else hi = mid - 1;
-    }
-    int64_t i = lo;
     int j = a.pair_j[q];
     int64_t th, tl;
     make_key(a.species[i], int(i), -a.pair_shift[3 * q], -a.pair_shift[3 * q + 1], -a.pair_shift[3 * q + 2], th, tl);
@@ -1011,6 +1001,17 @@ __global__ void k_transpose(NeighborArgs a)
     }
     a.pair_transpose[q] = found ? int32_t(b) : -1;
     if (!found) put_status(a.status, SOAP_EGEOMETRY);
+}
+
+// one wave per centre i, lanes over its pairs q = (i, j, s): the reverse
+// pair (j, i, -s) is found by binary search in j's sorted list
+__global__ void __launch_bounds__(256) k_transpose(NeighborArgs a)
+{
+    const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (i >= a.n_atoms || a.pair_offsets[a.n_atoms] > a.capacity) return;
+    const int64_t q_end = a.pair_offsets[i + 1];
+    for (int64_t q = a.pair_offsets[i] + (threadIdx.x & 63); q < q_end; q += 64)
+        transpose_pair(a, i, q);
 }
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
@@ -1081,8 +1082,8 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
             else { if (one) SOAP_FILL(true, false); else SOAP_FILL(false, false); }
         }
 #undef SOAP_FILL
-        if (a.pair_transpose)
-            hipLaunchKernelGGL(k_transpose, dim3(blocks(a.capacity, T)), dim3(T), 0, stream, a);
+        if (a.pair_transpose && a.n_atoms > 0)
+            hipLaunchKernelGGL(k_transpose, dim3(blocks(a.n_atoms, 4)), dim3(256), 0, stream, a);
     }
     return hipGetLastError();
 }
