@@ -307,8 +307,11 @@ soap_status soap_compress_init_pca(const soap_calculator* calc, const soap_exec*
 /* Forward pass: coeffs [N][K][L2] -> coeffs_out [N][n_out][L2] and/or
  * p_out [N][lmax+1][n_out (n_out+1)/2] (either may be NULL, not both).
  * precision SOAP_F32: float arithmetic throughout.  SOAP_BF16_F32ACC: the
- * two layers run on MFMA with bfloat16 operands (c and the weights rounded
- * to bfloat16) and float accumulation; the gate and p~ in float.       */
+ * two layers run on MFMA with bfloat16 operands (c, the weights and the
+ * gated hidden layer rounded to bfloat16) and float accumulation; the gate
+ * in float; p~ from the float c~ (where K, hidden <= 128 are multiples of
+ * 4 and n_out <= 32, as a Gram matrix on MFMA with a bfloat16 high/low
+ * split of c~, relative error about 2^-16).                           */
 soap_status soap_compress_forward(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
                                   int32_t n_out, int32_t hidden, int64_t n_atoms, const float* weights,
                                   const float* coeffs, float* coeffs_out, float* p_out);
