@@ -270,6 +270,24 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
                                               const void* grad_coeffs, void* grad_pair_vec,
                                               void* grad_positions);
 
+/* Virial of the loss per structure (Sec. 4.G, Eq. energy-virial: the
+ * stress term of a homogeneous deformation r -> (1 + eps) r of positions
+ * and cell):
+ *   virial_s[a][b] = sum over the pairs q of the centres of structure s of
+ *                    g_{q,a} r_{q,b},
+ * with g_q = dL/dr_ji from soap_spherical_expansion_backward (grad_pair_vec)
+ * and r_q = pair_vec (images included: a pair to an image carries its
+ * shifted vector).  atom_offsets [n_structures+1] (device, int64) tiles
+ * the atoms; centre_partials is caller scratch of 9 * n_atoms elements.
+ * Sums run in a fixed order (bitwise reproducible).
+ * out virial [n_structures][3][3] (overwritten).
+ * precision: SOAP_F64 or SOAP_F32 (the type of pair_vec, grad_pair_vec,
+ * centre_partials and virial).                                        */
+soap_status soap_virial(const soap_exec* exec, soap_precision precision, int32_t n_structures,
+                        const int64_t* atom_offsets, int64_t n_atoms, const int64_t* pair_offsets,
+                        const void* pair_vec, const void* grad_pair_vec, int64_t pair_capacity,
+                        void* centre_partials, void* virial);
+
 /* ------------------------------------------------------------------
  * Learned channel compression (a learned counterpart of the reduction of
  * the feature space of Sec. 4.H and the lossy strategy of Sec. 7, keeping

@@ -260,6 +260,22 @@ def vjp(hypers, species, nl, grad_p):
     return out, gp[:P]
 
 
+def virial(atom_offsets, nl, grad_pair):
+    """Sec. 4.G, Eq. energy-virial: per structure s, W_s[a][b] = sum over the
+    pairs q of the centres of s of dL/dr_q[a] * r_q[b] (r_q the pair vector,
+    images included), the derivative of L under the deformation
+    r -> (1 + eps) r of positions and cell."""
+    offs = np.asarray(atom_offsets, dtype=np.int64)
+    po = np.asarray(nl.pair_offsets, dtype=np.int64)
+    vec = np.asarray(nl.pair_vec, dtype=np.float64).reshape(-1, 3)
+    g = np.asarray(grad_pair, dtype=np.float64).reshape(-1, 3)
+    W = np.zeros((len(offs) - 1, 3, 3))
+    for s in range(len(offs) - 1):
+        q0, q1 = po[offs[s]], po[offs[s + 1]]
+        W[s] = g[q0:q1].T @ vec[q0:q1]
+    return W
+
+
 def features(batch, centres=None):
     """Neighbours, coefficients and power spectrum of a batch (FP64)."""
     nl = neighbors(batch)

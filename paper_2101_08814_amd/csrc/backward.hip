@@ -228,6 +228,76 @@ __global__ void __launch_bounds__(256) k_exp_backward_gather(FeatureArgs a, cons
     }
 }
 
+// Virial: per centre (one wave, lanes over its pairs) the nine sums
+// g_a r_b, then per structure (one work-group, lanes over its centres) a
+// fixed-order reduction of the centre sums.
+template <typename T>
+__global__ void __launch_bounds__(256) k_virial_centres(int64_t n_atoms, const int64_t* pair_offsets,
+                                                        int64_t capacity, const T* vec, const T* g, T* part,
+                                                        int32_t* status)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (i >= n_atoms) return;
+    T acc[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[e] = T(0);
+    if (pair_offsets[n_atoms] <= capacity) {
+        for (int64_t q = pair_offsets[i] + lane; q < pair_offsets[i + 1]; q += 64) {
+            const T g0 = g[3 * q], g1 = g[3 * q + 1], g2 = g[3 * q + 2];
+            const T r0 = vec[3 * q], r1 = vec[3 * q + 1], r2 = vec[3 * q + 2];
+            acc[0] += g0 * r0; acc[1] += g0 * r1; acc[2] += g0 * r2;
+            acc[3] += g1 * r0; acc[4] += g1 * r1; acc[5] += g1 * r2;
+            acc[6] += g2 * r0; acc[7] += g2 * r1; acc[8] += g2 * r2;
+        }
+    } else if (lane == 0 && i == 0) {
+        put_status(status, SOAP_ECAPACITY);
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const T v = wave_sum(acc[e]);
+        if (lane == 0) part[9 * i + e] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_virial_structures(const int64_t* atom_offsets, const T* part, T* out)
+{
+    __shared__ T red[9][256];
+    const int s = blockIdx.x, t = threadIdx.x;
+    const int64_t lo = atom_offsets[s], hi = atom_offsets[s + 1];
+    T acc[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[e] = T(0);
+    for (int64_t i = lo + t; i < hi; i += 256)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[e] += part[9 * i + e];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) red[e][t] = acc[e];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) red[e][t] += red[e][t + w];
+        __syncthreads();
+    }
+    if (t < 9) out[9 * int64_t(s) + t] = red[t][0];
+}
+
+template <typename T>
+hipError_t virial_t(int32_t n_structures, const int64_t* atom_offsets, int64_t n_atoms, const int64_t* pair_offsets,
+                    const void* vec, const void* g, int64_t capacity, void* part, void* out, int32_t* status,
+                    hipStream_t stream)
+{
+    if (n_atoms > 0)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_virial_centres<T>), dim3(unsigned((n_atoms + 3) / 4)), dim3(256), 0,
+                           stream, n_atoms, pair_offsets, capacity, static_cast<const T*>(vec),
+                           static_cast<const T*>(g), static_cast<T*>(part), status);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_virial_structures<T>), dim3(unsigned(n_structures)), dim3(256), 0, stream,
+                       atom_offsets, static_cast<const T*>(part), static_cast<T*>(out));
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t ps_backward_t(const FeatureArgs& a, const void* grad_p, void* grad_c, hipStream_t stream)
 {
@@ -282,6 +352,16 @@ hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const 
 {
     return f64 ? ps_backward_t<double>(a, grad_p, grad_coeffs, stream)
                : ps_backward_t<float>(a, grad_p, grad_coeffs, stream);
+}
+
+hipError_t launch_virial(bool f64, int32_t n_structures, const int64_t* atom_offsets, int64_t n_atoms,
+                         const int64_t* pair_offsets, const void* pair_vec, const void* grad_pair_vec,
+                         int64_t capacity, void* partials, void* virial, int32_t* status, hipStream_t stream)
+{
+    return f64 ? virial_t<double>(n_structures, atom_offsets, n_atoms, pair_offsets, pair_vec, grad_pair_vec,
+                                  capacity, partials, virial, status, stream)
+               : virial_t<float>(n_structures, atom_offsets, n_atoms, pair_offsets, pair_vec, grad_pair_vec,
+                                 capacity, partials, virial, status, stream);
 }
 
 hipError_t launch_expansion_backward(const FeatureArgs& a, bool f64, const int32_t* pair_transpose,

@@ -615,6 +615,34 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
 }
 
 
+soap_status soap_virial(const soap_exec* exec, soap_precision precision, int32_t n_structures,
+                        const int64_t* atom_offsets, int64_t n_atoms, const int64_t* pair_offsets,
+                        const void* pair_vec, const void* grad_pair_vec, int64_t pair_capacity,
+                        void* centre_partials, void* virial)
+{
+    clear_error();
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_structures >= 0, "n_structures must be >= 0");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(pair_capacity >= 0, "pair_capacity must be >= 0");
+    if (n_structures == 0) return SOAP_OK;
+    const size_t es = elem_size(precision);
+    CHECK(check_ptr(atom_offsets, 8, "atom_offsets"));
+    CHECK(check_ptr(virial, es, "virial"));
+    if (n_atoms > 0) {
+        CHECK(check_ptr(pair_offsets, 8, "pair_offsets"));
+        CHECK(check_ptr(centre_partials, es, "centre_partials"));
+        if (pair_capacity > 0) {
+            CHECK(check_ptr(pair_vec, es, "pair_vec"));
+            CHECK(check_ptr(grad_pair_vec, es, "grad_pair_vec"));
+        }
+    }
+    return launched(launch_virial(precision == SOAP_F64, n_structures, atom_offsets, n_atoms, pair_offsets, pair_vec,
+                                  grad_pair_vec, pair_capacity, centre_partials, virial, status_of(exec),
+                                  stream_of(exec)),
+                    "virial");
+}
+
 soap_status soap_compress_n_params(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t* n_params)
 {
     clear_error();

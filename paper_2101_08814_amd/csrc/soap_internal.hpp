@@ -99,6 +99,9 @@ hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipS
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream);
 hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const void* grad_p,
                                           void* grad_coeffs, hipStream_t stream);
+hipError_t launch_virial(bool f64, int32_t n_structures, const int64_t* atom_offsets, int64_t n_atoms,
+                         const int64_t* pair_offsets, const void* pair_vec, const void* grad_pair_vec,
+                         int64_t capacity, void* partials, void* virial, int32_t* status, hipStream_t stream);
 hipError_t launch_expansion_backward(const FeatureArgs& a, bool f64, const int32_t* pair_transpose,
                                      const void* grad_coeffs, void* grad_pair_vec,
                                      void* grad_positions, hipStream_t stream);

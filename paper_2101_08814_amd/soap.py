@@ -276,6 +276,24 @@ class Calculator:
         dps = torch.empty((N, 3, self.lmax + 1, self.KK), dtype=td, device=dev)
         return (c, p, dc, dcs, dp, dps)
 
+    def virial(self, nl: Neighbors, grad_pair_vec: torch.Tensor, atom_offsets) -> torch.Tensor:
+        """soap_virial: [S, 3, 3], W_s[a][b] = sum over the pairs of the centres
+        of structure s of grad_pair_vec[q, a] * pair_vec[q, b]."""
+        td = grad_pair_vec.dtype
+        prec = _precision(td)
+        vec = _vec_as(nl, td)
+        dev = grad_pair_vec.device
+        ao = torch.as_tensor(np.asarray(atom_offsets, dtype=np.int64) if not isinstance(atom_offsets, torch.Tensor)
+                             else atom_offsets, dtype=torch.int64).to(dev).contiguous()
+        S = int(ao.shape[0]) - 1
+        N = nl.pair_offsets.shape[0] - 1
+        part = torch.empty((max(N, 1), 9), dtype=td, device=dev)
+        out = torch.empty((max(S, 1), 3, 3), dtype=td, device=dev)
+        e = self._exec()
+        check(self._L.soap_virial(ctypes.byref(e), prec, S, _ptr(ao), N, _ptr(nl.pair_offsets), _ptr(vec),
+                                  _ptr(grad_pair_vec), nl.capacity, _ptr(part), _ptr(out)))
+        return out[:S]
+
     def power_spectrum_backward(self, coeffs: torch.Tensor, grad_p: torch.Tensor) -> torch.Tensor:
         prec = _precision(coeffs.dtype)
         N = coeffs.shape[0]

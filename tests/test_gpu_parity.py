@@ -382,6 +382,46 @@ def test_vjp_matches_oracle(dt):
     assert ep <= (1e-7 if dt == torch.float64 else 1e-5)
 
 
+def _virial_batch():
+    """A 256-atom liquid cube, an empty structure and a 40-atom triclinic
+    cell, all with the liquid's hypers (2 species, nmax 10, lmax 8, rcut 6)."""
+    a = synthetic.liquid_bulk(n_atoms=256)
+    cell = np.array([[9.1, 0.0, 0.0], [1.7, 8.6, 0.0], [-0.9, 1.2, 9.4]])
+    t = synthetic.random_cell_structure(31, 40, cell, 2, min_sep=1.5, hypers=a.hypers)
+    na, nt = a.n_atoms, t.n_atoms
+    return synthetic.Batch(np.concatenate([a.positions, t.positions]), np.concatenate([a.species, t.species]),
+                           np.array([0, na, na, na + nt], dtype=np.int64),
+                           np.concatenate([a.cells, np.zeros((1, 3, 3)), t.cells]),
+                           np.concatenate([a.pbc, np.zeros((1, 3), dtype=np.uint8), t.pbc]), a.hypers)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_virial_matches_oracle(dt):
+    """Per-structure virial (Sec. 4.G, Eq. energy-virial) of L = <W, p>,
+    W ~ N(0, 1) (seed 2005): GPU adjoint then soap_virial against the
+    oracle's VJP and virial; the empty structure gives exactly zero."""
+    b = _virial_batch()
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, pos, spc = gpu_neighbors(calc, b, dt)
+    c, p = calc.features(nl, spc, dt)
+    W = np.random.default_rng(2005).normal(size=tuple(p.shape))
+    gc = calc.power_spectrum_backward(c, torch.tensor(W, dtype=dt, device="cuda"))
+    _, gpair = calc.spherical_expansion_backward(nl, spc, gc)
+    vir = calc.virial(nl, gpair, b.atom_offsets)
+    assert calc.device_status() == 0
+    ref_nl = oracle.neighbors(b)
+    _, gp_ref = oracle.vjp(b.hypers, b.species, ref_nl, W)
+    ref = oracle.virial(b.atom_offsets, ref_nl, gp_ref)
+    got = vir.double().cpu().numpy()
+    assert got.shape == (3, 3, 3)
+    assert np.all(got[1] == 0.0)
+    tol = 1e-7 if dt == torch.float64 else 1e-5
+    for s in (0, 2):
+        e = rel(got[s], ref[s])
+        print(f"[virial {dt}] structure {s} rel={e:.3e}")
+        assert e <= tol
+
+
 def test_vjp_full_size_against_finite_differences():
     """4096-atom liquid (2 species, nmax 10, lmax 8, rcut 6): the FP32 adjoint
     against central differences (h = 1e-4 A) of the FP64 GPU forward on 32

@@ -579,3 +579,39 @@ def test_torque_free_cluster_gradient():
     torque = np.cross(b.positions, g).sum(0)
     assert np.abs(torque).max() <= 1e-9 * np.abs(g).max() * np.abs(b.positions).max()
     assert np.abs(g.sum(0)).max() <= 1e-10 * np.abs(g).max()
+
+
+def test_virial_matches_strain_finite_differences():
+    """Eq. energy-virial: dL/d eps_ab under r -> (1 + eps) r of positions and
+    cell equals sum_q g_{q,a} r_{q,b}; central differences of the whole
+    oracle pipeline (new neighbour list at every step) on a small periodic
+    triclinic cell; two copies of the cell as two structures give two equal
+    virials."""
+    b = _small_periodic()
+    h = b.hypers
+    nl, c, p = oracle.features(b)
+    G = np.random.default_rng(2).normal(size=p.shape)
+    _, gpair = oracle.vjp(h, b.species, nl, G)
+    W = oracle.virial(b.atom_offsets, nl, gpair)
+    eps = 1e-5
+    fd = np.zeros((3, 3))
+    for a_ in range(3):
+        for b_ in range(3):
+            L = []
+            for sgn in (1, -1):
+                D = np.eye(3)
+                D[a_, b_] += sgn * eps
+                pos = b.positions @ D.T
+                cells = np.stack([cl @ D.T for cl in b.cells])
+                L.append(np.sum(G * oracle.features(synthetic.Batch(pos, b.species, b.atom_offsets, cells, b.pbc, h))[2]))
+            fd[a_, b_] = (L[0] - L[1]) / (2 * eps)
+    assert W.shape == (1, 3, 3)
+    assert np.abs(W[0] - fd).max() <= 1e-6 * max(1.0, np.abs(fd).max())
+    # a single structure's virial is the sum over its centres (two copies add)
+    b2 = synthetic.Batch(np.concatenate([b.positions, b.positions]), np.concatenate([b.species, b.species]),
+                         np.array([0, b.n_atoms, 2 * b.n_atoms]), np.stack([b.cells[0], b.cells[0]]),
+                         np.stack([b.pbc[0], b.pbc[0]]), h)
+    nl2, _, p2 = oracle.features(b2)
+    _, gp2 = oracle.vjp(h, b2.species, nl2, np.concatenate([G, G]))
+    W2 = oracle.virial(b2.atom_offsets, nl2, gp2)
+    assert np.allclose(W2[0], W[0], rtol=1e-12, atol=1e-12) and np.allclose(W2[1], W[0], rtol=1e-12, atol=1e-12)
