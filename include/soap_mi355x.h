@@ -270,7 +270,7 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
                                               const void* grad_coeffs, void* grad_pair_vec,
                                               void* grad_positions);
 
-/* Virial of the loss per structure (Sec. 4.G, Eq. energy-virial: the
+/* Virial of the loss per structure (App. B, Eq. energy-virial: the
  * stress term of a homogeneous deformation r -> (1 + eps) r of positions
  * and cell):
  *   virial_s[a][b] = sum over the pairs q of the centres of structure s of

@@ -261,7 +261,7 @@ def vjp(hypers, species, nl, grad_p):
 
 
 def virial(atom_offsets, nl, grad_pair):
-    """Sec. 4.G, Eq. energy-virial: per structure s, W_s[a][b] = sum over the
+    """App. B, Eq. energy-virial: per structure s, W_s[a][b] = sum over the
     pairs q of the centres of s of dL/dr_q[a] * r_q[b] (r_q the pair vector,
     images included), the derivative of L under the deformation
     r -> (1 + eps) r of positions and cell."""
@@ -274,6 +274,28 @@ def virial(atom_offsets, nl, grad_pair):
         q0, q1 = po[offs[s]], po[offs[s + 1]]
         W[s] = g[q0:q1].T @ vec[q0:q1]
     return W
+
+
+def gpr_predict(species, feats, active_species, active_feats, weights, zeta):
+    """Sparse kernel model of Sec. 5.B.  Per centre i (Eq. sparse-gp with the
+    polynomial kernel k = (M_I . p_i)^zeta):
+        E_i = sum over active points I of species a_i of w_I (M_I . p_i)^zeta,
+    and the derivative of E_i with respect to the features, with the sum
+    over the active set taken first (Eq. gpr-force-order):
+        dE_i/dp_i = sum over the same I of w_I zeta (M_I . p_i)^(zeta-1) M_I.
+    feats [N, F], active_feats [n_active, F]; returns (E [N], dE/dp [N, F]).
+    Structure energies are the sums of E_i over their centres (Eq.
+    additive-energy-model); forces and virial follow from dE/dp through the
+    adjoint (vjp, virial)."""
+    p = np.asarray(feats, dtype=np.float64).reshape(len(species), -1)
+    M = np.asarray(active_feats, dtype=np.float64).reshape(len(active_species), -1)
+    w = np.asarray(weights, dtype=np.float64)
+    same = np.asarray(species)[:, None] == np.asarray(active_species)[None, :]
+    k1 = p @ M.T                                    # M_I . p_i
+    coef = np.where(same, w[None, :], 0.0)
+    E = (coef * k1 ** zeta).sum(axis=1)
+    dk = coef * zeta * k1 ** (zeta - 1)
+    return E, dk @ M
 
 
 def features(batch, centres=None):

@@ -397,7 +397,7 @@ def _virial_batch():
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 def test_virial_matches_oracle(dt):
-    """Per-structure virial (Sec. 4.G, Eq. energy-virial) of L = <W, p>,
+    """Per-structure virial (App. B, Eq. energy-virial) of L = <W, p>,
     W ~ N(0, 1) (seed 2005): GPU adjoint then soap_virial against the
     oracle's VJP and virial; the empty structure gives exactly zero."""
     b = _virial_batch()

@@ -615,3 +615,74 @@ def test_virial_matches_strain_finite_differences():
     _, gp2 = oracle.vjp(h, b2.species, nl2, np.concatenate([G, G]))
     W2 = oracle.virial(b2.atom_offsets, nl2, gp2)
     assert np.allclose(W2[0], W[0], rtol=1e-12, atol=1e-12) and np.allclose(W2[1], W[0], rtol=1e-12, atol=1e-12)
+
+
+def test_gpr_predict_worked_example():
+    """Eq. sparse-gp with the polynomial kernel, worked by hand: F = 2,
+    centres p0 = (1, 2) of species 0 and p1 = (2, -1) of species 1; active
+    points (3, 1), (0, 1) of species 0 and (1, 1) of species 1, weights
+    0.5, 2, -1; zeta = 2.
+      E0 = 0.5*5^2 + 2*2^2 = 20.5,  dE0/dp = 0.5*2*5*(3, 1) + 2*2*2*(0, 1) = (15, 13)
+      E1 = -1*1^2 = -1,             dE1/dp = -1*2*1*(1, 1) = (-2, -2)
+    and at zeta = 1 the model is linear: dE/dp is the weighted sum of the
+    active points of the centre's species, E = p . dE/dp."""
+    sp = np.array([0, 1])
+    p = np.array([[1.0, 2.0], [2.0, -1.0]])
+    asp = np.array([0, 0, 1])
+    M = np.array([[3.0, 1.0], [0.0, 1.0], [1.0, 1.0]])
+    w = np.array([0.5, 2.0, -1.0])
+    E, g = oracle.gpr_predict(sp, p, asp, M, w, 2)
+    assert np.array_equal(E, [20.5, -1.0])
+    assert np.array_equal(g, [[15.0, 13.0], [-2.0, -2.0]])
+    E1, g1 = oracle.gpr_predict(sp, p, asp, M, w, 1)
+    assert np.array_equal(g1, [[1.5, 2.5], [-1.0, -1.0]])
+    assert np.array_equal(E1, [6.5, -1.0])
+    assert np.array_equal(E1, (p * g1).sum(axis=1))
+
+
+def test_gpr_forces_and_virial_match_finite_differences():
+    """Eqs. gpr-force-order and gpr-stress: forces and virial of the sparse
+    model's total energy (Eq. additive-energy-model), formed as the adjoint
+    of dE/dp from the active-set contraction, against central differences
+    of the whole oracle pipeline (atom displacements and homogeneous strain)
+    on a small periodic triclinic cell; zeta = 3, active points from the
+    normalised features of another cell."""
+    b = _small_periodic()
+    h = b.hypers
+    nl, c, p = oracle.features(b)
+    other = synthetic.random_cell_structure(23, 9, b.cells[0], 2, min_sep=1.1, hypers=h)
+    _, _, pa = oracle.features(other)
+    pa = pa.reshape(other.n_atoms, -1)
+    M = pa / np.linalg.norm(pa, axis=1, keepdims=True)
+    w = np.random.default_rng(3).normal(size=other.n_atoms)
+    zeta = 3
+
+    def energy(batch):
+        _, _, pp = oracle.features(batch)
+        return oracle.gpr_predict(batch.species, pp.reshape(batch.n_atoms, -1), other.species, M, w, zeta)[0].sum()
+
+    E, dEdp = oracle.gpr_predict(b.species, p.reshape(b.n_atoms, -1), other.species, M, w, zeta)
+    assert abs(E.sum() - energy(b)) == 0.0
+    grad, gpair = oracle.vjp(h, b.species, nl, dEdp.reshape(p.shape))
+    vir = oracle.virial(b.atom_offsets, nl, gpair)[0]
+    eps = 1e-5
+    scale = np.abs(grad).max()
+    for k in range(b.n_atoms):
+        for x in range(3):
+            e = []
+            for sgn in (1, -1):
+                pos = b.positions.copy()
+                pos[k, x] += sgn * eps
+                e.append(energy(synthetic.Batch(pos, b.species, b.atom_offsets, b.cells, b.pbc, h)))
+            assert abs((e[0] - e[1]) / (2 * eps) - grad[k, x]) <= 1e-6 * scale
+    fd = np.zeros((3, 3))
+    for a_ in range(3):
+        for b_ in range(3):
+            e = []
+            for sgn in (1, -1):
+                D = np.eye(3)
+                D[a_, b_] += sgn * eps
+                cells = np.stack([cl @ D.T for cl in b.cells])
+                e.append(energy(synthetic.Batch(b.positions @ D.T, b.species, b.atom_offsets, cells, b.pbc, h)))
+            fd[a_, b_] = (e[0] - e[1]) / (2 * eps)
+    assert np.abs(vir - fd).max() <= 1e-6 * max(1.0, np.abs(fd).max())
