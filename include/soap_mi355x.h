@@ -270,6 +270,35 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
                                               const void* grad_coeffs, void* grad_pair_vec,
                                               void* grad_positions);
 
+/* Sparse kernel model (Sec. 5.B, Eq. sparse-gp with the polynomial kernel):
+ * for each centre i,
+ *   energies[i] = sum over active points I with active_species[I] ==
+ *                 centre_species[i] of weights[I] (M_I . p_i)^zeta,
+ * and, when grad_features is not NULL,
+ *   grad_features[i] = sum over the same I of weights[I] zeta
+ *                      (M_I . p_i)^(zeta-1) M_I,
+ * the active-set sum taken first (Eq. gpr-force-order): passing
+ * grad_features as grad_p to soap_power_spectrum_backward and on through
+ * soap_spherical_expansion_backward and soap_virial gives the model's
+ * energy gradient and virial.  A structure's energy is the sum of its
+ * centres' energies (Eq. additive-energy-model).
+ * features [n_centres][n_features] (p_i, any per-centre feature vector such
+ * as the packed power spectrum), active_features [n_active][n_features]
+ * (M_I), weights [n_active], all device memory in the precision's type,
+ * row-major; species int32 (device).  zeta in [1, 64]; n_features and
+ * n_active at most 4,194,240, n_centres below 2^31 (else SOAP_EINVAL).
+ * workspace: device scratch of soap_gpr_workspace_size bytes (two
+ * [n_centres][n_active] matrices), owned by the caller.
+ * energies [n_centres] and grad_features [n_centres][n_features] are
+ * overwritten.  Sums run in a fixed order (bitwise reproducible).
+ * precision: SOAP_F64 or SOAP_F32.                                     */
+soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_active, size_t* bytes);
+soap_status soap_gpr_predict(const soap_exec* exec, soap_precision precision, int64_t n_centres, int64_t n_features,
+                             const int32_t* centre_species, const void* features, int64_t n_active,
+                             const int32_t* active_species, const void* active_features, const void* weights,
+                             int32_t zeta, void* workspace, size_t workspace_bytes, void* energies,
+                             void* grad_features);
+
 /* Virial of the loss per structure (App. B, Eq. energy-virial: the
  * stress term of a homogeneous deformation r -> (1 + eps) r of positions
  * and cell):

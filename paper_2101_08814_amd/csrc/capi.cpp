@@ -643,6 +643,49 @@ soap_status soap_virial(const soap_exec* exec, soap_precision precision, int32_t
                     "virial");
 }
 
+soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_active, size_t* bytes)
+{
+    clear_error();
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_centres >= 0 && n_centres < (int64_t(1) << 31), "n_centres must be in [0, 2^31)");
+    REQUIRE(n_active >= 1 && n_active < (int64_t(1) << 31), "n_active must be in [1, 2^31)");
+    REQUIRE(bytes != nullptr, "bytes must not be NULL");
+    *bytes = gpr_workspace_bytes(precision == SOAP_F64, n_centres, n_active);
+    return SOAP_OK;
+}
+
+soap_status soap_gpr_predict(const soap_exec* exec, soap_precision precision, int64_t n_centres, int64_t n_features,
+                             const int32_t* centre_species, const void* features, int64_t n_active,
+                             const int32_t* active_species, const void* active_features, const void* weights,
+                             int32_t zeta, void* workspace, size_t workspace_bytes, void* energies,
+                             void* grad_features)
+{
+    clear_error();
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_centres >= 0 && n_centres < (int64_t(1) << 31), "n_centres must be in [0, 2^31)");
+    // column tiles of 64 run along the grid's y dimension (at most 65535)
+    REQUIRE(n_features >= 1 && n_features <= 64 * int64_t(65535), "n_features must be in [1, 4194240]");
+    REQUIRE(n_active >= 1 && n_active <= 64 * int64_t(65535), "n_active must be in [1, 4194240]");
+    REQUIRE(zeta >= 1 && zeta <= 64, "zeta must be in [1, 64]");
+    if (n_centres == 0) return SOAP_OK;
+    const bool f64 = precision == SOAP_F64;
+    const size_t es = elem_size(precision);
+    const size_t need = gpr_workspace_bytes(f64, n_centres, n_active);
+    REQUIRE(workspace_bytes >= need, "workspace_bytes (%zu) is below the %zu bytes needed", workspace_bytes, need);
+    CHECK(check_ptr(centre_species, 4, "centre_species"));
+    CHECK(check_ptr(features, es, "features"));
+    CHECK(check_ptr(active_species, 4, "active_species"));
+    CHECK(check_ptr(active_features, es, "active_features"));
+    CHECK(check_ptr(weights, es, "weights"));
+    CHECK(check_ptr(workspace, es, "workspace"));
+    CHECK(check_ptr(energies, es, "energies"));
+    CHECK(check_ptr(grad_features, es, "grad_features", true));
+    return launched(launch_gpr_predict(f64, n_centres, n_features, centre_species, features, n_active, active_species,
+                                       active_features, weights, zeta, workspace, energies, grad_features,
+                                       stream_of(exec)),
+                    "gpr_predict");
+}
+
 soap_status soap_compress_n_params(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t* n_params)
 {
     clear_error();

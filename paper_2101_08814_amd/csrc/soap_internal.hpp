@@ -99,6 +99,10 @@ hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipS
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream);
 hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const void* grad_p,
                                           void* grad_coeffs, hipStream_t stream);
+size_t gpr_workspace_bytes(bool f64, int64_t n, int64_t n_active);
+hipError_t launch_gpr_predict(bool f64, int64_t n, int64_t n_feat, const int32_t* species, const void* p,
+                              int64_t n_active, const int32_t* active_species, const void* m, const void* w,
+                              int zeta, void* workspace, void* energies, void* grad, hipStream_t stream);
 hipError_t launch_virial(bool f64, int32_t n_structures, const int64_t* atom_offsets, int64_t n_atoms,
                          const int64_t* pair_offsets, const void* pair_vec, const void* grad_pair_vec,
                          int64_t capacity, void* partials, void* virial, int32_t* status, hipStream_t stream);

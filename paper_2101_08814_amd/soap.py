@@ -294,6 +294,35 @@ class Calculator:
                                   _ptr(grad_pair_vec), nl.capacity, _ptr(part), _ptr(out)))
         return out[:S]
 
+    def gpr_predict(self, species: torch.Tensor, features: torch.Tensor, active_species: torch.Tensor,
+                    active_features: torch.Tensor, weights: torch.Tensor, zeta: int, want_grad: bool = True):
+        """soap_gpr_predict: per-centre energies [N] of the sparse kernel model
+        and, if want_grad, dE/dp [N, F] (None otherwise); features [N, ...]
+        are flattened per centre."""
+        td = features.dtype
+        prec = _precision(td)
+        N = features.shape[0]
+        p = features.reshape(N, -1).contiguous()
+        F = p.shape[1]
+        M = active_features.reshape(active_features.shape[0], -1).to(td).contiguous()
+        if M.shape[1] != F:
+            raise ValueError(f"active_features have {M.shape[1]} features per point, features {F}")
+        nA = M.shape[0]
+        w = weights.to(td).contiguous()
+        sp = species.to(torch.int32).contiguous()
+        asp = active_species.to(device=p.device, dtype=torch.int32).contiguous()
+        if w.shape[0] != nA or asp.shape[0] != nA or sp.shape[0] != N:
+            raise ValueError("species, active_species and weights must match the feature rows")
+        nb = ctypes.c_size_t()
+        check(self._L.soap_gpr_workspace_size(prec, N, nA, ctypes.byref(nb)))
+        ws = torch.empty(max(nb.value // p.element_size(), 1), dtype=td, device=p.device)
+        energies = torch.empty(max(N, 1), dtype=td, device=p.device)
+        grad = torch.empty((max(N, 1), F), dtype=td, device=p.device) if want_grad else None
+        e = self._exec()
+        check(self._L.soap_gpr_predict(ctypes.byref(e), prec, N, F, _ptr(sp), _ptr(p), nA, _ptr(asp), _ptr(M),
+                                       _ptr(w), int(zeta), _ptr(ws), nb.value, _ptr(energies), _ptr(grad)))
+        return energies[:N], (grad[:N] if want_grad else None)
+
     def power_spectrum_backward(self, coeffs: torch.Tensor, grad_p: torch.Tensor) -> torch.Tensor:
         prec = _precision(coeffs.dtype)
         N = coeffs.shape[0]

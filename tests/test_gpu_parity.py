@@ -422,6 +422,76 @@ def test_virial_matches_oracle(dt):
         assert e <= tol
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_gpr_predict_matches_oracle(dt):
+    """Sparse kernel model (Eq. sparse-gp, polynomial kernel, zeta = 3) on
+    seeded inputs (seed 2006) with ragged tiles: 300 centres, 1890 features,
+    150 active points; centres of species 3 have no active point and active
+    points of species 2 no centre, so those energies and gradients are 0."""
+    rng = np.random.default_rng(2006)
+    N, F, nA = 300, 1890, 150
+    sp = rng.choice([0, 1, 3], size=N, p=[0.5, 0.4, 0.1]).astype(np.int32)
+    asp = rng.choice([0, 1, 2], size=nA).astype(np.int32)
+    p = rng.normal(size=(N, F))
+    M = rng.normal(size=(nA, F))
+    M /= np.linalg.norm(M, axis=1, keepdims=True)
+    w = rng.normal(size=nA)
+    E_ref, g_ref = oracle.gpr_predict(sp, p, asp, M, w, 3)
+    calc = P.Calculator.from_hypers(synthetic.liquid_bulk(n_atoms=64).hypers)
+    dev = lambda a, t=dt: torch.tensor(a, dtype=t, device="cuda")
+    E, g = calc.gpr_predict(dev(sp, torch.int32), dev(p), dev(asp, torch.int32), dev(M), dev(w), 3)
+    E2, g2 = calc.gpr_predict(dev(sp, torch.int32), dev(p), dev(asp, torch.int32), dev(M), dev(w), 3,
+                              want_grad=False)
+    assert calc.device_status() == 0 and g2 is None
+    E, g, E2 = (x.double().cpu().numpy() for x in (E, g, E2))
+    tol = 1e-12 if dt == torch.float64 else 1e-5
+    print(f"[gpr {dt}] rel E={rel(E, E_ref):.3e} dE/dp={rel(g, g_ref):.3e}")
+    assert rel(E, E_ref) <= tol and rel(g, g_ref) <= tol
+    assert np.array_equal(E, E2)
+    none = sp == 3
+    assert np.all(E[none] == 0.0) and np.all(g[none] == 0.0)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_gpr_energy_forces_virial_end_to_end(dt):
+    """Energies per structure (Eq. additive-energy-model), forces and virial
+    (Eqs. gpr-force-order, gpr-stress) of a zeta = 2 sparse model on the
+    liquid cube, an empty structure and a triclinic cell: GPU features,
+    soap_gpr_predict, the adjoint and soap_virial against the same chain in
+    the oracle.  Active points: the normalised oracle features of 24 atoms
+    of another liquid cube, weights N(0, 1) (seed 2007)."""
+    b = _virial_batch()
+    other = synthetic.liquid_bulk(seed=77, n_atoms=64)
+    _, _, pa = oracle.features(other)
+    pa = pa.reshape(other.n_atoms, -1)[:24]
+    M = pa / np.linalg.norm(pa, axis=1, keepdims=True)
+    asp = other.species[:24]
+    w = np.random.default_rng(2007).normal(size=24)
+    calc = P.Calculator.from_hypers(b.hypers)
+    nl, pos, spc = gpu_neighbors(calc, b, dt)
+    c, p = calc.features(nl, spc, dt)
+    dev = lambda a, t=dt: torch.tensor(a, dtype=t, device="cuda")
+    E, dEdp = calc.gpr_predict(spc, p, dev(asp, torch.int32), dev(M), dev(w), 2)
+    gc = calc.power_spectrum_backward(c, dEdp.reshape(p.shape))
+    grad, gpair = calc.spherical_expansion_backward(nl, spc, gc)
+    vir = calc.virial(nl, gpair, b.atom_offsets)
+    assert calc.device_status() == 0
+    ref_nl, _, p_ref = oracle.features(b)
+    E_ref, g_ref = oracle.gpr_predict(b.species, p_ref.reshape(b.n_atoms, -1), asp, M, w, 2)
+    grad_ref, gp_ref = oracle.vjp(b.hypers, b.species, ref_nl, g_ref.reshape(p_ref.shape))
+    vir_ref = oracle.virial(b.atom_offsets, ref_nl, gp_ref)
+    offs = b.atom_offsets
+    Es = np.array([E.double().cpu().numpy()[offs[s]:offs[s + 1]].sum() for s in range(3)])
+    Es_ref = np.array([E_ref[offs[s]:offs[s + 1]].sum() for s in range(3)])
+    tol = 1e-7 if dt == torch.float64 else 1e-5
+    ef = rel(grad.double().cpu().numpy(), grad_ref)
+    print(f"[gpr e2e {dt}] rel E={rel(Es, Es_ref):.3e} forces={ef:.3e} "
+          f"virial={rel(vir.double().cpu().numpy(), vir_ref):.3e}")
+    assert rel(Es, Es_ref) <= tol and ef <= tol
+    assert rel(vir.double().cpu().numpy(), vir_ref) <= tol
+    assert Es[1] == 0.0
+
+
 def test_vjp_full_size_against_finite_differences():
     """4096-atom liquid (2 species, nmax 10, lmax 8, rcut 6): the FP32 adjoint
     against central differences (h = 1e-4 A) of the FP64 GPU forward on 32
