@@ -227,6 +227,8 @@ def config_bytes(kind: str, N: int, P: int, S: int, nmax: int, lmax: int, es: in
         return N * (2 * c + p)
     if kind == "expansion_backward":  # per-pair g and grad_r from grad_c and the pairs
         return N * (c + 8 + 3 * es) + P * (pair_in + 4 + 3 * es)
+    if kind == "virial":             # 3x3 per structure from the pairs' g and r
+        return P * 6 * es + N * 8
     raise ValueError(kind)
 
 
@@ -237,7 +239,12 @@ def run_config(args) -> int:
     molecules: 256 molecules of 20-200 atoms, 4 species, FP32 c then p from
       the bfloat16 hi/lo MFMA contraction (one launch for all structures).
     liquid: 4096-atom periodic liquid, 2 species, FP32 c and p, then the
-      adjoint for an upstream gradient drawn N(0, 1) (seed 2004)."""
+      adjoint for an upstream gradient drawn N(0, 1) (seed 2004).
+    gpr: the 1024-atom diamond cell with the bulk-silicon feature set
+      (nmax 10, lmax 12: 715 features), a polynomial sparse model (zeta 4,
+      2000 active points, |N(0, 1)| rows normalised, weights N(0, 1), seed
+      2008): energies, forces and virial (features, model with dE/dp, the
+      adjoint, the virial)."""
     import numpy as np
     import torch
 
@@ -248,7 +255,9 @@ def run_config(args) -> int:
     dev = torch.device("cuda", 0)
     wl = args.workload
     batch = {"clusters": synthetic.clusters_2species, "molecules": synthetic.molecule_batch,
-             "liquid": synthetic.liquid_bulk}[wl]()
+             "liquid": synthetic.liquid_bulk, "gpr": synthetic.diamond_bulk}[wl]()
+    if wl == "gpr":
+        batch.hypers = dict(batch.hypers, nmax=10, lmax=12)
     h = batch.hypers
     calc = P.Calculator.from_hypers(h)
     td = torch.float64 if wl == "clusters" else torch.float32
@@ -256,7 +265,7 @@ def run_config(args) -> int:
     pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
     spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
     ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
-    adjoint = wl == "liquid"
+    adjoint = wl in ("liquid", "gpr")
     nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=td, transpose=adjoint)
     N, Pn = batch.n_atoms, nl.count()
     S, nmax, lmax = h["n_species"], h["nmax"], h["lmax"]
@@ -286,19 +295,40 @@ def run_config(args) -> int:
         kname = "k_centres<double, -1, false, true, false>" if td == torch.float64 else \
             f"k_centres<float, {lmax}, false, true, false>"
         phases.append(("features", ph_features, (kname, "features")))
-        if adjoint:
+        if wl == "gpr":
+            n_active, zeta = 2000, 4
+            g = torch.Generator(device="cpu").manual_seed(2008)
+            F = out[1][0].numel()
+            M = torch.randn((n_active, F), generator=g, dtype=torch.float64).abs()
+            M = (M / M.norm(dim=1, keepdim=True)).to(dev, td)
+            wts = torch.randn(n_active, generator=g, dtype=torch.float64).to(dev, td)
+            asp = torch.zeros(n_active, dtype=torch.int32, device=dev)
+
+            def ph_gpr():
+                state["E"], state["dEdp"] = calc.gpr_predict(spc, out[1], asp, M, wts, zeta)
+
+            phases.append(("gpr_predict", ph_gpr, ("k_gpr_dots<float> + k_gpr_energy + k_gpr_grad", "gpr")))
+            grad_p = None
+        elif adjoint:
             g = torch.Generator(device="cpu").manual_seed(2004)
             grad_p = torch.randn(out[1].shape, generator=g, dtype=torch.float64).to(dev, td)
+        if adjoint:
 
             def ph_ps_backward():
-                state["gc"] = calc.power_spectrum_backward(out[0], grad_p)
+                state["gc"] = calc.power_spectrum_backward(out[0], grad_p if grad_p is not None else
+                                                           state["dEdp"].reshape(out[1].shape))
 
             def ph_exp_backward():
-                state["gpos"] = calc.spherical_expansion_backward(nl, spc, state["gc"])[0]
+                state["gpos"], state["gpair"] = calc.spherical_expansion_backward(nl, spc, state["gc"])
 
             phases += [("spectrum_backward", ph_ps_backward, ("k_ps_backward<float>", "spectrum_backward")),
                        ("expansion_backward", ph_exp_backward,
                         ("k_exp_backward_pairs + k_exp_backward_gather", "expansion_backward"))]
+            if wl == "gpr":
+                def ph_virial():
+                    state["virial"] = calc.virial(nl, state["gpair"], ao)
+
+                phases.append(("virial", ph_virial, ("k_virial_centres + k_virial_structures", "virial")))
     for _ in range(max(3, args.warmup)):
         for _, f, _ in phases:
             f()
@@ -329,14 +359,29 @@ def run_config(args) -> int:
         if info is None:
             continue
         kern, kind = info
+        if kind == "gpr":
+            KK = (S * nmax) * (S * nmax + 1) // 2
+            F = (lmax + 1) * KK
+            fl = 4.0 * N * n_active * F     # the two products, one multiply-add per term each
+            rows[name] = {"kernel": kern, "ms": ph_ms[name], "algorithmic_flops": fl,
+                          "TFLOP_s": fl / (ph_ms[name] * 1e-3) / 1e12,
+                          "algorithmic_bytes": es * (N * F * 2 + n_active * F + N + n_active)}
+            rows[name]["GB_s"] = rows[name]["algorithmic_bytes"] / (ph_ms[name] * 1e-3) / 1e9
+            continue
         b = config_bytes(kind, N, Pn, S, nmax, lmax, es)
         rows[name] = {"kernel": kern, "ms": ph_ms[name], "algorithmic_bytes": b,
                       "GB_s": b / (ph_ms[name] * 1e-3) / 1e9}
     dom = max(rows, key=lambda k: rows[k]["ms"])
     d = rows[dom]
-    roof = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": d["GB_s"] / HBM_PEAK_GBS, "traffic": None, "kernel_ms": d["ms"],
-            "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
+    if "TFLOP_s" in d:
+        # dense FP32 products on the vector units: 157.3 TFLOP/s
+        roof = {"bound": "alu", "kernel": d["kernel"], "achieved": d["TFLOP_s"], "peak": 157.3, "unit": "TFLOP/s",
+                "frac": d["TFLOP_s"] / 157.3, "traffic": None, "kernel_ms": d["ms"],
+                "algorithmic_flops_per_launch": d["algorithmic_flops"]}
+    else:
+        roof = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["GB_s"] / HBM_PEAK_GBS, "traffic": None, "kernel_ms": d["ms"],
+                "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
     if wl == "molecules":
         KK = (S * nmax) * (S * nmax + 1) // 2
         flops = 2.0 * N * KK * (lmax + 1) ** 2                 # packed p: K(K+1)/2 dot products of L2 terms
@@ -358,11 +403,17 @@ def run_config(args) -> int:
                           "lmax 6; neighbours + FP32 expansion + bfloat16 hi/lo MFMA power spectrum, one launch",
              "liquid": "4096-atom periodic liquid (side 43.44 A), 2 species 2867/1229, rcut 6 A, sigma 0.5 A, "
                        "nmax 10, lmax 8; neighbours with reverse-pair index + FP32 expansion and power spectrum + "
-                       "adjoint (vector-Jacobian product for an N(0,1) upstream gradient)"}
+                       "adjoint (vector-Jacobian product for an N(0,1) upstream gradient)",
+             "gpr": "periodic perturbed diamond, 1024 atoms, 1 species, rcut 5 A, sigma 0.5 A, nmax 10, lmax 12 "
+                    "(715 features); sparse polynomial model zeta 4 with 2000 active points; neighbours with "
+                    "reverse-pair index + FP32 expansion and power spectrum + model energies and dE/dp + adjoint "
+                    "(forces) + virial"}
     line = {
         "metric": "atom-centres/s (neighbours + " + {"clusters": "FP64 expansion + power spectrum)",
                                                     "molecules": "expansion + bf16 MFMA power spectrum)",
-                                                    "liquid": "expansion + power spectrum + adjoint)"}[wl],
+                                                    "liquid": "expansion + power spectrum + adjoint)",
+                                                    "gpr": "expansion + power spectrum + sparse model energies, "
+                                                           "forces and virial)"}[wl],
         "value": N / (ms_per_step * 1e-3), "unit": "atom-centres/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if es == 8 else ("bf16" if wl == "molecules" else "f32"),
@@ -387,7 +438,7 @@ def main() -> int:
                     "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["diamond", "clusters", "molecules", "liquid", "compression"],
+    ap.add_argument("--workload", choices=["diamond", "clusters", "molecules", "liquid", "gpr", "compression"],
                     default="diamond",
                     help="diamond: the headline step (default); clusters, molecules, liquid: the FP64, MFMA and "
                          "adjoint parity workloads as timed steps; compression: the learned channel compression "
@@ -408,7 +459,7 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.workload == "compression":
         return run_compression(args)
-    if args.workload in ("clusters", "molecules", "liquid"):
+    if args.workload in ("clusters", "molecules", "liquid", "gpr"):
         return run_config(args)
     torch.cuda.set_device(0)
     if args.calibrate_copy:

@@ -288,11 +288,13 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
  * row-major; species int32 (device).  zeta in [1, 64]; n_features and
  * n_active at most 4,194,240, n_centres below 2^31 (else SOAP_EINVAL).
  * workspace: device scratch of soap_gpr_workspace_size bytes (two
- * [n_centres][n_active] matrices), owned by the caller.
+ * [n_centres][n_active] matrices, and partial gradients when the active
+ * set is split to fill the GPU), owned by the caller.
  * energies [n_centres] and grad_features [n_centres][n_features] are
  * overwritten.  Sums run in a fixed order (bitwise reproducible).
  * precision: SOAP_F64 or SOAP_F32.                                     */
-soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_active, size_t* bytes);
+soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_features,
+                                    int64_t n_active, size_t* bytes);
 soap_status soap_gpr_predict(const soap_exec* exec, soap_precision precision, int64_t n_centres, int64_t n_features,
                              const int32_t* centre_species, const void* features, int64_t n_active,
                              const int32_t* active_species, const void* active_features, const void* weights,

@@ -99,7 +99,7 @@ def lib():
     L.soap_virial.argtypes = [P(soap_exec), st, i32, vp, i64, vp, vp, vp, i64, vp, vp]
     u64, f32, sz = ctypes.c_uint64, ctypes.c_float, ctypes.c_size_t
     L.soap_gpr_workspace_size.restype = st
-    L.soap_gpr_workspace_size.argtypes = [st, i64, i64, P(sz)]
+    L.soap_gpr_workspace_size.argtypes = [st, i64, i64, i64, P(sz)]
     L.soap_gpr_predict.restype = st
     L.soap_gpr_predict.argtypes = [P(soap_exec), st, i64, i64, vp, vp, i64, vp, vp, vp, i32, vp, sz, vp, vp]
     L.soap_compress_n_params.restype = st

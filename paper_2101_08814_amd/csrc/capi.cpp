@@ -643,14 +643,16 @@ soap_status soap_virial(const soap_exec* exec, soap_precision precision, int32_t
                     "virial");
 }
 
-soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_active, size_t* bytes)
+soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_features,
+                                    int64_t n_active, size_t* bytes)
 {
     clear_error();
     REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
     REQUIRE(n_centres >= 0 && n_centres < (int64_t(1) << 31), "n_centres must be in [0, 2^31)");
-    REQUIRE(n_active >= 1 && n_active < (int64_t(1) << 31), "n_active must be in [1, 2^31)");
+    REQUIRE(n_features >= 1 && n_features <= 64 * int64_t(65535), "n_features must be in [1, 4194240]");
+    REQUIRE(n_active >= 1 && n_active <= 64 * int64_t(65535), "n_active must be in [1, 4194240]");
     REQUIRE(bytes != nullptr, "bytes must not be NULL");
-    *bytes = gpr_workspace_bytes(precision == SOAP_F64, n_centres, n_active);
+    *bytes = gpr_workspace_bytes(precision == SOAP_F64, n_centres, n_features, n_active);
     return SOAP_OK;
 }
 
@@ -670,7 +672,7 @@ soap_status soap_gpr_predict(const soap_exec* exec, soap_precision precision, in
     if (n_centres == 0) return SOAP_OK;
     const bool f64 = precision == SOAP_F64;
     const size_t es = elem_size(precision);
-    const size_t need = gpr_workspace_bytes(f64, n_centres, n_active);
+    const size_t need = gpr_workspace_bytes(f64, n_centres, n_features, n_active);
     REQUIRE(workspace_bytes >= need, "workspace_bytes (%zu) is below the %zu bytes needed", workspace_bytes, need);
     CHECK(check_ptr(centre_species, 4, "centre_species"));
     CHECK(check_ptr(features, es, "features"));

@@ -99,7 +99,7 @@ hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipS
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream);
 hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const void* grad_p,
                                           void* grad_coeffs, hipStream_t stream);
-size_t gpr_workspace_bytes(bool f64, int64_t n, int64_t n_active);
+size_t gpr_workspace_bytes(bool f64, int64_t n, int64_t n_feat, int64_t n_active);
 hipError_t launch_gpr_predict(bool f64, int64_t n, int64_t n_feat, const int32_t* species, const void* p,
                               int64_t n_active, const int32_t* active_species, const void* m, const void* w,
                               int zeta, void* workspace, void* energies, void* grad, hipStream_t stream);

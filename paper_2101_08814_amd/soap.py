@@ -314,7 +314,7 @@ class Calculator:
         if w.shape[0] != nA or asp.shape[0] != nA or sp.shape[0] != N:
             raise ValueError("species, active_species and weights must match the feature rows")
         nb = ctypes.c_size_t()
-        check(self._L.soap_gpr_workspace_size(prec, N, nA, ctypes.byref(nb)))
+        check(self._L.soap_gpr_workspace_size(prec, N, F, nA, ctypes.byref(nb)))
         ws = torch.empty(max(nb.value // p.element_size(), 1), dtype=td, device=p.device)
         energies = torch.empty(max(N, 1), dtype=td, device=p.device)
         grad = torch.empty((max(N, 1), F), dtype=td, device=p.device) if want_grad else None
