@@ -287,9 +287,10 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
  * (M_I), weights [n_active], all device memory in the precision's type,
  * row-major; species int32 (device).  zeta in [1, 64]; n_features and
  * n_active at most 4,194,240, n_centres below 2^31 (else SOAP_EINVAL).
- * workspace: device scratch of soap_gpr_workspace_size bytes (two
- * [n_centres][n_active] matrices, and partial gradients when the active
- * set is split to fill the GPU), owned by the caller.
+ * workspace: device scratch of soap_gpr_workspace_size bytes (energy
+ * partials per 64 active points, an [n_centres][n_active] coefficient
+ * matrix, and partial gradients when the active set is split to fill the
+ * GPU), owned by the caller.
  * energies [n_centres] and grad_features [n_centres][n_features] are
  * overwritten.  Sums run in a fixed order (bitwise reproducible).
  * precision: SOAP_F64 or SOAP_F32.                                     */

@@ -13,9 +13,11 @@
 // D[4g + v][r], r = lane & 15, g = lane >> 4); in double every lane
 // accumulates a 4 x 4 set of outputs on the vector units.
 //   k_gpr_dots:   D = P M^T ([N, F] x [F, n_active]); the epilogue forms the
-//                 species-masked energy terms w (M.p)^zeta and the gradient
-//                 coefficients w zeta (M.p)^(zeta-1) into the workspace;
-//   k_gpr_energy: one wave per centre sums its row of energy terms in a
+//                 species-masked energy terms w (M.p)^zeta, sums each row's
+//                 64 of them in LDS in column order into one partial per
+//                 (centre, column tile), and writes the gradient
+//                 coefficients w zeta (M.p)^(zeta-1) to the workspace;
+//   k_gpr_energy: one wave per centre adds its column-tile partials in a
 //                 fixed order;
 //   k_gpr_grad:   dE/dp = G M ([N, n_active] x [n_active, F]); when the
 //                 output has too few tiles to fill the chip, the n_active
@@ -165,8 +167,9 @@ __global__ void __launch_bounds__(256) k_gpr_dots(int64_t n, int64_t n_feat, con
                                                   const T* __restrict__ p, int64_t n_active,
                                                   const int32_t* __restrict__ active_species,
                                                   const T* __restrict__ m, const T* __restrict__ w, int zeta,
-                                                  T* __restrict__ e_terms, T* __restrict__ g_coef)
+                                                  T* __restrict__ e_part, T* __restrict__ g_coef)
 {
+    __shared__ T es[kTile][kTile + 1];   // energy terms of the tile, [row][column]
     const int64_t row0 = int64_t(blockIdx.x) * kTile, col0 = int64_t(blockIdx.y) * kTile;
     T acc[4][4];
     tile_product<T, true>(p, n_feat, n, m, n_feat, n_active, 0, n_feat, row0, col0, acc);
@@ -174,36 +177,39 @@ __global__ void __launch_bounds__(256) k_gpr_dots(int64_t n, int64_t n_feat, con
     for (int u = 0; u < 4; ++u) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t i = row0 + tile_row<T>(u, v), I = col0 + tile_col<T>(u, v);
-            if (i >= n || I >= n_active) continue;
-            const int si = species[i];
-            const bool same = active_species[I] == si;
-            const T d = acc[u][v], wi = w[I];
-            const T km1 = ipow(d, zeta - 1);
-            e_terms[i * n_active + I] = same ? wi * (km1 * d) : T(0);
-            if (g_coef) g_coef[i * n_active + I] = same ? wi * T(zeta) * km1 : T(0);
+            const int tr = tile_row<T>(u, v), tc = tile_col<T>(u, v);
+            const int64_t i = row0 + tr, I = col0 + tc;
+            T e = T(0);
+            if (i < n && I < n_active) {
+                const bool same = active_species[I] == species[i];
+                const T d = acc[u][v], wi = w[I];
+                const T km1 = ipow(d, zeta - 1);
+                e = same ? wi * (km1 * d) : T(0);
+                if (g_coef) g_coef[i * n_active + I] = same ? wi * T(zeta) * km1 : T(0);
+            }
+            es[tr][tc] = e;
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kTile && row0 + threadIdx.x < n) {
+        T s = T(0);
+        for (int c = 0; c < kTile; ++c) s += es[threadIdx.x][c];
+        e_part[int64_t(blockIdx.y) * n + row0 + threadIdx.x] = s;
     }
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_sum(T x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_gpr_energy(int64_t n, int64_t n_active, const T* __restrict__ e_terms,
+__global__ void __launch_bounds__(256) k_gpr_energy(int64_t n, int col_tiles, const T* __restrict__ e_part,
                                                     T* __restrict__ energies)
 {
     const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
+    // lane t holds tiles t, t + 64, ... in order, then a fixed butterfly
     T s = T(0);
-    for (int64_t I = lane; I < n_active; I += 64) s += e_terms[i * n_active + I];
-    s = wave_sum(s);
+    for (int t = lane; t < col_tiles; t += 64) s += e_part[int64_t(t) * n + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) energies[i] = s;
 }
 
@@ -263,15 +269,18 @@ hipError_t gpr_t(int64_t n, int64_t n_feat, const int32_t* species, const void* 
                  const int32_t* active_species, const void* m, const void* w, int zeta, void* workspace,
                  void* energies, void* grad, hipStream_t stream)
 {
-    T* e_terms = static_cast<T*>(workspace);
-    T* g_coef = grad ? e_terms + n * n_active : nullptr;
+    // workspace: energy partials [col_tiles][n], gradient coefficients
+    // [n][n_active], partial gradients [slices][n][n_feat]
+    const int col_tiles = int((n_active + kTile - 1) / kTile);
+    T* e_part = static_cast<T*>(workspace);
+    T* g_coef = grad ? e_part + int64_t(col_tiles) * n : nullptr;
     // row tiles along x (up to 2^31 - 1 work-groups), column tiles along y
-    const dim3 tiles_a(unsigned((n + kTile - 1) / kTile), unsigned((n_active + kTile - 1) / kTile));
+    const dim3 tiles_a(unsigned((n + kTile - 1) / kTile), unsigned(col_tiles));
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gpr_dots<T>), tiles_a, dim3(256), 0, stream, n, n_feat, species,
                        static_cast<const T*>(p), n_active, active_species, static_cast<const T*>(m),
-                       static_cast<const T*>(w), zeta, e_terms, g_coef);
+                       static_cast<const T*>(w), zeta, e_part, g_coef);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gpr_energy<T>), dim3(unsigned((n + 3) / 4)), dim3(256), 0, stream, n,
-                       n_active, static_cast<const T*>(e_terms), static_cast<T*>(energies));
+                       col_tiles, static_cast<const T*>(e_part), static_cast<T*>(energies));
     if (grad) {
         const int z = grad_slices(n, n_feat, n_active);
         const int64_t slice = slice_depth(n_active, z);
@@ -296,7 +305,8 @@ size_t gpr_workspace_bytes(bool f64, int64_t n, int64_t n_feat, int64_t n_active
     const int z = grad_slices(n, n_feat, n_active);
     const int64_t zs = (n_active + slice_depth(n_active, z) - 1) / slice_depth(n_active, z);
     const size_t part = zs > 1 ? size_t(zs) * size_t(n) * size_t(n_feat) : 0;
-    return (size_t(2) * size_t(n) * size_t(n_active) + part) * (f64 ? 8 : 4);
+    const size_t col_tiles = size_t((n_active + kTile - 1) / kTile);
+    return (col_tiles * size_t(n) + size_t(n) * size_t(n_active) + part) * (f64 ? 8 : 4);
 }
 
 hipError_t launch_gpr_predict(bool f64, int64_t n, int64_t n_feat, const int32_t* species, const void* p,
