@@ -214,6 +214,21 @@ def power_spectrum(hypers, coeffs):
     return p
 
 
+def power_spectrum_selected(hypers, coeffs, selected):
+    """Sec. 4.H: only the chosen invariants q = (k1, k2, l), each the sum
+    over m of c[k1, lm] c[k2, lm] (channels k = a n, R4's normalisation),
+    for every centre.  coeffs [N, S, nmax, L2]; selected [n_sel, 3];
+    returns [N, n_sel]."""
+    S, nmax = int(hypers["n_species"]), int(hypers["nmax"])
+    c = np.asarray(coeffs, dtype=np.float64)
+    c = c.reshape(c.shape[0], S * nmax, -1)
+    out = np.zeros((c.shape[0], len(selected)))
+    for q, (k1, k2, l) in enumerate(np.asarray(selected, dtype=np.int64)):
+        m = slice(l * l, l * l + 2 * l + 1)
+        out[:, q] = (c[:, k1, m] * c[:, k2, m]).sum(axis=1)
+    return out
+
+
 def gradients(hypers, species, nl, centres=None):
     """Forward-mode gradient rows for the listed centres.  Returns
     (dc [rows,3,nmax,L2], dc_self [n,3,S,nmax,L2], dp [rows,3,lmax+1,KK],

@@ -686,3 +686,39 @@ def test_gpr_forces_and_virial_match_finite_differences():
                 e.append(energy(synthetic.Batch(b.positions @ D.T, b.species, b.atom_offsets, cells, b.pbc, h)))
             fd[a_, b_] = (e[0] - e[1]) / (2 * eps)
     assert np.abs(vir - fd).max() <= 1e-6 * max(1.0, np.abs(fd).max())
+
+
+def test_selected_invariants_match_full_spectrum():
+    """Sec. 4.H: the selected-invariant oracle, given every packed column as
+    its triple, reproduces the full power spectrum written independently
+    (C oracle); a transposed triple (k2, k1, l) gives the same value."""
+    from paper_2101_08814_amd.selection import packed_to_triples
+    b = synthetic.clusters_2species().subset([1])
+    h = b.hypers
+    nl, c, p = oracle.features(b)
+    K, lmax = h["n_species"] * h["nmax"], h["lmax"]
+    tri = packed_to_triples(K, lmax, np.arange(p[0].size))
+    ps = oracle.power_spectrum_selected(h, c, tri)
+    assert np.allclose(ps, p.reshape(p.shape[0], -1), rtol=1e-13, atol=1e-15)
+    sw = tri[:, [1, 0, 2]]
+    assert np.array_equal(oracle.power_spectrum_selected(h, c, sw), ps)
+
+
+def test_fps_columns_brute_force():
+    """Farthest-point sampling on a tiny matrix: each pick maximises the
+    minimum distance to the columns already picked (checked by brute force
+    over all columns), the first pick is the largest-norm column."""
+    from paper_2101_08814_amd.selection import fps_columns
+    X = np.random.default_rng(5).normal(size=(7, 12))
+    picked = fps_columns(X, 6)
+    assert picked[0] == np.argmax((X ** 2).sum(0))
+    for t in range(1, 6):
+        best, arg = -1.0, None
+        for j in range(12):
+            if j in picked[:t]:
+                continue
+            dmin = min(np.sum((X[:, j] - X[:, i]) ** 2) for i in picked[:t])
+            if dmin > best + 1e-12:
+                best, arg = dmin, j
+        assert picked[t] == arg
+    assert len(set(picked.tolist())) == 6
