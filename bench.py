@@ -208,6 +208,80 @@ def run_compression(args) -> int:
     return 0
 
 
+def run_selected(args) -> int:
+    """Selected invariants (Sec. 4.H) on the 8-species workload: 512
+    periodic cells x 256 atoms, nmax 12, lmax 8 (96 channels, 41,904 packed
+    features).  From FP32 coefficients already in HBM, times the full FP32
+    spectrum against 2000 seeded packed columns (seed 2010, uniform over the
+    packed features) computed alone."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    import paper_2101_08814_amd as P
+    from paper_2101_08814_amd.selection import packed_to_triples
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    batch = synthetic.multi_species_cells()
+    h = batch.hypers
+    calc = P.Calculator.from_hypers(h)
+    pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
+    spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
+    ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
+    nl = calc.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float32, transpose=False)
+    N = batch.n_atoms
+    K, lmax = calc.K, calc.lmax
+    KK = K * (K + 1) // 2
+    n_sel = 2000
+    cols = np.sort(np.random.default_rng(2010).choice((lmax + 1) * KK, size=n_sel, replace=False))
+    tri = torch.tensor(packed_to_triples(K, lmax, cols), device=dev)
+    c = calc.spherical_expansion(nl, spc, torch.float32)
+    phases = [("full_spectrum", lambda: calc.power_spectrum(c)),
+              ("selected", lambda: calc.power_spectrum_selected(c, tri))]
+    for _ in range(max(2, args.warmup)):
+        for _, f in phases:
+            f()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 20))
+    ms = {}
+    for name, f in phases:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / steps
+    if calc.device_status() != 0:
+        log(f"device status {calc.device_status()}")
+        return 4
+    L2 = (lmax + 1) ** 2
+    sel_bytes = N * (K * L2 + n_sel) * 4 + n_sel * 12
+    full_bytes = N * (K * L2 + (lmax + 1) * KK) * 4
+    gbs = sel_bytes / (ms["selected"] * 1e-3) / 1e9
+    log(f"[bench:selected] N={N} full={ms['full_spectrum']:.3f} ms selected({n_sel})={ms['selected']:.3f} ms "
+        f"({gbs:.0f} GB/s)")
+    line = {
+        "metric": "atom-centres/s (2000 selected invariants from c)", "value": N / (ms["selected"] * 1e-3),
+        "unit": "atom-centres/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": ms["selected"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512 periodic cells x 256 atoms (side 16.22 A), 8 species x 32, rcut 5 A, sigma 0.5 A, "
+                               "nmax 12, lmax 8 (96 channels, 41,904 packed features); 2000 seeded packed columns "
+                               "from FP32 c in HBM",
+                   "centres": N, "n_selected": n_sel,
+                   "full_spectrum_ms": ms["full_spectrum"], "full_spectrum_GB_s":
+                       full_bytes / (ms["full_spectrum"] * 1e-3) / 1e9,
+                   "speedup_vs_full": ms["full_spectrum"] / ms["selected"]},
+        "roofline": {"bound": "hbm", "kernel": "k_ps_selected<float>", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel_ms": ms["selected"],
+                     "algorithmic_bytes_per_launch": sel_bytes},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def config_bytes(kind: str, N: int, P: int, S: int, nmax: int, lmax: int, es: int):
     """Algorithmic bytes of one launch of a phase of the parity workloads
     (inputs read once, outputs written once; the L2-resident spline table
@@ -438,7 +512,8 @@ def main() -> int:
                     "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["diamond", "clusters", "molecules", "liquid", "gpr", "compression"],
+    ap.add_argument("--workload", choices=["diamond", "clusters", "molecules", "liquid", "gpr", "selected",
+                                           "compression"],
                     default="diamond",
                     help="diamond: the headline step (default); clusters, molecules, liquid: the FP64, MFMA and "
                          "adjoint parity workloads as timed steps; compression: the learned channel compression "
@@ -457,6 +532,8 @@ def main() -> int:
     import paper_2101_08814_amd as P
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.workload == "selected":
+        return run_selected(args)
     if args.workload == "compression":
         return run_compression(args)
     if args.workload in ("clusters", "molecules", "liquid", "gpr"):

@@ -270,6 +270,20 @@ soap_status soap_spherical_expansion_backward(const soap_calculator* calc, const
                                               const void* grad_coeffs, void* grad_pair_vec,
                                               void* grad_positions);
 
+/* Selected invariants (Sec. 4.H): for each centre i and each triple
+ * q = selected[q] = (k1, k2, l) (int32, device, [n_selected][3]),
+ *   p_selected[i][q] = sum over m < 2l+1 of c[i][k1][l^2 + m] c[i][k2][l^2 + m],
+ * the entry (l, k1, k2) of the full power spectrum (same normalisation as
+ * soap_power_spectrum; k1 > k2 is allowed and gives the (k2, k1) value).
+ * coeffs [n_atoms][n_channels][(lmax+1)^2] with n_channels = S * nmax
+ * (the layout soap_spherical_expansion writes); one centre's coefficients
+ * must fit 160 KB.  p_selected [n_atoms][n_selected] is overwritten.  A
+ * triple out of range gives 0 and SOAP_EINVAL in the device status word.
+ * precision: SOAP_F64 or SOAP_F32.                                     */
+soap_status soap_power_spectrum_selected(const soap_exec* exec, soap_precision precision, int64_t n_atoms,
+                                         int32_t n_channels, int32_t lmax, const void* coeffs, int64_t n_selected,
+                                         const int32_t* selected, void* p_selected);
+
 /* Sparse kernel model (Sec. 5.B, Eq. sparse-gp with the polynomial kernel):
  * for each centre i,
  *   energies[i] = sum over active points I with active_species[I] ==

@@ -643,6 +643,30 @@ soap_status soap_virial(const soap_exec* exec, soap_precision precision, int32_t
                     "virial");
 }
 
+soap_status soap_power_spectrum_selected(const soap_exec* exec, soap_precision precision, int64_t n_atoms,
+                                         int32_t n_channels, int32_t lmax, const void* coeffs, int64_t n_selected,
+                                         const int32_t* selected, void* p_selected)
+{
+    clear_error();
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(n_channels >= 1, "n_channels must be >= 1");
+    REQUIRE(lmax >= 0 && lmax <= 12, "lmax must be in [0, 12]");
+    REQUIRE(n_selected >= 0 && n_selected < (int64_t(1) << 31), "n_selected must be in [0, 2^31)");
+    const bool f64 = precision == SOAP_F64;
+    REQUIRE(power_spectrum_selected_lds(f64, n_channels, lmax) <= 160 * 1024,
+            "one centre's coefficients (%zu bytes) must fit 160 KB of LDS",
+            power_spectrum_selected_lds(f64, n_channels, lmax));
+    if (n_atoms == 0 || n_selected == 0) return SOAP_OK;
+    const size_t es = elem_size(precision);
+    CHECK(check_ptr(coeffs, es, "coeffs"));
+    CHECK(check_ptr(selected, 4, "selected"));
+    CHECK(check_ptr(p_selected, es, "p_selected"));
+    return launched(launch_power_spectrum_selected(f64, n_atoms, n_channels, lmax, coeffs, n_selected, selected,
+                                                   p_selected, status_of(exec), stream_of(exec)),
+                    "power_spectrum_selected");
+}
+
 soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_features,
                                     int64_t n_active, size_t* bytes)
 {

@@ -294,6 +294,23 @@ class Calculator:
                                   _ptr(grad_pair_vec), nl.capacity, _ptr(part), _ptr(out)))
         return out[:S]
 
+    def power_spectrum_selected(self, coeffs: torch.Tensor, selected) -> torch.Tensor:
+        """soap_power_spectrum_selected: [N, n_sel] invariants for the
+        (k1, k2, l) triples ``selected`` ([n_sel, 3]; see
+        ``selection.packed_to_triples``) from coefficients [N, S, nmax, L2]."""
+        td = coeffs.dtype
+        prec = _precision(td)
+        N = coeffs.shape[0]
+        c = coeffs.contiguous()
+        sel = torch.as_tensor(np.asarray(selected, dtype=np.int32) if not isinstance(selected, torch.Tensor)
+                              else selected, dtype=torch.int32).to(c.device).contiguous()
+        n_sel = sel.shape[0]
+        out = torch.empty((max(N, 1), max(n_sel, 1)), dtype=td, device=c.device)
+        e = self._exec()
+        check(self._L.soap_power_spectrum_selected(ctypes.byref(e), prec, N, self.K, self.lmax,
+                                                   _ptr(c), n_sel, _ptr(sel), _ptr(out)))
+        return out[:N, :n_sel]
+
     def gpr_predict(self, species: torch.Tensor, features: torch.Tensor, active_species: torch.Tensor,
                     active_features: torch.Tensor, weights: torch.Tensor, zeta: int, want_grad: bool = True):
         """soap_gpr_predict: per-centre energies [N] of the sparse kernel model

@@ -492,6 +492,39 @@ def test_gpr_energy_forces_virial_end_to_end(dt):
     assert Es[1] == 0.0
 
 
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_selected_invariants_match_oracle(dt):
+    """Selected invariants (Sec. 4.H) on two 8-species cells (K = 96,
+    lmax 8): 700 seeded triples (seed 2009, both k1 <= k2 and k1 > k2, every
+    l) plus 64 columns picked by farthest-point sampling over the oracle's
+    spectra, from GPU coefficients against the oracle's selection of its own
+    coefficients; a triple out of range gives 0 and SOAP_EINVAL."""
+    from paper_2101_08814_amd.selection import fps_columns, packed_to_triples
+    b = synthetic.multi_species_cells(n_cells=2)
+    h = b.hypers
+    K, lmax = h["n_species"] * h["nmax"], h["lmax"]
+    calc = P.Calculator.from_hypers(h)
+    nl, pos, spc = gpu_neighbors(calc, b, dt)
+    c = calc.spherical_expansion(nl, spc, dt)
+    ref_nl, c_ref, p_ref = oracle.features(b)
+    rng = np.random.default_rng(2009)
+    tri = np.stack([rng.integers(0, K, 700), rng.integers(0, K, 700), rng.integers(0, lmax + 1, 700)], 1)
+    cols = fps_columns(p_ref.reshape(p_ref.shape[0], -1)[:64], 64)
+    tri = np.concatenate([tri, packed_to_triples(K, lmax, cols)]).astype(np.int32)
+    got = calc.power_spectrum_selected(c, tri)
+    assert calc.device_status() == 0
+    ref = oracle.power_spectrum_selected(h, c_ref, tri)
+    e = rel(got.double().cpu().numpy(), ref)
+    print(f"[selected {dt}] rel={e:.3e} worst centre={worst_centre(got.double().cpu().numpy(), ref):.3e}")
+    assert e <= (1e-7 if dt == torch.float64 else 1e-6)
+    bad = tri[:3].copy()
+    bad[1] = (0, K, 0)
+    out = calc.power_spectrum_selected(c, bad)
+    assert calc.device_status() == P._lib.SOAP_EINVAL
+    assert torch.all(out[:, 1] == 0)
+    calc.reset_status()
+
+
 def test_vjp_full_size_against_finite_differences():
     """4096-atom liquid (2 species, nmax 10, lmax 8, rcut 6): the FP32 adjoint
     against central differences (h = 1e-4 A) of the FP64 GPU forward on 32
