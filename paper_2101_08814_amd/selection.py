@@ -1,7 +1,7 @@
 """Feature selection for computing only some invariants (Sec. 4.H).
 
 Host-side, offline: pick columns of a [samples, features] matrix of power
-spectra by farthest-point sampling, and translate packed feature columns
+spectra by farthest-point sampling or by iterative CUR, and translate packed feature columns
 into the (k1, k2, l) triples that ``Calculator.power_spectrum_selected``
 takes.  Packed layout: column l * K(K+1)/2 + kk, with kk running over
 k1 <= k2 row by row (k = species * nmax + n).
@@ -44,3 +44,27 @@ def packed_to_triples(n_channels: int, lmax: int, columns) -> np.ndarray:
         raise ValueError("feature column out of range")
     l, kk = np.divmod(cols, KK)
     return np.stack([k1_of[kk], k2_of[kk], l], axis=1).astype(np.int32)
+
+
+def cur_columns(X: np.ndarray, n_select: int, k: int = 1) -> np.ndarray:
+    """Iterative CUR column selection: take the column with the largest
+    leverage score (squared norm of its entries in the top-k right singular
+    vectors of the current matrix), project every column onto the
+    orthogonal complement of the chosen one, and repeat on the residual
+    (ties: lowest index)."""
+    R = np.array(X, dtype=np.float64, copy=True)
+    n_feat = R.shape[1]
+    if not 0 < n_select <= n_feat:
+        raise ValueError(f"n_select must be in [1, {n_feat}]")
+    picked = []
+    for _ in range(n_select):
+        _, _, vt = np.linalg.svd(R, full_matrices=False)
+        score = (vt[:k] ** 2).sum(axis=0)
+        score[picked] = -1.0
+        j = int(np.argmax(score))
+        picked.append(j)
+        v = R[:, j]
+        nv = float(v @ v)
+        if nv > 0.0:
+            R -= np.outer(v, (v @ R) / nv)
+    return np.asarray(picked, dtype=np.int64)

@@ -722,3 +722,20 @@ def test_fps_columns_brute_force():
                 best, arg = dmin, j
         assert picked[t] == arg
     assert len(set(picked.tolist())) == 6
+
+
+def test_cur_columns_special_cases():
+    """CUR column selection: on a matrix whose columns are a dominant
+    direction, a scaled copy of it, and two weaker independent directions,
+    the dominant column comes first, its copy (zero residual after the
+    projection) is never taken before the independent ones, and after as
+    many picks as the rank the residual is zero."""
+    from paper_2101_08814_amd.selection import cur_columns
+    rng = np.random.default_rng(6)
+    a, b, c = rng.normal(size=(3, 9))
+    X = np.stack([0.5 * b, 10.0 * a, 2.0 * c, 5.0 * a], axis=1)
+    picked = cur_columns(X, 3)
+    assert picked[0] == 1
+    assert set(picked[1:].tolist()) == {0, 2}
+    Q, _ = np.linalg.qr(X[:, picked])
+    assert np.abs(X - Q @ (Q.T @ X)).max() <= 1e-12 * np.abs(X).max()
