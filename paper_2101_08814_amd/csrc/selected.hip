@@ -3,7 +3,8 @@
 //
 // One 256-lane work-group per centre stages the centre's K x (lmax+1)^2
 // coefficients in LDS with coalesced loads, then lanes take the selected
-// invariants in turn, so a centre's outputs leave as one contiguous row.
+// invariants in turn (eight per lane per round, their triples loaded
+// together), so a centre's outputs leave as one contiguous row.
 // The work per centre is sum over q of (2 l_q + 1) products instead of the
 // full spectrum's (lmax+1)^2 K(K+1)/2.
 #include "soap_internal.hpp"
@@ -12,10 +13,41 @@ namespace soap {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kQBatch = 8;       // invariants per lane whose triples are loaded together
+constexpr int kStageBatch = 8;   // coefficient loads per lane in flight
 
 __device__ __forceinline__ void report(int32_t* st, int v)
 {
     if (st) *st = v;
+}
+
+// copy n elements to LDS with kStageBatch 16-byte loads per lane in flight
+// (scalar loads when the row is not a whole number of aligned vectors)
+template <typename T>
+__device__ __forceinline__ void stage(const T* __restrict__ src, T* dst, int n)
+{
+    typedef __attribute__((ext_vector_type(16 / sizeof(T)))) T V;
+    constexpr int VW = 16 / sizeof(T);
+    if (n % VW == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const V* s = reinterpret_cast<const V*>(src);
+        V* d = reinterpret_cast<V*>(dst);
+        const int nv = n / VW;
+        for (int e0 = threadIdx.x; e0 < nv; e0 += kStageBatch * kThreads) {
+            V v[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int e = e0 + u * kThreads;
+                v[u] = s[e < nv ? e : nv - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int e = e0 + u * kThreads;
+                if (e < nv) d[e] = v[u];
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < n; e += kThreads) dst[e] = src[e];
+    }
 }
 
 template <typename T>
@@ -29,21 +61,44 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected(int K, int lmax, const
     const int KL2 = K * L2;
     const int64_t i = blockIdx.x;
     const T* ci = c + i * KL2;
-    for (int e = threadIdx.x; e < KL2; e += kThreads) cs[e] = ci[e];
-    __syncthreads();
     T* oi = out + i * n_sel;
-    for (int64_t q = threadIdx.x; q < n_sel; q += kThreads) {
-        const int k1 = sel[3 * q], k2 = sel[3 * q + 1], l = sel[3 * q + 2];
-        if (k1 < 0 || k1 >= K || k2 < 0 || k2 >= K || l < 0 || l > lmax) {
-            report(status, SOAP_EINVAL);
-            oi[q] = T(0);
-            continue;
+    stage(ci, cs, KL2);
+    // the triples of kQBatch invariants per lane are loaded together (index
+    // clamped, so no load waits behind a branch); the first batch is in
+    // flight across the barrier
+    int t1[kQBatch], t2[kQBatch], tl[kQBatch];
+    auto load = [&](int64_t qb) {
+#pragma unroll
+        for (int u = 0; u < kQBatch; ++u) {
+            const int64_t q = qb + int64_t(u) * kThreads;
+            const int64_t qq = q < n_sel ? q : n_sel - 1;
+            t1[u] = sel[3 * qq];
+            t2[u] = sel[3 * qq + 1];
+            tl[u] = sel[3 * qq + 2];
         }
-        const T* a = cs + k1 * L2 + l * l;
-        const T* b = cs + k2 * L2 + l * l;
-        T s = T(0);
-        for (int m = 0; m <= 2 * l; ++m) s += a[m] * b[m];
-        oi[q] = s;
+    };
+    int64_t qb = threadIdx.x;
+    if (qb < n_sel) load(qb);
+    __syncthreads();
+    for (; qb < n_sel; qb += int64_t(kQBatch) * kThreads) {
+#pragma unroll
+        for (int u = 0; u < kQBatch; ++u) {
+            const int64_t q = qb + int64_t(u) * kThreads;
+            if (q >= n_sel) break;
+            const int k1 = t1[u], k2 = t2[u], l = tl[u];
+            if (k1 < 0 || k1 >= K || k2 < 0 || k2 >= K || l < 0 || l > lmax) {
+                report(status, SOAP_EINVAL);
+                oi[q] = T(0);
+                continue;
+            }
+            const T* a = cs + k1 * L2 + l * l;
+            const T* b = cs + k2 * L2 + l * l;
+            T sum = T(0);
+            for (int m = 0; m <= 2 * l; ++m) sum += a[m] * b[m];
+            oi[q] = sum;
+        }
+        const int64_t next = qb + int64_t(kQBatch) * kThreads;
+        if (next < n_sel) load(next);
     }
 }
 
