@@ -229,6 +229,23 @@ def power_spectrum_selected(hypers, coeffs, selected):
     return out
 
 
+def power_spectrum_selected_vjp(hypers, coeffs, selected, grad):
+    """Adjoint of power_spectrum_selected: dL/dc for L = sum_i sum_q
+    grad[i, q] p_sel[i, q]; each invariant q = (k1, k2, l) gives
+    grad[q] c[k2, lm] to (k1, lm) and grad[q] c[k1, lm] to (k2, lm)."""
+    S, nmax = int(hypers["n_species"]), int(hypers["nmax"])
+    c = np.asarray(coeffs, dtype=np.float64)
+    shape = c.shape
+    c = c.reshape(shape[0], S * nmax, -1)
+    g = np.asarray(grad, dtype=np.float64)
+    out = np.zeros_like(c)
+    for q, (k1, k2, l) in enumerate(np.asarray(selected, dtype=np.int64)):
+        m = slice(l * l, l * l + 2 * l + 1)
+        out[:, k1, m] += g[:, q:q + 1] * c[:, k2, m]
+        out[:, k2, m] += g[:, q:q + 1] * c[:, k1, m]
+    return out.reshape(shape)
+
+
 def gradients(hypers, species, nl, centres=None):
     """Forward-mode gradient rows for the listed centres.  Returns
     (dc [rows,3,nmax,L2], dc_self [n,3,S,nmax,L2], dp [rows,3,lmax+1,KK],

@@ -739,3 +739,25 @@ def test_cur_columns_special_cases():
     assert set(picked[1:].tolist()) == {0, 2}
     Q, _ = np.linalg.qr(X[:, picked])
     assert np.abs(X - Q @ (Q.T @ X)).max() <= 1e-12 * np.abs(X).max()
+
+
+def test_selected_invariants_vjp_matches_finite_differences():
+    """The selected invariants are quadratic in c, so central differences of
+    L = <G, p_sel(c)> are exact up to rounding: the oracle's adjoint must
+    match them for every coefficient of a random two-centre input, with
+    repeated and k1 = k2 triples included."""
+    h = dict(n_species=2, nmax=3, lmax=2)
+    rng = np.random.default_rng(7)
+    c = rng.normal(size=(2, 2, 3, 9))
+    tri = np.array([[0, 0, 0], [1, 4, 1], [4, 1, 1], [5, 5, 2], [2, 3, 2], [2, 3, 2], [0, 5, 0]])
+    G = rng.normal(size=(2, len(tri)))
+    gc = oracle.power_spectrum_selected_vjp(h, c, tri, G)
+    eps = 1e-3
+    fd = np.zeros_like(c)
+    for idx in np.ndindex(c.shape):
+        cp, cm = c.copy(), c.copy()
+        cp[idx] += eps
+        cm[idx] -= eps
+        fd[idx] = (np.sum(G * oracle.power_spectrum_selected(h, cp, tri)) -
+                   np.sum(G * oracle.power_spectrum_selected(h, cm, tri))) / (2 * eps)
+    assert np.abs(gc - fd).max() <= 1e-10 * np.abs(fd).max()
