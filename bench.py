@@ -213,7 +213,8 @@ def run_selected(args) -> int:
     periodic cells x 256 atoms, nmax 12, lmax 8 (96 channels, 41,904 packed
     features).  From FP32 coefficients already in HBM, times the full FP32
     spectrum against 2000 seeded packed columns (seed 2010, uniform over the
-    packed features) computed alone."""
+    packed features) computed alone, and the adjoint of those columns for an
+    N(0, 1) upstream gradient (its host plan built inside the timed call)."""
     import numpy as np
     import torch
 
@@ -237,8 +238,11 @@ def run_selected(args) -> int:
     cols = np.sort(np.random.default_rng(2010).choice((lmax + 1) * KK, size=n_sel, replace=False))
     tri = torch.tensor(packed_to_triples(K, lmax, cols), device=dev)
     c = calc.spherical_expansion(nl, spc, torch.float32)
+    g_sel = torch.randn((N, n_sel), generator=torch.Generator(device="cpu").manual_seed(2010)).to(dev)
+    tri_host = tri.cpu().numpy()
     phases = [("full_spectrum", lambda: calc.power_spectrum(c)),
-              ("selected", lambda: calc.power_spectrum_selected(c, tri))]
+              ("selected", lambda: calc.power_spectrum_selected(c, tri)),
+              ("selected_backward", lambda: calc.power_spectrum_selected_backward(c, tri_host, g_sel))]
     for _ in range(max(2, args.warmup)):
         for _, f in phases:
             f()
@@ -261,7 +265,7 @@ def run_selected(args) -> int:
     full_bytes = N * (K * L2 + (lmax + 1) * KK) * 4
     gbs = sel_bytes / (ms["selected"] * 1e-3) / 1e9
     log(f"[bench:selected] N={N} full={ms['full_spectrum']:.3f} ms selected({n_sel})={ms['selected']:.3f} ms "
-        f"({gbs:.0f} GB/s)")
+        f"({gbs:.0f} GB/s) selected backward={ms['selected_backward']:.3f} ms")
     line = {
         "metric": "atom-centres/s (2000 selected invariants from c)", "value": N / (ms["selected"] * 1e-3),
         "unit": "atom-centres/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -273,7 +277,9 @@ def run_selected(args) -> int:
                    "centres": N, "n_selected": n_sel,
                    "full_spectrum_ms": ms["full_spectrum"], "full_spectrum_GB_s":
                        full_bytes / (ms["full_spectrum"] * 1e-3) / 1e9,
-                   "speedup_vs_full": ms["full_spectrum"] / ms["selected"]},
+                   "speedup_vs_full": ms["full_spectrum"] / ms["selected"],
+                   "selected_backward_ms": ms["selected_backward"],
+                   "selected_backward_GB_s": N * (2 * K * L2 + n_sel) * 4 / (ms["selected_backward"] * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "kernel": "k_ps_selected<float>", "achieved": gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel_ms": ms["selected"],
                      "algorithmic_bytes_per_launch": sel_bytes},

@@ -284,6 +284,28 @@ soap_status soap_power_spectrum_selected(const soap_exec* exec, soap_precision p
                                          int32_t n_channels, int32_t lmax, const void* coeffs, int64_t n_selected,
                                          const int32_t* selected, void* p_selected);
 
+/* Adjoint of soap_power_spectrum_selected (the chain rule of App. B
+ * through the selected invariants):
+ *   grad_coeffs[i][k][lm] = sum over selected q = (k1, k2, l) with l(lm) = l of
+ *       grad_p_selected[i][q] (c[i][k2][lm] [k == k1] + c[i][k1][lm] [k == k2]).
+ * The sums follow a plan built once per selection on the host by
+ * soap_power_spectrum_selected_plan from the host copy of `selected`
+ * (checked there: an out-of-range triple is SOAP_EINVAL):
+ * row_offsets [n_channels * (lmax+1) + 1] and entries [2 * n_selected][2]
+ * (q, partner channel), caller-owned host memory; the caller copies both to
+ * the device for the backward call.  Per centre the coefficients and the
+ * gradient row must fit 160 KB.  grad_coeffs [n_atoms][n_channels][L2] is
+ * overwritten; sums run in plan order (bitwise reproducible).  A plan that
+ * does not fit n_selected gives 0 and SOAP_EINVAL in the device status.
+ * precision: SOAP_F64 or SOAP_F32.                                     */
+soap_status soap_power_spectrum_selected_plan(int32_t n_channels, int32_t lmax, int64_t n_selected,
+                                              const int32_t* selected, int32_t* row_offsets, int32_t* entries);
+soap_status soap_power_spectrum_selected_backward(const soap_exec* exec, soap_precision precision, int64_t n_atoms,
+                                                  int32_t n_channels, int32_t lmax, const void* coeffs,
+                                                  int64_t n_selected, const void* grad_p_selected,
+                                                  const int32_t* row_offsets, const int32_t* entries,
+                                                  void* grad_coeffs);
+
 /* Sparse kernel model (Sec. 5.B, Eq. sparse-gp with the polynomial kernel):
  * for each centre i,
  *   energies[i] = sum over active points I with active_species[I] ==

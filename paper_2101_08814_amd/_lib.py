@@ -24,7 +24,8 @@ EXPORTS = [
     "soap_calculator_info", "soap_calculator_upload", "soap_radial_integral_host",
     "soap_neighbors_workspace_size", "soap_compute_neighbors", "soap_spherical_expansion",
     "soap_power_spectrum", "soap_features", "soap_gradient_rows", "soap_power_spectrum_backward",
-    "soap_spherical_expansion_backward", "soap_virial", "soap_power_spectrum_selected", "soap_gpr_workspace_size", "soap_gpr_predict",
+    "soap_spherical_expansion_backward", "soap_virial", "soap_power_spectrum_selected",
+    "soap_power_spectrum_selected_plan", "soap_power_spectrum_selected_backward", "soap_gpr_workspace_size", "soap_gpr_predict",
     "soap_compress_n_params", "soap_compress_workspace_size",
     "soap_compress_init_pca", "soap_compress_forward", "soap_compress_backward", "soap_spectrum_gram",
     "soap_spectrum_kernel_loss", "soap_adam_step", "soap_read_device_status",
@@ -100,6 +101,10 @@ def lib():
     u64, f32, sz = ctypes.c_uint64, ctypes.c_float, ctypes.c_size_t
     L.soap_power_spectrum_selected.restype = st
     L.soap_power_spectrum_selected.argtypes = [P(soap_exec), st, i64, i32, i32, vp, i64, vp, vp]
+    L.soap_power_spectrum_selected_plan.restype = st
+    L.soap_power_spectrum_selected_plan.argtypes = [i32, i32, i64, vp, vp, vp]
+    L.soap_power_spectrum_selected_backward.restype = st
+    L.soap_power_spectrum_selected_backward.argtypes = [P(soap_exec), st, i64, i32, i32, vp, i64, vp, vp, vp, vp]
     L.soap_gpr_workspace_size.restype = st
     L.soap_gpr_workspace_size.argtypes = [st, i64, i64, i64, P(sz)]
     L.soap_gpr_predict.restype = st

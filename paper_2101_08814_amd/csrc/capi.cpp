@@ -667,6 +667,56 @@ soap_status soap_power_spectrum_selected(const soap_exec* exec, soap_precision p
                     "power_spectrum_selected");
 }
 
+soap_status soap_power_spectrum_selected_plan(int32_t n_channels, int32_t lmax, int64_t n_selected,
+                                              const int32_t* selected, int32_t* row_offsets, int32_t* entries)
+{
+    clear_error();
+    REQUIRE(n_channels >= 1, "n_channels must be >= 1");
+    REQUIRE(lmax >= 0 && lmax <= 12, "lmax must be in [0, 12]");
+    REQUIRE(n_selected >= 0 && n_selected < (int64_t(1) << 29), "n_selected must be in [0, 2^29)");
+    REQUIRE(row_offsets != nullptr, "row_offsets must not be NULL");
+    if (n_selected > 0) {
+        REQUIRE(selected != nullptr && entries != nullptr, "selected and entries must not be NULL");
+        for (int64_t q = 0; q < n_selected; ++q) {
+            const int k1 = selected[3 * q], k2 = selected[3 * q + 1], l = selected[3 * q + 2];
+            REQUIRE(k1 >= 0 && k1 < n_channels && k2 >= 0 && k2 < n_channels && l >= 0 && l <= lmax,
+                    "selected[%lld] = (%d, %d, %d) is out of range", (long long)q, k1, k2, l);
+        }
+    }
+    selected_backward_plan(n_channels, lmax, n_selected, selected, row_offsets, entries);
+    return SOAP_OK;
+}
+
+soap_status soap_power_spectrum_selected_backward(const soap_exec* exec, soap_precision precision, int64_t n_atoms,
+                                                  int32_t n_channels, int32_t lmax, const void* coeffs,
+                                                  int64_t n_selected, const void* grad_p_selected,
+                                                  const int32_t* row_offsets, const int32_t* entries,
+                                                  void* grad_coeffs)
+{
+    clear_error();
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(n_channels >= 1, "n_channels must be >= 1");
+    REQUIRE(lmax >= 0 && lmax <= 12, "lmax must be in [0, 12]");
+    REQUIRE(n_selected >= 0 && n_selected < (int64_t(1) << 29), "n_selected must be in [0, 2^29)");
+    const bool f64 = precision == SOAP_F64;
+    const size_t lds = power_spectrum_selected_backward_lds(f64, n_channels, lmax, n_selected);
+    REQUIRE(lds <= 160 * 1024, "one centre's coefficients and gradient row (%zu bytes) must fit 160 KB of LDS", lds);
+    if (n_atoms == 0) return SOAP_OK;
+    const size_t es = elem_size(precision);
+    CHECK(check_ptr(coeffs, es, "coeffs"));
+    CHECK(check_ptr(grad_coeffs, es, "grad_coeffs"));
+    CHECK(check_ptr(row_offsets, 4, "row_offsets"));
+    if (n_selected > 0) {
+        CHECK(check_ptr(grad_p_selected, es, "grad_p_selected"));
+        CHECK(check_ptr(entries, 4, "entries"));
+    }
+    return launched(launch_power_spectrum_selected_backward(f64, n_atoms, n_channels, lmax, coeffs, n_selected,
+                                                            grad_p_selected, row_offsets, entries, grad_coeffs,
+                                                            status_of(exec), stream_of(exec)),
+                    "power_spectrum_selected_backward");
+}
+
 soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres, int64_t n_features,
                                     int64_t n_active, size_t* bytes)
 {

@@ -9,6 +9,8 @@
 // full spectrum's (lmax+1)^2 K(K+1)/2.
 #include "soap_internal.hpp"
 
+#include <vector>
+
 namespace soap {
 namespace {
 
@@ -102,6 +104,79 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected(int K, int lmax, const
     }
 }
 
+// dL/dc of one centre per work-group: coefficients and the centre's
+// gradient row in LDS, the plan read through L2 (staging it in LDS as well
+// halves the work-groups per CU and was measured slower); lane e = k L2 + lm
+// sums, over the plan entries of row (k, l), grad[q] c[partner, lm] in plan
+// order.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ps_selected_backward(int K, int lmax, const T* __restrict__ c,
+                                                                   int64_t n_sel, const T* __restrict__ grad,
+                                                                   const int32_t* __restrict__ row_offsets,
+                                                                   const int32_t* __restrict__ entries,
+                                                                   T* __restrict__ grad_c, int32_t* status)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L2 = (lmax + 1) * (lmax + 1);
+    const int KL2 = K * L2;
+    T* cs = reinterpret_cast<T*>(smem_raw);
+    T* gs = cs + ((KL2 + 3) & ~3);
+    const int64_t i = blockIdx.x;
+    stage(c + i * KL2, cs, KL2);
+    stage(grad + i * n_sel, gs, int(n_sel));
+    const int32_t* off = row_offsets;
+    const int32_t* ent = entries;
+    __syncthreads();
+    for (int e = threadIdx.x; e < KL2; e += kThreads) {
+        const int k = e / L2, lm = e - k * L2;
+        // l = floor(sqrt(lm)): exact in float for lm < 169, corrected anyway
+        int l = int(__builtin_sqrtf(float(lm)));
+        if (l * l > lm) --l;
+        if ((l + 1) * (l + 1) <= lm) ++l;
+        const int r = k * (lmax + 1) + l;
+        T s = T(0);
+        const int t0 = off[r], t1 = off[r + 1];
+        if (t0 < 0 || t1 < t0 || int64_t(t1) > 2 * n_sel) {   // not a plan of these triples
+            report(status, SOAP_EINVAL);
+            grad_c[i * KL2 + e] = T(0);
+            continue;
+        }
+        for (int t = t0; t < t1; ++t) {
+            const int q = ent[2 * t], partner = ent[2 * t + 1];
+            if (q < 0 || q >= n_sel || partner < 0 || partner >= K) {
+                report(status, SOAP_EINVAL);
+                continue;
+            }
+            s += gs[q] * cs[partner * L2 + lm];
+        }
+        grad_c[i * KL2 + e] = s;
+    }
+}
+
+// LDS bytes: coefficients and gradient row
+size_t backward_lds(size_t es, int K, int lmax, int64_t n_sel)
+{
+    const size_t KL2 = size_t(K) * (lmax + 1) * (lmax + 1);
+    return (((KL2 + 3) & ~size_t(3)) + ((size_t(n_sel) + 3) & ~size_t(3))) * es;
+}
+
+template <typename T>
+hipError_t selected_backward_t(int64_t n, int K, int lmax, const void* c, int64_t n_sel, const void* grad,
+                               const int32_t* row_offsets, const int32_t* entries, void* grad_c, int32_t* status,
+                               hipStream_t stream)
+{
+    const size_t lds = backward_lds(sizeof(T), K, lmax, n_sel);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ps_selected_backward<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ps_selected_backward<T>), dim3(unsigned(n)), dim3(kThreads), lds, stream, K,
+                       lmax, static_cast<const T*>(c), n_sel, static_cast<const T*>(grad), row_offsets, entries,
+                       static_cast<T*>(grad_c), status);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t selected_t(int64_t n, int K, int lmax, const void* c, int64_t n_sel, const int32_t* sel, void* out,
                       int32_t* status, hipStream_t stream)
@@ -122,6 +197,46 @@ hipError_t selected_t(int64_t n, int K, int lmax, const void* c, int64_t n_sel, 
 size_t power_spectrum_selected_lds(bool f64, int K, int lmax)
 {
     return size_t(K) * (lmax + 1) * (lmax + 1) * (f64 ? 8 : 4);
+}
+
+size_t power_spectrum_selected_backward_lds(bool f64, int K, int lmax, int64_t n_sel)
+{
+    return backward_lds(f64 ? 8 : 4, K, lmax, n_sel);
+}
+
+void selected_backward_plan(int K, int lmax, int64_t n_sel, const int32_t* selected, int32_t* row_offsets,
+                            int32_t* entries)
+{
+    // counting sort of the 2 n_sel (row, q, partner) entries by row, q order
+    // kept within a row; row = k (lmax + 1) + l
+    const int rows = K * (lmax + 1);
+    for (int r = 0; r <= rows; ++r) row_offsets[r] = 0;
+    for (int64_t q = 0; q < n_sel; ++q) {
+        const int k1 = selected[3 * q], k2 = selected[3 * q + 1], l = selected[3 * q + 2];
+        ++row_offsets[k1 * (lmax + 1) + l + 1];
+        ++row_offsets[k2 * (lmax + 1) + l + 1];
+    }
+    for (int r = 0; r < rows; ++r) row_offsets[r + 1] += row_offsets[r];
+    std::vector<int32_t> fill(row_offsets, row_offsets + rows);
+    for (int64_t q = 0; q < n_sel; ++q) {
+        const int k1 = selected[3 * q], k2 = selected[3 * q + 1], l = selected[3 * q + 2];
+        int32_t t = fill[k1 * (lmax + 1) + l]++;
+        entries[2 * t] = int32_t(q);
+        entries[2 * t + 1] = k2;
+        t = fill[k2 * (lmax + 1) + l]++;
+        entries[2 * t] = int32_t(q);
+        entries[2 * t + 1] = k1;
+    }
+}
+
+hipError_t launch_power_spectrum_selected_backward(bool f64, int64_t n, int K, int lmax, const void* c,
+                                                   int64_t n_sel, const void* grad, const int32_t* row_offsets,
+                                                   const int32_t* entries, void* grad_c, int32_t* status,
+                                                   hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    return f64 ? selected_backward_t<double>(n, K, lmax, c, n_sel, grad, row_offsets, entries, grad_c, status, stream)
+               : selected_backward_t<float>(n, K, lmax, c, n_sel, grad, row_offsets, entries, grad_c, status, stream);
 }
 
 hipError_t launch_power_spectrum_selected(bool f64, int64_t n, int K, int lmax, const void* c, int64_t n_sel,

@@ -102,6 +102,13 @@ hipError_t launch_power_spectrum_backward(const FeatureArgs& a, bool f64, const 
 size_t power_spectrum_selected_lds(bool f64, int K, int lmax);
 hipError_t launch_power_spectrum_selected(bool f64, int64_t n, int K, int lmax, const void* c, int64_t n_sel,
                                           const int32_t* sel, void* out, int32_t* status, hipStream_t stream);
+size_t power_spectrum_selected_backward_lds(bool f64, int K, int lmax, int64_t n_sel);
+void selected_backward_plan(int K, int lmax, int64_t n_sel, const int32_t* selected, int32_t* row_offsets,
+                            int32_t* entries);
+hipError_t launch_power_spectrum_selected_backward(bool f64, int64_t n, int K, int lmax, const void* c,
+                                                   int64_t n_sel, const void* grad, const int32_t* row_offsets,
+                                                   const int32_t* entries, void* grad_c, int32_t* status,
+                                                   hipStream_t stream);
 size_t gpr_workspace_bytes(bool f64, int64_t n, int64_t n_feat, int64_t n_active);
 hipError_t launch_gpr_predict(bool f64, int64_t n, int64_t n_feat, const int32_t* species, const void* p,
                               int64_t n_active, const int32_t* active_species, const void* m, const void* w,

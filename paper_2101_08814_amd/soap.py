@@ -311,6 +311,30 @@ class Calculator:
                                                    _ptr(c), n_sel, _ptr(sel), _ptr(out)))
         return out[:N, :n_sel]
 
+    def power_spectrum_selected_backward(self, coeffs: torch.Tensor, selected, grad_p: torch.Tensor) -> torch.Tensor:
+        """soap_power_spectrum_selected_backward: dL/dc [N, S, nmax, L2] for
+        grad_p = dL/dp_sel [N, n_sel]; the plan is built on the host from
+        ``selected`` and copied to the device."""
+        td = coeffs.dtype
+        prec = _precision(td)
+        N = coeffs.shape[0]
+        c = coeffs.contiguous()
+        tri = np.ascontiguousarray(selected.cpu().numpy() if isinstance(selected, torch.Tensor) else selected,
+                                   dtype=np.int32).reshape(-1, 3)
+        n_sel = tri.shape[0]
+        offs = np.zeros(self.K * (self.lmax + 1) + 1, dtype=np.int32)
+        ent = np.zeros((max(2 * n_sel, 1), 2), dtype=np.int32)
+        check(self._L.soap_power_spectrum_selected_plan(self.K, self.lmax, n_sel, _np_ptr(tri), _np_ptr(offs),
+                                                        _np_ptr(ent)))
+        offs_d = torch.from_numpy(offs).to(c.device)
+        ent_d = torch.from_numpy(ent).to(c.device)
+        g = grad_p.to(td).contiguous()
+        gc = torch.empty_like(c)
+        e = self._exec()
+        check(self._L.soap_power_spectrum_selected_backward(ctypes.byref(e), prec, N, self.K, self.lmax, _ptr(c), n_sel,
+                                                            _ptr(g), _ptr(offs_d), _ptr(ent_d), _ptr(gc)))
+        return gc
+
     def gpr_predict(self, species: torch.Tensor, features: torch.Tensor, active_species: torch.Tensor,
                     active_features: torch.Tensor, weights: torch.Tensor, zeta: int, want_grad: bool = True):
         """soap_gpr_predict: per-centre energies [N] of the sparse kernel model

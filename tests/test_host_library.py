@@ -183,3 +183,32 @@ def test_spline_accuracy_is_honoured():
     assert coarse.info()["n_intervals"] == 1024
     assert fine.info()["n_intervals"] > 1024
     assert fine.info()["max_error"] <= 1e-12
+
+
+def test_selected_backward_plan_host():
+    """The host plan of the selected-invariant adjoint: per row (k, l) the
+    entries (q, partner) of every triple touching channel k at degree l, in
+    q order, two per triple (k1 = k2 gives two entries in the same row);
+    out-of-range triples are rejected with SOAP_EINVAL."""
+    import ctypes
+    from paper_2101_08814_amd import _lib
+    L = _lib.lib()
+    K, lmax = 4, 2
+    tri = np.array([[0, 1, 0], [2, 2, 1], [1, 0, 0], [3, 1, 2]], dtype=np.int32)
+    offs = np.zeros(K * (lmax + 1) + 1, dtype=np.int32)
+    ent = np.zeros((2 * len(tri), 2), dtype=np.int32)
+    st = L.soap_power_spectrum_selected_plan(K, lmax, len(tri), tri.ctypes.data, offs.ctypes.data,
+                                             ent.ctypes.data)
+    assert st == _lib.SOAP_OK
+    expect = {}
+    for q, (k1, k2, l) in enumerate(tri):
+        expect.setdefault(k1 * (lmax + 1) + l, []).append((q, k2))
+        expect.setdefault(k2 * (lmax + 1) + l, []).append((q, k1))
+    for r in range(K * (lmax + 1)):
+        got = [tuple(x) for x in ent[offs[r]:offs[r + 1]]]
+        assert got == expect.get(r, [])
+    bad = tri.copy()
+    bad[2] = (0, 4, 0)
+    st = L.soap_power_spectrum_selected_plan(K, lmax, len(bad), bad.ctypes.data, offs.ctypes.data,
+                                             ent.ctypes.data)
+    assert st == _lib.SOAP_EINVAL
