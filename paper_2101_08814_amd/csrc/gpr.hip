@@ -71,10 +71,6 @@ __device__ __forceinline__ int tile_col(int u, int v)
     return int(threadIdx.x & 15) + 16 * v;
 }
 
-// the 64 x 64 tile at (row0, col0) of
-//   C = A B,  A(i, k) = a[i * lda + k]  (rows < n_rows),
-//             B(k, j) = TRANS_B ? b[j * ldb + k] : b[k * ldb + j]  (cols < n_cols),
-// over k_begin <= k < depth; out-of-range operand elements read as zero.
 // acc[v] += the 16 x 16 x 4 product of this wave's A and B lane values
 __device__ __forceinline__ void mfma_acc(float (&acc)[4], float a, float b)
 {
@@ -87,6 +83,12 @@ __device__ __forceinline__ void mfma_acc(float (&acc)[4], float a, float b)
 }
 __device__ __forceinline__ void mfma_acc(double (&)[4], double, double) {}
 
+// the 64 x 64 tile at (row0, col0) of
+//   C = A B,  A(i, k) = a[i * lda + k]  (rows < n_rows),
+//             B(k, j) = TRANS_B ? b[j * ldb + k] : b[k * ldb + j]  (cols < n_cols),
+// over k_begin <= k < depth; out-of-range operand elements read as zero
+// (as guarded loads: clamped unconditional loads were measured twice as slow
+// here).
 template <typename T, bool TRANS_B>
 __device__ __forceinline__ void tile_product(const T* __restrict__ a, int64_t lda, int64_t n_rows,
                                              const T* __restrict__ b, int64_t ldb, int64_t n_cols, int64_t k_begin,
