@@ -212,3 +212,32 @@ def test_selected_backward_plan_host():
     st = L.soap_power_spectrum_selected_plan(K, lmax, len(bad), bad.ctypes.data, offs.ctypes.data,
                                              ent.ctypes.data)
     assert st == _lib.SOAP_EINVAL
+
+
+def test_new_entry_points_reject_bad_arguments_on_host():
+    """Host-side checks of the virial, sparse-model and selected-invariant
+    entry points return SOAP_EINVAL before any device work."""
+    import ctypes
+    L = _lib.lib()
+    e = _lib.soap_exec(None, None)
+    ref = ctypes.byref(e)
+    nb = ctypes.c_size_t()
+    # virial: BF16 is not a virial precision; negative structure count
+    assert L.soap_virial(ref, _lib.SOAP_BF16_F32ACC, 1, None, 0, None, None, None, 0, None, None) == _lib.SOAP_EINVAL
+    assert L.soap_virial(ref, _lib.SOAP_F32, -1, None, 0, None, None, None, 0, None, None) == _lib.SOAP_EINVAL
+    # sparse model: zeta out of range, too many features, workspace too small
+    assert L.soap_gpr_predict(ref, _lib.SOAP_F32, 4, 8, None, None, 2, None, None, None, 0, None, 0, None,
+                              None) == _lib.SOAP_EINVAL
+    assert L.soap_gpr_predict(ref, _lib.SOAP_F32, 4, 64 * 65535 + 1, None, None, 2, None, None, None, 2, None, 0,
+                              None, None) == _lib.SOAP_EINVAL
+    assert L.soap_gpr_workspace_size(_lib.SOAP_F32, 4, 8, 2, ctypes.byref(nb)) == _lib.SOAP_OK and nb.value > 0
+    assert L.soap_gpr_predict(ref, _lib.SOAP_F32, 4, 8, None, None, 2, None, None, None, 2, None, nb.value - 1,
+                              None, None) == _lib.SOAP_EINVAL
+    assert L.soap_gpr_workspace_size(_lib.SOAP_F32, 4, 8, 0, ctypes.byref(nb)) == _lib.SOAP_EINVAL
+    # selected invariants: lmax above 12; one centre's coefficients beyond 160 KB of LDS
+    assert L.soap_power_spectrum_selected(ref, _lib.SOAP_F32, 1, 4, 13, None, 1, None, None) == _lib.SOAP_EINVAL
+    assert L.soap_power_spectrum_selected(ref, _lib.SOAP_F64, 1, 400, 12, None, 1, None, None) == _lib.SOAP_EINVAL
+    assert L.soap_power_spectrum_selected_backward(ref, _lib.SOAP_F32, 1, 4, 2, None, -1, None, None, None,
+                                                   None) == _lib.SOAP_EINVAL
+    msg = L.soap_last_error().decode()
+    assert "n_selected" in msg
