@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected(int K, int lmax, const
 // gradient row in LDS, the plan read through L2 (staging it in LDS as well
 // halves the work-groups per CU and was measured slower); lane e = k L2 + lm
 // sums, over the plan entries of row (k, l), grad[q] c[partner, lm] in plan
-// order.
+// order; lane steps carry (k, lm) forward and l comes from an LDS table.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_ps_selected_backward(int K, int lmax, const T* __restrict__ c,
                                                                    int64_t n_sel, const T* __restrict__ grad,
@@ -121,43 +121,54 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected_backward(int K, int lm
     const int KL2 = K * L2;
     T* cs = reinterpret_cast<T*>(smem_raw);
     T* gs = cs + ((KL2 + 3) & ~3);
+    int32_t* ltab = reinterpret_cast<int32_t*>(gs + ((n_sel + 3) & ~int64_t(3)));   // l of each lm
     const int64_t i = blockIdx.x;
     stage(c + i * KL2, cs, KL2);
     stage(grad + i * n_sel, gs, int(n_sel));
-    const int32_t* off = row_offsets;
-    const int32_t* ent = entries;
+    for (int lm = threadIdx.x; lm < L2; lm += kThreads) {
+        int l = 0;
+        while ((l + 1) * (l + 1) <= lm) ++l;
+        ltab[lm] = l;
+    }
     __syncthreads();
+    // e = k L2 + lm advances by kThreads per step: (k, lm) is carried
+    // forward instead of divided out again
+    const int step_k = kThreads / L2, step_lm = kThreads - step_k * L2;
+    int k = int(threadIdx.x) / L2, lm = int(threadIdx.x) - k * L2;
+    T* gi = grad_c + i * KL2;
     for (int e = threadIdx.x; e < KL2; e += kThreads) {
-        const int k = e / L2, lm = e - k * L2;
-        // l = floor(sqrt(lm)): exact in float for lm < 169, corrected anyway
-        int l = int(__builtin_sqrtf(float(lm)));
-        if (l * l > lm) --l;
-        if ((l + 1) * (l + 1) <= lm) ++l;
+        const int l = ltab[lm];
         const int r = k * (lmax + 1) + l;
         T s = T(0);
-        const int t0 = off[r], t1 = off[r + 1];
+        const int t0 = row_offsets[r], t1 = row_offsets[r + 1];
         if (t0 < 0 || t1 < t0 || int64_t(t1) > 2 * n_sel) {   // not a plan of these triples
             report(status, SOAP_EINVAL);
-            grad_c[i * KL2 + e] = T(0);
-            continue;
-        }
-        for (int t = t0; t < t1; ++t) {
-            const int q = ent[2 * t], partner = ent[2 * t + 1];
-            if (q < 0 || q >= n_sel || partner < 0 || partner >= K) {
-                report(status, SOAP_EINVAL);
-                continue;
+        } else {
+            for (int t = t0; t < t1; ++t) {
+                const int q = entries[2 * t], partner = entries[2 * t + 1];
+                if (q < 0 || q >= n_sel || partner < 0 || partner >= K) {
+                    report(status, SOAP_EINVAL);
+                    continue;
+                }
+                s += gs[q] * cs[partner * L2 + lm];
             }
-            s += gs[q] * cs[partner * L2 + lm];
         }
-        grad_c[i * KL2 + e] = s;
+        gi[e] = s;
+        lm += step_lm;
+        k += step_k;
+        if (lm >= L2) {
+            lm -= L2;
+            ++k;
+        }
     }
 }
 
-// LDS bytes: coefficients and gradient row
+// LDS bytes: coefficients, gradient row, table of l per lm
 size_t backward_lds(size_t es, int K, int lmax, int64_t n_sel)
 {
     const size_t KL2 = size_t(K) * (lmax + 1) * (lmax + 1);
-    return (((KL2 + 3) & ~size_t(3)) + ((size_t(n_sel) + 3) & ~size_t(3))) * es;
+    const size_t L2 = size_t(lmax + 1) * (lmax + 1);
+    return (((KL2 + 3) & ~size_t(3)) + ((size_t(n_sel) + 3) & ~size_t(3))) * es + L2 * 4;
 }
 
 template <typename T>
