@@ -176,6 +176,26 @@ soap_status soap_compute_neighbors(const soap_calculator* calc, const soap_exec*
                                    int32_t* pair_j, int32_t* pair_shift, void* pair_vec,
                                    int32_t* pair_transpose);
 
+/* soap_compute_neighbors for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, outputs and device errors are those of
+ * soap_compute_neighbors without workspace / workspace_bytes: the
+ * workspace is a static device array of SOAP_NEIGHBORS_NOALLOC_BYTES bytes
+ * per device, held until the process ends.  A request whose
+ * soap_neighbors_workspace_size exceeds it returns SOAP_EINVAL with
+ * nothing enqueued (16 MiB holds about 150,000 atoms).  The call allocates
+ * nothing and needs no clearing between calls.  Every call on one device
+ * shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race, so the caller orders them.              */
+#define SOAP_NEIGHBORS_NOALLOC_BYTES ((size_t)16 << 20)
+soap_status soap_compute_neighbors_noalloc(const soap_calculator* calc, const soap_exec* exec,
+                                           int32_t n_structures, int64_t n_atoms, const int64_t* atom_offsets,
+                                           const double* cells, const uint8_t* pbc,
+                                           const double* positions, const int32_t* species,
+                                           int64_t capacity, soap_precision vec_precision,
+                                           int64_t* pair_offsets, int32_t* pair_j, int32_t* pair_shift,
+                                           void* pair_vec, int32_t* pair_transpose);
+
 /* Spherical expansion (Sec. 4.A Eq. spherical_expansion_coefficients_
  * gaussians with the splined radial integral of Sec. 4.D and real Y_lm of
  * Sec. 4.E), optionally with forward-mode gradient rows (Sec. 4.G).

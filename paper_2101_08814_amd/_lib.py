@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "SOAP_OK", -1: "SOAP_EINVAL", -2: "SOAP_ECAPACITY", -3: "SOAP
 EXPORTS = [
     "soap_abi_version", "soap_last_error", "soap_calculator_create", "soap_calculator_destroy",
     "soap_calculator_info", "soap_calculator_upload", "soap_radial_integral_host",
-    "soap_neighbors_workspace_size", "soap_compute_neighbors", "soap_spherical_expansion",
+    "soap_neighbors_workspace_size", "soap_compute_neighbors", "soap_compute_neighbors_noalloc",
+    "soap_spherical_expansion",
     "soap_power_spectrum", "soap_features", "soap_gradient_rows", "soap_power_spectrum_backward",
     "soap_spherical_expansion_backward", "soap_virial", "soap_power_spectrum_selected",
     "soap_power_spectrum_selected_plan", "soap_power_spectrum_selected_backward", "soap_gpr_workspace_size", "soap_gpr_predict",
@@ -84,6 +85,9 @@ def lib():
     L.soap_compute_neighbors.restype = st
     L.soap_compute_neighbors.argtypes = [vp, P(soap_exec), i32, i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, i64,
                                          st, vp, vp, vp, vp, vp]
+    L.soap_compute_neighbors_noalloc.restype = st
+    L.soap_compute_neighbors_noalloc.argtypes = [vp, P(soap_exec), i32, i64, vp, vp, vp, vp, vp, i64, st, vp, vp,
+                                                 vp, vp, vp]
     L.soap_spherical_expansion.restype = st
     L.soap_spherical_expansion.argtypes = [vp, P(soap_exec), st, i64, vp, vp, vp, vp, i64, vp, vp, vp]
     L.soap_power_spectrum.restype = st

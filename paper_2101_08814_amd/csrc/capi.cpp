@@ -165,6 +165,10 @@ NbLayout nb_layout(int32_t n_struct, int64_t N)
 
 }  // namespace
 
+namespace soap {
+size_t neighbors_workspace_bytes(int32_t n_structures, int64_t n_atoms) { return nb_layout(n_structures, n_atoms).total; }
+}  // namespace soap
+
 namespace {
 
 // ------------------------------------------------------------ compression

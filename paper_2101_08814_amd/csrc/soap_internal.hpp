@@ -182,5 +182,7 @@ struct NeighborArgs {
 };
 
 hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream);
+// bytes of neighbour-list workspace for these sizes (as soap_neighbors_workspace_size)
+size_t neighbors_workspace_bytes(int32_t n_structures, int64_t n_atoms);
 
 }  // namespace soap
