@@ -329,17 +329,25 @@ hipError_t exp_backward_t(const FeatureArgs& a, const int32_t* transpose, const 
                           void* grad_pos, hipStream_t stream)
 {
     Dims d = make_dims(a.S, a.nmax, a.lmax);
-    Layout L = choose_layout<T>(d, true, false, false);
-    if (L.total == 0) return hipErrorNotSupported;
-    size_t lds = size_t(L.total) * sizeof(T);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_exp_backward_pairs<T>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    const bool f64 = std::is_same<T, double>::value;
+    // one lane per pair when dL/dc of a centre fits the wave's LDS, else the
+    // LDS-staged kernel
+    const bool lanes = expansion_backward_lanes_fits(a, f64);
+    if (a.pair_capacity > 0 && lanes) {
+        hipError_t e = launch_expansion_backward_lanes(a, f64, grad_c, grad_pair, stream);
         if (e != hipSuccess) return e;
-    }
-    if (a.pair_capacity > 0)
+    } else if (a.pair_capacity > 0) {
+        Layout L = choose_layout<T>(d, true, false, false);
+        if (L.total == 0) return hipErrorNotSupported;
+        size_t lds = size_t(L.total) * sizeof(T);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_exp_backward_pairs<T>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_pairs<T>), dim3(unsigned(a.n_atoms)), dim3(kThreads), lds,
                            stream, a, L, static_cast<const T*>(grad_c), static_cast<T*>(grad_pair));
+    }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exp_backward_gather<T>), dim3(unsigned((a.n_atoms + 3) / 4)), dim3(256),
                        0, stream, a, transpose, static_cast<const T*>(grad_pair), static_cast<T*>(grad_pos));
     return hipGetLastError();

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -28,6 +29,15 @@ soap_status fail(soap_status st, const char* fmt, ...)
 
 void clear_error() { g_error[0] = '\0'; }
 
+// SOAP_FAIL_ALLOC=1 in the environment makes every allocation the library
+// makes or sizes for the caller (calculator, device tables, workspace
+// queries) fail with SOAP_ENOMEM, so callers can test that path.
+bool alloc_failure_forced()
+{
+    const char* v = std::getenv("SOAP_FAIL_ALLOC");
+    return v && v[0] == '1';
+}
+
 soap_status device_tables(const soap_calculator* calc, const DeviceTables** out)
 {
     int dev = 0;
@@ -39,11 +49,31 @@ soap_status device_tables(const soap_calculator* calc, const DeviceTables** out)
         size_t b64 = calc->coef64.size() * sizeof(double), b32 = calc->coef32.size() * sizeof(float);
         size_t c64 = calc->center.size() * sizeof(double), c32 = calc->center.size() * sizeof(float);
         std::vector<float> cf(calc->center.begin(), calc->center.end());
-        if (hipMalloc(&t.coef64, b64) != hipSuccess || hipMalloc(&t.coef32, b32) != hipSuccess ||
+        // degree-major copy: the nmax cubics of one (interval, l) contiguous
+        const int lm1t = calc->h.lmax + 1, nmx = calc->h.nmax, nlt = calc->nl;
+        // (32 zero cubics past the end, so a lane may read up to 32 entries
+        // past its interval's block without a bounds check)
+        const size_t pad_ln = 32 * 4;
+        std::vector<double> ln64(calc->coef64.size() + pad_ln, 0.0);
+        std::vector<float> ln32(calc->coef32.size() + pad_ln, 0.0f);
+        for (int64_t k = 0; k < calc->M; ++k)
+            for (int n = 0; n < nmx; ++n)
+                for (int l = 0; l < lm1t; ++l)
+                    for (int e = 0; e < 4; ++e) {
+                        const size_t src = ((size_t(k) * nlt + n * lm1t + l) * 4) + e;
+                        const size_t dst = ((size_t(k) * lm1t + l) * nmx + n) * 4 + e;
+                        ln64[dst] = calc->coef64[src];
+                        ln32[dst] = calc->coef32[src];
+                    }
+        if (alloc_failure_forced() || hipMalloc(&t.coef64, b64) != hipSuccess ||
+            hipMalloc(&t.coef32, b32) != hipSuccess || hipMalloc(&t.coef64_ln, ln64.size() * sizeof(double)) != hipSuccess ||
+            hipMalloc(&t.coef32_ln, ln32.size() * sizeof(float)) != hipSuccess ||
             hipMalloc(&t.center64, c64) != hipSuccess || hipMalloc(&t.center32, c32) != hipSuccess)
             return fail(SOAP_ENOMEM, "allocation of the spline tables failed on device %d", dev);
         if (hipMemcpy(t.coef64, calc->coef64.data(), b64, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(t.coef32, calc->coef32.data(), b32, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(t.coef64_ln, ln64.data(), ln64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(t.coef32_ln, ln32.data(), ln32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(t.center64, calc->center.data(), c64, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(t.center32, cf.data(), c32, hipMemcpyHostToDevice) != hipSuccess)
             return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
@@ -58,6 +88,19 @@ soap_status device_tables(const soap_calculator* calc, const DeviceTables** out)
             if (hipMalloc(&t.dp_pos, pos.size() * sizeof(int32_t)) != hipSuccess)
                 return fail(SOAP_ENOMEM, "allocation of the spline tables failed on device %d", dev);
             if (hipMemcpy(t.dp_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+                return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
+        }
+        {
+            const int nmx = calc->h.nmax, np = (nmx + 3) & ~3, nlt = calc->nl;
+            std::vector<int32_t> dst(size_t(nlt) + 16);
+            for (int j = 0; j < nlt + 16; ++j) {
+                const int jj = j < nlt ? j : nlt - 1;
+                dst[j] = (jj / nmx) * np + jj % nmx;
+            }
+            if (hipMalloc(&t.radial_dst, dst.size() * sizeof(int32_t)) != hipSuccess)
+                return fail(SOAP_ENOMEM, "allocation of the spline tables failed on device %d", dev);
+            if (hipMemcpy(t.radial_dst, dst.data(), dst.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                hipSuccess)
                 return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
         }
         t.ready = true;
@@ -125,8 +168,10 @@ FeatureArgs base_args(const soap_calculator* calc, const soap_exec* exec, bool f
     a.M = calc->M;
     a.inv_delta = calc->inv_delta;
     a.coef = f64 ? static_cast<const void*>(t->coef64) : static_cast<const void*>(t->coef32);
+    a.coef_ln = f64 ? static_cast<const void*>(t->coef64_ln) : static_cast<const void*>(t->coef32_ln);
     a.center = f64 ? static_cast<const void*>(t->center64) : static_cast<const void*>(t->center32);
     a.dp_pos = t->dp_pos;
+    a.radial_dst = t->radial_dst;
     a.status = status_of(exec);
     return a;
 }
@@ -252,6 +297,7 @@ soap_status soap_calculator_create(const soap_hypers* h, soap_calculator** out)
     REQUIRE(std::isfinite(h->sigma) && h->sigma > 0, "sigma must be > 0");
     REQUIRE(h->include_center == 0 || h->include_center == 1, "include_center must be 0 or 1");
     REQUIRE(std::isfinite(h->spline_accuracy) && h->spline_accuracy > 0, "spline_accuracy must be > 0");
+    if (alloc_failure_forced()) return fail(SOAP_ENOMEM, "allocation failure forced by SOAP_FAIL_ALLOC");
     soap_calculator* c = new (std::nothrow) soap_calculator();
     if (!c) return fail(SOAP_ENOMEM, "out of host memory");
     c->h = *h;
@@ -280,9 +326,12 @@ soap_status soap_calculator_destroy(soap_calculator* calc)
         if (have) (void)hipSetDevice(int(d));
         (void)hipFree(t.coef64);
         (void)hipFree(t.coef32);
+        (void)hipFree(t.coef64_ln);
+        (void)hipFree(t.coef32_ln);
         (void)hipFree(t.center64);
         (void)hipFree(t.center32);
         (void)hipFree(t.dp_pos);
+        (void)hipFree(t.radial_dst);
     }
     if (have) (void)hipSetDevice(cur);
     delete calc;
@@ -335,6 +384,7 @@ soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n
     REQUIRE(bytes != nullptr, "bytes must not be NULL");
     REQUIRE(n_structures >= 0, "n_structures must be >= 0 (got %d)", n_structures);
     REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    if (alloc_failure_forced()) return fail(SOAP_ENOMEM, "allocation failure forced by SOAP_FAIL_ALLOC");
     *bytes = nb_layout(n_structures, n_atoms).total;
     return SOAP_OK;
 }
@@ -730,6 +780,7 @@ soap_status soap_gpr_workspace_size(soap_precision precision, int64_t n_centres,
     REQUIRE(n_features >= 1 && n_features <= 64 * int64_t(65535), "n_features must be in [1, 4194240]");
     REQUIRE(n_active >= 1 && n_active <= 64 * int64_t(65535), "n_active must be in [1, 4194240]");
     REQUIRE(bytes != nullptr, "bytes must not be NULL");
+    if (alloc_failure_forced()) return fail(SOAP_ENOMEM, "allocation failure forced by SOAP_FAIL_ALLOC");
     *bytes = gpr_workspace_bytes(precision == SOAP_F64, n_centres, n_features, n_active);
     return SOAP_OK;
 }
@@ -780,6 +831,7 @@ soap_status soap_compress_workspace_size(const soap_calculator* calc, int32_t n_
     clear_error();
     CHECK(check_compress(calc, n_out, hidden));
     REQUIRE(bytes != nullptr, "bytes must not be NULL");
+    if (alloc_failure_forced()) return fail(SOAP_ENOMEM, "allocation failure forced by SOAP_FAIL_ALLOC");
     *bytes = compress_workspace(calc, n_out, hidden);
     return SOAP_OK;
 }

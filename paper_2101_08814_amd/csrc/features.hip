@@ -511,6 +511,13 @@ hipError_t features_t(const FeatureArgs& a, hipStream_t stream)
         if (L.total != 0)
             return by_lmax<T, CentresFn>(a.lmax, c, L, size_t(L.total) * sizeof(T), true, stream);
     }
+    if (!grad) {
+        // c (and p) with one lane per pair; the pair rows, if asked for,
+        // from the row kernel
+        hipError_t e = launch_expansion_lanes(c, std::is_same<T, double>::value, stream);
+        if (e == hipSuccess) return launch_gradient_rows(a, std::is_same<T, double>::value, stream);
+        if (e != hipErrorNotSupported) return e;
+    }
     Layout L = choose_layout<T>(d, grad, true, want_p);
     // c alone in float, when its LDS accumulator forces chunks below 32
     // pairs: register sums instead (128 VGPRs, four work-groups per CU; in

@@ -18,9 +18,13 @@ struct DeviceTables {
     bool ready = false;
     double* coef64 = nullptr;    // [M][nmax][lmax+1][4] local-t cubic coefficients
     float* coef32 = nullptr;
+    double* coef64_ln = nullptr; // the same cubics reordered [M][lmax+1][nmax][4], 32 zero cubics past the end
+    float* coef32_ln = nullptr;
     double* center64 = nullptr;  // [nmax] I~_n0(0) Y_00, then [L2] harmonic normalisations K_lm
     float* center32 = nullptr;
     int32_t* dp_pos = nullptr;   // [lmax+1][K(K+1)/2]: l | k1 << 4 | k2 << 14 of each dp row position
+    int32_t* radial_dst = nullptr; // [nl + 16]: LDS offset l np + n of radial value j = l nmax + n
+                                   // (np = nmax rounded up to 4; entries past nl repeat the last)
 };
 
 // Geometry of one structure for the neighbour search (built on the device
@@ -59,6 +63,7 @@ namespace soap {
 // error reporting (thread-local message)
 soap_status fail(soap_status st, const char* fmt, ...);
 void clear_error();
+bool alloc_failure_forced();   // SOAP_FAIL_ALLOC=1 in the environment
 
 // tables.cpp
 soap_status build_tables(soap_calculator* calc);
@@ -82,8 +87,10 @@ struct FeatureArgs {
     const void* pair_vec;
     int64_t pair_capacity;
     const void* coef;       // table of the working precision
+    const void* coef_ln;    // the same table in [M][lmax+1][nmax] order
     const void* center;     // [nmax] centre terms, then [L2] harmonic normalisations
     const int32_t* dp_pos;  // (l, k1, k2) of each position of a dp row, packed; NULL if K > 1023
+    const int32_t* radial_dst;  // LDS offset of each radial value in the padded [l][np] rows
     void* coeffs;
     void* p;
     void* dcoeffs;
@@ -94,6 +101,22 @@ struct FeatureArgs {
 };
 
 hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream);
+
+// Per-wave LDS layout of the one-lane-per-pair expansion (elements of T):
+// ch pairs of radial rows [lmax+1][np] and harmonic rows [l2s], and the
+// species blocks of c as [np/4][L2][4] (cb elements each): one buffer, or
+// with the power spectrum all S of them (an LDS copy of c_i).
+struct LaneLayout {
+    int ch, np, nls, l2s, rs, ys, sp, cb, cs, total;
+};
+LaneLayout choose_lane_layout(int S, int nmax, int lmax, bool want_p, size_t elem);
+// c (and p when a.p is set) with one lane per pair; hipErrorNotSupported
+// when the layout does not fit
+hipError_t launch_expansion_lanes(const FeatureArgs& a, bool f64, hipStream_t stream);
+// per-pair dL/dr_ji of the adjoint with one lane per pair
+bool expansion_backward_lanes_fits(const FeatureArgs& a, bool f64);
+hipError_t launch_expansion_backward_lanes(const FeatureArgs& a, bool f64, const void* grad_c, void* grad_pair,
+                                           hipStream_t stream);
 hipError_t launch_gradient_rows(const FeatureArgs& a, bool f64, hipStream_t stream);
 hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipStream_t stream);
 hipError_t launch_power_spectrum_valu(const FeatureArgs& a, bool f64, hipStream_t stream);

@@ -241,3 +241,29 @@ def test_new_entry_points_reject_bad_arguments_on_host():
                                                    None) == _lib.SOAP_EINVAL
     msg = L.soap_last_error().decode()
     assert "n_selected" in msg
+
+
+def test_forced_allocation_failure(calc, monkeypatch):
+    """SOAP_FAIL_ALLOC=1 makes the calculator creation and every workspace
+    query report SOAP_ENOMEM (the library's out-of-memory path), and the
+    library recovers once it is unset."""
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    nparam = ctypes.c_int64()
+    monkeypatch.setenv("SOAP_FAIL_ALLOC", "1")
+    st, out = _create()
+    assert st == _lib.SOAP_ENOMEM and not out.value
+    assert b"SOAP_FAIL_ALLOC" in L.soap_last_error()
+    assert L.soap_neighbors_workspace_size(calc.handle, 1, 10, ctypes.byref(n)) == _lib.SOAP_ENOMEM
+    assert L.soap_gpr_workspace_size(_lib.SOAP_F32, 10, 20, 30, ctypes.byref(n)) == _lib.SOAP_ENOMEM
+    assert L.soap_compress_workspace_size(calc.handle, 4, 8, ctypes.byref(n)) == _lib.SOAP_ENOMEM
+    # queries that size nothing are unaffected
+    assert L.soap_compress_n_params(calc.handle, 4, 8, ctypes.byref(nparam)) == _lib.SOAP_OK
+    with pytest.raises(_lib.SoapError) as err:
+        calc.neighbors_workspace_size(1, 10)
+    assert err.value.status == _lib.SOAP_ENOMEM
+    monkeypatch.delenv("SOAP_FAIL_ALLOC")
+    st, out = _create()
+    assert st == _lib.SOAP_OK and out.value
+    assert L.soap_calculator_destroy(out) == _lib.SOAP_OK
+    assert L.soap_neighbors_workspace_size(calc.handle, 1, 10, ctypes.byref(n)) == _lib.SOAP_OK and n.value > 0
