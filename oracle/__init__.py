@@ -55,7 +55,12 @@ def lib():
         L.orc_neighbors.restype = i
         L.orc_neighbors.argtypes = [i, P(i64), P(d), P(d), P(u8), P(ctypes.c_int32), d, P(i64),
                                     P(ctypes.c_int32), P(ctypes.c_int32), P(d)]
-        hy = [i, i, i, i, d, d, d]
+        hy = [i, i, i, i, d, d, d, i]
+        L.orc_gauss_legendre.argtypes = [i, P(d), P(d)]
+        L.orc_sph_bessel_i.restype = d
+        L.orc_sph_bessel_i.argtypes = [i, d, P(d)]
+        L.orc_dvr_points.argtypes = [i, d, d, P(d), P(d)]
+        L.orc_dvr_radial_integral.argtypes = [i, i, d, d, d, P(d), P(d)]
         L.orc_expansion.restype = i
         L.orc_expansion.argtypes = hy + [P(ctypes.c_int32), P(i64), P(ctypes.c_int32), P(d), i64, P(i64), P(d)]
         L.orc_power_spectrum.argtypes = [i, i, i, i64, P(d), P(d)]
@@ -76,7 +81,8 @@ def _p(a, ct=ctypes.c_double):
 
 def _hy(h):
     return (int(h["n_species"]), int(h["nmax"]), int(h["lmax"]), int(h.get("include_center", 1)),
-            float(h["rcut"]), float(h.get("cutoff_width", 0.5)), float(h["sigma"]))
+            float(h["rcut"]), float(h.get("cutoff_width", 0.5)), float(h["sigma"]),
+            int(h.get("radial_basis", 0)))
 
 
 # ---------------------------------------------------------------- elements
@@ -133,6 +139,35 @@ def radial_integral_orth(nmax, lmax, rcut, sigma, r, deriv=False):
     I = np.zeros((nmax, lmax + 1))
     dI = np.zeros((nmax, lmax + 1)) if deriv else None
     lib().orc_radial_integral_orth(nmax, lmax, rcut, sigma, float(r), _p(I), _p(dI))
+    return (I, dI) if deriv else I
+
+
+def gauss_legendre(n):
+    """Gauss-Legendre points and weights on [-1, 1] (ascending)."""
+    t, w = np.zeros(n), np.zeros(n)
+    lib().orc_gauss_legendre(int(n), _p(t), _p(w))
+    return t, w
+
+
+def sph_bessel_i(l, z, deriv=False):
+    """Modified spherical Bessel function i_l(z) (and d/dz) by its series."""
+    d = ctypes.c_double()
+    v = lib().orc_sph_bessel_i(int(l), float(z), ctypes.byref(d))
+    return (v, d.value) if deriv else v
+
+
+def dvr_points(nmax, rcut, sigma):
+    """DVR points x_n and weights w_n on [0, rcut + 3 sigma] (Sec. 4.C)."""
+    x, w = np.zeros(nmax), np.zeros(nmax)
+    lib().orc_dvr_points(int(nmax), float(rcut), float(sigma), _p(x), _p(w))
+    return x, w
+
+
+def dvr_radial_integral(nmax, lmax, rcut, sigma, r, deriv=False):
+    """DVR radial integral I_nl(r) [nmax, lmax+1] (and d/dr), Sec. 4.C."""
+    I = np.zeros((nmax, lmax + 1))
+    dI = np.zeros((nmax, lmax + 1)) if deriv else None
+    lib().orc_dvr_radial_integral(nmax, lmax, rcut, sigma, float(r), _p(I), _p(dI))
     return (I, dI) if deriv else I
 
 

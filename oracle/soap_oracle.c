@@ -17,6 +17,9 @@
  *     spline;
  *   - orthogonalisation: S^{-1/2} from a cyclic Jacobi eigen-decomposition of
  *     the analytic GTO overlap (Sec. 4.B);
+ *   - DVR radial basis (Sec. 4.C Eq. rad-int-dvr): Gauss-Legendre points by
+ *     Newton iteration on the Legendre polynomial, the modified spherical
+ *     Bessel function by its defining power series;
  *   - real spherical harmonics: explicit polynomials (binomial sum of the
  *     Legendre polynomial, differentiated term by term), not a recurrence;
  *   - coefficients, power spectrum, gradients and the vector-Jacobian
@@ -35,7 +38,15 @@
  *                      k = species*nmax + n; the paper's Eq. nu2-basis-coupled
  *                      is this divided by sqrt(2l+1);
  *   centre atom      : include_center adds the r = 0 term of the central atom
- *                      to its own species channel.
+ *                      to its own species channel;
+ *   DVR radial basis : I_nl(r) = 4 pi exp(-c r^2) x_n sqrt(w_n) exp(-c x_n^2)
+ *                      i_l(2 c x_n r) on the nmax Gauss-Legendre points x_n
+ *                      (weights w_n) of [0, rcut + 3 sigma]: Eq. rad-int-dvr
+ *                      with the factor 4 pi exp(-c r^2) of Eq. radial-
+ *                      integral-gaussian-density restored; the single power
+ *                      of x_n is that of DVR functions normalised with the
+ *                      radial measure x^2 dx (value 1 / (x_n sqrt(w_n)) at
+ *                      their own point), which are orthonormal, so no S^-1/2.
  */
 #include <math.h>
 #include <stdint.h>
@@ -239,6 +250,104 @@ int orc_radial_integral_orth(int nmax, int lmax, double rcut, double sigma, doub
     if (dIt) orth_apply(nmax, lmax, X, dI, dIt);
     free(X); free(I); free(dI);
     return st;
+}
+
+/* ---------------------------------------------------------------------- */
+/* DVR radial basis, Sec. 4.C Eq. (rad-int-dvr).                          */
+/* ---------------------------------------------------------------------- */
+/* Gauss-Legendre points t_k and weights w_k on [-1, 1]: the roots of P_n by
+ * Newton iteration from cos(pi (k - 1/4) / (n + 1/2)), P_n and P_n' from the
+ * three-term recurrence j P_j = (2j-1) t P_{j-1} - (j-1) P_{j-2},
+ * w = 2 / ((1 - t^2) P_n'(t)^2).  Ascending order.                       */
+void orc_gauss_legendre(int n, double* t, double* w)
+{
+    for (int k = 1; k <= n; ++k) {
+        double x = cos(ORC_PI * (k - 0.25) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            if (n == 0) p1 = 1.0;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            /* p1 = P_n(x), p0 = P_{n-1}(x) */
+            dp = (n == 1) ? 1.0 : n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = x;
+        for (int j = 2; j <= n; ++j) {
+            double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = (n == 1) ? 1.0 : n * (x * p1 - p0) / (x * x - 1.0);
+        t[n - k] = x;
+        w[n - k] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+/* Modified spherical Bessel function of the first kind by its defining
+ * power series,
+ *   i_l(z) = sum_k z^(l+2k) / (2^k k! (2l+2k+1)!!),
+ * each term from the previous one by z^2 / (2 (k+1) (2l+2k+3)) (all terms
+ * positive).  *d (nullable) receives d i_l / dz = sum_k (l+2k) z^(l+2k-1)
+ * / (2^k k! (2l+2k+1)!!).                                                */
+double orc_sph_bessel_i(int l, double z, double* d)
+{
+    double t = 1.0;
+    for (int k = 1; k <= l; ++k) t *= z / (2.0 * k + 1.0);   /* z^l / (2l+1)!! */
+    double sum = 0.0, dsum = 0.0;
+    for (int k = 0; k < 100000; ++k) {
+        sum += t;
+        if (d && z > 0.0) dsum += t * (l + 2.0 * k) / z;
+        double nt = t * z * z / (2.0 * (k + 1.0) * (2.0 * l + 2.0 * k + 3.0));
+        if (nt < 1e-17 * sum || nt == 0.0) break;
+        t = nt;
+    }
+    if (d) *d = (z > 0.0) ? dsum : (l == 1 ? 1.0 / 3.0 : 0.0);
+    return sum;
+}
+
+void orc_dvr_points(int nmax, double rcut, double sigma, double* x, double* w)
+{
+    double* t = (double*)malloc(sizeof(double) * nmax);
+    double* wt = (double*)malloc(sizeof(double) * nmax);
+    orc_gauss_legendre(nmax, t, wt);
+    double b = rcut + 3.0 * sigma;
+    for (int n = 0; n < nmax; ++n) {
+        x[n] = 0.5 * b * (t[n] + 1.0);
+        w[n] = 0.5 * b * wt[n];
+    }
+    free(t); free(wt);
+}
+
+/* I_nl(r) = 4 pi x_n sqrt(w_n) exp(-c (x_n^2 + r^2)) i_l(2 c x_n r) and
+ * d/dr, c = 1/(2 sigma^2) (the reading in the file header).  The Gaussian
+ * and Bessel factors are combined in logarithms (the Bessel factor grows
+ * like e^z).  Layout I[n*(lmax+1)+l].                                    */
+void orc_dvr_radial_integral(int nmax, int lmax, double rcut, double sigma, double r, double* I, double* dI)
+{
+    double x[64], w[64];
+    orc_dvr_points(nmax, rcut, sigma, x, w);
+    double c = 1.0 / (2.0 * sigma * sigma);
+    for (int n = 0; n < nmax; ++n) {
+        double z = 2.0 * c * x[n] * r;
+        double g = -c * (x[n] * x[n] + r * r);
+        double A = 4.0 * ORC_PI * x[n] * sqrt(w[n]);
+        for (int l = 0; l <= lmax; ++l) {
+            double di;
+            double bi = orc_sph_bessel_i(l, z, &di);
+            double v = (bi > 0.0) ? A * exp(g + log(bi)) : 0.0;
+            I[n * (lmax + 1) + l] = v;
+            if (dI) {
+                double dterm = (di > 0.0) ? A * exp(g + log(di)) * 2.0 * c * x[n] : 0.0;
+                dI[n * (lmax + 1) + l] = -2.0 * c * r * v + dterm;
+            }
+        }
+    }
 }
 
 /* ---------------------------------------------------------------------- */
@@ -477,19 +586,31 @@ int orc_neighbors(int n_struct, const int64_t* atom_offsets, const double* pos, 
 /* plus, with include_center, the central atom's r = 0 term in channel a_i */
 /* (only l = 0 survives at r = 0).  Layout c[centre][a][n][lm].            */
 /* ---------------------------------------------------------------------- */
+/* Radial basis: 0 = orthogonalised GTO (Sec. 4.B), 1 = DVR (Sec. 4.C). */
 typedef struct {
-    int S, nmax, lmax, include_center;
+    int S, nmax, lmax, include_center, basis;
     double rcut, width, sigma;
     double* X;
 } orc_ctx;
 
 static int ctx_init(orc_ctx* c, int S, int nmax, int lmax, int include_center, double rcut,
-                    double width, double sigma)
+                    double width, double sigma, int basis)
 {
     c->S = S; c->nmax = nmax; c->lmax = lmax; c->include_center = include_center;
-    c->rcut = rcut; c->width = width; c->sigma = sigma;
+    c->rcut = rcut; c->width = width; c->sigma = sigma; c->basis = basis;
     c->X = (double*)malloc(sizeof(double) * nmax * nmax);
+    if (basis == 1) {   /* DVR: orthonormal by construction */
+        for (int i = 0; i < nmax * nmax; ++i) c->X[i] = (i % (nmax + 1) == 0) ? 1.0 : 0.0;
+        return 0;
+    }
     return orc_orth_matrix(nmax, rcut, c->X);
+}
+
+/* raw radial integral of the context's basis */
+static void ctx_radial(const orc_ctx* c, double r, double* I, double* dI)
+{
+    if (c->basis == 1) orc_dvr_radial_integral(c->nmax, c->lmax, c->rcut, c->sigma, r, I, dI);
+    else orc_radial_integral(c->nmax, c->lmax, c->rcut, c->sigma, r, I, dI);
 }
 
 /* The per-pair radial and angular factors of one neighbour vector. */
@@ -501,7 +622,7 @@ static void pair_terms(const orc_ctx* c, const double* v, double* f, double* df,
     double* dI = (double*)malloc(sizeof(double) * nl);
     double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     *f = orc_fcut(r, c->rcut, c->width, df);
-    orc_radial_integral(c->nmax, c->lmax, c->rcut, c->sigma, r, I, dIt ? dI : NULL);
+    ctx_radial(c, r, I, dIt ? dI : NULL);
     orth_apply(c->nmax, c->lmax, c->X, I, It);
     if (dIt) orth_apply(c->nmax, c->lmax, c->X, dI, dIt);
     orc_ylm(c->lmax, v, Y, dY);
@@ -519,7 +640,7 @@ static void centre_coeffs(const orc_ctx* c, int64_t i, const int32_t* species,
     double* Y = (double*)malloc(sizeof(double) * L2);
     if (c->include_center) {
         double* I0 = (double*)malloc(sizeof(double) * nl);
-        orc_radial_integral(nmax, lmax, c->rcut, c->sigma, 0.0, I0, NULL);
+        ctx_radial(c, 0.0, I0, NULL);
         orth_apply(nmax, lmax, c->X, I0, It);
         double y00 = 1.0 / sqrt(4.0 * ORC_PI);
         for (int n = 0; n < nmax; ++n)
@@ -539,11 +660,11 @@ static void centre_coeffs(const orc_ctx* c, int64_t i, const int32_t* species,
 }
 
 int orc_expansion(int S, int nmax, int lmax, int include_center, double rcut, double width, double sigma,
-                  const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
+                  int basis, const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
                   const double* pair_vec, int64_t n_centres, const int64_t* centres, double* coeffs)
 {
     orc_ctx c;
-    int st = ctx_init(&c, S, nmax, lmax, include_center, rcut, width, sigma);
+    int st = ctx_init(&c, S, nmax, lmax, include_center, rcut, width, sigma, basis);
     int64_t blk = (int64_t)S * nmax * (lmax + 1) * (lmax + 1);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < n_centres; ++t)
@@ -613,12 +734,12 @@ static void contract_dp(int K, int lmax, const double* c, const double* dcfull, 
 }
 
 int orc_gradients(int S, int nmax, int lmax, int include_center, double rcut, double width, double sigma,
-                  const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
+                  int basis, const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
                   const double* pair_vec, int64_t n_centres, const int64_t* centres,
                   double* dc, double* dc_self, double* dp, double* dp_self)
 {
     orc_ctx c;
-    int st = ctx_init(&c, S, nmax, lmax, include_center, rcut, width, sigma);
+    int st = ctx_init(&c, S, nmax, lmax, include_center, rcut, width, sigma, basis);
     int K = S * nmax, L2 = (lmax + 1) * (lmax + 1), nl = nmax * (lmax + 1);
     int64_t KK = (int64_t)K * (K + 1) / 2;
     int64_t blk = (int64_t)nmax * L2;            /* one species block */
@@ -678,7 +799,7 @@ int orc_gradients(int S, int nmax, int lmax, int include_center, double rcut, do
 /* respect to the pair vector r_ji (the input of the virial, App. B).       */
 /* ---------------------------------------------------------------------- */
 int orc_vjp(int S, int nmax, int lmax, int include_center, double rcut, double width, double sigma,
-            int64_t n_atoms, const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
+            int basis, int64_t n_atoms, const int32_t* species, const int64_t* pair_offsets, const int32_t* pair_j,
             const double* pair_vec, const double* grad_p, double* grad_pos, double* grad_pair)
 {
     int K = S * nmax, L2 = (lmax + 1) * (lmax + 1);
@@ -694,7 +815,7 @@ int orc_vjp(int S, int nmax, int lmax, int include_center, double rcut, double w
         double* dcs = (double*)malloc(sizeof(double) * 3 * K * L2);
         double* dp = (double*)malloc(sizeof(double) * (np > 0 ? np : 1) * dprow);
         double* dps = (double*)malloc(sizeof(double) * dprow);
-        int st = orc_gradients(S, nmax, lmax, include_center, rcut, width, sigma, species, pair_offsets,
+        int st = orc_gradients(S, nmax, lmax, include_center, rcut, width, sigma, basis, species, pair_offsets,
                                pair_j, pair_vec, 1, &i, dc, dcs, dp, dps);
         if (st) {
 #pragma omp critical

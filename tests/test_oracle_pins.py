@@ -168,6 +168,112 @@ def test_radial_derivative_fd(r):
     assert np.abs(dIt - fdt).max() <= 1e-7 * max(1.0, np.abs(dIt).max())
 
 
+
+# --------------------------------------------------------------------- DVR
+@pytest.mark.parametrize("n", [1, 2, 5, 12, 40])
+def test_gauss_legendre_matches_numpy(n):
+    """The oracle's Newton iteration on P_n against numpy's Gauss-Legendre
+    rule."""
+    t, w = oracle.gauss_legendre(n)
+    tr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.abs(t - tr).max() <= 1e-14 and np.abs(w - wr).max() <= 1e-14
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 5, 8, 12])
+def test_sph_bessel_i_matches_scipy(l):
+    for z in [0.0, 1e-3, 0.4, 2.5, 11.0, 37.0, 120.0, 190.0]:
+        v, d = oracle.sph_bessel_i(l, z, deriv=True)
+        ref = special.spherical_in(l, z)
+        dref = special.spherical_in(l, z, derivative=True)
+        assert abs(v - ref) <= 1e-13 * max(abs(ref), 1e-300), (l, z)
+        assert abs(d - dref) <= 1e-13 * max(abs(dref), 1e-300) or (z == 0 and abs(d - dref) < 1e-15), (l, z)
+
+
+def test_dvr_points_map_to_the_interval():
+    x, w = oracle.dvr_points(7, 4.0, 0.5)
+    b = 4.0 + 1.5
+    t, wt = np.polynomial.legendre.leggauss(7)
+    assert np.allclose(x, 0.5 * b * (t + 1), rtol=1e-14) and np.allclose(w, 0.5 * b * wt, rtol=1e-14)
+    assert abs(w.sum() - b) <= 1e-13
+
+
+@pytest.mark.parametrize("r", [0.0, 0.6, 2.3, 3.9])
+def test_dvr_coefficients_by_angular_quadrature(r):
+    """Eq. (density-nlm) with the DVR basis, whose function n is
+    concentrated on the sphere |x| = x_n (value 1/(x_n sqrt(w_n)) there with
+    the radial measure x^2 dx): c_{n,lm} = x_n sqrt(w_n) times the plain
+    angular integral of Y_lm(x^) g(x_n x^ - r) over the sphere, done here by
+    Gauss-Legendre x trapezoid quadrature with scipy's harmonics -- the
+    Bessel function, 4 pi and exp(-c r^2) of Eq. rad-int-dvr come out of the
+    integral, not from the oracle."""
+    nmax, lmax, rcut, sigma = 6, 5, 4.0, 0.5
+    v = r * np.array([0.36, -0.48, 0.8])
+    x, w = np.polynomial.legendre.leggauss(nmax)
+    b = rcut + 3 * sigma
+    xn, wn = 0.5 * b * (x + 1), 0.5 * b * w
+    ct, wt = np.polynomial.legendre.leggauss(80)
+    nphi = 160
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    TH, PH = np.meshgrid(np.arccos(ct), phi, indexing="ij")
+    Yg = _scipy_real_ylm_grid(lmax, TH, PH)
+    dirs = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1)
+    wang = wt[:, None] * (2 * np.pi / nphi)
+    ref = np.zeros((nmax, (lmax + 1) ** 2))
+    for n in range(nmax):
+        g = np.exp(-np.sum((xn[n] * dirs - v) ** 2, -1) / (2 * sigma ** 2))
+        ref[n] = xn[n] * math.sqrt(wn[n]) * np.einsum("lij,ij->l", Yg, g * wang)
+    I = oracle.dvr_radial_integral(nmax, lmax, rcut, sigma, r)
+    Y = oracle.ylm(lmax, v if r > 0 else np.array([0.0, 0.0, 1.0]))
+    got = np.stack([np.concatenate([I[n, l] * Y[l * l:(l + 1) ** 2] for l in range(lmax + 1)])
+                    for n in range(nmax)])
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), np.abs(got - ref).max()
+
+
+@pytest.mark.parametrize("l", [0, 3, 6])
+def test_dvr_parseval(l):
+    """The DVR coefficients of the radial density component
+    f(x) = 4 pi exp(-c (x^2 + r^2)) i_l(2 c x r) carry its norm: as nmax
+    grows, sum_n I_nl(r)^2 -> int_0^b x^2 f(x)^2 dx (adaptive quadrature with
+    scipy's Bessel function).  A wrong power of x_n or a wrong prefactor
+    does not converge to it."""
+    rcut, sigma, r = 4.0, 0.5, 1.7
+    c = 1 / (2 * sigma ** 2)
+    b = rcut + 3 * sigma
+    f = lambda x: 4 * math.pi * math.exp(-c * (x * x + r * r)) * special.spherical_in(l, 2 * c * x * r)
+    ref = integrate.quad(lambda x: x * x * f(x) ** 2, 0, b, epsabs=0, epsrel=1e-13, limit=200)[0]
+    I = oracle.dvr_radial_integral(48, l, rcut, sigma, r)[:, l]
+    assert abs(np.sum(I ** 2) - ref) <= 1e-10 * ref
+
+
+@pytest.mark.parametrize("r", [0.05, 1.3, 2.8, 4.4])
+def test_dvr_radial_derivative_fd(r):
+    h = 1e-5
+    I, dI = oracle.dvr_radial_integral(7, 6, 5.0, 0.5, r, deriv=True)
+    fd = (oracle.dvr_radial_integral(7, 6, 5.0, 0.5, r + h) - oracle.dvr_radial_integral(7, 6, 5.0, 0.5, r - h)) / (2 * h)
+    assert np.abs(dI - fd).max() <= 1e-8 * max(1, np.abs(dI).max())
+
+
+def test_dvr_expansion_single_neighbour():
+    """With the DVR basis the oracle's expansion of one neighbour is
+    f I_nl(r) Y_lm(r^) and its spectrum is direction-free."""
+    hyp = dict(n_species=1, nmax=6, lmax=5, rcut=5.0, sigma=0.5, cutoff_width=0.5, include_center=0,
+               radial_basis=1)
+    ps = []
+    for v in [np.array([1.0, 2.0, -0.5]), np.array([0.0, 0.0, -math.sqrt(5.25)])]:
+        nl = oracle.Neighbors(np.array([0, 1], dtype=np.int64), np.array([1], dtype=np.int32),
+                              np.zeros((1, 3), dtype=np.int32), v[None, :].copy())
+        c = oracle.expansion(hyp, np.zeros(2, dtype=np.int32), nl, centres=[0])[0, 0]
+        r = np.linalg.norm(v)
+        f = oracle.fcut(r, 5.0, 0.5)[0]
+        I = oracle.dvr_radial_integral(6, 5, 5.0, 0.5, r)
+        Y = oracle.ylm(5, v)
+        for l in range(6):
+            assert np.allclose(c[:, l * l:(l + 1) ** 2], f * np.outer(I[:, l], Y[l * l:(l + 1) ** 2]),
+                               rtol=1e-14, atol=1e-16)
+        ps.append(oracle.power_spectrum(hyp, c[None, None])[0])
+    assert np.allclose(ps[0], ps[1], rtol=1e-12, atol=1e-15)
+
+
 # ------------------------------------------------------- harmonics
 def _scipy_real_ylm(lmax, v):
     r = np.linalg.norm(v)
@@ -492,17 +598,19 @@ def test_neighbors_periodic_bulk_and_clusters():
 
 
 # ---------------------------------------------------------- gradients
-def _small_periodic():
+def _small_periodic(basis=0):
     cell = np.array([[5.2, 0.0, 0.0], [0.8, 4.9, 0.0], [0.3, -0.6, 5.5]])
-    hyp = dict(n_species=2, nmax=4, lmax=4, rcut=4.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+    hyp = dict(n_species=2, nmax=4, lmax=4, rcut=4.0, sigma=0.5, cutoff_width=0.5, include_center=1,
+               radial_basis=basis)
     return synthetic.random_cell_structure(17, 5, cell, 2, min_sep=1.1, hypers=hyp)
 
 
-def test_gradient_rows_match_finite_differences():
+@pytest.mark.parametrize("basis", [0, 1])
+def test_gradient_rows_match_finite_differences(basis):
     """Sum of the rows tagged with atom k (pair rows of neighbour k, self
     row of centre k) equals the FD derivative of c_i and p_i when every
-    periodic image of k moves together (App. B)."""
-    b = _small_periodic()
+    periodic image of k moves together (App. B); GTO and DVR radial bases."""
+    b = _small_periodic(basis)
     h = b.hypers
     nl, c, p = oracle.features(b)
     dc, dcs, dp, dps = oracle.gradients(h, b.species, nl)
@@ -546,8 +654,9 @@ def test_gradient_rows_sum_to_zero():
         assert np.abs(tot).max() <= 1e-12 * max(1, np.abs(dp).max())
 
 
-def test_vjp_matches_finite_differences():
-    b = _small_periodic()
+@pytest.mark.parametrize("basis", [0, 1])
+def test_vjp_matches_finite_differences(basis):
+    b = _small_periodic(basis)
     h = b.hypers
     nl, c, p = oracle.features(b)
     W = np.random.default_rng(0).normal(size=p.shape)
