@@ -85,27 +85,65 @@ def algorithmic_bytes(N: int, P: int, S: int, nmax: int, lmax: int, es: int = 4)
     return centres, rows, fused
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batch, seconds: float):
     """The FP64 oracle, as it stands, on the host cores: the same step
-    (neighbours, expansion, power spectrum, every gradient row) repeated on
-    the whole workload until `seconds` have passed."""
+    (neighbours, expansion, power spectrum, every gradient row) on the whole
+    workload, from a -march=native build of the oracle's source made here.
+    Three samples with every thread and three with one thread (the paper's
+    code is serial), each repeating whole steps until its share of
+    `seconds` has passed; the medians are reported."""
+    import statistics
+    import tempfile
+
     import oracle
-    oracle.lib()
+    path = os.path.join(tempfile.mkdtemp(prefix="soap_oracle_"), "libsoap_oracle_native.so")
+    build = "gcc " + " ".join(oracle.FLAGS + ["-march=native"])
+    try:
+        oracle.build(path=path, native=True)
+        oracle.use_build(path)
+    except Exception as e:     # no gcc: the generic build that ships
+        log(f"[cpu_baseline] native build failed ({e}); timing the generic build")
+        build = "gcc " + " ".join(oracle.FLAGS)
+        oracle.use_build(oracle._LIB_PATH)
     h = batch.hypers
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        nl = oracle.neighbors(batch)
-        c = oracle.expansion(h, batch.species, nl)
-        oracle.power_spectrum(h, c)
-        oracle.gradients(h, batch.species, nl)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": batch.n_atoms * reps / el, "unit": "atom-centres/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{reps} full passes of the same 1024-atom step (neighbours, expansion, power spectrum, "
-                      f"all gradient rows) in FP64, {el:.1f} s"}
+    n_all = oracle.num_threads()
+
+    def sample(budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            nl = oracle.neighbors(batch)
+            c = oracle.expansion(h, batch.species, nl)
+            oracle.power_spectrum(h, c)
+            oracle.gradients(h, batch.species, nl)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return batch.n_atoms * reps / el, reps, el
+
+    multi = [sample(seconds / 6) for _ in range(3)]
+    oracle.set_num_threads(1)
+    single = [sample(seconds / 6) for _ in range(3)]
+    oracle.set_num_threads(n_all)
+    v_multi = statistics.median(m[0] for m in multi)
+    v_single = statistics.median(m[0] for m in single)
+    return {"value": v_multi, "unit": "atom-centres/s", "cores": n_all, "kind": "oracle",
+            "sample": f"median of 3 samples of whole 1024-atom steps (neighbours, expansion, power spectrum, all "
+                      f"gradient rows) in FP64 on {n_all} threads: "
+                      + ", ".join(f"{r} steps in {el:.1f} s" for _, r, el in multi),
+            "single_thread": {"value": v_single, "unit": "atom-centres/s", "cores": 1,
+                              "sample": "median of 3: " + ", ".join(f"{r} steps in {el:.1f} s" for _, r, el in single)},
+            "cpu_model": cpu_model(), "build": build}
 
 
 def run_compression(args) -> int:
@@ -312,7 +350,7 @@ def config_bytes(kind: str, N: int, P: int, S: int, nmax: int, lmax: int, es: in
     raise ValueError(kind)
 
 
-def run_config(args) -> int:
+def measure_config(wl: str, steps: int, warmup: int):
     """The parity workloads as timed steps (neighbours included, as in the
     headline step); each phase is timed with HIP events on the launch stream.
     clusters: 8 x 64-atom clusters, FP64 c and p.
@@ -333,7 +371,6 @@ def run_config(args) -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    wl = args.workload
     batch = {"clusters": synthetic.clusters_2species, "molecules": synthetic.molecule_batch,
              "liquid": synthetic.liquid_bulk, "gpr": synthetic.diamond_bulk}[wl]()
     if wl == "gpr":
@@ -364,7 +401,7 @@ def run_config(args) -> int:
         def ph_spectrum():
             state["p"] = calc.power_spectrum(state["c"], "bf16")
 
-        phases += [("expansion", ph_expansion, ("k_centres<float, 6, false, false, false>", "expansion")),
+        phases += [("expansion", ph_expansion, ("k_expansion_lanes<float, 6, false>", "expansion")),
                    ("spectrum_bf16_mfma", ph_spectrum, ("k_power_spectrum_bf16", "spectrum"))]
     else:
         out = calc.allocate_features(N, nl.capacity, td, dev, False)
@@ -372,8 +409,7 @@ def run_config(args) -> int:
         def ph_features():
             calc.features(nl, spc, td, out=out)
 
-        kname = "k_centres<double, -1, false, true, false>" if td == torch.float64 else \
-            f"k_centres<float, {lmax}, false, true, false>"
+        kname = f"k_expansion_lanes<{'double' if td == torch.float64 else 'float'}, {lmax}, true>"
         phases.append(("features", ph_features, (kname, "features")))
         if wl == "gpr":
             n_active, zeta = 2000, 4
@@ -403,18 +439,18 @@ def run_config(args) -> int:
 
             phases += [("spectrum_backward", ph_ps_backward, ("k_ps_backward<float>", "spectrum_backward")),
                        ("expansion_backward", ph_exp_backward,
-                        ("k_exp_backward_pairs + k_exp_backward_gather", "expansion_backward"))]
+                        ("k_exp_backward_lanes + k_exp_backward_gather", "expansion_backward"))]
             if wl == "gpr":
                 def ph_virial():
                     state["virial"] = calc.virial(nl, state["gpair"], ao)
 
                 phases.append(("virial", ph_virial, ("k_virial_centres + k_virial_structures", "virial")))
-    for _ in range(max(3, args.warmup)):
+    for _ in range(max(3, warmup)):
         for _, f, _ in phases:
             f()
     torch.cuda.synchronize()
     calc.reset_status()
-    K = args.steps
+    K = steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(K)]
     t_all0, t_all1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -429,7 +465,7 @@ def run_config(args) -> int:
     status = calc.device_status()
     if status != 0:
         log(f"device status {status}")
-        return 4
+        return None
     total_ms = t_all0.elapsed_time(t_all1)
     ph_ms = {name: float(np.median([e[j].elapsed_time(e[j + 1]) for e in ev])) for j, (name, _, _) in
              enumerate(phases)}
@@ -495,11 +531,85 @@ def run_config(args) -> int:
                                                     "gpr": "expansion + power spectrum + sparse model energies, "
                                                            "forces and virial)"}[wl],
         "value": N / (ms_per_step * 1e-3), "unit": "atom-centres/s", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if es == 8 else ("bf16" if wl == "molecules" else "f32"),
         "data": "synthetic",
         "config": {"workload": names[wl], "centres": N, "pairs": Pn, "phases_ms": ph_ms, "phases": rows},
         "roofline": roof,
+    }
+    return line
+
+
+def run_config(args) -> int:
+    line = measure_config(args.workload, args.steps, args.warmup)
+    if line is None:
+        return 4
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def run_radial(args) -> int:
+    """Cost of one radial-integral evaluation per radius (Sec. 4.D): the
+    pair distances of the 4096-atom liquid (rcut 6 A, sigma 0.5 A, nmax 10,
+    lmax 8, about 45 neighbours per atom) evaluated through
+    soap_radial_integral from the FP32 and FP64 splines the kernels use and
+    directly in FP64, for the orthogonalised GTO basis (restricted 1F1 and
+    S^{-1/2}) and for the DVR basis (modified spherical Bessel functions).
+    Values and derivatives are written, [nmax][lmax+1][n_r]."""
+    import torch
+
+    import synthetic
+    import paper_2101_08814_amd as P
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    batch = synthetic.liquid_bulk()
+    h = batch.hypers
+    gto = P.Calculator.from_hypers(h)
+    dvr = P.Calculator.from_hypers(dict(h, radial_basis=1))
+    pos = torch.tensor(batch.positions, dtype=torch.float64, device=dev)
+    spc = torch.tensor(batch.species, dtype=torch.int32, device=dev)
+    ao, ce, pb = P.soap.structures_to_device(batch.atom_offsets, batch.cells, batch.pbc, dev)
+    nl = gto.compute_neighbors(pos, spc, ao, ce, pb, vec_dtype=torch.float64, transpose=False)
+    n_r = nl.count()
+    r = nl.pair_vec[:n_r].norm(dim=1).contiguous()
+    nlm = gto.nmax * (gto.lmax + 1)
+    cases = [("spline_f32", gto, False, torch.float32), ("spline_f64", gto, False, torch.float64),
+             ("direct_gto_f64", gto, True, torch.float64), ("direct_dvr_f64", dvr, True, torch.float64)]
+    steps = max(1, min(args.steps, 50))
+    ms = {}
+    for name, calc, exact, dt in cases:
+        def f():
+            return calc.radial_integral(r, exact=exact, dtype=dt)
+        for _ in range(max(2, min(args.warmup, 10))):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / steps
+        if calc.device_status() != 0:
+            log(f"device status {calc.device_status()} in {name}")
+            return 4
+    ns = {k: v * 1e6 / n_r for k, v in ms.items()}
+    log("[bench:radial] n_r=%d " % n_r + " ".join(f"{k}={v:.3f} ms ({ns[k]:.3f} ns/radius)" for k, v in ms.items()))
+    out_bytes = 2 * nlm * 4 * n_r + 8 * n_r
+    gbs = out_bytes / (ms["spline_f32"] * 1e-3) / 1e9
+    line = {
+        "metric": "radii/s (FP32 spline, nmax x (lmax+1) values and derivatives per radius)",
+        "value": n_r / (ms["spline_f32"] * 1e-3), "unit": "radii/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms["spline_f32"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "pair distances of the 4096-atom periodic liquid (0.05 atoms/A^3, rcut 6 A, "
+                               "sigma 0.5 A, nmax 10, lmax 8)",
+                   "radii": n_r, "ms": ms, "ns_per_radius": ns,
+                   "direct_over_spline": {k: ms[k] / ms["spline_f64"] for k in ("direct_gto_f64", "direct_dvr_f64")}},
+        "roofline": {"bound": "hbm", "kernel": "k_radial_spline<float, 8>", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel_ms": ms["spline_f32"],
+                     "algorithmic_bytes_per_launch": out_bytes},
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -518,12 +628,16 @@ def main() -> int:
                     "(the reference kernel for scaling memory counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the sub-records of the clusters, molecules "
+                    "and liquid workloads in the headline line")
+    ap.add_argument("--config-steps", type=int, default=200, help="timed steps of each sub-record workload")
     ap.add_argument("--workload", choices=["diamond", "clusters", "molecules", "liquid", "gpr", "selected",
-                                           "compression"],
+                                           "compression", "radial"],
                     default="diamond",
                     help="diamond: the headline step (default); clusters, molecules, liquid: the FP64, MFMA and "
                          "adjoint parity workloads as timed steps; compression: the learned channel compression "
-                         "of the 8-species cells, trained and timed against the full power spectrum")
+                         "of the 8-species cells, trained and timed against the full power spectrum; radial: the cost per "
+                         "radius of the splined and the directly evaluated radial integrals")
     ap.add_argument("--train-steps", type=int, default=600)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -542,6 +656,8 @@ def main() -> int:
         return run_selected(args)
     if args.workload == "compression":
         return run_compression(args)
+    if args.workload == "radial":
+        return run_radial(args)
     if args.workload in ("clusters", "molecules", "liquid", "gpr"):
         return run_config(args)
     torch.cuda.set_device(0)
@@ -687,6 +803,21 @@ def main() -> int:
             "algorithmic_bytes_per_launch": alg,
         },
     }
+    if not args.no_configs:
+        # the other single-GPU parity workloads as sub-records: each its own
+        # timed steps (neighbours included) and its dominant kernel against
+        # its roofline
+        subs = {}
+        for wl in ("clusters", "molecules", "liquid"):
+            sub = measure_config(wl, args.config_steps, 5)
+            if sub is None:
+                return 4
+            subs[wl] = {"workload": sub["config"]["workload"], "metric": sub["metric"], "value": sub["value"],
+                        "unit": sub["unit"], "dtype": sub["dtype"], "steps": sub["steps"],
+                        "ms_per_step": sub["ms_per_step"], "centres": sub["config"]["centres"],
+                        "pairs": sub["config"]["pairs"], "phases_ms": sub["config"]["phases_ms"],
+                        "roofline": sub["roofline"]}
+        line["configs"] = subs
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(line), flush=True)

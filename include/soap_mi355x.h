@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define SOAP_ABI_VERSION 1
+#define SOAP_ABI_VERSION 2
 
 typedef enum {
     SOAP_OK = 0,
@@ -71,13 +71,33 @@ typedef enum {
     SOAP_ESPECIES = -7       /* species index outside [0, n_species)          */
 } soap_status;
 
-typedef enum { SOAP_F64 = 0, SOAP_F32 = 1, SOAP_BF16_F32ACC = 2 } soap_precision;
+/* The two _RANGE_ members are not precisions: they give the type the range
+ * of int32_t, so that an invalid value from a caller is a defined value the
+ * library rejects with SOAP_EINVAL. */
+typedef enum {
+    SOAP_F64 = 0,
+    SOAP_F32 = 1,
+    SOAP_BF16_F32ACC = 2,
+    SOAP_PRECISION_RANGE_MIN_ = -2147483647 - 1,
+    SOAP_PRECISION_RANGE_MAX_ = 2147483647
+} soap_precision;
+
+/* Radial basis (Sec. 4.B, 4.C). */
+typedef enum {
+    SOAP_RADIAL_GTO = 0,   /* GTOs orthogonalised with S^{-1/2} (Eq. GTO)   */
+    SOAP_RADIAL_DVR = 1    /* DVR on the nmax Gauss-Legendre points of
+                              [0, rcut + 3 sigma] (Eq. rad-int-dvr, with the
+                              factor 4 pi exp(-c r^2) of the Gaussian-density
+                              radial integral; orthonormal)                 */
+} soap_radial_basis;
 
 /* Hyper-parameters (Sec. 3 and 4: species, rcut, smoothing, sigma, nmax,
- * lmax).  Limits: 1 <= n_species <= 64, 1 <= nmax <= 16, 0 <= lmax <= 12,
- * rcut > 0, 0 < cutoff_width <= rcut, sigma > 0, include_center in {0, 1}
- * (1: the central atom adds its own r = 0 term, l = 0 only, to channel
- * a_i), 0 < spline_accuracy (the paper uses 1e-8, Fig. ri-qm9 caption). */
+ * lmax, radial basis).  Limits: 1 <= n_species <= 64, 1 <= nmax <= 16,
+ * 0 <= lmax <= 12, rcut > 0, 0 < cutoff_width <= rcut, sigma > 0,
+ * include_center in {0, 1} (1: the central atom adds its own r = 0 term,
+ * l = 0 only, to channel a_i), 0 < spline_accuracy (the paper uses 1e-8,
+ * Fig. ri-qm9 caption), radial_basis a soap_radial_basis.  Either basis is
+ * tabulated as the same cubic spline, so every kernel runs unchanged. */
 typedef struct {
     int32_t n_species;
     int32_t nmax;
@@ -87,6 +107,8 @@ typedef struct {
     double cutoff_width;
     double sigma;
     double spline_accuracy;
+    int32_t radial_basis;
+    int32_t reserved;      /* 0 */
 } soap_hypers;
 
 /* Facts about a calculator's spline table (host). */
@@ -132,6 +154,20 @@ soap_status soap_calculator_upload(const soap_calculator* calc);
  * [n_r][nmax][lmax+1] [host]; dI may be NULL. */
 soap_status soap_radial_integral_host(const soap_calculator* calc, int32_t exact, int64_t n_r,
                                       const double* r, double* I, double* dI);
+
+/* The radial integrals I~_nl(r_k) and d/dr on the device for n_r radii
+ * (the per-neighbour step the expansion performs, Sec. 4.B-4.D), either
+ * from the spline the kernels use (exact = 0) or evaluated directly per
+ * radius (exact = 1): for the GTO basis the restricted 1F1 of App. A
+ * (series or asymptotic form at the two largest l, the downward recurrence
+ * for the others) and S^{-1/2}; for the DVR basis the closed form with the
+ * modified spherical Bessel function.  For comparing the cost of the three
+ * evaluations (Sec. 4.D, Fig. ri-qm9) and checking the table.
+ * r [n_r] double, device, in [0, rcut].  I and dI (dI may be NULL) are
+ * device arrays [nmax][lmax+1][n_r] (radius fastest) of double (SOAP_F64)
+ * or float (SOAP_F32; spline only: the direct path is SOAP_F64).        */
+soap_status soap_radial_integral(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                 int32_t exact, int64_t n_r, const double* r, void* I, void* dI);
 
 /* Device bytes of scratch soap_compute_neighbors needs for n_structures
  * structures holding n_atoms atoms in total (independent of positions and

@@ -9,11 +9,14 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsoap_mi355x.so")
+# another build of the same sources (for example one with host-side
+# sanitizers) can be named in SOAP_MI355X_LIBRARY
+LIB_PATH = os.environ.get("SOAP_MI355X_LIBRARY") or os.path.join(HERE, "libsoap_mi355x.so")
 
 SOAP_OK, SOAP_EINVAL, SOAP_ECAPACITY, SOAP_EDEVICE = 0, -1, -2, -3
 SOAP_ENOMEM, SOAP_EUNSUPPORTED, SOAP_EGEOMETRY, SOAP_ESPECIES = -4, -5, -6, -7
 SOAP_F64, SOAP_F32, SOAP_BF16_F32ACC = 0, 1, 2
+SOAP_RADIAL_GTO, SOAP_RADIAL_DVR = 0, 1
 
 STATUS_NAMES = {0: "SOAP_OK", -1: "SOAP_EINVAL", -2: "SOAP_ECAPACITY", -3: "SOAP_EDEVICE",
                 -4: "SOAP_ENOMEM", -5: "SOAP_EUNSUPPORTED", -6: "SOAP_EGEOMETRY", -7: "SOAP_ESPECIES"}
@@ -21,7 +24,7 @@ STATUS_NAMES = {0: "SOAP_OK", -1: "SOAP_EINVAL", -2: "SOAP_ECAPACITY", -3: "SOAP
 # every symbol the header declares
 EXPORTS = [
     "soap_abi_version", "soap_last_error", "soap_calculator_create", "soap_calculator_destroy",
-    "soap_calculator_info", "soap_calculator_upload", "soap_radial_integral_host",
+    "soap_calculator_info", "soap_calculator_upload", "soap_radial_integral_host", "soap_radial_integral",
     "soap_neighbors_workspace_size", "soap_compute_neighbors", "soap_compute_neighbors_noalloc",
     "soap_spherical_expansion",
     "soap_power_spectrum", "soap_features", "soap_gradient_rows", "soap_power_spectrum_backward",
@@ -36,7 +39,8 @@ EXPORTS = [
 class soap_hypers(ctypes.Structure):
     _fields_ = [("n_species", ctypes.c_int32), ("nmax", ctypes.c_int32), ("lmax", ctypes.c_int32),
                 ("include_center", ctypes.c_int32), ("rcut", ctypes.c_double), ("cutoff_width", ctypes.c_double),
-                ("sigma", ctypes.c_double), ("spline_accuracy", ctypes.c_double)]
+                ("sigma", ctypes.c_double), ("spline_accuracy", ctypes.c_double), ("radial_basis", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class soap_table_info(ctypes.Structure):
@@ -80,6 +84,8 @@ def lib():
     L.soap_calculator_upload.argtypes = [vp]
     L.soap_radial_integral_host.restype = st
     L.soap_radial_integral_host.argtypes = [vp, i32, i64, vp, vp, vp]
+    L.soap_radial_integral.restype = st
+    L.soap_radial_integral.argtypes = [vp, P(soap_exec), st, i32, i64, vp, vp, vp]
     L.soap_neighbors_workspace_size.restype = st
     L.soap_neighbors_workspace_size.argtypes = [vp, i32, i64, P(ctypes.c_size_t)]
     L.soap_compute_neighbors.restype = st

@@ -103,6 +103,34 @@ soap_status device_tables(const soap_calculator* calc, const DeviceTables** out)
                 hipSuccess)
                 return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
         }
+        {
+            // constants of the direct radial integral, packed in one array
+            const ExactRadial& e = calc->exact;
+            const int nmx = e.nmax, lm1e = e.lmax + 1;
+            std::vector<double> pack;
+            size_t o_alpha = 0, o_pref = 0, o_top = 0, o_X = 0, o_x = 0, o_A = 0;
+            if (e.basis == SOAP_RADIAL_DVR) {
+                o_x = pack.size(); pack.insert(pack.end(), e.x.begin(), e.x.end());
+                o_A = pack.size(); pack.insert(pack.end(), e.A.begin(), e.A.end());
+            } else {
+                o_alpha = pack.size(); pack.insert(pack.end(), e.alpha.begin(), e.alpha.end());
+                o_pref = pack.size(); pack.insert(pack.end(), e.pref.begin(), e.pref.end());
+                o_top = pack.size();
+                for (const rad::GParams& g : e.top) {
+                    pack.push_back(g.a); pack.push_back(g.b); pack.push_back(g.lgr); pack.push_back(g.zswitch);
+                }
+                o_X = pack.size(); pack.insert(pack.end(), e.X.begin(), e.X.end());
+            }
+            if (pack.empty()) pack.push_back(0.0);
+            if (hipMalloc(&t.exact, pack.size() * sizeof(double)) != hipSuccess)
+                return fail(SOAP_ENOMEM, "allocation of the spline tables failed on device %d", dev);
+            if (hipMemcpy(t.exact, pack.data(), pack.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                return fail(SOAP_EDEVICE, "upload of the spline tables failed on device %d", dev);
+            t.gto = rad::GtoTables{nmx, e.c, t.exact + o_alpha, t.exact + o_pref,
+                                   reinterpret_cast<const rad::GParams*>(t.exact + o_top), t.exact + o_X};
+            t.dvr = rad::DvrTables{nmx, e.c, t.exact + o_x, t.exact + o_A};
+            (void)lm1e;
+        }
         t.ready = true;
     }
     *out = &t;
@@ -297,6 +325,9 @@ soap_status soap_calculator_create(const soap_hypers* h, soap_calculator** out)
     REQUIRE(std::isfinite(h->sigma) && h->sigma > 0, "sigma must be > 0");
     REQUIRE(h->include_center == 0 || h->include_center == 1, "include_center must be 0 or 1");
     REQUIRE(std::isfinite(h->spline_accuracy) && h->spline_accuracy > 0, "spline_accuracy must be > 0");
+    REQUIRE(h->radial_basis == SOAP_RADIAL_GTO || h->radial_basis == SOAP_RADIAL_DVR,
+            "radial_basis must be SOAP_RADIAL_GTO or SOAP_RADIAL_DVR (got %d)", h->radial_basis);
+    REQUIRE(h->reserved == 0, "reserved must be 0");
     if (alloc_failure_forced()) return fail(SOAP_ENOMEM, "allocation failure forced by SOAP_FAIL_ALLOC");
     soap_calculator* c = new (std::nothrow) soap_calculator();
     if (!c) return fail(SOAP_ENOMEM, "out of host memory");
@@ -332,6 +363,7 @@ soap_status soap_calculator_destroy(soap_calculator* calc)
         (void)hipFree(t.center32);
         (void)hipFree(t.dp_pos);
         (void)hipFree(t.radial_dst);
+        (void)hipFree(t.exact);
     }
     if (have) (void)hipSetDevice(cur);
     delete calc;
@@ -374,6 +406,39 @@ soap_status soap_radial_integral_host(const soap_calculator* calc, int32_t exact
         for (int64_t k = 0; k < n_r; ++k) radial_spline_host(calc, r[k], I + k * nl, dI ? dI + k * nl : nullptr);
     }
     return SOAP_OK;
+}
+
+soap_status soap_radial_integral(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                 int32_t exact, int64_t n_r, const double* r, void* I, void* dI)
+{
+    clear_error();
+    CHECK(check_calc(calc));
+    REQUIRE(precision == SOAP_F64 || precision == SOAP_F32, "precision must be SOAP_F64 or SOAP_F32");
+    REQUIRE(exact == 0 || exact == 1, "exact must be 0 or 1");
+    REQUIRE(!(exact && precision != SOAP_F64), "the direct evaluation is SOAP_F64 only");
+    REQUIRE(n_r >= 0 && n_r < (int64_t(1) << 31), "n_r must be in [0, 2^31)");
+    if (n_r == 0) return SOAP_OK;
+    const size_t es = elem_size(precision);
+    CHECK(check_ptr(r, 8, "r"));
+    CHECK(check_ptr(I, es, "I"));
+    CHECK(check_ptr(dI, es, "dI", true));
+    const DeviceTables* t = nullptr;
+    CHECK(device_tables(calc, &t));
+    RadialArgs a{};
+    a.nmax = calc->h.nmax;
+    a.lmax = calc->h.lmax;
+    a.basis = calc->h.radial_basis;
+    a.exact = exact != 0;
+    a.M = calc->M;
+    a.inv_delta = calc->inv_delta;
+    a.coef = precision == SOAP_F64 ? static_cast<const void*>(t->coef64) : static_cast<const void*>(t->coef32);
+    a.gto = t->gto;
+    a.dvr = t->dvr;
+    a.n_r = n_r;
+    a.r = r;
+    a.I = I;
+    a.dI = dI;
+    return launched(launch_radial(a, precision == SOAP_F64, stream_of(exec)), "radial integral");
 }
 
 soap_status soap_neighbors_workspace_size(const soap_calculator* calc, int32_t n_structures, int64_t n_atoms,

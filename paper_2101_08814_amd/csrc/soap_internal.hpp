@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "radial_exact.hpp"
 #include "soap_mi355x.h"
 
 namespace soap {
@@ -25,6 +26,9 @@ struct DeviceTables {
     int32_t* dp_pos = nullptr;   // [lmax+1][K(K+1)/2]: l | k1 << 4 | k2 << 14 of each dp row position
     int32_t* radial_dst = nullptr; // [nl + 16]: LDS offset l np + n of radial value j = l nmax + n
                                    // (np = nmax rounded up to 4; entries past nl repeat the last)
+    double* exact = nullptr;       // constants of the direct radial integral (see ExactRadial)
+    rad::GtoTables gto{};          // views into `exact` (device pointers)
+    rad::DvrTables dvr{};
 };
 
 // Geometry of one structure for the neighbour search (built on the device
@@ -41,6 +45,17 @@ struct StructGeom {
     int64_t pad1;
 };
 
+// Constants of the direct (unsplined) radial integral of a calculator: GTO
+// (alpha, pref, the four restricted 1F1 of the top degrees per n, S^-1/2)
+// or DVR (points x and amplitudes A = 4 pi x sqrt(w)).
+struct ExactRadial {
+    int basis = 0, nmax = 0, lmax = 0;
+    double c = 0.0;
+    std::vector<double> alpha, pref, X;
+    std::vector<rad::GParams> top;
+    std::vector<double> x, A;
+};
+
 }  // namespace soap
 
 struct soap_calculator {
@@ -52,7 +67,8 @@ struct soap_calculator {
     std::vector<double> coef64;       // host copy of the FP64 table
     std::vector<float> coef32;
     std::vector<double> center;       // [nmax] centre terms, then [L2] K_lm
-    std::vector<double> orth;         // S^{-1/2}, [nmax][nmax]
+    std::vector<double> orth;         // S^{-1/2}, [nmax][nmax] (identity for DVR)
+    soap::ExactRadial exact;          // constants of the direct radial integral
     soap_table_info info{};
     mutable std::mutex mu;
     mutable std::vector<soap::DeviceTables> dev;
@@ -68,6 +84,8 @@ bool alloc_failure_forced();   // SOAP_FAIL_ALLOC=1 in the environment
 // tables.cpp
 soap_status build_tables(soap_calculator* calc);
 void radial_exact(const soap_calculator* calc, int64_t n, const double* r, double* I, double* dI);
+void build_exact_radial(const soap_hypers& h, const std::vector<double>& orth, ExactRadial& e);
+void exact_radial_eval(const ExactRadial& e, double r, double* I, double* dI);
 void radial_spline_host(const soap_calculator* calc, double r, double* I, double* dI);
 soap_status device_tables(const soap_calculator* calc, const DeviceTables** out);
 // symmetric eigen-decomposition A = Q diag(w) Q^T of a small dense matrix
@@ -101,6 +119,22 @@ struct FeatureArgs {
 };
 
 hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream);
+
+// radial integrals of a batch of radii on the device (spline or direct)
+struct RadialArgs {
+    int nmax, lmax, basis;
+    bool exact;
+    int64_t M;
+    double inv_delta;
+    const void* coef;         // spline table [M][nl][4] of the output precision
+    rad::GtoTables gto;
+    rad::DvrTables dvr;
+    int64_t n_r;
+    const double* r;
+    void* I;
+    void* dI;
+};
+hipError_t launch_radial(const RadialArgs& a, bool f64, hipStream_t stream);
 
 // Per-wave LDS layout of the one-lane-per-pair expansion (elements of T):
 // ch pairs of radial rows [lmax+1][np] and harmonic rows [l2s], and the

@@ -10,6 +10,10 @@
 //           bisection, the large-z asymptotic expansion above it) and by the
 //           two-step downward recurrence in l for the rest; dG/dr from G at
 //           (a+1, b+1).
+// Sec. 4.C: DVR radial basis (radial_basis = 1): Gauss-Legendre points of
+//           [0, rcut + 3 sigma] by the Golub-Welsch method (eigenvalues of the
+//           Jacobi matrix of the Legendre recurrence), the radial integral in
+//           the closed form of radial_exact.hpp; orthonormal, so no S^{-1/2}.
 // Sec. 4.D: the orthogonalised radial integral tabulated on a uniform grid
 //           over [0, rcut] and interpolated by a cubic spline (clamped with
 //           the exact end derivatives).  The grid is doubled, from 1024
@@ -20,8 +24,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
+#include "radial_exact.hpp"
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -78,38 +84,14 @@ public:
         }
     }
     double zswitch() const { return zswitch_; }
-    double operator()(double r) const
-    {
-        double z = alpha_ * r * r;
-        if (z < zswitch_) return std::exp(lgr_ - c_ * r * r) * series(z);
-        // exp(z - c r^2) z^(a-b) sum_s (b-a)_s (1-a)_s / s! z^-s; the
-        // Gamma ratio of the asymptotic form cancels the one in G.
-        return std::exp(z - c_ * r * r + (a_ - b_) * std::log(z)) * asym_sum(z);
-    }
+    // series below the switch point, exp(z - c r^2) z^(a-b) sum_s
+    // (b-a)_s (1-a)_s / s! z^-s above it (the Gamma ratio of the asymptotic
+    // form cancels the one in G)
+    rad::GParams params() const { return rad::GParams{a_, b_, lgr_, zswitch_}; }
 
 private:
-    double series(double z) const
-    {
-        double term = 1.0, sum = 1.0;
-        for (int s = 1; s < 100000; ++s) {
-            term *= (a_ + s - 1) * z / ((b_ + s - 1) * s);
-            sum += term;
-            if (term < 1e-17 * sum) break;
-        }
-        return sum;
-    }
-    double asym_sum(double z) const
-    {
-        double term = 1.0, sum = 1.0, prev = 1e300;
-        for (int s = 1; s < 1000; ++s) {
-            term *= (b_ - a_ + s - 1) * (1.0 - a_ + s - 1) / (s * z);
-            if (std::fabs(term) >= prev || term == 0.0) break;   // divergent tail starts
-            sum += term;
-            prev = std::fabs(term);
-            if (prev < 1e-17 * std::fabs(sum)) break;
-        }
-        return sum;
-    }
+    double series(double z) const { return rad::hyp1f1_series(a_, b_, z); }
+    double asym_sum(double z) const { return rad::hyp1f1_asym_sum(a_, b_, z); }
     bool agree(double z) const
     {
         if (z <= 0) return false;
@@ -121,88 +103,125 @@ private:
     double a_, b_, c_, alpha_, lgr_, zswitch_;
 };
 
-struct RadialExact {
-    int nmax, lmax;
-    double c;
-    Gto gto;
-    std::vector<double> alpha, pref;          // per n: alpha_n; per (n,l): prefactor
-    std::vector<GFunction> top;               // per n: G and H at l = lmax, lmax-1
-    std::vector<double> X;                    // S^{-1/2}
+// lmax as a template parameter for the shared direct evaluation
+template <typename F>
+void with_degree(int lmax, F&& f)
+{
+    switch (lmax) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    case 11: f(std::integral_constant<int, 11>{}); break;
+    default: f(std::integral_constant<int, 12>{}); break;
+    }
+}
 
-    RadialExact(const soap_hypers& h, const std::vector<double>& orth)
-        : nmax(h.nmax), lmax(h.lmax), c(0.5 / (h.sigma * h.sigma)), gto(h.nmax, h.rcut), X(orth)
-    {
-        alpha.resize(nmax);
-        pref.resize(nmax * (lmax + 1));
-        for (int n = 0; n < nmax; ++n) {
-            alpha[n] = c * c / (c + gto.d[n]);
-            for (int l = 0; l <= lmax; ++l) {
-                double a = 0.5 * (n + l + 3);
-                // pi^{3/2} N_n c^l (c + d_n)^{-a}
-                pref[n * (lmax + 1) + l] = std::pow(kPi, 1.5) * gto.norm[n] *
-                                           std::exp(l * std::log(c) - a * std::log(c + gto.d[n]));
+}  // namespace
+
+// Constants of the direct evaluation of either basis (also uploaded for the
+// device's direct path).
+void build_exact_radial(const soap_hypers& h, const std::vector<double>& orth, ExactRadial& e)
+{
+    const int nmax = h.nmax, lmax = h.lmax;
+    e.basis = h.radial_basis;
+    e.nmax = nmax;
+    e.lmax = lmax;
+    e.c = 0.5 / (h.sigma * h.sigma);
+    if (h.radial_basis == 1) {
+        // Golub-Welsch: the Gauss-Legendre points are the eigenvalues of the
+        // symmetric Jacobi matrix with off-diagonal k / sqrt(4 k^2 - 1), the
+        // weights 2 (first eigenvector component)^2
+        std::vector<double> J(nmax * nmax, 0.0), w, Q;
+        for (int k = 1; k < nmax; ++k) J[(k - 1) * nmax + k] = J[k * nmax + k - 1] = k / std::sqrt(4.0 * k * k - 1.0);
+        sym_eigen(nmax, J, w, Q);
+        std::vector<int> order(nmax);
+        for (int i = 0; i < nmax; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return w[x] < w[y]; });
+        const double bmax = h.rcut + 3.0 * h.sigma;
+        e.x.resize(nmax);
+        e.A.resize(nmax);
+        for (int i = 0; i < nmax; ++i) {
+            const int k = order[i];
+            const double t = nmax == 1 ? 0.0 : w[k];
+            const double wt = nmax == 1 ? 2.0 : 2.0 * Q[0 * nmax + k] * Q[0 * nmax + k];
+            e.x[i] = 0.5 * bmax * (t + 1.0);
+            const double wn = 0.5 * bmax * wt;
+            e.A[i] = 4.0 * kPi * e.x[i] * std::sqrt(wn);
+        }
+        return;
+    }
+    Gto gto(nmax, h.rcut);
+    e.alpha.resize(nmax);
+    e.pref.resize(nmax * (lmax + 1));
+    e.top.clear();
+    for (int n = 0; n < nmax; ++n) {
+        e.alpha[n] = e.c * e.c / (e.c + gto.d[n]);
+        for (int l = 0; l <= lmax; ++l) {
+            double a = 0.5 * (n + l + 3);
+            // pi^{3/2} N_n c^l (c + d_n)^{-a}
+            e.pref[n * (lmax + 1) + l] = std::pow(kPi, 1.5) * gto.norm[n] *
+                                         std::exp(l * std::log(e.c) - a * std::log(e.c + gto.d[n]));
+        }
+        for (int L = lmax; L >= lmax - 1; --L) {
+            if (L < 0) {   // lmax = 0: unused slots
+                e.top.push_back(rad::GParams{1.0, 1.0, 0.0, 0.0});
+                e.top.push_back(rad::GParams{1.0, 1.0, 0.0, 0.0});
+                continue;
             }
-            for (int L = lmax; L >= std::max(0, lmax - 1); --L) {
-                double a = 0.5 * (n + L + 3), b = L + 1.5;
-                top.emplace_back(a, b, c, alpha[n]);              // G(a, b)
-                top.emplace_back(a + 1, b + 1, c, alpha[n]);      // H = G(a+1, b+1)
-            }
+            double a = 0.5 * (n + L + 3), b = L + 1.5;
+            e.top.push_back(GFunction(a, b, e.c, e.alpha[n]).params());           // G(a, b)
+            e.top.push_back(GFunction(a + 1, b + 1, e.c, e.alpha[n]).params());   // H = G(a+1, b+1)
         }
     }
+    e.X = orth;
+}
 
-    // raw (non-orthogonal) I_nl(r) and dI_nl/dr
-    void raw(double r, double* I, double* dI) const
-    {
-        int per_n = (lmax >= 1) ? 4 : 2;
-        std::vector<double> G(lmax + 3), H(lmax + 3);
-        for (int n = 0; n < nmax; ++n) {
-            double z = alpha[n] * r * r;
-            const GFunction* t = &top[n * per_n];
-            G[lmax] = t[0](r);
-            H[lmax] = t[1](r);
-            if (lmax >= 1) {
-                G[lmax - 1] = t[2](r);
-                H[lmax - 1] = t[3](r);
-            }
-            // two-step downward recurrence (App. A Eq. 1f1-recurrence):
-            //   H_l = z H_{l+2} + (b_l + 1) G_{l+2}
-            //   G_l = z (a - b)/a G_{l+2} + (b/a) H_l
-            for (int l = lmax - 2; l >= 0; --l) {
-                double a = 0.5 * (n + l + 3), b = l + 1.5;
-                H[l] = z * H[l + 2] + (b + 1) * G[l + 2];
-                G[l] = z * (a - b) / a * G[l + 2] + (b / a) * H[l];
-            }
-            for (int l = 0; l <= lmax; ++l) {
-                double P = pref[n * (lmax + 1) + l];
-                double rl = (l == 0) ? 1.0 : std::pow(r, l);
-                I[n * (lmax + 1) + l] = P * rl * G[l];
-                if (dI) {
-                    // dG/dr = 2 alpha r H - 2 c r G
-                    double dG = 2.0 * alpha[n] * r * H[l] - 2.0 * c * r * G[l];
-                    double drl = (l == 0) ? 0.0 : (l == 1 ? 1.0 : l * std::pow(r, l - 1));
-                    dI[n * (lmax + 1) + l] = P * (drl * G[l] + rl * dG);
+// I~_nl(r) and d/dr [nmax][lmax+1] (dI may be NULL)
+void exact_radial_eval(const ExactRadial& e, double r, double* I, double* dI)
+{
+    const int nmax = e.nmax, lm1 = e.lmax + 1;
+    std::vector<double> tI(lm1), tdI(lm1);
+    if (e.basis == 1) {
+        rad::DvrTables t{nmax, e.c, e.x.data(), e.A.data()};
+        with_degree(e.lmax, [&](auto Lc) {
+            constexpr int L = decltype(Lc)::value;
+            for (int n = 0; n < nmax; ++n) {
+                rad::dvr_n<L>(t, n, r, tI.data(), tdI.data());
+                for (int l = 0; l < lm1; ++l) {
+                    I[n * lm1 + l] = tI[l];
+                    if (dI) dI[n * lm1 + l] = tdI[l];
                 }
             }
+        });
+        return;
+    }
+    rad::GtoTables t{nmax, e.c, e.alpha.data(), e.pref.data(), e.top.data(), e.X.data()};
+    std::vector<double> raw(nmax * lm1), draw(nmax * lm1);
+    with_degree(e.lmax, [&](auto Lc) {
+        constexpr int L = decltype(Lc)::value;
+        for (int n = 0; n < nmax; ++n) rad::gto_raw_n<L>(t, n, r, &raw[n * lm1], &draw[n * lm1]);
+    });
+    for (int n = 0; n < nmax; ++n)
+        for (int l = 0; l < lm1; ++l) {
+            double s = 0.0, ds = 0.0;
+            for (int m = 0; m < nmax; ++m) {
+                s += e.X[n * nmax + m] * raw[m * lm1 + l];
+                ds += e.X[n * nmax + m] * draw[m * lm1 + l];
+            }
+            I[n * lm1 + l] = s;
+            if (dI) dI[n * lm1 + l] = ds;
         }
-    }
+}
 
-    void orth(double r, double* I, double* dI) const
-    {
-        int nl = nmax * (lmax + 1);
-        std::vector<double> raw_I(nl), raw_dI(nl);
-        raw(r, raw_I.data(), dI ? raw_dI.data() : nullptr);
-        for (int n = 0; n < nmax; ++n)
-            for (int l = 0; l <= lmax; ++l) {
-                double s = 0.0, ds = 0.0;
-                for (int m = 0; m < nmax; ++m) {
-                    s += X[n * nmax + m] * raw_I[m * (lmax + 1) + l];
-                    if (dI) ds += X[n * nmax + m] * raw_dI[m * (lmax + 1) + l];
-                }
-                I[n * (lmax + 1) + l] = s;
-                if (dI) dI[n * (lmax + 1) + l] = ds;
-            }
-    }
-};
+namespace {
 
 // Clamped cubic spline through y_0..y_M on a uniform grid of step h; returns
 // the second derivatives at the knots (tridiagonal solve).
@@ -335,21 +354,29 @@ soap_status build_tables(soap_calculator* calc)
 {
     const soap_hypers& h = calc->h;
     int nmax = h.nmax, lmax = h.lmax, nl = nmax * (lmax + 1);
-    Gto gto(nmax, h.rcut);
-    std::vector<double> S = gto_overlap(gto, nmax), w, Q;
-    sym_eigen(nmax, S, w, Q);
-    double wmin = *std::min_element(w.begin(), w.end()), wmax = *std::max_element(w.begin(), w.end());
-    if (!(wmin > 0)) return fail(SOAP_EINVAL, "GTO overlap matrix is not positive definite (nmax=%d)", nmax);
     calc->orth.assign(nmax * nmax, 0.0);
-    for (int i = 0; i < nmax; ++i)
-        for (int j = 0; j < nmax; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < nmax; ++k) s += Q[i * nmax + k] * Q[j * nmax + k] / std::sqrt(w[k]);
-            calc->orth[i * nmax + j] = s;
-        }
-    calc->info.overlap_condition = wmax / wmin;
-
-    RadialExact ex(h, calc->orth);
+    if (h.radial_basis == 1) {
+        for (int i = 0; i < nmax; ++i) calc->orth[i * nmax + i] = 1.0;
+        calc->info.overlap_condition = 1.0;
+    } else {
+        Gto gto(nmax, h.rcut);
+        std::vector<double> S = gto_overlap(gto, nmax), w, Q;
+        sym_eigen(nmax, S, w, Q);
+        double wmin = *std::min_element(w.begin(), w.end()), wmax = *std::max_element(w.begin(), w.end());
+        if (!(wmin > 0)) return fail(SOAP_EINVAL, "GTO overlap matrix is not positive definite (nmax=%d)", nmax);
+        for (int i = 0; i < nmax; ++i)
+            for (int j = 0; j < nmax; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < nmax; ++k) s += Q[i * nmax + k] * Q[j * nmax + k] / std::sqrt(w[k]);
+                calc->orth[i * nmax + j] = s;
+            }
+        calc->info.overlap_condition = wmax / wmin;
+    }
+    build_exact_radial(h, calc->orth, calc->exact);
+    struct {
+        const ExactRadial& e;
+        void orth(double r, double* I, double* dI) const { exact_radial_eval(e, r, I, dI); }
+    } ex{calc->exact};
     std::vector<double> I0(nl), dI0(nl);
     ex.orth(0.0, I0.data(), dI0.data());
     // device constants: [nmax] centre terms I~_n0(0) Y_00, then [(lmax+1)^2]
@@ -425,8 +452,7 @@ soap_status build_tables(soap_calculator* calc)
 
 void radial_exact(const soap_calculator* calc, int64_t n, const double* r, double* I, double* dI)
 {
-    RadialExact ex(calc->h, calc->orth);
-    for (int64_t k = 0; k < n; ++k) ex.orth(r[k], I + k * calc->nl, dI ? dI + k * calc->nl : nullptr);
+    for (int64_t k = 0; k < n; ++k) exact_radial_eval(calc->exact, r[k], I + k * calc->nl, dI ? dI + k * calc->nl : nullptr);
 }
 
 void radial_spline_host(const soap_calculator* calc, double r, double* I, double* dI)

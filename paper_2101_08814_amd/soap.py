@@ -68,16 +68,20 @@ class Calculator:
     """Owns a soap_calculator (hyper-parameters + spline tables)."""
 
     def __init__(self, n_species: int, nmax: int, lmax: int, rcut: float, sigma: float,
-                 cutoff_width: float = 0.5, include_center: int = 1, spline_accuracy: float = 1e-8):
+                 cutoff_width: float = 0.5, include_center: int = 1, spline_accuracy: float = 1e-8,
+                 radial_basis=0):
+        """radial_basis: 0 or "gto" (orthogonalised GTOs), 1 or "dvr"."""
         self._L = _lib.lib()
+        basis = {"gto": _lib.SOAP_RADIAL_GTO, "dvr": _lib.SOAP_RADIAL_DVR}.get(radial_basis, radial_basis)
         h = soap_hypers(int(n_species), int(nmax), int(lmax), int(include_center), float(rcut),
-                        float(cutoff_width), float(sigma), float(spline_accuracy))
+                        float(cutoff_width), float(sigma), float(spline_accuracy), int(basis), 0)
         handle = ctypes.c_void_p()
         check(self._L.soap_calculator_create(ctypes.byref(h), ctypes.byref(handle)))
         self.handle = handle
         self.hypers = dict(n_species=int(n_species), nmax=int(nmax), lmax=int(lmax), rcut=float(rcut),
                            sigma=float(sigma), cutoff_width=float(cutoff_width),
-                           include_center=int(include_center), spline_accuracy=float(spline_accuracy))
+                           include_center=int(include_center), spline_accuracy=float(spline_accuracy),
+                           radial_basis=int(basis))
         self.S, self.nmax, self.lmax = int(n_species), int(nmax), int(lmax)
         self.L2 = (self.lmax + 1) ** 2
         self.K = self.S * self.nmax
@@ -88,7 +92,7 @@ class Calculator:
     @classmethod
     def from_hypers(cls, h: dict) -> "Calculator":
         return cls(h["n_species"], h["nmax"], h["lmax"], h["rcut"], h["sigma"], h.get("cutoff_width", 0.5),
-                   h.get("include_center", 1), h.get("spline_accuracy", 1e-8))
+                   h.get("include_center", 1), h.get("spline_accuracy", 1e-8), h.get("radial_basis", 0))
 
     def __del__(self):
         try:
@@ -112,6 +116,22 @@ class Calculator:
                                                 _np_ptr(dI)))
         return I, dI
 
+    def radial_integral(self, r: torch.Tensor, exact: bool = False, dtype=torch.float64, deriv: bool = True):
+        """soap_radial_integral on the device: I~_nl(r_k) (and d/dr) as
+        [nmax, lmax+1, n_r] tensors, from the spline (exact=False) or
+        evaluated directly (exact=True, FP64)."""
+        assert r.dtype == torch.float64 and r.is_cuda
+        r = r.contiguous()
+        prec = _precision(dtype)
+        td = _torch_dtype(prec)
+        n = int(r.shape[0])
+        I = torch.empty((self.nmax, self.lmax + 1, max(n, 1)), dtype=td, device=r.device)
+        dI = torch.empty_like(I) if deriv else None
+        e = self._exec()
+        check(self._L.soap_radial_integral(self.handle, ctypes.byref(e), prec, int(bool(exact)), n, _ptr(r), _ptr(I),
+                                           _ptr(dI)))
+        return (I[..., :n], dI[..., :n]) if deriv else I[..., :n]
+
     # ------------------------------------------------------------ execution
     def _exec(self, status: Optional[torch.Tensor] = None, device=None) -> soap_exec:
         stream = torch.cuda.current_stream(device).cuda_stream
@@ -131,9 +151,10 @@ class Calculator:
         return int(self._L.soap_read_device_status(ctypes.byref(e)))
 
     def check_device(self):
+        """Raises SoapError if a kernel stored an error in the status word."""
         st = self.device_status()
         if st != 0:
-            raise _lib.SoapError(st, "device-side error")
+            raise _lib.SoapError(st, "reported by a kernel in the device status word")
 
     def neighbors_workspace_size(self, n_structures: int, n_atoms: int) -> int:
         n = ctypes.c_size_t()
@@ -414,12 +435,18 @@ class SOAPFunction(torch.autograd.Function):
     """positions -> power spectrum, differentiable with respect to positions
     through the hand-written adjoint kernels (soap_power_spectrum_backward
     followed by soap_spherical_expansion_backward).  The neighbour list is
-    built once per forward call and reused by the backward call."""
+    built once per forward call and reused by the backward call.
+
+    Both passes read the device status word before returning (one
+    synchronisation each) and raise SoapError if a kernel reported an error:
+    a coincident pair, an invalid species or a pair without its reverse
+    would otherwise give wrong features or forces silently."""
 
     @staticmethod
     def forward(ctx, positions, calc: Calculator, species, atom_offsets, cells, pbc, dtype=torch.float32):
         nl = calc.compute_neighbors(positions.detach(), species, atom_offsets, cells, pbc, vec_dtype=dtype)
         c, p = calc.features(nl, species, dtype=dtype)
+        calc.check_device()
         ctx.calc, ctx.nl, ctx.species = calc, nl, species
         ctx.save_for_backward(c)
         return p
@@ -429,6 +456,7 @@ class SOAPFunction(torch.autograd.Function):
         (c,) = ctx.saved_tensors
         gc = ctx.calc.power_spectrum_backward(c, grad_p.to(c.dtype))
         gpos, _ = ctx.calc.spherical_expansion_backward(ctx.nl, ctx.species, gc)
+        ctx.calc.check_device()
         return gpos.to(torch.float64), None, None, None, None, None, None
 
 

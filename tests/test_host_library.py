@@ -8,6 +8,7 @@ import re
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import paper_2101_08814_amd as P
@@ -30,15 +31,15 @@ def test_library_loads_and_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), f"{name} declared in the header but not exported"
     assert sorted(_lib.EXPORTS) == declared
-    assert L.soap_abi_version() == 1
+    assert L.soap_abi_version() == 2
 
 
 def _create(**kw):
     h = dict(n_species=1, nmax=8, lmax=6, include_center=1, rcut=5.0, cutoff_width=0.5, sigma=0.5,
-             spline_accuracy=1e-8)
+             spline_accuracy=1e-8, radial_basis=0, reserved=0)
     h.update(kw)
     hy = _lib.soap_hypers(h["n_species"], h["nmax"], h["lmax"], h["include_center"], h["rcut"],
-                          h["cutoff_width"], h["sigma"], h["spline_accuracy"])
+                          h["cutoff_width"], h["sigma"], h["spline_accuracy"], h["radial_basis"], h["reserved"])
     out = ctypes.c_void_p()
     st = _lib.lib().soap_calculator_create(ctypes.byref(hy), ctypes.byref(out))
     return st, out
@@ -267,3 +268,93 @@ def test_forced_allocation_failure(calc, monkeypatch):
     assert st == _lib.SOAP_OK and out.value
     assert L.soap_calculator_destroy(out) == _lib.SOAP_OK
     assert L.soap_neighbors_workspace_size(calc.handle, 1, 10, ctypes.byref(n)) == _lib.SOAP_OK and n.value > 0
+
+
+@pytest.mark.parametrize("h", HYPERS)
+def test_library_dvr_radial_integral_matches_oracle(h):
+    """DVR basis (Sec. 4.C): the library's Golub-Welsch points and its
+    scaled Bessel functions (series below a switch point, closed forms and
+    upward recurrence above) reproduce the oracle's Newton points and power
+    series, for the direct values and, within the requested accuracy, for
+    the spline the kernels use."""
+    c = P.Calculator(h["n_species"], h["nmax"], h["lmax"], h["rcut"], h["sigma"], radial_basis="dvr")
+    info = c.info()
+    assert info["overlap_condition"] == 1.0
+    assert info["max_error"] <= 1e-8
+    rs = np.concatenate([[0.0, 1e-3], np.linspace(0.05, h["rcut"], 37)])
+    I, dI = c.radial_integral_host(rs, exact=True)
+    Is, dIs = c.radial_integral_host(rs, exact=False)
+    for k, r in enumerate(rs):
+        Io, dIo = oracle.dvr_radial_integral(h["nmax"], h["lmax"], h["rcut"], h["sigma"], r, deriv=True)
+        scale = max(1.0, np.abs(Io).max())
+        assert np.abs(I[k] - Io).max() <= 1e-13 * scale, (r, np.abs(I[k] - Io).max())
+        assert np.abs(dI[k] - dIo).max() <= 1e-12 * max(1.0, np.abs(dIo).max()), r
+        assert np.abs(Is[k] - Io).max() <= 1e-8
+        assert np.abs(dIs[k] - dIo).max() <= 2e-6
+
+
+def test_radial_basis_validated():
+    st, out = _create(radial_basis=2)
+    assert st == _lib.SOAP_EINVAL and not out.value
+    st, out = _create(reserved=1)
+    assert st == _lib.SOAP_EINVAL and not out.value
+    st, out = _create(radial_basis=1)
+    assert st == _lib.SOAP_OK and out.value
+    assert _lib.lib().soap_calculator_destroy(out) == _lib.SOAP_OK
+
+
+class _StubNeighbors:
+    pass
+
+
+class _StubCalc:
+    """Stands in for a calculator on the CPU: returns zero tensors from every
+    kernel call and a chosen value from the device status word."""
+
+    check_device = P.Calculator.check_device
+
+    def __init__(self, forward_status, backward_status):
+        self.statuses = [forward_status, backward_status]
+
+    def device_status(self):
+        return self.statuses.pop(0) if len(self.statuses) > 1 else self.statuses[0]
+
+    def compute_neighbors(self, positions, species, *a, **k):
+        return _StubNeighbors()
+
+    def features(self, nl, species, dtype):
+        n = species.shape[0]
+        return torch.zeros((n, 4), dtype=dtype), torch.zeros((n, 3), dtype=dtype)
+
+    def power_spectrum_backward(self, c, grad_p):
+        return torch.zeros_like(c)
+
+    def spherical_expansion_backward(self, nl, species, gc):
+        return torch.zeros((species.shape[0], 3), dtype=gc.dtype), None
+
+
+@pytest.mark.parametrize("where", ["forward", "backward"])
+def test_autograd_function_raises_on_device_status(where):
+    """SOAPFunction reads the status word after each pass: a kernel error
+    (here SOAP_EGEOMETRY) raises instead of returning features or forces."""
+    from paper_2101_08814_amd.soap import SOAPFunction
+    calc = _StubCalc(_lib.SOAP_EGEOMETRY if where == "forward" else 0,
+                     _lib.SOAP_EGEOMETRY if where == "backward" else 0)
+    pos = torch.zeros((5, 3), dtype=torch.float64, requires_grad=True)
+    spc = torch.zeros(5, dtype=torch.int32)
+    if where == "forward":
+        with pytest.raises(_lib.SoapError, match="SOAP_EGEOMETRY"):
+            SOAPFunction.apply(pos, calc, spc, None, None, None, torch.float32)
+        return
+    p = SOAPFunction.apply(pos, calc, spc, None, None, None, torch.float32)
+    with pytest.raises(_lib.SoapError, match="SOAP_EGEOMETRY"):
+        p.sum().backward()
+
+
+def test_autograd_function_passes_clean_status():
+    from paper_2101_08814_amd.soap import SOAPFunction
+    calc = _StubCalc(0, 0)
+    pos = torch.zeros((5, 3), dtype=torch.float64, requires_grad=True)
+    p = SOAPFunction.apply(pos, calc, torch.zeros(5, dtype=torch.int32), None, None, None, torch.float32)
+    p.sum().backward()
+    assert pos.grad is not None and pos.grad.shape == (5, 3)
