@@ -15,29 +15,44 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "soap_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "libsoap_oracle.so")
+# another build of the same source (for example one with sanitizers) can be
+# named in SOAP_ORACLE_LIBRARY
+_LIB_PATH = os.environ.get("SOAP_ORACLE_LIBRARY") or os.path.join(_HERE, "libsoap_oracle.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP over centres, generic x86-64)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+FLAGS = ["-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 
 
-def lib():
+def build(force: bool = True, path: str = _LIB_PATH, native: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP over centres; generic x86-64, or
+    tuned for the host it runs on with native=True, for timing there)."""
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        flags = FLAGS + (["-march=native"] if native else [])
+        subprocess.check_call(["gcc"] + flags + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
+
+
+def use_build(path: str):
+    """Load the oracle from another build of the same source (for example a
+    -march=native one); later calls go to it."""
+    global _lib
+    _lib = None
+    return lib(path)
+
+
+def lib(path: str = _LIB_PATH):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+        if not os.path.exists(path) or (path == _LIB_PATH and os.path.getmtime(path) < os.path.getmtime(_SRC)):
+            build(path=path)
+        L = ctypes.CDLL(path)
         d, i, i64, u8 = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_uint8
         P = ctypes.POINTER
         L.orc_num_threads.restype = i
+        L.orc_set_num_threads.argtypes = [i]
         L.orc_fcut.restype = d
         L.orc_fcut.argtypes = [d, d, d, P(d)]
         L.orc_gto_constants.argtypes = [i, d, P(d), P(d), P(d)]
@@ -88,6 +103,10 @@ def _hy(h):
 # ---------------------------------------------------------------- elements
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    lib().orc_set_num_threads(int(n))
 
 
 def fcut(r, rcut, width):

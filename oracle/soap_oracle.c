@@ -68,6 +68,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Sets the number of threads of later parallel loops (n >= 1). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------------- */
 /* Cutoff function (reading: shifted cosine of width w, see header).        */
 /* ---------------------------------------------------------------------- */

@@ -17,6 +17,11 @@ import paper_2101_08814_amd as P
 pytestmark = pytest.mark.gpu
 
 
+# bfloat16 forward bounds on c~ and p~ (relative Frobenius), derived in
+# test_forward_bf16_mfma
+BF16_CT, BF16_PT = 7e-3, 8.5e-3
+
+
 def rel(a, b):
     a = a.detach().double().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -58,9 +63,15 @@ def test_forward_fp32(cells):
 @pytest.mark.parametrize("n_centres,Q,H", [(512, 16, 128), (37, 16, 128), (301, 32, 128), (37, 32, 96),
                                            (45, 12, 40)])
 def test_forward_bf16_mfma(cells, n_centres, Q, H):
-    """bfloat16 operands, float accumulation: each product carries a
-    relative rounding of about 2^-8 on each operand, so c~ and p~ agree with
-    the FP64 result to about 1e-2 (Frobenius).  Centre counts leave a
+    """bfloat16 operands, float accumulation.  Rounding to 8 significant
+    bits leaves a relative error uniform in +-2^-8 (rms 2^-8/sqrt(3) =
+    2.3e-3) on each operand; a product has two such operands and c~ passes
+    two layers, so the errors of c~ add up to about 2 sqrt(2) x 2.3e-3 =
+    6.4e-3 when they do not cancel, and p~ (a Gram matrix of c~ with a hi/lo
+    split, so no further rounding of its own) to twice c~'s relative error
+    at worst.  Measured: c~ 3.3-3.4e-3, p~ 3.8-4.2e-3 (errors partly
+    cancel); the tests hold them to about twice that (7e-3, 8.5e-3), inside
+    the estimates, so a regression of 2x or more fails.  Centre counts leave a
     partial work-group; Q = 32 takes two output tiles, Q = 12 and H = 40,
     96 padded ones; c~ alone and p~ alone agree with the pair."""
     calc, c32, cd = cells
@@ -75,7 +86,7 @@ def test_forward_bf16_mfma(cells, n_centres, Q, H):
     ref_pt = C.power_spectrum(ref_ct)
     e1, e2 = rel(ct, ref_ct), rel(pt, ref_pt)
     print(f"[compress bf16 Q={Q} H={H} n={n_centres}] c~ {e1:.2e}  p~ {e2:.2e}")
-    assert e1 <= 1e-2 and e2 <= 2e-2
+    assert e1 <= BF16_CT and e2 <= BF16_PT
     assert torch.equal(ct_only, ct) and torch.equal(pt_only, pt)
 
 
@@ -216,4 +227,4 @@ def test_full_workload_sampled_cells():
     ref_pt = C.power_spectrum(C.compress(ref_c.astype(np.float32).astype(np.float64), w.astype(np.float64), Q, H))
     ep = rel(pt[rows_t], ref_pt)
     print(f"[compression full size] {c.shape[0]} centres; sampled c {ec:.2e}, p~ bf16 {ep:.2e}")
-    assert ec <= 1e-6 and ep <= 2e-2
+    assert ec <= 1e-6 and ep <= BF16_PT
