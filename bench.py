@@ -27,10 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-DOMINANT_KERNEL = "k_centres<float, 6, true, true, true>"
+DOMINANT_KERNEL = "k_features_rows<float, 6>"
 TWO_PASS_KERNEL = "k_pair_rows<float, 6, true, true>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "features_diamond1024_traffic.txt")
-KERNEL_SOURCES = ["features.hip", "chunk.hpp", "sph.hpp"]
+KERNEL_SOURCES = ["features_rows.hip", "lane_pair.hpp", "chunk.hpp", "sph.hpp"]
 
 
 def log(*a):

@@ -507,6 +507,10 @@ hipError_t features_t(const FeatureArgs& a, hipStream_t stream)
     FeatureArgs c = a;
     c.dp_self = want_p ? a.dp_self : nullptr;
     if (grad && want_p && a.dcoeffs && a.dp && a.dp_pos && a.pair_capacity > 0) {
+        // each pair staged once (features_rows.hip); the kernel below when
+        // its layout does not fit
+        hipError_t e = launch_features_rows(a, std::is_same<T, double>::value, stream);
+        if (e != hipErrorNotSupported) return e;
         Layout L = choose_rows_layout<T>(d);
         if (L.total != 0)
             return by_lmax<T, CentresFn>(a.lmax, c, L, size_t(L.total) * sizeof(T), true, stream);

@@ -69,6 +69,82 @@ struct HarmonicNorms {
 };
 constexpr HarmonicNorms kHarmonicNorms{};
 
+// Gradient of the solid harmonic Z_lm in terms of the harmonics of degree
+// l - 1.  With F_l^M = Qt_l^M (x + i y)^M (M >= 0) the raising and lowering
+// identities
+//   (d_x + i d_y) F_l^M = -F_{l-1}^{M+1},
+//   (d_x - i d_y) F_l^M = (l+M)(l+M-1) F_{l-1}^{M-1}   (M >= 1),
+//   d_z F_l^M = (l+M) F_{l-1}^M
+// (the first from d_{x,y} Qt_l^M = -{x, y} Qt_{l-1}^{M+1}, the others from the
+// Legendre recurrences) give, for Z_lm = K_lm Re F_l^M (m > 0), K_lm Im F_l^M
+// (m < 0) or K_l0 F_l^0, each component as at most two harmonics Y_{l-1,m'}
+// (= Z_{l-1,m'} at a unit vector).  Term j of component x of lm is
+// gx[lm][j] * Y[ix[lm][j]]; absent terms have coefficient 0 and index 0.
+struct HarmonicGradTerms {
+    int ix[169][2], iy[169][2], iz[169];
+    double gx[169][2], gy[169][2], gz[169];
+
+    // Re F_{l}^{M} and Im F_{l}^{M} as (index of Y_{l,m'}, factor 1/K_{l,m'})
+    static constexpr void re_f(int l, int M, int& idx, double& s)
+    {
+        idx = 0;
+        s = 0.0;
+        if (l < 0 || M > l) return;
+        idx = l * l + l + M;
+        s = 1.0 / kHarmonicNorms.v[idx];
+    }
+    static constexpr void im_f(int l, int M, int& idx, double& s)
+    {
+        idx = 0;
+        s = 0.0;
+        if (l < 0 || M < 1 || M > l) return;
+        idx = l * l + l - M;
+        s = 1.0 / kHarmonicNorms.v[idx];
+    }
+
+    constexpr HarmonicGradTerms() : ix(), iy(), iz(), gx(), gy(), gz()
+    {
+        for (int l = 1; l <= 12; ++l)
+            for (int m = -l; m <= l; ++m) {
+                const int lm = l * l + l + m, M = m < 0 ? -m : m;
+                const double K = kHarmonicNorms.v[lm];
+                const double beta = double(l + M) * double(l + M - 1);
+                int a = 0, b = 0, c = 0;
+                double sa = 0.0, sb = 0.0, sc = 0.0;
+                if (m > 0) {
+                    re_f(l - 1, M + 1, a, sa);
+                    re_f(l - 1, M - 1, b, sb);
+                    ix[lm][0] = a; gx[lm][0] = -0.5 * K * sa;
+                    ix[lm][1] = b; gx[lm][1] = 0.5 * K * beta * sb;
+                    im_f(l - 1, M + 1, a, sa);
+                    im_f(l - 1, M - 1, b, sb);
+                    iy[lm][0] = a; gy[lm][0] = -0.5 * K * sa;
+                    iy[lm][1] = b; gy[lm][1] = -0.5 * K * beta * sb;
+                    re_f(l - 1, M, c, sc);
+                } else if (m < 0) {
+                    im_f(l - 1, M + 1, a, sa);
+                    im_f(l - 1, M - 1, b, sb);
+                    ix[lm][0] = a; gx[lm][0] = -0.5 * K * sa;
+                    ix[lm][1] = b; gx[lm][1] = 0.5 * K * beta * sb;
+                    re_f(l - 1, M + 1, a, sa);
+                    re_f(l - 1, M - 1, b, sb);
+                    iy[lm][0] = a; gy[lm][0] = 0.5 * K * sa;
+                    iy[lm][1] = b; gy[lm][1] = 0.5 * K * beta * sb;
+                    im_f(l - 1, M, c, sc);
+                } else {
+                    re_f(l - 1, 1, a, sa);
+                    ix[lm][0] = a; gx[lm][0] = -K * sa;
+                    im_f(l - 1, 1, a, sa);
+                    iy[lm][0] = a; gy[lm][0] = -K * sa;
+                    re_f(l - 1, 0, c, sc);
+                }
+                iz[lm] = c;
+                gz[lm] = K * double(l + M) * sc;
+            }
+    }
+};
+constexpr HarmonicGradTerms kHarmonicGrad{};
+
 template <typename T, int LMAX>
 struct YlmStream {
     T x, y, z;

@@ -119,6 +119,9 @@ struct FeatureArgs {
 };
 
 hipError_t launch_features(const FeatureArgs& a, bool f64, hipStream_t stream);
+// c, p, self rows and pair rows with each pair staged once (hipErrorNotSupported
+// when the layout does not fit)
+hipError_t launch_features_rows(const FeatureArgs& a, bool f64, hipStream_t stream);
 
 // radial integrals of a batch of radii on the device (spline or direct)
 struct RadialArgs {
