@@ -44,11 +44,15 @@ using namespace dev;
 
 constexpr int kRowsThreads = 256;
 constexpr int kRowsWaves = kRowsThreads / 64;
+constexpr int kNB = 4;   // radial channels n summed by one lane
 
-// LDS layout in elements of T (ints in T-sized slots).
+// LDS layout in elements of T (ints in T-sized slots).  R and D hold npad
+// = nmax rounded up to kNB channels per pair, the padding zero, so a lane
+// reads its kNB channels without a bounds test.
 struct RowsLayout {
     int ch;                 // pairs per chunk
-    int c, dcs, ux, uy, uz, rinv, spc, Y, R, D, seg, pos, yd, yz, total;
+    int npad;
+    int c, dcs, ux, uy, uz, rinv, f, df, t, k, spc, Y, R, D, seg, flag, pos, pyz, lk, yd, yz, ab, total;
 };
 
 inline RowsLayout rows_layout(int S, int nmax, int lmax, int ch)
@@ -57,6 +61,7 @@ inline RowsLayout rows_layout(int S, int nmax, int lmax, int ch)
     const int KK = K * (K + 1) / 2;
     RowsLayout L{};
     L.ch = ch;
+    L.npad = (nmax + kNB - 1) / kNB * kNB;
     int o = 0;
     L.c = o; o += K * L2;
     L.dcs = o; o += 3 * K * L2;
@@ -64,93 +69,175 @@ inline RowsLayout rows_layout(int S, int nmax, int lmax, int ch)
     L.uy = o; o += ch;
     L.uz = o; o += ch;
     L.rinv = o; o += ch;
+    L.f = o; o += ch;
+    L.df = o; o += ch;
+    L.t = o; o += ch;
+    L.k = o; o += ch;
     L.spc = o; o += ch;
     L.Y = o; o += ch * L2;
-    L.R = o; o += ch * nmax * lm1;
-    L.D = o; o += ch * nmax * lm1;
+    L.R = o; o += ch * L.npad * lm1;
+    L.D = o; o += ch * L.npad * lm1;
     L.seg = o; o += 2 * S;
+    L.flag = o; o += 1;
     L.pos = o; o += lm1 * KK;
+    L.pyz = o; o += lm1 * KK;
+    L.lk = o; o += lm1 * K;
     o = (o + 3) & ~3;
     L.yd = o; o += kRowsWaves * 4 * L2;
     L.yz = o; o += kRowsWaves * 4 * lm1 * K;
+    L.ab = o; o += kRowsWaves * 2 * lm1 * K;
     L.total = o;
     return L;
 }
 
 template <typename T>
 struct RowsSmem {
-    T *c, *dcs, *ux, *uy, *uz, *rinv, *Y, *R, *D;
+    T *c, *dcs, *ux, *uy, *uz, *rinv, *f, *df, *t, *Y, *R, *D;
     V4<T>*yd, *yz;
-    int *spc, *seg, *pos;
+    V2<T>* ab;
+    int *k, *spc, *seg, *flag, *pos, *pyz, *lk;
     __device__ RowsSmem(T* b, const RowsLayout& L)
-        : c(b + L.c), dcs(b + L.dcs), ux(b + L.ux), uy(b + L.uy), uz(b + L.uz), rinv(b + L.rinv), Y(b + L.Y),
-          R(b + L.R), D(b + L.D), yd(reinterpret_cast<V4<T>*>(b + L.yd)), yz(reinterpret_cast<V4<T>*>(b + L.yz)),
-          spc(reinterpret_cast<int*>(b + L.spc)), seg(reinterpret_cast<int*>(b + L.seg)),
-          pos(reinterpret_cast<int*>(b + L.pos))
+        : c(b + L.c), dcs(b + L.dcs), ux(b + L.ux), uy(b + L.uy), uz(b + L.uz), rinv(b + L.rinv), f(b + L.f),
+          df(b + L.df), t(b + L.t), Y(b + L.Y), R(b + L.R), D(b + L.D), yd(reinterpret_cast<V4<T>*>(b + L.yd)),
+          yz(reinterpret_cast<V4<T>*>(b + L.yz)), ab(reinterpret_cast<V2<T>*>(b + L.ab)),
+          k(reinterpret_cast<int*>(b + L.k)), spc(reinterpret_cast<int*>(b + L.spc)),
+          seg(reinterpret_cast<int*>(b + L.seg)), flag(reinterpret_cast<int*>(b + L.flag)),
+          pos(reinterpret_cast<int*>(b + L.pos)), pyz(reinterpret_cast<int*>(b + L.pyz)),
+          lk(reinterpret_cast<int*>(b + L.lk))
     {
     }
 };
 
-// Stage pairs [q0, q0 + nc) (nc <= ch); every lane of the block takes part
-// and the caller synchronises afterwards.  The species segments must have
-// been reset to (nc, 0) before, by the caller, behind a barrier.
+// Stage pairs [q0, q0 + nc) (nc <= ch <= 64); every lane of the block takes
+// part and the caller synchronises afterwards.  The species segments must
+// have been reset to (nc, 0) before, by the caller, behind a barrier.
+// The first wave forms each pair's geometry (one lane per pair) and, after
+// the block barrier, its harmonics from the registers it still holds; the
+// other waves read the geometry back and evaluate the radial integrals one
+// lane per (pair, n).  *flag becomes 1 when the pairs come grouped by
+// species in ascending order (then the combination needs no species test).
 template <typename T, int LMAX>
-__device__ __forceinline__ void stage_rows(const FeatureArgs& a, RowsSmem<T>& s, int64_t q0, int nc)
+__device__ __forceinline__ void stage_rows(const FeatureArgs& a, RowsSmem<T>& s, const RowsLayout& LY, int64_t q0,
+                                           int nc)
 {
     constexpr int LM1 = LMAX + 1, L2 = LM1 * LM1;
     const int tid = threadIdx.x;
     const T* __restrict__ vec = static_cast<const T*>(a.pair_vec);
-    const int nmax = a.nmax, nl = nmax * LM1;
-    // harmonics: one lane per pair in the first wave
-    for (int p = tid; tid < 64 && p < nc; p += 64) {
-        const int64_t q = q0 + p;
-        const PairGeom<T> g = pair_geometry<T>(a, vec[3 * q], vec[3 * q + 1], vec[3 * q + 2]);
-        const int sp = pair_species(a, q);
-        s.ux[p] = g.ux;
-        s.uy[p] = g.uy;
-        s.uz[p] = g.uz;
-        s.rinv[p] = g.rinv;
-        s.spc[p] = sp;
-        atomicMin(&s.seg[2 * sp], p);
-        atomicMax(&s.seg[2 * sp + 1], p + 1);
-        YlmStream<T, LMAX> ys(g.ux, g.uy, g.uz);
-        T* Yp = s.Y + p * L2;
-        static_for<0, LM1>([&](auto Lc) __attribute__((always_inline)) {
-            constexpr int L = decltype(Lc)::value;
-            ys.template degree<L, false>(
-                [&](int mi, T Y, T, T, T) __attribute__((always_inline)) { Yp[L * L + mi] = Y; });
-        });
+    const int nmax = a.nmax, npad = LY.npad, nl = npad * LM1;
+    PairGeom<T> g{};
+    const bool mine = tid < nc;
+    if (tid < 64) {
+        int sp = 0;
+        if (mine) {
+            const int64_t q = q0 + tid;
+            g = pair_geometry<T>(a, vec[3 * q], vec[3 * q + 1], vec[3 * q + 2]);
+            sp = pair_species(a, q);
+            s.ux[tid] = g.ux;
+            s.uy[tid] = g.uy;
+            s.uz[tid] = g.uz;
+            s.rinv[tid] = g.rinv;
+            s.f[tid] = g.f;
+            s.df[tid] = g.df;
+            s.t[tid] = g.t;
+            s.k[tid] = g.k;
+            s.spc[tid] = sp;
+            atomicMin(&s.seg[2 * sp], tid);
+            atomicMax(&s.seg[2 * sp + 1], tid + 1);
+        }
+        const int prev = __shfl_up(sp, 1);
+        const bool ordered = !mine || tid == 0 || prev <= sp;
+        if (tid == 0) s.flag[0] = __ballot(!ordered) == 0ull ? 1 : 0;
     }
-    // radial integrals: one lane per (pair, n) in the other waves (in every
-    // lane when the block has no other wave to spare)
+    __syncthreads();
+    if (tid < 64) {
+        if (mine) {
+            YlmStream<T, LMAX> ys(g.ux, g.uy, g.uz);
+            T* Yp = s.Y + tid * L2;
+            static_for<0, LM1>([&](auto Lc) __attribute__((always_inline)) {
+                constexpr int L = decltype(Lc)::value;
+                ys.template degree<L, false>(
+                    [&](int mi, T Y, T, T, T) __attribute__((always_inline)) { Yp[L * L + mi] = Y; });
+            });
+        }
+        return;
+    }
     const V4<T>* __restrict__ coef = static_cast<const V4<T>*>(a.coef);
     const T inv_delta = T(a.inv_delta);
-    const int first = nc <= 64 * (kRowsWaves - 1) / 2 ? 64 : 0;
-    const int items = nc * nmax;
-    for (int t = tid - first; t < items; t += kRowsThreads - first) {
-        if (t < 0) break;
-        const int p = t / nmax, n = t - p * nmax;
-        const int64_t q = q0 + p;
-        const PairGeom<T> g = pair_geometry<T>(a, vec[3 * q], vec[3 * q + 1], vec[3 * q + 2]);
-        const V4<T>* cf = coef + int64_t(g.k) * nl + n * LM1;
+    const int items = nc * npad;
+    for (int it = tid - 64; it < items; it += kRowsThreads - 64) {
+        const int p = it / npad, n = it - p * npad;
+        T* Rp = s.R + p * nl + n * LM1;
+        T* Dp = s.D + p * nl + n * LM1;
+        if (n >= nmax) {
+#pragma unroll
+            for (int l = 0; l < LM1; ++l) Rp[l] = Dp[l] = T(0);
+            continue;
+        }
+        const T f = s.f[p], df = s.df[p], t = s.t[p], ri = s.rinv[p];
+        const V4<T>* cf = coef + int64_t(s.k[p]) * (nmax * LM1) + n * LM1;
         V4<T> c4[LM1];
 #pragma unroll
         for (int l = 0; l < LM1; ++l) c4[l] = cf[l];
-        T* Rp = s.R + p * nl + n * LM1;
-        T* Dp = s.D + p * nl + n * LM1;
 #pragma unroll
         for (int l = 0; l < LM1; ++l) {
             T v, dv;
-            spline_poly<T>(c4[l].x, c4[l].y, c4[l].z, c4[l].w, g.t, inv_delta, v, dv);
-            const T R = g.f * v;
+            spline_poly<T>(c4[l].x, c4[l].y, c4[l].z, c4[l].w, t, inv_delta, v, dv);
+            const T R = f * v;
             Rp[l] = R;
-            Dp[l] = g.df * v + g.f * dv - T(l) * R * g.rinv;
+            Dp[l] = df * v + f * dv - T(l) * R * ri;
+        }
+    }
+}
+
+// c of kNB channels n0.. of one (species, lm) and the self rows, summed over
+// the pairs [p0, p1); each pair's dc values are stored as they are formed.
+// CHECK: skip pairs of another species (lists not grouped by species).
+template <typename T, int LMAX, bool CHECK>
+__device__ __forceinline__ void combine_item(const RowsSmem<T>& s, int nl, int nmax, int sp, int n0, int lm, int p0,
+                                             int p1, T* __restrict__ dq0, int64_t row_stride, T (&cs)[kNB],
+                                             T (&gs)[kNB][3])
+{
+    constexpr int LM1 = LMAX + 1, L2 = LM1 * LM1;
+    const int l = l_of(lm);
+    const int nL2 = nmax * L2;
+    const int ix0 = kHarmonicGrad.ix[lm][0], ix1 = kHarmonicGrad.ix[lm][1];
+    const int iy0 = kHarmonicGrad.iy[lm][0], iy1 = kHarmonicGrad.iy[lm][1], iz = kHarmonicGrad.iz[lm];
+    const T gx0 = T(kHarmonicGrad.gx[lm][0]), gx1 = T(kHarmonicGrad.gx[lm][1]);
+    const T gy0 = T(kHarmonicGrad.gy[lm][0]), gy1 = T(kHarmonicGrad.gy[lm][1]);
+    const T gz = T(kHarmonicGrad.gz[lm]);
+    const int roff = n0 * LM1 + l;
+    for (int p = p0; p < p1; ++p) {
+        if (CHECK && s.spc[p] != sp) continue;
+        const T* Yp = s.Y + p * L2;
+        const T Yv = Yp[lm];
+        const T zx = gx0 * Yp[ix0] + gx1 * Yp[ix1];
+        const T zy = gy0 * Yp[iy0] + gy1 * Yp[iy1];
+        const T zz = gz * Yp[iz];
+        const T ri = s.rinv[p];
+        const T al0 = s.ux[p] * Yv, al1 = s.uy[p] * Yv, al2 = s.uz[p] * Yv;
+        const T* Rp = s.R + p * nl + roff;
+        const T* Dp = s.D + p * nl + roff;
+        T* dq = dq0 + int64_t(p) * row_stride;
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) {
+            const T R = Rp[u * LM1], D = Dp[u * LM1];
+            const T P = R * ri;
+            const T r0 = D * al0 + P * zx, r1 = D * al1 + P * zy, r2 = D * al2 + P * zz;
+            cs[u] += R * Yv;
+            gs[u][0] += r0;
+            gs[u][1] += r1;
+            gs[u][2] += r2;
+            if (n0 + u < nmax) {
+                dq[u * L2] = r0;
+                dq[nL2 + u * L2] = r1;
+                dq[2 * nL2 + u * L2] = r2;
+            }
         }
     }
 }
 
 template <typename T, int LMAX>
-__global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, RowsLayout LY)
+__global__ void __launch_bounds__(kRowsThreads, sizeof(T) == 4 ? 4 : 2) k_features_rows(FeatureArgs a, RowsLayout LY)
 {
     constexpr int LM1 = LMAX + 1, L2 = LM1 * LM1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -162,7 +249,7 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
         return;
     }
     const int64_t q_begin = a.pair_offsets[i], q_end = a.pair_offsets[i + 1];
-    const int S = a.S, nmax = a.nmax, K = S * nmax, nl = nmax * LM1;
+    const int S = a.S, nmax = a.nmax, K = S * nmax, npad = LY.npad, nl = npad * LM1;
     const int KL2 = K * L2, nL2 = nmax * L2, KK = K * (K + 1) / 2, PL = LM1 * KK;
     const int ch = LY.ch;
     const int n_chunks = int((q_end - q_begin + ch - 1) / ch);
@@ -173,11 +260,20 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
         s.dcs[KL2 + e] = T(0);
         s.dcs[2 * KL2 + e] = T(0);
     }
-    for (int o = tid; o < PL; o += kRowsThreads) s.pos[o] = a.dp_pos[o];
-    // items (species, n pair, lm): two n per lane share the harmonic loads
-    const int ng = (nmax + 1) / 2;
-    const int items = S * ng * L2;
+    // dp positions: (l, k1, k2) for p and its self rows, and the {y, z}
+    // slots l K + k1 | (l K + k2) << 16 for the pair rows
+    for (int o = tid; o < PL; o += kRowsThreads) {
+        const int v = a.dp_pos[o];
+        const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
+        s.pos[o] = v;
+        s.pyz[o] = (l * K + k1) | ((l * K + k2) << 16);
+    }
+    for (int t = tid; t < LM1 * K; t += kRowsThreads) s.lk[t] = (t / K) | ((t % K) << 8);
+    // items (species, block of kNB channels, lm)
+    const int nb = npad / kNB;
+    const int items = S * nb * L2;
     T* __restrict__ dc_out = static_cast<T*>(a.dcoeffs);
+    const int64_t row_stride = 3 * int64_t(nL2);
     for (int ck = 0; ck < n_chunks; ++ck) {
         const int64_t q0 = q_begin + (ck == 0 ? 0 : int64_t(ck) * ch - pad);
         const int nc = ck == 0 ? ch - pad : ch;
@@ -186,65 +282,29 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
             s.seg[2 * sp + 1] = 0;
         }
         __syncthreads();
-        stage_rows<T, LMAX>(a, s, q0, nc);
+        stage_rows<T, LMAX>(a, s, LY, q0, nc);
         __syncthreads();
+        const bool grouped = s.flag[0] != 0;
         for (int t = tid; t < items; t += kRowsThreads) {
-            const int sp = t / (ng * L2), rem = t - sp * (ng * L2), g = rem / L2, lm = rem - g * L2;
-            const int n0 = 2 * g;
-            const bool two = n0 + 1 < nmax;
-            const int l = l_of(lm);
-            const int e0 = (sp * nmax + n0) * L2 + lm;
-            const int ix0 = kHarmonicGrad.ix[lm][0], ix1 = kHarmonicGrad.ix[lm][1];
-            const int iy0 = kHarmonicGrad.iy[lm][0], iy1 = kHarmonicGrad.iy[lm][1], iz = kHarmonicGrad.iz[lm];
-            const T gx0 = T(kHarmonicGrad.gx[lm][0]), gx1 = T(kHarmonicGrad.gx[lm][1]);
-            const T gy0 = T(kHarmonicGrad.gy[lm][0]), gy1 = T(kHarmonicGrad.gy[lm][1]);
-            const T gz = T(kHarmonicGrad.gz[lm]);
-            T c0 = T(0), c1 = T(0);
-            T a0 = T(0), a1 = T(0), a2 = T(0), b0 = T(0), b1 = T(0), b2 = T(0);
+            const int sp = t / (nb * L2), rem = t - sp * (nb * L2), b = rem / L2, lm = rem - b * L2;
+            const int n0 = b * kNB;
+            T cs[kNB], gs[kNB][3];
+#pragma unroll
+            for (int u = 0; u < kNB; ++u) cs[u] = gs[u][0] = gs[u][1] = gs[u][2] = T(0);
             const int p0 = s.seg[2 * sp], p1 = s.seg[2 * sp + 1];
-            for (int p = p0; p < p1; ++p) {
-                if (s.spc[p] != sp) continue;
-                const T* Yp = s.Y + p * L2;
-                const T Yv = Yp[lm];
-                const T zx = gx0 * Yp[ix0] + gx1 * Yp[ix1];
-                const T zy = gy0 * Yp[iy0] + gy1 * Yp[iy1];
-                const T zz = gz * Yp[iz];
-                const T* Rp = s.R + p * nl + n0 * LM1 + l;
-                const T* Dp = s.D + p * nl + n0 * LM1 + l;
-                const T R0 = Rp[0], R1 = two ? Rp[LM1] : T(0);
-                const T D0 = Dp[0], D1 = two ? Dp[LM1] : T(0);
-                const T ri = s.rinv[p];
-                const T al0 = s.ux[p] * Yv, al1 = s.uy[p] * Yv, al2 = s.uz[p] * Yv;
-                const T P0 = R0 * ri, P1 = R1 * ri;
-                const T r00 = D0 * al0 + P0 * zx, r01 = D0 * al1 + P0 * zy, r02 = D0 * al2 + P0 * zz;
-                const T r10 = D1 * al0 + P1 * zx, r11 = D1 * al1 + P1 * zy, r12 = D1 * al2 + P1 * zz;
-                c0 += R0 * Yv;
-                c1 += R1 * Yv;
-                a0 += r00;
-                a1 += r01;
-                a2 += r02;
-                b0 += r10;
-                b1 += r11;
-                b2 += r12;
-                T* dq = dc_out + (q0 + p) * int64_t(3 * nL2) + (n0 * L2 + lm);
-                dq[0] = r00;
-                dq[nL2] = r01;
-                dq[2 * nL2] = r02;
-                if (two) {
-                    dq[L2] = r10;
-                    dq[nL2 + L2] = r11;
-                    dq[2 * nL2 + L2] = r12;
-                }
-            }
-            s.c[e0] += c0;
-            s.dcs[e0] -= a0;
-            s.dcs[KL2 + e0] -= a1;
-            s.dcs[2 * KL2 + e0] -= a2;
-            if (two) {
-                s.c[e0 + L2] += c1;
-                s.dcs[e0 + L2] -= b0;
-                s.dcs[KL2 + e0 + L2] -= b1;
-                s.dcs[2 * KL2 + e0 + L2] -= b2;
+            T* dq0 = dc_out + q0 * row_stride + (n0 * L2 + lm);
+            if (grouped)
+                combine_item<T, LMAX, false>(s, nl, nmax, sp, n0, lm, p0, p1, dq0, row_stride, cs, gs);
+            else
+                combine_item<T, LMAX, true>(s, nl, nmax, sp, n0, lm, p0, p1, dq0, row_stride, cs, gs);
+#pragma unroll
+            for (int u = 0; u < kNB; ++u) {
+                if (n0 + u >= nmax) break;
+                const int e = (sp * nmax + n0 + u) * L2 + lm;
+                s.c[e] += cs[u];
+                s.dcs[e] -= gs[u][0];
+                s.dcs[KL2 + e] -= gs[u][1];
+                s.dcs[2 * KL2 + e] -= gs[u][2];
             }
         }
         __syncthreads();
@@ -259,25 +319,30 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
     for (int e = tid; e < KL2; e += kRowsThreads) c_out[e] = s.c[e];
     T* dcs_out = static_cast<T*>(a.dcoeffs_self) + i * 3 * KL2;
     for (int e = tid; e < 3 * KL2; e += kRowsThreads) dcs_out[e] = s.dcs[e];
-    // p and its self rows (the product rule on the self rows of c)
+    // p and its self rows (the product rule on the self rows of c); the m
+    // loop runs to 2 lmax + 1 for every lane with the terms past 2l + 1 zero
+    // (their reads clamped), so all reads of a lane are issued together
     T* p_out = static_cast<T*>(a.p) + i * int64_t(PL);
     T* dps_out = static_cast<T*>(a.dp_self) + i * int64_t(3 * PL);
     for (int o = tid; o < PL; o += kRowsThreads) {
         const int v = s.pos[o];
         const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
-        const T* c1 = s.c + k1 * L2 + l * l;
-        const T* c2 = s.c + k2 * L2 + l * l;
-        T acc = T(0);
-        for (int m = 0; m < 2 * l + 1; ++m) acc += c1[m] * c2[m];
-        p_out[o] = acc;
+        const int b1 = k1 * L2 + l * l, b2 = k2 * L2 + l * l;
+        T acc = T(0), d0 = T(0), d1 = T(0), d2 = T(0);
 #pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            const T* g1 = s.dcs + x * KL2 + k1 * L2 + l * l;
-            const T* g2 = s.dcs + x * KL2 + k2 * L2 + l * l;
-            T acc2 = T(0);
-            for (int m = 0; m < 2 * l + 1; ++m) acc2 += g1[m] * c2[m] + c1[m] * g2[m];
-            dps_out[x * PL + o] = acc2;
+        for (int m = 0; m < 2 * LMAX + 1; ++m) {
+            const bool in = m <= 2 * l;
+            const int mm = in ? m : 0;
+            const T c1 = in ? s.c[b1 + mm] : T(0), c2 = in ? s.c[b2 + mm] : T(0);
+            acc += c1 * c2;
+            d0 += s.dcs[b1 + mm] * c2 + c1 * s.dcs[b2 + mm];
+            d1 += s.dcs[KL2 + b1 + mm] * c2 + c1 * s.dcs[KL2 + b2 + mm];
+            d2 += s.dcs[2 * KL2 + b1 + mm] * c2 + c1 * s.dcs[2 * KL2 + b2 + mm];
         }
+        p_out[o] = acc;
+        dps_out[o] = d0;
+        dps_out[PL + o] = d1;
+        dps_out[2 * PL + o] = d2;
     }
     // pair rows of p: the last chunk is still staged, earlier ones are
     // staged again; waves synchronise only with themselves in between
@@ -285,6 +350,7 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
     const int nlk = LM1 * K;
     V4<T>* ydw = s.yd + wave * L2;
     V4<T>* yzw = s.yz + wave * nlk;
+    V2<T>* abw = s.ab + wave * nlk;
     T* __restrict__ dp_out = static_cast<T*>(a.dp);
     for (int ck = n_chunks - 1; ck >= 0; --ck) {
         const int64_t q0 = q_begin + (ck == 0 ? 0 : int64_t(ck) * ch - pad);
@@ -296,7 +362,7 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
                 s.seg[2 * sp + 1] = 0;
             }
             __syncthreads();
-            stage_rows<T, LMAX>(a, s, q0, nc);
+            stage_rows<T, LMAX>(a, s, LY, q0, nc);
             __syncthreads();
         }
         for (int p = wave; p < nc; p += kRowsWaves) {
@@ -313,40 +379,47 @@ __global__ void __launch_bounds__(kRowsThreads) k_features_rows(FeatureArgs a, R
                 ydw[lm] = V4<T>{Yv, (zx - lY * ux) * ri, (zy - lY * uy) * ri, (zz - lY * uz) * ri};
             }
             wave_sync();
+            // {y, z} and {A, B} of every (l, k); the m loop as for p above
+            const int blk = s.spc[p] * nmax;
+            const T* Rp = s.R + p * nl;
+            const T* Dp = s.D + p * nl;
             for (int t = lane; t < nlk; t += 64) {
-                const int l2 = t / K, k = t - l2 * K;
-                const int m0 = l2 * l2;
-                const T* ck_ = s.c + k * L2;
+                const int v = s.lk[t];
+                const int l2 = v & 255, k = v >> 8;
+                const T* ck_ = s.c + k * L2 + l2 * l2;
+                const V4<T>* yl = ydw + l2 * l2;
                 T y = T(0), z0 = T(0), z1 = T(0), z2 = T(0);
-                for (int m = m0; m < m0 + 2 * l2 + 1; ++m) {
-                    const T cv = ck_[m];
-                    const V4<T> yd = ydw[m];
+#pragma unroll
+                for (int m = 0; m < 2 * LMAX + 1; ++m) {
+                    const bool in = m <= 2 * l2;
+                    const int mm = in ? m : 0;
+                    const T cv = in ? ck_[mm] : T(0);
+                    const V4<T> yd = yl[mm];
                     y += yd.x * cv;
                     z0 += yd.y * cv;
                     z1 += yd.z * cv;
                     z2 += yd.w * cv;
                 }
                 yzw[t] = V4<T>{y, z0, z1, z2};
+                const int n = k - blk;
+                const bool inb = n >= 0 && n < nmax;
+                const int rn = inb ? n * LM1 + l2 : 0;
+                const T B = inb ? Rp[rn] : T(0);
+                // (f I~)' = D + l R / r
+                const T A = inb ? Dp[rn] + T(l2) * B * ri : T(0);
+                abw[t] = V2<T>{A, B};
             }
             wave_sync();
-            const int blk = s.spc[p] * nmax;
-            const T* Rp = s.R + p * nl;
-            const T* Dp = s.D + p * nl;
             T* row = dp_out + (q0 + p) * int64_t(3 * PL);
             for (int o = lane; o < PL; o += 64) {
-                const int v = s.pos[o];
-                const int l2 = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
-                const V4<T> q1 = yzw[l2 * K + k1], q2 = yzw[l2 * K + k2];
-                const int n1 = k1 - blk, n2 = k2 - blk;
-                const bool in1 = n1 >= 0 && n1 < nmax, in2 = n2 >= 0 && n2 < nmax;
-                const T B1 = in1 ? Rp[n1 * LM1 + l2] : T(0), B2 = in2 ? Rp[n2 * LM1 + l2] : T(0);
-                // (f I~)' = D + l R / r
-                const T A1 = in1 ? Dp[n1 * LM1 + l2] + T(l2) * B1 * ri : T(0);
-                const T A2 = in2 ? Dp[n2 * LM1 + l2] + T(l2) * B2 * ri : T(0);
-                const T a0 = A1 * q2.x + A2 * q1.x;
-                row[o] = ux * a0 + B1 * q2.y + B2 * q1.y;
-                row[PL + o] = uy * a0 + B1 * q2.z + B2 * q1.z;
-                row[2 * PL + o] = uz * a0 + B1 * q2.w + B2 * q1.w;
+                const int v = s.pyz[o];
+                const int i1 = v & 0xFFFF, i2 = v >> 16;
+                const V4<T> q1 = yzw[i1], q2 = yzw[i2];
+                const V2<T> e1 = abw[i1], e2 = abw[i2];
+                const T a0 = e1.x * q2.x + e2.x * q1.x;
+                row[o] = ux * a0 + e1.y * q2.y + e2.y * q1.y;
+                row[PL + o] = uy * a0 + e1.y * q2.z + e2.y * q1.z;
+                row[2 * PL + o] = uz * a0 + e1.y * q2.w + e2.y * q1.w;
             }
             wave_sync();
         }
