@@ -9,6 +9,7 @@
 // full spectrum's (lmax+1)^2 K(K+1)/2.
 #include "soap_internal.hpp"
 
+#include <algorithm>
 #include <vector>
 
 namespace soap {
@@ -163,6 +164,161 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected_backward(int K, int lm
     }
 }
 
+// The same adjoint with the plan held in LDS by persistent work-groups.
+// A work-group loads and checks the plan once (row bounds, entry ranges:
+// anything outside them is reported and contributes nothing), then walks
+// its centres i = blockIdx.x, blockIdx.x + gridDim.x, ...; the next
+// centre's coefficients and gradient row are loaded into registers while
+// the current one is summed, so the HBM round trip overlaps the sums.
+// Lane e = k L2 + lm reads its row's entries (q, partner) from LDS (the
+// 2l+1 lanes of a row read the same entry: a broadcast) and sums
+// grad[q] c[partner, lm] in plan order, as the kernel above.
+constexpr int kPrefetch = 8;   // 16-byte vectors of c per lane held for the next centre
+constexpr int kPrefetchG = 4;  // and of the gradient row
+
+struct PlanLayout {
+    int rows;                  // K (lmax + 1)
+    int64_t n_entries;         // 2 n_sel
+    size_t off_bounds, off_entries, off_c, off_g, total;
+};
+
+inline PlanLayout plan_layout(size_t es, int K, int lmax, int64_t n_sel)
+{
+    PlanLayout P{};
+    P.rows = K * (lmax + 1);
+    P.n_entries = 2 * n_sel;
+    size_t o = 0;
+    P.off_bounds = o; o += size_t(2 * P.rows) * 4;
+    P.off_entries = o; o += size_t(P.n_entries) * 8;
+    o = (o + 15) & ~size_t(15);
+    P.off_c = o; o += ((size_t(K) * (lmax + 1) * (lmax + 1) * es + 15) & ~size_t(15));
+    P.off_g = o; o += (((size_t(n_sel) + 1) * es + 15) & ~size_t(15));
+    P.total = o;
+    return P;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ps_selected_backward_plan(int64_t n, int K, int lmax,
+                                                                        const T* __restrict__ c, int64_t n_sel,
+                                                                        const T* __restrict__ grad,
+                                                                        const int32_t* __restrict__ row_offsets,
+                                                                        const int32_t* __restrict__ entries,
+                                                                        T* __restrict__ grad_c, int32_t* status,
+                                                                        PlanLayout P)
+{
+    typedef __attribute__((ext_vector_type(16 / sizeof(T)))) T V;
+    constexpr int VW = 16 / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int2* bounds = reinterpret_cast<int2*>(smem_raw + P.off_bounds);
+    int2* ent = reinterpret_cast<int2*>(smem_raw + P.off_entries);
+    T* cs = reinterpret_cast<T*>(smem_raw + P.off_c);
+    T* gs = reinterpret_cast<T*>(smem_raw + P.off_g);
+    const int L2 = (lmax + 1) * (lmax + 1);
+    const int KL2 = K * L2;
+    const int tid = threadIdx.x;
+    // plan, checked once
+    for (int r = tid; r < P.rows; r += kThreads) {
+        int t0 = row_offsets[r], t1 = row_offsets[r + 1];
+        if (t0 < 0 || t1 < t0 || int64_t(t1) > P.n_entries) {
+            report(status, SOAP_EINVAL);
+            t0 = t1 = 0;
+        }
+        bounds[r] = make_int2(t0, t1);
+    }
+    for (int64_t t = tid; t < P.n_entries; t += kThreads) {
+        int q = entries[2 * t], partner = entries[2 * t + 1];
+        if (q < 0 || q >= n_sel || partner < 0 || partner >= K) {
+            report(status, SOAP_EINVAL);
+            q = int(n_sel);      // the zero after the gradient row
+            partner = 0;
+        }
+        ent[t] = make_int2(q, partner);
+    }
+    if (tid == 0) gs[n_sel] = T(0);
+    // rows of whole 16-byte vectors go through registers; others directly
+    const bool vec_c = KL2 % VW == 0 && KL2 / VW <= kPrefetch * kThreads;
+    const bool vec_g = n_sel % VW == 0 && n_sel / VW <= kPrefetchG * kThreads;
+    const int ncv = KL2 / VW, ngv = int(n_sel / VW);
+    V pre[kPrefetch], preg[kPrefetchG];
+    auto prefetch = [&](int64_t i) {
+        if (vec_c) {
+            const V* src = reinterpret_cast<const V*>(c + i * KL2);
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < ncv) pre[u] = src[e];
+            }
+        }
+        if (vec_g) {
+            const V* src = reinterpret_cast<const V*>(grad + i * n_sel);
+#pragma unroll
+            for (int u = 0; u < kPrefetchG; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < ngv) preg[u] = src[e];
+            }
+        }
+    };
+    int64_t i = blockIdx.x;
+    if (i < n) prefetch(i);
+    const int step_k = kThreads / L2, step_lm = kThreads - step_k * L2;
+    const int2 none = make_int2(int(n_sel), 0);   // the zero after the gradient row
+    for (; i < n; i += gridDim.x) {
+        __syncthreads();   // the previous centre's sums are done with cs and gs
+        if (vec_c) {
+            V* dst = reinterpret_cast<V*>(cs);
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < ncv) dst[e] = pre[u];
+            }
+        } else {
+            for (int e = tid; e < KL2; e += kThreads) cs[e] = c[i * KL2 + e];
+        }
+        if (vec_g) {
+            V* dst = reinterpret_cast<V*>(gs);
+#pragma unroll
+            for (int u = 0; u < kPrefetchG; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < ngv) dst[e] = preg[u];
+            }
+        } else {
+            for (int64_t e = tid; e < n_sel; e += kThreads) gs[e] = grad[i * n_sel + e];
+        }
+        __syncthreads();
+        if (i + gridDim.x < n) prefetch(i + gridDim.x);
+        int k = tid / L2, lm = tid - k * L2;
+        T* gi = grad_c + i * KL2;
+        for (int e = tid; e < KL2; e += kThreads) {
+            // floor(sqrt(lm + 1/2)) is l for lm in [l^2, (l+1)^2)
+            const int l = int(sqrtf(float(lm) + 0.5f));
+            const int2 b = bounds[k * (lmax + 1) + l];
+            // four entries per step, read together (past the row's end the
+            // entry points at the zero), summed in plan order
+            T sum = T(0);
+            for (int t = b.x; t < b.y; t += 4) {
+                int2 qe[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) qe[u] = t + u < b.y ? ent[t + u] : none;
+                T gv[4], cv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    gv[u] = gs[qe[u].x];
+                    cv[u] = cs[qe[u].y * L2 + lm];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sum += gv[u] * cv[u];
+            }
+            gi[e] = sum;
+            lm += step_lm;
+            k += step_k;
+            if (lm >= L2) {
+                lm -= L2;
+                ++k;
+            }
+        }
+    }
+}
+
 // LDS bytes: coefficients, gradient row, table of l per lm
 size_t backward_lds(size_t es, int K, int lmax, int64_t n_sel)
 {
@@ -176,6 +332,26 @@ hipError_t selected_backward_t(int64_t n, int K, int lmax, const void* c, int64_
                                const int32_t* row_offsets, const int32_t* entries, void* grad_c, int32_t* status,
                                hipStream_t stream)
 {
+    // the plan in LDS when it fits beside one centre's rows with at least
+    // two work-groups per CU
+    const PlanLayout P = plan_layout(sizeof(T), K, lmax, n_sel);
+    if (P.total <= 80 * 1024) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+            if (P.total > 65536) {
+                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ps_selected_backward_plan<T>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(P.total));
+                if (e != hipSuccess) return e;
+            }
+            const int64_t per_cu = int64_t(160 * 1024 / P.total);
+            const int64_t blocks = std::min<int64_t>(n, int64_t(cus) * per_cu);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ps_selected_backward_plan<T>), dim3(unsigned(blocks)),
+                               dim3(kThreads), P.total, stream, n, K, lmax, static_cast<const T*>(c), n_sel,
+                               static_cast<const T*>(grad), row_offsets, entries, static_cast<T*>(grad_c), status, P);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = backward_lds(sizeof(T), K, lmax, n_sel);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ps_selected_backward<T>),

@@ -574,6 +574,86 @@ def test_selected_invariants_backward_matches_oracle(dt):
     assert e <= (1e-7 if dt == torch.float64 else 1e-5)
 
 
+def _selected_backward_raw(calc, c, tri, G, corrupt=None):
+    """soap_power_spectrum_selected_backward through the C ABI with the
+    host plan, optionally corrupted by corrupt(offsets, entries) first."""
+    import ctypes
+    from paper_2101_08814_amd.soap import _ptr, _np_ptr, _precision
+    L = P._lib.lib()
+    n_sel = tri.shape[0]
+    offs = np.zeros(calc.K * (calc.lmax + 1) + 1, dtype=np.int32)
+    ent = np.zeros((max(2 * n_sel, 1), 2), dtype=np.int32)
+    assert L.soap_power_spectrum_selected_plan(calc.K, calc.lmax, n_sel, _np_ptr(tri), _np_ptr(offs),
+                                               _np_ptr(ent)) == 0
+    if corrupt is not None:
+        corrupt(offs, ent)
+    offs_d, ent_d = torch.from_numpy(offs).cuda(), torch.from_numpy(ent).cuda()
+    g = torch.tensor(G, dtype=c.dtype, device="cuda")
+    gc = torch.empty_like(c)
+    e = calc._exec()
+    assert L.soap_power_spectrum_selected_backward(ctypes.byref(e), _precision(c.dtype), c.shape[0], calc.K,
+                                                   calc.lmax, _ptr(c), n_sel, _ptr(g), _ptr(offs_d), _ptr(ent_d),
+                                                   _ptr(gc)) == 0
+    return gc, offs, ent
+
+
+def test_selected_backward_corrupted_plan():
+    """An entry of the plan out of range is reported (SOAP_EINVAL) and
+    contributes nothing; every other term is summed as before."""
+    b = synthetic.multi_species_cells(n_cells=1)
+    h = b.hypers
+    K, lmax = h["n_species"] * h["nmax"], h["lmax"]
+    calc = P.Calculator.from_hypers(h)
+    nl, pos, spc = gpu_neighbors(calc, b, torch.float64)
+    c = calc.spherical_expansion(nl, spc, torch.float64)
+    rng = np.random.default_rng(2012)
+    tri = np.stack([rng.integers(0, K, 300), rng.integers(0, K, 300), rng.integers(0, lmax + 1, 300)],
+                   1).astype(np.int32)
+    G = rng.normal(size=(b.n_atoms, 300))
+    good, offs, ent = _selected_backward_raw(calc, c, tri, G)
+    assert calc.device_status() == 0
+    r = int(np.argmax(np.diff(offs) > 0))     # a row with entries
+    t = int(offs[r])
+    q, partner = int(ent[t, 0]), int(ent[t, 1])
+    k, l = divmod(r, lmax + 1)
+
+    def corrupt(o, e):
+        e[t, 0] = tri.shape[0] + 5
+
+    bad, _, _ = _selected_backward_raw(calc, c, tri, G, corrupt)
+    assert calc.device_status() == P._lib.SOAP_EINVAL
+    calc.reset_status()
+    expect = good.clone().reshape(b.n_atoms, K, (lmax + 1) ** 2)
+    cf = c.reshape(b.n_atoms, K, (lmax + 1) ** 2)
+    Gd = torch.tensor(G, device="cuda")
+    expect[:, k, l * l:(l + 1) ** 2] -= Gd[:, q:q + 1] * cf[:, partner, l * l:(l + 1) ** 2]
+    assert torch.allclose(bad.reshape(expect.shape), expect, rtol=0, atol=1e-12)
+
+
+def test_selected_backward_large_selection():
+    """6000 triples: the plan no longer fits beside a centre's rows in LDS,
+    so the per-centre kernel that reads the plan through L2 runs; against
+    the oracle."""
+    b = synthetic.multi_species_cells(n_cells=1)
+    h = b.hypers
+    K, lmax = h["n_species"] * h["nmax"], h["lmax"]
+    calc = P.Calculator.from_hypers(h)
+    nl, pos, spc = gpu_neighbors(calc, b, torch.float32)
+    c = calc.spherical_expansion(nl, spc, torch.float32)
+    _, c_ref, _ = oracle.features(b)
+    rng = np.random.default_rng(2013)
+    n_sel = 6000
+    tri = np.stack([rng.integers(0, K, n_sel), rng.integers(0, K, n_sel), rng.integers(0, lmax + 1, n_sel)],
+                   1).astype(np.int32)
+    G = rng.normal(size=(b.n_atoms, n_sel))
+    gc = calc.power_spectrum_selected_backward(c, tri, torch.tensor(G, dtype=torch.float32, device="cuda"))
+    assert calc.device_status() == 0
+    ref = oracle.power_spectrum_selected_vjp(h, c_ref, tri, G)
+    e = rel(gc.double().cpu().numpy(), ref)
+    print(f"[selected backward 6000] rel={e:.3e}")
+    assert e <= 1e-5
+
+
 def test_vjp_full_size_against_finite_differences():
     """4096-atom liquid (2 species, nmax 10, lmax 8, rcut 6): the FP32 adjoint
     against central differences (h = 1e-4 A) of the FP64 GPU forward on 32
