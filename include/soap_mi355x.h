@@ -430,6 +430,25 @@ soap_status soap_virial(const soap_exec* exec, soap_precision precision, int32_t
 /* Number of weights for (n_out, hidden): (lmax+1) (hidden K + n_out hidden + 2 hidden). */
 soap_status soap_compress_n_params(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t* n_params);
 
+/* Checkpoint of a compression network and its optimiser state (the
+ * training of the learned compression, Sec. 4.H and Sec. 7): writes the
+ * weights, the Adam moments m and v (device arrays of n_params floats each)
+ * and the step count to the host file path, with the shape (n_out, hidden,
+ * channels, lmax) and a 64-bit hash of the contents; the file is written
+ * under path.tmp and renamed over path.  Synchronous (device-to-host
+ * copies).  SOAP_EINVAL when the file cannot be written.               */
+soap_status soap_compress_save(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t step,
+                               const float* weights, const float* adam_m, const float* adam_v, const char* path);
+
+/* Reads a file written by soap_compress_save into the device arrays
+ * weights, adam_m, adam_v (n_params floats each) and *step (host).
+ * SOAP_EINVAL, with nothing written, when the file is missing, not a
+ * checkpoint, of another version or shape (n_out, hidden, the calculator's
+ * channels and lmax), truncated, longer than its contents, or fails its
+ * hash.                                                                 */
+soap_status soap_compress_load(const soap_calculator* calc, int32_t n_out, int32_t hidden, const char* path,
+                               float* weights, float* adam_m, float* adam_v, int64_t* step);
+
 /* Bytes of device workspace that soap_compress_init_pca and
  * soap_compress_backward need.                                          */
 soap_status soap_compress_workspace_size(const soap_calculator* calc, int32_t n_out, int32_t hidden,

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "soap_internal.hpp"
@@ -888,6 +889,126 @@ soap_status soap_compress_n_params(const soap_calculator* calc, int32_t n_out, i
     CHECK(check_compress(calc, n_out, hidden));
     REQUIRE(n_params != nullptr, "n_params must not be NULL");
     *n_params = compress_params(calc, n_out, hidden);
+    return SOAP_OK;
+}
+
+// ------------------------------------------------ compression checkpoint
+// File: "SOAPCMP1", then int32 version, n_out, hidden, channels, lmax,
+// reserved (0), int64 step, n_params, the three float arrays (weights,
+// Adam m, Adam v), and the FNV-1a 64-bit hash of everything before it.
+// Little-endian, as the host writes it.
+namespace {
+
+constexpr char kCkptMagic[8] = {'S', 'O', 'A', 'P', 'C', 'M', 'P', '1'};
+constexpr int32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    int32_t version, n_out, hidden, channels, lmax, reserved;
+    int64_t step, n_params;
+};
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h)
+{
+    const unsigned char* b = static_cast<const unsigned char*>(data);
+    for (size_t k = 0; k < n; ++k) {
+        h ^= b[k];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+constexpr uint64_t kFnvBasis = 14695981039346656037ull;
+
+}  // namespace
+
+soap_status soap_compress_save(const soap_calculator* calc, int32_t n_out, int32_t hidden, int64_t step,
+                               const float* weights, const float* adam_m, const float* adam_v, const char* path)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(path != nullptr && path[0] != '\0', "path must be a file name");
+    REQUIRE(step >= 0, "step must be >= 0");
+    CHECK(check_ptr(weights, 4, "weights"));
+    CHECK(check_ptr(adam_m, 4, "adam_m"));
+    CHECK(check_ptr(adam_v, 4, "adam_v"));
+    const int64_t n = compress_params(calc, n_out, hidden);
+    std::vector<float> host(size_t(3 * n));
+    const float* src[3] = {weights, adam_m, adam_v};
+    for (int a = 0; a < 3; ++a)
+        if (hipMemcpy(host.data() + a * n, src[a], size_t(n) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(SOAP_EDEVICE, "copy of the compression state to the host failed");
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = kCkptVersion;
+    h.n_out = n_out;
+    h.hidden = hidden;
+    h.channels = calc->K;
+    h.lmax = calc->h.lmax;
+    h.step = step;
+    h.n_params = n;
+    uint64_t hash = fnv1a(&h, sizeof(h), kFnvBasis);
+    hash = fnv1a(host.data(), host.size() * 4, hash);
+    // written to a temporary name, then renamed over the target
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(SOAP_EINVAL, "cannot open %s for writing", tmp.c_str());
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(host.data(), 4, host.size(), f) == host.size() &&
+              std::fwrite(&hash, sizeof(hash), 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(SOAP_EINVAL, "writing %s failed", path);
+    }
+    return SOAP_OK;
+}
+
+soap_status soap_compress_load(const soap_calculator* calc, int32_t n_out, int32_t hidden, const char* path,
+                               float* weights, float* adam_m, float* adam_v, int64_t* step)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(path != nullptr && path[0] != '\0', "path must be a file name");
+    REQUIRE(step != nullptr, "step must not be NULL");
+    CHECK(check_ptr(weights, 4, "weights"));
+    CHECK(check_ptr(adam_m, 4, "adam_m"));
+    CHECK(check_ptr(adam_v, 4, "adam_v"));
+    const int64_t n = compress_params(calc, n_out, hidden);
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(SOAP_EINVAL, "cannot open %s", path);
+    CkptHeader h{};
+    std::vector<float> host;
+    uint64_t hash = 0;
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
+    if (ok && std::memcmp(h.magic, kCkptMagic, 8) != 0) {
+        std::fclose(f);
+        return fail(SOAP_EINVAL, "%s is not a compression checkpoint", path);
+    }
+    if (ok && (h.version != kCkptVersion || h.n_out != n_out || h.hidden != hidden || h.channels != calc->K ||
+               h.lmax != calc->h.lmax || h.n_params != n || h.step < 0 || h.reserved != 0)) {
+        std::fclose(f);
+        return fail(SOAP_EINVAL,
+                    "%s holds version %d, (n_out, hidden, channels, lmax) = (%d, %d, %d, %d); expected version %d, "
+                    "(%d, %d, %d, %d)",
+                    path, h.version, h.n_out, h.hidden, h.channels, h.lmax, kCkptVersion, n_out, hidden, calc->K,
+                    calc->h.lmax);
+    }
+    if (ok) {
+        host.resize(size_t(3 * n));
+        ok = std::fread(host.data(), 4, host.size(), f) == host.size() && std::fread(&hash, sizeof(hash), 1, f) == 1;
+        char extra;
+        ok = ok && std::fread(&extra, 1, 1, f) == 0;   // nothing after the hash
+    }
+    std::fclose(f);
+    if (!ok) return fail(SOAP_EINVAL, "%s is truncated or has trailing data", path);
+    uint64_t want = fnv1a(&h, sizeof(h), kFnvBasis);
+    want = fnv1a(host.data(), host.size() * 4, want);
+    if (want != hash) return fail(SOAP_EINVAL, "%s is corrupted (hash mismatch)", path);
+    float* dst[3] = {weights, adam_m, adam_v};
+    for (int a = 0; a < 3; ++a)
+        if (hipMemcpy(dst[a], host.data() + a * n, size_t(n) * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(SOAP_EDEVICE, "copy of the compression state to the device failed");
+    *step = h.step;
     return SOAP_OK;
 }
 

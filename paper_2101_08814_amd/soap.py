@@ -7,6 +7,7 @@ points (soap_compute_neighbors -> Calculator.compute_neighbors, ...).
 from __future__ import annotations
 
 import ctypes
+import os
 import dataclasses
 from typing import Optional
 
@@ -568,27 +569,19 @@ class Compressor:
         return loss
 
     def save(self, path: str) -> None:
-        """Writes the weights, the Adam moments and step, and the shape (n_out,
-        hidden, the calculator's channel count and lmax) to an .npz file
-        (plain arrays, no pickled objects)."""
-        np.savez(path, weights=self.weights.cpu().numpy(), m=self._m.cpu().numpy(), v=self._v.cpu().numpy(),
-                 step=np.int64(self.step), n_out=np.int64(self.Q), hidden=np.int64(self.H),
-                 channels=np.int64(self.calc.K), lmax=np.int64(self.lmax))
+        """soap_compress_save: the weights, the Adam moments and step, with the
+        shape (n_out, hidden, channels, lmax) and a hash, to a binary file."""
+        check(self.calc._L.soap_compress_save(self.calc.handle, self.Q, self.H, int(self.step), _ptr(self.weights),
+                                              _ptr(self._m), _ptr(self._v), os.fsencode(path)))
 
     def load(self, path: str) -> None:
-        """Reads a file written by save(); its shape must match this
-        compressor's (ValueError otherwise)."""
-        with np.load(path, allow_pickle=False) as f:
-            shape = tuple(int(f[k]) for k in ("n_out", "hidden", "channels", "lmax"))
-            if shape != (self.Q, self.H, self.calc.K, self.lmax):
-                raise ValueError(f"saved compressor has (n_out, hidden, channels, lmax) = {shape}, this one "
-                                 f"{(self.Q, self.H, self.calc.K, self.lmax)}")
-            for name, t in (("weights", self.weights), ("m", self._m), ("v", self._v)):
-                a = f[name]
-                if a.shape != (self.n_params,) or a.dtype != np.float32:
-                    raise ValueError(f"saved {name} has shape {a.shape} and type {a.dtype}")
-                t.copy_(torch.from_numpy(a))
-            self.step = int(f["step"])
+        """soap_compress_load: reads a file written by save(); SoapError
+        (SOAP_EINVAL) if its shape differs from this compressor's, or it is
+        truncated or corrupted."""
+        step = ctypes.c_int64()
+        check(self.calc._L.soap_compress_load(self.calc.handle, self.Q, self.H, os.fsencode(path), _ptr(self.weights),
+                                              _ptr(self._m), _ptr(self._v), ctypes.byref(step)))
+        self.step = int(step.value)
 
     def kernel_error(self, coeffs: torch.Tensor, precision=torch.float32) -> float:
         """eps_K = |K~ - K|_F / |K|_F over the centres of coeffs (synchronises)."""

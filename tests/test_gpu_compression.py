@@ -179,13 +179,14 @@ def test_training_lowers_the_kernel_error(cells):
 
 
 def test_save_and_load_round_trip(cells, tmp_path):
-    """Weights, Adam moments and step survive save/load; the loaded
-    compressor gives the same p~; a file of another shape is refused."""
+    """Weights, Adam moments and step survive soap_compress_save/load; the
+    loaded compressor gives the same p~; a file of another shape, or with a
+    flipped byte, is refused."""
     calc, c32, cd = cells
     a = P.Compressor(calc, 8, 32)
     a.weights.copy_(torch.tensor(random_weights(3, calc.K, 8, 32, calc.lmax)))
     a.train_step(cd[:64].contiguous(), lr=1e-3)
-    path = str(tmp_path / "compressor.npz")
+    path = str(tmp_path / "compressor.ckpt")
     a.save(path)
     b = P.Compressor(calc, 8, 32)
     b.load(path)
@@ -193,8 +194,18 @@ def test_save_and_load_round_trip(cells, tmp_path):
     for x, y in [(a.weights, b.weights), (a._m, b._m), (a._v, b._v)]:
         assert torch.equal(x, y)
     assert torch.equal(a.forward(cd[:64].contiguous())[1], b.forward(cd[:64].contiguous())[1])
-    with pytest.raises(ValueError):
+    with pytest.raises(P.SoapError):
         P.Compressor(calc, 8, 40).load(path)
+    # a flipped byte fails the hash and leaves the target untouched
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 0x40
+    bad = str(tmp_path / "flipped.ckpt")
+    open(bad, "wb").write(bytes(raw))
+    c = P.Compressor(calc, 8, 32)
+    before = c.weights.clone()
+    with pytest.raises(P.SoapError, match="corrupted"):
+        c.load(bad)
+    assert torch.equal(c.weights, before)
 
 
 

@@ -358,3 +358,51 @@ def test_autograd_function_passes_clean_status():
     p = SOAPFunction.apply(pos, calc, torch.zeros(5, dtype=torch.int32), None, None, None, torch.float32)
     p.sum().backward()
     assert pos.grad is not None and pos.grad.shape == (5, 3)
+
+
+def _checkpoint_bytes(n_out, hidden, channels, lmax, n_params, step=3, version=1, magic=b"SOAPCMP1", seed=0):
+    """A compression checkpoint in the documented file format (header,
+    three float arrays, FNV-1a 64-bit hash of everything before it)."""
+    import struct
+    head = magic + struct.pack("<6i2q", version, n_out, hidden, channels, lmax, 0, step, n_params)
+    body = np.random.default_rng(seed).normal(size=3 * n_params).astype("<f4").tobytes()
+    h = 14695981039346656037
+    for b in head + body:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return head + body + struct.pack("<Q", h)
+
+
+def test_compress_checkpoint_validation(tmp_path):
+    """soap_compress_load checks the file before any device copy: missing,
+    foreign, wrong shape, truncated, trailing data and hash mismatch are all
+    SOAP_EINVAL; a well-formed file passes to the copy (which has no device
+    here)."""
+    c = P.Calculator(2, 4, 3, 4.0, 0.5)
+    L = _lib.lib()
+    n = ctypes.c_int64()
+    assert L.soap_compress_n_params(c.handle, 4, 8, ctypes.byref(n)) == 0
+    npar = int(n.value)
+    fake = ctypes.c_void_p(1 << 20)      # aligned, never dereferenced on these paths
+    step = ctypes.c_int64()
+
+    def load(data):
+        path = tmp_path / "x.ckpt"
+        if data is None:
+            path = tmp_path / "missing.ckpt"
+        else:
+            path.write_bytes(data)
+        return L.soap_compress_load(c.handle, 4, 8, os.fsencode(str(path)), fake, fake, fake, ctypes.byref(step))
+
+    good = _checkpoint_bytes(4, 8, c.K, c.lmax, npar)
+    assert load(None) == _lib.SOAP_EINVAL
+    assert load(b"not a checkpoint at all" * 4) == _lib.SOAP_EINVAL
+    assert load(_checkpoint_bytes(4, 9, c.K, c.lmax, npar)) == _lib.SOAP_EINVAL
+    assert load(_checkpoint_bytes(4, 8, c.K, c.lmax, npar, version=2)) == _lib.SOAP_EINVAL
+    assert load(good[:-9]) == _lib.SOAP_EINVAL
+    assert load(good + b"\0") == _lib.SOAP_EINVAL
+    flipped = bytearray(good)
+    flipped[60] ^= 1
+    assert load(bytes(flipped)) == _lib.SOAP_EINVAL
+    assert b"corrupted" in L.soap_last_error()
+    st = load(good)
+    assert st in (_lib.SOAP_OK, _lib.SOAP_EDEVICE), st
