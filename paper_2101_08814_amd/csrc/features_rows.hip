@@ -78,7 +78,7 @@ inline RowsLayout rows_layout(int S, int nmax, int lmax, int ch)
     L.R = o; o += ch * L.npad * lm1;
     L.D = o; o += ch * L.npad * lm1;
     L.seg = o; o += 2 * S;
-    L.flag = o; o += 1;
+    L.flag = o; o += 2;
     L.pos = o; o += lm1 * KK;
     L.pyz = o; o += lm1 * KK;
     L.lk = o; o += lm1 * K;
@@ -260,13 +260,14 @@ __global__ void __launch_bounds__(kRowsThreads, sizeof(T) == 4 ? 4 : 2) k_featur
         s.dcs[KL2 + e] = T(0);
         s.dcs[2 * KL2 + e] = T(0);
     }
-    // dp positions: (l, k1, k2) for p and its self rows, and the {y, z}
-    // slots l K + k1 | (l K + k2) << 16 for the pair rows
-    for (int o = tid; o < PL; o += kRowsThreads) {
-        const int v = a.dp_pos[o];
-        const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
-        s.pos[o] = v;
-        s.pyz[o] = (l * K + k1) | ((l * K + k2) << 16);
+    // dp positions (l, k1, k2): the first two per lane are loaded now and
+    // reach LDS after the combination, so their round trip overlaps the
+    // staging
+    int posr[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int o = tid + j * kRowsThreads;
+        posr[j] = o < PL ? a.dp_pos[o] : 0;
     }
     for (int t = tid; t < LM1 * K; t += kRowsThreads) s.lk[t] = (t / K) | ((t % K) << 8);
     // items (species, block of kNB channels, lm)
@@ -309,6 +310,16 @@ __global__ void __launch_bounds__(kRowsThreads, sizeof(T) == 4 ? 4 : 2) k_featur
         }
         __syncthreads();
     }
+    // the position tables: (l, k1, k2) for p and its self rows, and the
+    // {y, z} slots l K + k1 | (l K + k2) << 16 for the pair rows
+    for (int o = tid; o < PL; o += kRowsThreads) {
+        const int j = (o - tid) / kRowsThreads;
+        const int v = j == 0 ? posr[0] : (j == 1 ? posr[1] : a.dp_pos[o]);
+        const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
+        s.pos[o] = v;
+        s.pyz[o] = (l * K + k1) | ((l * K + k2) << 16);
+    }
+    if (tid == 0) s.flag[1] = 0;
     if (a.include_center && tid < nmax) {
         const int sp = a.species[i];
         if (sp >= 0 && sp < S) s.c[(sp * nmax + tid) * L2] += static_cast<const T*>(a.center)[tid];
@@ -324,7 +335,10 @@ __global__ void __launch_bounds__(kRowsThreads, sizeof(T) == 4 ? 4 : 2) k_featur
     // (their reads clamped), so all reads of a lane are issued together
     T* p_out = static_cast<T*>(a.p) + i * int64_t(PL);
     T* dps_out = static_cast<T*>(a.dp_self) + i * int64_t(3 * PL);
-    for (int o = tid; o < PL; o += kRowsThreads) {
+    // the last wave forms p and its self rows while the others start on the
+    // pair rows; waves take pairs from a counter in LDS as they come free
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int o = wave == kRowsWaves - 1 ? lane : PL; o < PL; o += 64) {
         const int v = s.pos[o];
         const int l = v & 15, k1 = (v >> 4) & 1023, k2 = v >> 14;
         const int b1 = k1 * L2 + l * l, b2 = k2 * L2 + l * l;
@@ -346,7 +360,6 @@ __global__ void __launch_bounds__(kRowsThreads, sizeof(T) == 4 ? 4 : 2) k_featur
     }
     // pair rows of p: the last chunk is still staged, earlier ones are
     // staged again; waves synchronise only with themselves in between
-    const int wave = tid >> 6, lane = tid & 63;
     const int nlk = LM1 * K;
     V4<T>* ydw = s.yd + wave * L2;
     V4<T>* yzw = s.yz + wave * nlk;
@@ -362,10 +375,15 @@ __global__ void __launch_bounds__(kRowsThreads, sizeof(T) == 4 ? 4 : 2) k_featur
                 s.seg[2 * sp + 1] = 0;
             }
             __syncthreads();
+            if (tid == 0) s.flag[1] = 0;
             stage_rows<T, LMAX>(a, s, LY, q0, nc);
             __syncthreads();
         }
-        for (int p = wave; p < nc; p += kRowsWaves) {
+        for (;;) {
+            int p = 0;
+            if (lane == 0) p = atomicAdd(&s.flag[1], 1);
+            p = __builtin_amdgcn_readfirstlane(p);
+            if (p >= nc) break;
             const T ux = s.ux[p], uy = s.uy[p], uz = s.uz[p], ri = s.rinv[p];
             const T* Yp = s.Y + p * L2;
             for (int lm = lane; lm < L2; lm += 64) {
