@@ -166,19 +166,23 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected_backward(int K, int lm
 
 // The same adjoint with the plan held in LDS by persistent work-groups.
 // A work-group loads and checks the plan once (row bounds, entry ranges:
-// anything outside them is reported and contributes nothing), then walks
-// its centres i = blockIdx.x, blockIdx.x + gridDim.x, ...; the next
-// centre's coefficients and gradient row are loaded into registers while
-// the current one is summed, so the HBM round trip overlaps the sums.
-// Lane e = k L2 + lm reads its row's entries (q, partner) from LDS (the
-// 2l+1 lanes of a row read the same entry: a broadcast) and sums
-// grad[q] c[partner, lm] in plan order, as the kernel above.
+// anything outside them is reported and contributes nothing) and lays it
+// out again in LDS: every row padded to a multiple of four entries with
+// entries that point at a zero after the gradient row, each entry packed
+// as the byte offsets (q, partner row) of its two operands.  It then walks
+// its centres i = blockIdx.x, blockIdx.x + gridDim.x, ..., the next
+// centre's coefficients and gradient row prefetched into registers while
+// the current one is summed.  Lane e = k L2 + lm reads its row's entries
+// four at a time (one 16-byte LDS read; the 2l+1 lanes of a row read the
+// same ones) and sums grad[q] c[partner, lm] in plan order, as the kernel
+// above.
 constexpr int kPrefetch = 8;   // 16-byte vectors of c per lane held for the next centre
 constexpr int kPrefetchG = 4;  // and of the gradient row
 
 struct PlanLayout {
     int rows;                  // K (lmax + 1)
     int64_t n_entries;         // 2 n_sel
+    int64_t cap;               // entries with each row padded to a multiple of four
     size_t off_bounds, off_entries, off_c, off_g, total;
 };
 
@@ -187,14 +191,22 @@ inline PlanLayout plan_layout(size_t es, int K, int lmax, int64_t n_sel)
     PlanLayout P{};
     P.rows = K * (lmax + 1);
     P.n_entries = 2 * n_sel;
+    P.cap = P.n_entries + 3 * int64_t(P.rows);
     size_t o = 0;
     P.off_bounds = o; o += size_t(2 * P.rows) * 4;
-    P.off_entries = o; o += size_t(P.n_entries) * 8;
+    o = (o + 15) & ~size_t(15);
+    P.off_entries = o; o += size_t(P.cap) * 4;
     o = (o + 15) & ~size_t(15);
     P.off_c = o; o += ((size_t(K) * (lmax + 1) * (lmax + 1) * es + 15) & ~size_t(15));
     P.off_g = o; o += (((size_t(n_sel) + 1) * es + 15) & ~size_t(15));
     P.total = o;
     return P;
+}
+
+// operand byte offsets fit 16 bits each
+inline bool plan_packable(size_t es, int K, int lmax, int64_t n_sel)
+{
+    return (n_sel + 1) * int64_t(es) < 65536 && int64_t(K) * (lmax + 1) * (lmax + 1) * int64_t(es) < 65536;
 }
 
 template <typename T>
@@ -210,29 +222,55 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected_backward_plan(int64_t 
     constexpr int VW = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int2* bounds = reinterpret_cast<int2*>(smem_raw + P.off_bounds);
-    int2* ent = reinterpret_cast<int2*>(smem_raw + P.off_entries);
+    uint32_t* ent = reinterpret_cast<uint32_t*>(smem_raw + P.off_entries);
     T* cs = reinterpret_cast<T*>(smem_raw + P.off_c);
     T* gs = reinterpret_cast<T*>(smem_raw + P.off_g);
     const int L2 = (lmax + 1) * (lmax + 1);
     const int KL2 = K * L2;
     const int tid = threadIdx.x;
-    // plan, checked once
-    for (int r = tid; r < P.rows; r += kThreads) {
-        int t0 = row_offsets[r], t1 = row_offsets[r + 1];
-        if (t0 < 0 || t1 < t0 || int64_t(t1) > P.n_entries) {
-            report(status, SOAP_EINVAL);
-            t0 = t1 = 0;
+    const uint32_t none = uint32_t(n_sel) * uint32_t(sizeof(T));   // the zero after the gradient row
+    // padded row starts: an exclusive scan of the padded counts by the
+    // first wave, 64 rows at a time
+    if (tid < 64) {
+        int carry = 0;
+        for (int r0 = 0; r0 < P.rows; r0 += 64) {
+            const int r = r0 + tid;
+            int pc = 0, t0 = 0, t1 = 0;
+            if (r < P.rows) {
+                t0 = row_offsets[r];
+                t1 = row_offsets[r + 1];
+                if (t0 < 0 || t1 < t0 || int64_t(t1) > P.n_entries) {
+                    report(status, SOAP_EINVAL);
+                    t0 = t1 = 0;
+                }
+                pc = (t1 - t0 + 3) & ~3;
+            }
+            int inc = pc;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int up = __shfl_up(inc, d, 64);
+                if (tid >= d) inc += up;
+            }
+            if (r < P.rows) bounds[r] = make_int2(carry + inc - pc, t1 - t0);
+            carry += __shfl(inc, 63, 64);
         }
-        bounds[r] = make_int2(t0, t1);
     }
-    for (int64_t t = tid; t < P.n_entries; t += kThreads) {
-        int q = entries[2 * t], partner = entries[2 * t + 1];
-        if (q < 0 || q >= n_sel || partner < 0 || partner >= K) {
-            report(status, SOAP_EINVAL);
-            q = int(n_sel);      // the zero after the gradient row
-            partner = 0;
+    __syncthreads();
+    // entries: row r's go to [start, start + count), the rest of its padded
+    // span points at the zero
+    for (int r = tid; r < P.rows; r += kThreads) {
+        const int2 b = bounds[r];
+        const int t0 = b.y > 0 ? row_offsets[r] : 0;
+        for (int u = 0; u < ((b.y + 3) & ~3); ++u) {
+            uint32_t e = none;
+            if (u < b.y) {
+                const int q = entries[2 * (t0 + u)], partner = entries[2 * (t0 + u) + 1];
+                if (q < 0 || q >= n_sel || partner < 0 || partner >= K) report(status, SOAP_EINVAL);
+                else e = uint32_t(q) * uint32_t(sizeof(T)) | (uint32_t(partner * L2) * uint32_t(sizeof(T)) << 16);
+            }
+            ent[b.x + u] = e;
         }
-        ent[t] = make_int2(q, partner);
+        bounds[r] = make_int2(b.x, b.x + ((b.y + 3) & ~3));
     }
     if (tid == 0) gs[n_sel] = T(0);
     // rows of whole 16-byte vectors go through registers; others directly
@@ -261,7 +299,8 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected_backward_plan(int64_t 
     int64_t i = blockIdx.x;
     if (i < n) prefetch(i);
     const int step_k = kThreads / L2, step_lm = kThreads - step_k * L2;
-    const int2 none = make_int2(int(n_sel), 0);   // the zero after the gradient row
+    const unsigned char* gsb = reinterpret_cast<const unsigned char*>(gs);
+    const unsigned char* csb = reinterpret_cast<const unsigned char*>(cs);
     for (; i < n; i += gridDim.x) {
         __syncthreads();   // the previous centre's sums are done with cs and gs
         if (vec_c) {
@@ -292,18 +331,16 @@ __global__ void __launch_bounds__(kThreads) k_ps_selected_backward_plan(int64_t 
             // floor(sqrt(lm + 1/2)) is l for lm in [l^2, (l+1)^2)
             const int l = int(sqrtf(float(lm) + 0.5f));
             const int2 b = bounds[k * (lmax + 1) + l];
-            // four entries per step, read together (past the row's end the
-            // entry points at the zero), summed in plan order
+            const unsigned char* cl = csb + lm * int(sizeof(T));
             T sum = T(0);
             for (int t = b.x; t < b.y; t += 4) {
-                int2 qe[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) qe[u] = t + u < b.y ? ent[t + u] : none;
+                const uint4 q4 = *reinterpret_cast<const uint4*>(ent + t);
+                const uint32_t qe[4] = {q4.x, q4.y, q4.z, q4.w};
                 T gv[4], cv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    gv[u] = gs[qe[u].x];
-                    cv[u] = cs[qe[u].y * L2 + lm];
+                    gv[u] = *reinterpret_cast<const T*>(gsb + (qe[u] & 0xFFFFu));
+                    cv[u] = *reinterpret_cast<const T*>(cl + (qe[u] >> 16));
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) sum += gv[u] * cv[u];
@@ -335,7 +372,7 @@ hipError_t selected_backward_t(int64_t n, int K, int lmax, const void* c, int64_
     // the plan in LDS when it fits beside one centre's rows with at least
     // two work-groups per CU
     const PlanLayout P = plan_layout(sizeof(T), K, lmax, n_sel);
-    if (P.total <= 80 * 1024) {
+    if (P.total <= 80 * 1024 && plan_packable(sizeof(T), K, lmax, n_sel)) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
