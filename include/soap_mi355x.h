@@ -449,8 +449,8 @@ soap_status soap_compress_save(const soap_calculator* calc, int32_t n_out, int32
 soap_status soap_compress_load(const soap_calculator* calc, int32_t n_out, int32_t hidden, const char* path,
                                float* weights, float* adam_m, float* adam_v, int64_t* step);
 
-/* Bytes of device workspace that soap_compress_init_pca and
- * soap_compress_backward need.                                          */
+/* Bytes of device workspace that soap_compress_init_pca,
+ * soap_compress_forward_ws and soap_compress_backward need.             */
 soap_status soap_compress_workspace_size(const soap_calculator* calc, int32_t n_out, int32_t hidden,
                                          size_t* bytes);
 
@@ -476,6 +476,20 @@ soap_status soap_compress_init_pca(const soap_calculator* calc, const soap_exec*
 soap_status soap_compress_forward(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
                                   int32_t n_out, int32_t hidden, int64_t n_atoms, const float* weights,
                                   const float* coeffs, float* coeffs_out, float* p_out);
+
+/* soap_compress_forward with a device workspace of at least
+ * soap_compress_workspace_size bytes.  With SOAP_BF16_F32ACC (and the
+ * shapes of the one-wave-per-centre kernel: K, hidden <= 128 and multiples
+ * of 4, n_out <= 32, 1 <= lmax <= 12) the weights are first laid out once in
+ * the workspace as the kernel holds them in LDS (bfloat16 rows, the same
+ * rounding), and each work-group copies the next degree's image while it
+ * computes the current one; the results are those of soap_compress_forward
+ * bit for bit.  The workspace is overwritten; calls that overlap must not
+ * share it.                                                             */
+soap_status soap_compress_forward_ws(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                     int32_t n_out, int32_t hidden, int64_t n_atoms, const float* weights,
+                                     const float* coeffs, float* coeffs_out, float* p_out, void* workspace,
+                                     size_t workspace_bytes);
 
 /* Reverse mode for training: given grad_p = dL/dp~ [N][lmax+1][n_out
  * (n_out+1)/2] of the forward pass at (weights, coeffs), writes

@@ -31,6 +31,7 @@ EXPORTS = [
     "soap_spherical_expansion_backward", "soap_virial", "soap_power_spectrum_selected",
     "soap_power_spectrum_selected_plan", "soap_power_spectrum_selected_backward", "soap_gpr_workspace_size", "soap_gpr_predict",
     "soap_compress_n_params", "soap_compress_workspace_size", "soap_compress_save", "soap_compress_load",
+    "soap_compress_forward_ws",
     "soap_compress_init_pca", "soap_compress_forward", "soap_compress_backward", "soap_spectrum_gram",
     "soap_spectrum_kernel_loss", "soap_adam_step", "soap_read_device_status",
 ]
@@ -121,6 +122,8 @@ def lib():
     L.soap_gpr_predict.argtypes = [P(soap_exec), st, i64, i64, vp, vp, i64, vp, vp, vp, i32, vp, sz, vp, vp]
     L.soap_compress_n_params.restype = st
     L.soap_compress_n_params.argtypes = [vp, i32, i32, P(i64)]
+    L.soap_compress_forward_ws.restype = st
+    L.soap_compress_forward_ws.argtypes = [vp, vp, ctypes.c_int, i32, i32, i64, vp, vp, vp, vp, vp, ctypes.c_size_t]
     L.soap_compress_save.restype = st
     L.soap_compress_save.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.c_char_p]
     L.soap_compress_load.restype = st

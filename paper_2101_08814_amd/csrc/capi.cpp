@@ -282,7 +282,8 @@ size_t compress_workspace(const soap_calculator* calc, int Q, int H)
 {
     const size_t grads = size_t(kCompressSlices) * size_t(compress_params(calc, Q, H)) * sizeof(float);
     const size_t cov = size_t(kCovSlices) * (calc->h.lmax + 1) * size_t(calc->K) * calc->K * sizeof(float);
-    return std::max(grads, cov);
+    const size_t img = compress_image_bytes(calc->K, Q, H, calc->h.lmax);
+    return std::max(std::max(grads, cov), img);
 }
 
 // splitmix64 (Steele, Lea, Flood 2014) and Box-Muller normals
@@ -1099,6 +1100,35 @@ soap_status soap_compress_forward(const soap_calculator* calc, const soap_exec* 
     a.pt = p_out;
     if (precision == SOAP_BF16_F32ACC)
         return launched(launch_compress_forward_bf16(a, stream_of(exec)), "compression (bf16)");
+    return launched(launch_compress_forward(a, stream_of(exec)), "compression");
+}
+
+soap_status soap_compress_forward_ws(const soap_calculator* calc, const soap_exec* exec, soap_precision precision,
+                                     int32_t n_out, int32_t hidden, int64_t n_atoms, const float* weights,
+                                     const float* coeffs, float* coeffs_out, float* p_out, void* workspace,
+                                     size_t workspace_bytes)
+{
+    clear_error();
+    CHECK(check_compress(calc, n_out, hidden));
+    REQUIRE(precision == SOAP_F32 || precision == SOAP_BF16_F32ACC, "precision must be SOAP_F32 or SOAP_BF16_F32ACC");
+    REQUIRE(n_atoms >= 0 && n_atoms < (int64_t(1) << 31), "n_atoms must be in [0, 2^31)");
+    REQUIRE(coeffs_out != nullptr || p_out != nullptr, "coeffs_out and p_out must not both be NULL");
+    if (n_atoms == 0) return SOAP_OK;
+    CHECK(check_ptr(weights, 4, "weights"));
+    CHECK(check_ptr(coeffs, 4, "coeffs"));
+    CHECK(check_ptr(coeffs_out, 4, "coeffs_out", true));
+    CHECK(check_ptr(p_out, 4, "p_out", true));
+    CHECK(check_ptr(workspace, 256, "workspace"));
+    REQUIRE(workspace_bytes >= compress_workspace(calc, n_out, hidden), "workspace too small");
+    CompressArgs a = compress_args(calc, exec, n_out, hidden, n_atoms);
+    a.w = weights;
+    a.c = coeffs;
+    a.ct = coeffs_out;
+    a.pt = p_out;
+    if (precision == SOAP_BF16_F32ACC) {
+        if (compress_image_bytes(calc->K, n_out, hidden, calc->h.lmax) > 0) a.img = workspace;
+        return launched(launch_compress_forward_bf16(a, stream_of(exec)), "compression (bf16)");
+    }
     return launched(launch_compress_forward(a, stream_of(exec)), "compression");
 }
 

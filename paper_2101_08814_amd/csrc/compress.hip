@@ -866,11 +866,13 @@ struct WaveLayout {
     int E1, E2, E;           // weight float4s per l: W1 rows, W2 rows, then {alpha, beta}
     int x_bytes, cb_bytes;   // per centre
     int w1, w2, ab, x, cb, total;   // byte offsets, 16-byte aligned
+    int wbytes;              // bytes of one l's weights in LDS
+    int wstride;             // with the image: one l's image rounded up to whole 1 KB pieces (two LDS buffers)
 };
 
 __host__ __device__ inline int up16(int b) { return (b + 15) & ~15; }
 
-__host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax, int cpw)
+__host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax, int cpw, bool img = false)
 {
     WaveLayout W;
     W.Kp = (K + 31) / 32 * 32;
@@ -892,6 +894,9 @@ __host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax,
     W.w1 = o; o += up16(W.HT * 16 * W.XS * 2);
     W.w2 = o; o += up16(W.QT * 16 * W.HS * 2);
     W.ab = o; o += up16(2 * W.Hp * 4);
+    W.wbytes = o;
+    W.wstride = (o + 1023) & ~1023;
+    if (img) o = 2 * W.wstride;
     W.x = o; o += cpw * W.x_bytes;
     W.cb = o; o += cpw * W.cb_bytes;
     W.total = o;
@@ -944,7 +949,26 @@ __device__ __forceinline__ void wave_weight_put(unsigned char* smem, const WaveL
     }
 }
 
-template <bool WANT_CT, bool WANT_PT, int QT>
+// The weights of every l as they sit in LDS (bfloat16 rows of W1 in the
+// unit order, W2 rows, then {alpha, beta} in float, zeros elsewhere): one
+// work-group per l writes bytes [0, W.x) of image l.
+__global__ void __launch_bounds__(256) k_cmp_image(CompressArgs a, WaveLayout W)
+{
+    const int l = blockIdx.x;
+    unsigned char* img = static_cast<unsigned char*>(a.img) + size_t(l) * W.wstride;
+    const float* wl = a.w + size_t(l) * (a.H * a.K + a.Q * a.H + 2 * a.H);
+    for (int e = threadIdx.x; e < W.wstride / 16; e += blockDim.x)
+        reinterpret_cast<uint4*>(img)[e] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < W.E; e += blockDim.x) {
+        int src, dst;
+        wave_weight_slot(a, W, e, src, dst);
+        wave_weight_put(img, W, dst, src >= 0 ? *reinterpret_cast<const float4*>(wl + src) : make_float4(0.f, 0.f, 0.f, 0.f));
+    }
+}
+
+
+template <bool WANT_CT, bool WANT_PT, int QT, bool IMG>
 __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs a, WaveLayout W)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -955,20 +979,35 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
     const bool live = i < a.n;
     const unsigned short* W1s = reinterpret_cast<const unsigned short*>(smem_raw + W.w1);
     const unsigned short* W2s = reinterpret_cast<const unsigned short*>(smem_raw + W.w2);
-    const float* ab = reinterpret_cast<const float*>(smem_raw + W.ab);
+    const float* ab = reinterpret_cast<const float*>(smem_raw + W.ab);   // (buffer l % 2 with the image)
     unsigned short* X = reinterpret_cast<unsigned short*>(smem_raw + W.x + wave * W.x_bytes);
     float* cb = reinterpret_cast<float*>(smem_raw + W.cb + wave * W.cb_bytes);
     const int lsize = H * K + Q * H + 2 * H;
 
     // this lane's weight float4s (the same offsets for every l)
-    int wsrc[kWQuads], wdst[kWQuads];
+    int wsrc[IMG ? 1 : kWQuads], wdst[IMG ? 1 : kWQuads];
+    if constexpr (!IMG) {
 #pragma unroll
-    for (int u = 0; u < kWQuads; ++u) {
-        const int e = tid + nthr * u;
-        wsrc[u] = -1;
-        wdst[u] = -1;
-        if (e < W.E) wave_weight_slot(a, W, e, wsrc[u], wdst[u]);
+        for (int u = 0; u < kWQuads; ++u) {
+            const int e = tid + nthr * u;
+            wsrc[u] = -1;
+            wdst[u] = -1;
+            if (e < W.E) wave_weight_slot(a, W, e, wsrc[u], wdst[u]);
+        }
     }
+    // with the image: l's weights go straight from global memory to LDS
+    // buffer l % 2 (16 bytes per lane, 1 KB per wave and instruction), the
+    // next l's while the current one is computed
+    const int nwaves = nthr >> 6;
+    auto fetch_image = [&](int l) __attribute__((always_inline)) {
+        const unsigned char* src = static_cast<const unsigned char*>(a.img) + size_t(l) * W.wstride;
+        unsigned char* dst = smem_raw + (l & 1) * W.wstride;
+        for (int piece = wave; piece < W.wstride / 1024; piece += nwaves)
+            __builtin_amdgcn_global_load_lds(src + piece * 1024 + lane * 16,
+                                             (__attribute__((address_space(3))) void*)(dst + piece * 1024),
+                                             16, 0, 0);
+    };
+    if constexpr (IMG) fetch_image(0);
 
     // X[lm][k] of this centre, bfloat16 (zero for k in [K, Kp))
     if (live) {
@@ -1010,7 +1049,17 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
     const float* wl = a.w;
     for (int l = 0; l <= lmax; ++l, wl += lsize) {
         __syncthreads();   // the weights of l - 1 are no longer read
-        {
+        if constexpr (IMG) {
+            // l's image is in buffer l % 2 once every wave's loads are done;
+            // buffer (l + 1) % 2 held l - 1, which no wave reads any more
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (l < lmax) fetch_image(l + 1);
+            const unsigned char* wb = smem_raw + (l & 1) * W.wstride;
+            W1s = reinterpret_cast<const unsigned short*>(wb + W.w1);
+            W2s = reinterpret_cast<const unsigned short*>(wb + W.w2);
+            ab = reinterpret_cast<const float*>(wb + W.ab);
+        } else {
             float4 wv[kWQuads];
 #pragma unroll
             for (int u = 0; u < kWQuads; ++u)   // every load issued before any is used
@@ -1025,8 +1074,8 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
                 wave_weight_put(smem_raw, W, d0,
                                 s0 >= 0 ? *reinterpret_cast<const float4*>(wl + s0) : make_float4(0.f, 0.f, 0.f, 0.f));
             }
+            __syncthreads();
         }
-        __syncthreads();
         if (!live) continue;
         const int M = 2 * l + 1, b = l * l, MT = (M + 15) >> 4;
         // layer 1: k-steps outside, the hidden tiles' accumulators inside;
@@ -1187,11 +1236,16 @@ hipError_t launch_compress_forward(const CompressArgs& a, hipStream_t stream)
 }
 
 
-template <int QT>
+template <int QT, bool IMG>
 hipError_t launch_cmp_wave_q(const CompressArgs& a, const WaveLayout& W, hipStream_t stream)
 {
-    auto kernel = a.ct ? (a.pt ? k_cmp_fwd_wave<true, true, QT> : k_cmp_fwd_wave<true, false, QT>)
-                       : k_cmp_fwd_wave<false, true, QT>;
+    if (IMG) {
+        hipLaunchKernelGGL(k_cmp_image, dim3(unsigned(a.lmax + 1)), dim3(256), 0, stream, a, W);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    auto kernel = a.ct ? (a.pt ? k_cmp_fwd_wave<true, true, QT, IMG> : k_cmp_fwd_wave<true, false, QT, IMG>)
+                       : k_cmp_fwd_wave<false, true, QT, IMG>;
     if (W.total > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, W.total);
@@ -1205,23 +1259,33 @@ hipError_t launch_cmp_wave_q(const CompressArgs& a, const WaveLayout& W, hipStre
 // multiples of 4 (weights and c read as float4), Q <= 32, 1 <= lmax <= 12
 // (a float4 of c then spans at most two lm rows), 16-byte aligned c and
 // weights, at least two centres per work-group
-bool cmp_wave_fits(const CompressArgs& a, WaveLayout& W)
+bool cmp_wave_fits(const CompressArgs& a, WaveLayout& W, bool img = false)
 {
     if (a.K > 128 || a.H > 128 || a.Q > 32 || a.lmax < 1 || a.lmax > 12) return false;
     if (a.K % 4 != 0 || a.H % 4 != 0) return false;
     if ((reinterpret_cast<uintptr_t>(a.c) & 15) != 0 || (reinterpret_cast<uintptr_t>(a.w) & 15) != 0) return false;
     for (int cpw = kWaveCentres; cpw >= 2; --cpw) {
-        W = wave_layout(a.K, a.Q, a.H, a.lmax, cpw);
+        W = wave_layout(a.K, a.Q, a.H, a.lmax, cpw, img);
         if (W.total <= 160 * 1024) return true;
     }
     return false;
+}
+
+size_t compress_image_bytes(int K, int Q, int H, int lmax)
+{
+    if (K > 128 || H > 128 || Q > 32 || lmax < 1 || lmax > 12 || K % 4 != 0 || H % 4 != 0) return 0;
+    const WaveLayout W = wave_layout(K, Q, H, lmax, 2, true);
+    return size_t(lmax + 1) * W.wstride;
 }
 
 hipError_t launch_compress_forward_bf16(const CompressArgs& a, hipStream_t stream)
 {
     if (a.n == 0) return hipSuccess;
     WaveLayout W;
-    if (cmp_wave_fits(a, W)) return a.Q <= 16 ? launch_cmp_wave_q<1>(a, W, stream) : launch_cmp_wave_q<2>(a, W, stream);
+    if (a.img && (reinterpret_cast<uintptr_t>(a.img) & 15) == 0 && cmp_wave_fits(a, W, true))
+        return a.Q <= 16 ? launch_cmp_wave_q<1, true>(a, W, stream) : launch_cmp_wave_q<2, true>(a, W, stream);
+    if (cmp_wave_fits(a, W))
+        return a.Q <= 16 ? launch_cmp_wave_q<1, false>(a, W, stream) : launch_cmp_wave_q<2, false>(a, W, stream);
     if (a.K > 32 * kKS1 || a.H > 16 * 4 * kMT || a.Q > 64) return hipErrorNotSupported;
     const size_t lds = compress_bf16_lds(a);
     if (lds > 160 * 1024) return hipErrorNotSupported;

@@ -192,8 +192,12 @@ struct CompressArgs {
     float* gpart;              // backward: per-slice partial gradients [slices][n_params]
     int slices;
     int32_t* status;
+    void* img;                 // bfloat16 forward: LDS image of every l's weights (device workspace) or NULL
 };
 
+// bytes of the weight image of the bfloat16 forward (0 when its shapes do
+// not take one)
+size_t compress_image_bytes(int K, int Q, int H, int lmax);
 size_t compress_fwd_lds(const CompressArgs& a);
 size_t compress_bwd_lds(const CompressArgs& a);
 hipError_t launch_compress_forward(const CompressArgs& a, hipStream_t stream);

@@ -513,6 +513,27 @@ class Compressor:
         pt = (torch.empty((N, self.lmax + 1, self.Q * (self.Q + 1) // 2), dtype=torch.float32, device=dev)
               if want_p else None)
         e = self.calc._exec()
+        if prec == SOAP_BF16_F32ACC and self._ws.device == dev:
+            # the weights laid out once in the workspace (bit for bit the
+            # same results as soap_compress_forward)
+            check(self.calc._L.soap_compress_forward_ws(self.calc.handle, ctypes.byref(e), prec, self.Q, self.H, N,
+                                                        _ptr(self.weights), _ptr(coeffs), _ptr(ct), _ptr(pt),
+                                                        _ptr(self._ws), self._ws.numel()))
+        else:
+            check(self.calc._L.soap_compress_forward(self.calc.handle, ctypes.byref(e), prec, self.Q, self.H, N,
+                                                     _ptr(self.weights), _ptr(coeffs), _ptr(ct), _ptr(pt)))
+        return ct, pt
+
+    def forward_plain(self, coeffs: torch.Tensor, precision=torch.float32, want_coeffs: bool = False,
+                      want_p: bool = True):
+        """soap_compress_forward without a workspace (the weights staged from
+        their float form for every degree)."""
+        N, dev = int(coeffs.shape[0]), coeffs.device
+        prec = SOAP_BF16_F32ACC if precision in ("bf16", torch.bfloat16, SOAP_BF16_F32ACC) else SOAP_F32
+        ct = torch.empty((N, self.Q, self.calc.L2), dtype=torch.float32, device=dev) if want_coeffs else None
+        pt = (torch.empty((N, self.lmax + 1, self.Q * (self.Q + 1) // 2), dtype=torch.float32, device=dev)
+              if want_p else None)
+        e = self.calc._exec()
         check(self.calc._L.soap_compress_forward(self.calc.handle, ctypes.byref(e), prec, self.Q, self.H, N,
                                                  _ptr(self.weights), _ptr(coeffs), _ptr(ct), _ptr(pt)))
         return ct, pt

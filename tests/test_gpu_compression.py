@@ -178,6 +178,21 @@ def test_training_lowers_the_kernel_error(cells):
     assert after < before
 
 
+@pytest.mark.parametrize("n_centres,Q,H", [(512, 16, 128), (301, 32, 128), (37, 32, 96), (45, 12, 40)])
+def test_forward_bf16_weight_image_is_bit_exact(cells, n_centres, Q, H):
+    """soap_compress_forward_ws (weights laid out once in the workspace,
+    copied to LDS by direct loads, two buffers) gives exactly the results of
+    soap_compress_forward (weights staged from their float form)."""
+    calc, c32, cd = cells
+    cmp_ = P.Compressor(calc, Q, H)
+    cmp_.weights.copy_(torch.tensor(random_weights(5, calc.K, Q, H, calc.lmax)))
+    cb = cd[:n_centres].contiguous()
+    ct_a, pt_a = cmp_.forward(cb, precision="bf16", want_coeffs=True)
+    ct_b, pt_b = cmp_.forward_plain(cb, precision="bf16", want_coeffs=True)
+    assert calc.device_status() == 0
+    assert torch.equal(ct_a, ct_b) and torch.equal(pt_a, pt_b)
+
+
 def test_save_and_load_round_trip(cells, tmp_path):
     """Weights, Adam moments and step survive soap_compress_save/load; the
     loaded compressor gives the same p~; a file of another shape, or with a
