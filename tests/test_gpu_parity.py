@@ -597,15 +597,17 @@ def _selected_backward_raw(calc, c, tri, G, corrupt=None):
     return gc, offs, ent
 
 
-def test_selected_backward_corrupted_plan():
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_selected_backward_corrupted_plan(dt):
     """An entry of the plan out of range is reported (SOAP_EINVAL) and
-    contributes nothing; every other term is summed as before."""
+    contributes nothing; every other term is summed as before (FP32: the
+    plan held in LDS; FP64: the plan read through L2)."""
     b = synthetic.multi_species_cells(n_cells=1)
     h = b.hypers
     K, lmax = h["n_species"] * h["nmax"], h["lmax"]
     calc = P.Calculator.from_hypers(h)
-    nl, pos, spc = gpu_neighbors(calc, b, torch.float64)
-    c = calc.spherical_expansion(nl, spc, torch.float64)
+    nl, pos, spc = gpu_neighbors(calc, b, dt)
+    c = calc.spherical_expansion(nl, spc, dt)
     rng = np.random.default_rng(2012)
     tri = np.stack([rng.integers(0, K, 300), rng.integers(0, K, 300), rng.integers(0, lmax + 1, 300)],
                    1).astype(np.int32)
@@ -625,15 +627,49 @@ def test_selected_backward_corrupted_plan():
     calc.reset_status()
     expect = good.clone().reshape(b.n_atoms, K, (lmax + 1) ** 2)
     cf = c.reshape(b.n_atoms, K, (lmax + 1) ** 2)
-    Gd = torch.tensor(G, device="cuda")
+    Gd = torch.tensor(G, dtype=dt, device="cuda")
     expect[:, k, l * l:(l + 1) ** 2] -= Gd[:, q:q + 1] * cf[:, partner, l * l:(l + 1) ** 2]
-    assert torch.allclose(bad.reshape(expect.shape), expect, rtol=0, atol=1e-12)
+    atol = 1e-12 if dt == torch.float64 else 1e-5 * float(good.abs().max())
+    assert torch.allclose(bad.reshape(expect.shape), expect, rtol=0, atol=atol)
 
 
-def test_selected_backward_large_selection():
-    """6000 triples: the plan no longer fits beside a centre's rows in LDS,
-    so the per-centre kernel that reads the plan through L2 runs; against
-    the oracle."""
+def test_selected_backward_overlapping_rows():
+    """Row offsets that are not monotonic pass the per-row check but make
+    rows overlap: more entries than the plan holds.  FP32 (plan in LDS):
+    reported as SOAP_EINVAL, the rows that no longer fit left empty, the
+    output finite."""
+    b = synthetic.multi_species_cells(n_cells=1)
+    h = b.hypers
+    K, lmax = h["n_species"] * h["nmax"], h["lmax"]
+    calc = P.Calculator.from_hypers(h)
+    nl, pos, spc = gpu_neighbors(calc, b, torch.float32)
+    c = calc.spherical_expansion(nl, spc, torch.float32)
+    rng = np.random.default_rng(2014)
+    tri = np.stack([rng.integers(0, K, 300), rng.integers(0, K, 300), rng.integers(0, lmax + 1, 300)],
+                   1).astype(np.int32)
+    G = rng.normal(size=(b.n_atoms, 300))
+    good, offs, ent = _selected_backward_raw(calc, c, tri, G)
+    assert calc.device_status() == 0
+
+    def corrupt(o, e):
+        # rows 0, 2, 4, 6 each claim every entry (rows 1, 3, 5, 7 run
+        # backwards and fail the check): with the rows after them about
+        # twice what the plan holds
+        o[1:8] = [o[-1], 0, o[-1], 0, o[-1], 0, o[-1]]
+
+    bad, _, _ = _selected_backward_raw(calc, c, tri, G, corrupt)
+    assert calc.device_status() == P._lib.SOAP_EINVAL
+    calc.reset_status()
+    assert torch.isfinite(bad).all()
+
+
+@pytest.mark.parametrize("n_sel", [6000, 9000])
+def test_selected_backward_large_selection(n_sel):
+    """Large selections against the oracle: at 6000 triples the LDS plan
+    takes 118 KB, one work-group per CU instead of two; at 9000 the gradient
+    row no longer fits beside the coefficients in the plan's 16-bit
+    addresses, so the per-centre kernel that reads the plan through L2
+    runs."""
     b = synthetic.multi_species_cells(n_cells=1)
     h = b.hypers
     K, lmax = h["n_species"] * h["nmax"], h["lmax"]
@@ -642,7 +678,6 @@ def test_selected_backward_large_selection():
     c = calc.spherical_expansion(nl, spc, torch.float32)
     _, c_ref, _ = oracle.features(b)
     rng = np.random.default_rng(2013)
-    n_sel = 6000
     tri = np.stack([rng.integers(0, K, n_sel), rng.integers(0, K, n_sel), rng.integers(0, lmax + 1, n_sel)],
                    1).astype(np.int32)
     G = rng.normal(size=(b.n_atoms, n_sel))
@@ -650,7 +685,7 @@ def test_selected_backward_large_selection():
     assert calc.device_status() == 0
     ref = oracle.power_spectrum_selected_vjp(h, c_ref, tri, G)
     e = rel(gc.double().cpu().numpy(), ref)
-    print(f"[selected backward 6000] rel={e:.3e}")
+    print(f"[selected backward {n_sel}] rel={e:.3e}")
     assert e <= 1e-5
 
 
