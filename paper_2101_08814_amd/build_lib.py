@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libsoap_mi355x.so")
 
 SOURCES = ["capi.cpp", "tables.cpp", "neighbors.hip", "features.hip", "gradient_rows.hip", "power_spectrum.hip",
            "backward.hip", "compress.hip", "gpr.hip", "selected.hip", "noalloc.hip",
-           "expansion_lanes.hip", "backward_lanes.hip",
+           "expansion_lanes.hip", "expansion_packed.hip", "backward_lanes.hip",
            "radial.hip", "features_rows.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -315,6 +315,10 @@ LaneLayout choose_lane_layout(int S, int nmax, int lmax, bool want_p, size_t ele
 hipError_t launch_expansion_lanes(const FeatureArgs& a, bool f64, hipStream_t stream)
 {
     const bool want_p = a.p != nullptr;
+    if (!want_p) {
+        hipError_t e = launch_expansion_packed(a, f64, stream);
+        if (e != hipErrorNotSupported) return e;
+    }
     const size_t elem = f64 ? 8 : 4;
     LaneLayout W = choose_lane_layout(a.S, a.nmax, a.lmax, want_p, elem);
     if (W.total == 0 || a.n_atoms == 0) return W.total == 0 ? hipErrorNotSupported : hipSuccess;

@@ -150,6 +150,12 @@ LaneLayout choose_lane_layout(int S, int nmax, int lmax, bool want_p, size_t ele
 // c (and p when a.p is set) with one lane per pair; hipErrorNotSupported
 // when the layout does not fit
 hipError_t launch_expansion_lanes(const FeatureArgs& a, bool f64, hipStream_t stream);
+// c alone with the pairs of several centres packed into each wave's
+// chunks; hipErrorNotSupported when p is asked for or the layout does not fit
+struct PackLayout {
+    int G, np, nls, l2s, ys, total, cpw;
+};
+hipError_t launch_expansion_packed(const FeatureArgs& a, bool f64, hipStream_t stream);
 // per-pair dL/dr_ji of the adjoint with one lane per pair
 bool expansion_backward_lanes_fits(const FeatureArgs& a, bool f64);
 hipError_t launch_expansion_backward_lanes(const FeatureArgs& a, bool f64, const void* grad_c, void* grad_pair,
