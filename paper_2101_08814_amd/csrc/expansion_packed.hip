@@ -35,22 +35,35 @@ constexpr int pack_slots()
     return (GMAX * (LMAX + 1) * (LMAX + 1) + 63) / 64;
 }
 
+// waves per SIMD the register allocation aims at (where it fits without
+// spilling: three at nmax <= 8, lmax <= 6 in FP32, where the LDS allows
+// eleven waves per CU; two up to lmax 8)
 template <typename T, int LMAX, int GMAX>
-__global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayout W)
+constexpr int pack_waves()
+{
+    return sizeof(T) != 4 ? 1 : (GMAX <= 2 && LMAX <= 6) ? 3 : LMAX <= 8 ? 2 : 1;
+}
+
+template <typename T, int LMAX, int GMAX>
+__global__ void __launch_bounds__(64, (pack_waves<T, LMAX, GMAX>())) k_expansion_packed(FeatureArgs a, PackLayout W)
 {
     constexpr int LM1 = LMAX + 1, L2 = LM1 * LM1, NS = pack_slots<LMAX, GMAX>();
+    constexpr int kNB = GMAX <= 2 ? 3 : 2;   // radial quads in flight
+    // LDS rows of a pair: radial values [l][4 GMAX] and a spare quad, and
+    // the harmonics (odd stride)
+    constexpr int NP = 4 * GMAX, NLS = LM1 * NP + 4, L2S = L2 | 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* Rs = reinterpret_cast<T*>(smem_raw);   // [pair][l][np] radial values
-    T* Ys = Rs + W.ys;                         // [pair][l2s] harmonics
+    T* Rs = reinterpret_cast<T*>(smem_raw);   // [pair][NLS] radial values
+    T* Ys = Rs + kPackCh * NLS;                // [pair][L2S] harmonics
     const int lane = threadIdx.x;
     if (a.pair_offsets[a.n_atoms] > a.pair_capacity) {
         if (lane == 0) put_status(a.status, SOAP_ECAPACITY);
         return;
     }
-    const int nmax = a.nmax, S = a.S, G = W.G, np = W.np;
+    const int nmax = a.nmax, S = a.S, G = W.G;
     const int nL2 = nmax * L2, NI = G * L2, nq = LM1 * G;
     const int nl = LM1 * nmax;
-    const int pad = np - nmax, gmul = (65536 + G - 1) / G;   // l of quad u: (u * gmul) >> 16
+    const int pad = 4 * G - nmax, gmul = (65536 + G - 1) / G;   // l of quad u: (u * gmul) >> 16
     const int64_t c0 = int64_t(blockIdx.x) * W.cpw;
     const int ncw = int(a.n_atoms - c0 < W.cpw ? a.n_atoms - c0 : W.cpw);
     int64_t bnd[kPackMaxCpw + 1];   // pair range of each of the wave's centres
@@ -71,8 +84,25 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
         const int ng = v / L2, lm = v - ng * L2;
         const bool in = v < NI;
         yoff[u] = in ? lm : 0;
-        roff[u] = in ? l_of(lm) * np + 4 * ng : 0;
+        roff[u] = in ? l_of(lm) * NP + 4 * ng : 0;
         acc[u] = V4<T>{T(0), T(0), T(0), T(0)};
+    }
+    // the central atom's terms in LDS, so that writing a block waits on no
+    // global load
+    T* Cs = Ys + kPackCh * L2S;
+    if (lane < kPackMaxN) Cs[lane] = lane < nmax ? centre_term[lane] : T(0);
+    // species of the wave's centres, 16 bits each (0xFFFF: no central term)
+    uint64_t cspc = ~uint64_t(0);
+#pragma unroll
+    for (int k = 0; k < kPackMaxCpw; ++k) {
+        if (a.include_center && k < ncw) {
+            const int si = a.species[c0 + k];
+            if (si < 0 || si >= S) {
+                if (lane == 0) put_status(a.status, SOAP_ESPECIES);
+            } else {
+                cspc = (cspc & ~(uint64_t(0xFFFF) << (16 * k))) | (uint64_t(si) << (16 * k));
+            }
+        }
     }
     const int nsl = (NI + 63) >> 6;   // slots with items
 
@@ -123,30 +153,41 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
             for (int k = 1; k < kPackMaxCpw; ++k) cl += q >= bnd[k] ? 1 : 0;
             key = cl * S + spq;
             const V4<T>* cf = coef + int64_t(g.k) * nl;
-            T* rrow = Rs + p * W.nls;
+            T* rrow = Rs + p * NLS;
             const T tt = g.t, f = g.f;
-            // radial quads u = h, h + 2, ...: four n of one l, coefficient
-            // j = l nmax + 4 (u - l G) = 4 u - l pad, LDS l np + 4 (u - l G) = 4 u.
+            // radial quads u = h + 2 i: four n of one l, coefficient
+            // j = l nmax + 4 (u - l G) = 4 u - l pad, LDS l NP + 4 (u - l G)
+            // = 4 u + 4 l (GMAX - G).
             // The last quad of a degree may read up to three values past it
             // (the next interval's, or the table's zero tail), which land in
-            // the row's padding.
+            // the row's padding.  Every lane takes QH quads: those past nq
+            // read the last quad's coefficients and write the row's spare
+            // quad, so that each load is used on every path.
+            constexpr int QH = (LM1 * GMAX + 1) / 2;
             auto coefs = [&](int u, V4<T>* A) __attribute__((always_inline)) {
+                u = u < nq ? u : nq - 1;
                 const int j = 4 * u - ((u * gmul) >> 16) * pad;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) A[k] = cf[j + k];
             };
             auto put = [&](int u, const V4<T>* A) __attribute__((always_inline)) {
+                const int o = u < nq ? 4 * u + 4 * ((u * gmul) >> 16) * (GMAX - G) : LM1 * NP;
                 V4<T> r;
                 r.x = f * (A[0].x + tt * (A[0].y + tt * (A[0].z + tt * A[0].w)));
                 r.y = f * (A[1].x + tt * (A[1].y + tt * (A[1].z + tt * A[1].w)));
                 r.z = f * (A[2].x + tt * (A[2].y + tt * (A[2].z + tt * A[2].w)));
                 r.w = f * (A[3].x + tt * (A[3].y + tt * (A[3].z + tt * A[3].w)));
-                *reinterpret_cast<V4<T>*>(rrow + 4 * u) = r;
+                *reinterpret_cast<V4<T>*>(rrow + o) = r;
             };
-            V4<T> A[4], B[4];
-            int u = h;
-            if (u < nq) coefs(u, A);   // in flight during the harmonics
-            T* yrow = Ys + p * W.l2s;
+            // the first three quads in flight during the harmonics, then each
+            // buffer refilled with the quad three ahead
+            constexpr int NB = QH < kNB ? QH : kNB;
+            V4<T> Bf[NB][4];
+            static_for<0, NB>([&](auto I) __attribute__((always_inline)) {
+                constexpr int i = decltype(I)::value;
+                coefs(h + 2 * i, Bf[i]);
+            });
+            T* yrow = Ys + p * L2S;
             YlmStream<T, LMAX> ys(g.ux, g.uy, g.uz);
             static_for<0, LM1>([&](auto Lc) __attribute__((always_inline)) {
                 constexpr int L = decltype(Lc)::value;
@@ -154,13 +195,11 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
                     yrow[L * L + mi] = Y;
                 });
             });
-            for (; u < nq; u += 4) {
-                if (u + 2 < nq) coefs(u + 2, B);
-                put(u, A);
-                if (u + 2 >= nq) break;
-                if (u + 4 < nq) coefs(u + 4, A);
-                put(u + 2, B);
-            }
+            static_for<0, QH>([&](auto I) __attribute__((always_inline)) {
+                constexpr int i = decltype(I)::value;
+                put(h + 2 * i, Bf[i % NB]);
+                if constexpr (i + NB < QH) coefs(h + 2 * (i + NB), Bf[i % NB]);
+            });
         }
         wave_sync();
         return key;
@@ -171,21 +210,31 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
         static_for<1, NS + 1>([&](auto Nc) __attribute__((always_inline)) {
             constexpr int NU = decltype(Nc)::value;
             if (nsl == NU) {
-                const T* yb = Ys + lo * W.l2s;
-                const T* rb = Rs + lo * W.nls;
-#pragma unroll 2
-                for (int p = lo; p < hi; ++p) {
+                const T* yb = Ys + lo * L2S;
+                const T* rb = Rs + lo * NLS;
+                auto pair = [&](int k) __attribute__((always_inline)) {
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
-                        const T Y = yb[yoff[u]];
-                        const V4<T> R = *reinterpret_cast<const V4<T>*>(rb + roff[u]);
+                        const T Y = yb[k * L2S + yoff[u]];
+                        const V4<T> R = *reinterpret_cast<const V4<T>*>(rb + k * NLS + roff[u]);
                         acc[u].x += R.x * Y;
                         acc[u].y += R.y * Y;
                         acc[u].z += R.z * Y;
                         acc[u].w += R.w * Y;
                     }
-                    yb += W.l2s;
-                    rb += W.nls;
+                };
+                // four pairs per step at fixed offsets from one address per slot
+                int p = lo;
+                for (; p + 4 <= hi; p += 4) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) pair(k);
+                    yb += 4 * L2S;
+                    rb += 4 * NLS;
+                }
+                for (; p < hi; ++p) {
+                    pair(0);
+                    yb += L2S;
+                    rb += NLS;
                 }
             }
         });
@@ -194,29 +243,28 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
     // atom adds its term to lm = 0 of its own species
     auto flush = [&](int cl, int sp) __attribute__((always_inline)) {
         const int key = cl * S + sp;
-        bool own = false;
-        if (a.include_center) {
-            const int si = a.species[c0 + cl];
-            if (si < 0 || si >= S) {
-                if (lane == 0) put_status(a.status, SOAP_ESPECIES);
-            } else {
-                own = si == sp;
-            }
-        }
+        const bool own = int((cspc >> (16 * cl)) & 0xFFFF) == sp;
         T* out = c_out + int64_t(key) * nL2;
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
-            const T x4[4] = {acc[u].x, acc[u].y, acc[u].z, acc[u].w};
             const int v = lane + 64 * u;
             const int ng = v / L2, lm = v - ng * L2;
             const int nn = v < NI ? min(4, nmax - 4 * ng) : 0;   // n of the item that exist
+            const bool cen = own && lm == 0;
+            T x4[4] = {acc[u].x, acc[u].y, acc[u].z, acc[u].w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (k < nn) {
-                    T x = x4[k];
-                    if (own && lm == 0) x += centre_term[4 * ng + k];
-                    out[(4 * ng + k) * L2 + lm] = x;
-                }
+                const T ck = Cs[min(4 * ng + k, kPackMaxN - 1)];
+                x4[k] += cen ? ck : T(0);
+            }
+            T* o = out + 4 * ng * L2 + lm;
+            if (nn == 4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[k * L2] = x4[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < nn) o[k * L2] = x4[k];
             }
             acc[u] = V4<T>{T(0), T(0), T(0), T(0)};
         }
@@ -237,6 +285,9 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
     auto chunk_n = [&](int64_t q0) __attribute__((always_inline)) {
         return int(pe - q0 < kPackCh ? pe - q0 : kPackCh);
     };
+    // The next chunk's inputs are loaded after this chunk's coefficient
+    // loads have been used (vector loads complete in order, so loads issued
+    // before them would hold them up) and arrive during the sums.
     PairIn nxt = load_in(bnd[0], chunk_n(bnd[0]));
     int nsp = species_of(nxt.j, (lane & (kPackCh - 1)) < chunk_n(bnd[0]));
     for (int64_t q0 = bnd[0]; q0 < pe; q0 += kPackCh) {
@@ -245,9 +296,8 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
         const int spq = nsp;
         const bool more = q0 + kPackCh < pe;
         const int nc1 = more ? chunk_n(q0 + kPackCh) : 0;
-        if (more) nxt = load_in(q0 + kPackCh, nc1);
         const int key = stage(q0, nc, in, spq);
-        if (more) nsp = species_of(nxt.j, (lane & (kPackCh - 1)) < nc1);
+        if (more) nxt = load_in(q0 + kPackCh, nc1);
         const int prev = __shfl_up(key, 1, 64);
         if (__ballot(lane < nc && key < (lane == 0 ? cur : prev))) {
             grouped = false;
@@ -260,6 +310,7 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
             accumulate(lo, lo + cnt);
             lo += cnt;
         }
+        if (more) nsp = species_of(nxt.j, (lane & (kPackCh - 1)) < nc1);
         wave_sync();   // the rows are read before the next chunk overwrites them
     }
     if (grouped) {
@@ -287,26 +338,28 @@ __global__ void __launch_bounds__(64) k_expansion_packed(FeatureArgs a, PackLayo
 
 template <typename T, int LM>
 struct PackedFn {
+    template <int GMAX>
+    static hipError_t launch(const FeatureArgs& a, const PackLayout& W, hipStream_t st)
+    {
+        const size_t lds = size_t(W.total) * sizeof(T);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_expansion_packed<T, LM, GMAX>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+            if (e != hipSuccess) return e;
+        }
+        const int64_t waves = (a.n_atoms + W.cpw - 1) / W.cpw;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_expansion_packed<T, LM, GMAX>), dim3(unsigned(waves)), dim3(64), lds, st,
+                           a, W);
+        return hipGetLastError();
+    }
     static hipError_t run(const FeatureArgs& a, const PackLayout& W, hipStream_t st)
     {
         if constexpr (LM < 0) {
             return hipErrorNotSupported;
         } else {
-            const size_t lds = size_t(W.total) * sizeof(T);
-            const void* fn = W.G <= 2 ? reinterpret_cast<const void*>(k_expansion_packed<T, LM, 2>)
-                                      : reinterpret_cast<const void*>(k_expansion_packed<T, LM, 4>);
-            if (lds > 65536) {
-                hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-                if (e != hipSuccess) return e;
-            }
-            const int64_t waves = (a.n_atoms + W.cpw - 1) / W.cpw;
-            if (W.G <= 2)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_expansion_packed<T, LM, 2>), dim3(unsigned(waves)), dim3(64), lds,
-                                   st, a, W);
-            else
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_expansion_packed<T, LM, 4>), dim3(unsigned(waves)), dim3(64), lds,
-                                   st, a, W);
-            return hipGetLastError();
+            if (W.gmax == 2) return launch<2>(a, W, st);
+            if (W.gmax == 3) return launch<3>(a, W, st);
+            return launch<4>(a, W, st);
         }
     }
 };
@@ -318,11 +371,9 @@ PackLayout pack_layout(int nmax, int lmax, int64_t n_atoms)
     PackLayout W{};
     const int lm1 = lmax + 1;
     W.G = (nmax + 3) / 4;
-    W.np = 4 * W.G;
-    W.nls = lm1 * W.np;
-    W.l2s = (lm1 * lm1) | 1;
-    W.ys = kPackCh * W.nls;
-    W.total = W.ys + kPackCh * W.l2s;
+    W.gmax = W.G < 2 ? 2 : W.G;   // the kernel's radial rows hold 4 gmax n per l
+    const int nls = lm1 * 4 * W.gmax + 4, l2s = (lm1 * lm1) | 1;   // a spare quad per row
+    W.total = kPackCh * (nls + l2s) + kPackMaxN;
     // enough waves to fill the chip before centres are packed
     W.cpw = n_atoms >= 8192 ? 4 : n_atoms >= 2048 ? 2 : 1;
     return W;

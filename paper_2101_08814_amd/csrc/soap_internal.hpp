@@ -153,7 +153,7 @@ hipError_t launch_expansion_lanes(const FeatureArgs& a, bool f64, hipStream_t st
 // c alone with the pairs of several centres packed into each wave's
 // chunks; hipErrorNotSupported when p is asked for or the layout does not fit
 struct PackLayout {
-    int G, np, nls, l2s, ys, total, cpw;
+    int G, gmax, total, cpw;
 };
 hipError_t launch_expansion_packed(const FeatureArgs& a, bool f64, hipStream_t stream);
 // per-pair dL/dr_ji of the adjoint with one lane per pair
