@@ -401,7 +401,7 @@ def measure_config(wl: str, steps: int, warmup: int):
         def ph_spectrum():
             state["p"] = calc.power_spectrum(state["c"], "bf16")
 
-        phases += [("expansion", ph_expansion, ("k_expansion_lanes<float, 6, false>", "expansion")),
+        phases += [("expansion", ph_expansion, ("k_expansion_packed<float, 6, 2>", "expansion")),
                    ("spectrum_bf16_mfma", ph_spectrum, ("k_power_spectrum_bf16", "spectrum"))]
     else:
         out = calc.allocate_features(N, nl.capacity, td, dev, False)
