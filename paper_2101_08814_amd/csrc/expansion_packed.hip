@@ -250,12 +250,14 @@ __global__ void __launch_bounds__(64, (pack_waves<T, LMAX, GMAX>())) k_expansion
             const int v = lane + 64 * u;
             const int ng = v / L2, lm = v - ng * L2;
             const int nn = v < NI ? min(4, nmax - 4 * ng) : 0;   // n of the item that exist
-            const bool cen = own && lm == 0;
             T x4[4] = {acc[u].x, acc[u].y, acc[u].z, acc[u].w};
+            if (own) {   // the same for the whole wave
+                const bool cen = lm == 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const T ck = Cs[min(4 * ng + k, kPackMaxN - 1)];
-                x4[k] += cen ? ck : T(0);
+                for (int k = 0; k < 4; ++k) {
+                    const T ck = Cs[min(4 * ng + k, kPackMaxN - 1)];
+                    x4[k] += cen ? ck : T(0);
+                }
             }
             T* o = out + 4 * ng * L2 + lm;
             if (nn == 4) {
