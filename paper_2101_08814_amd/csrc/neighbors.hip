@@ -857,6 +857,248 @@ __global__ void __launch_bounds__(64) k_fill1(NeighborArgs a)
     }
 }
 
+// ------------------------------------------------- small systems, all pairs
+// Systems of at most kBruteAtoms atoms in at most 64 structures of on
+// average at most kBrutePerStruct atoms: no bins.
+// A wave per centre checks the input itself (lane l builds the geometry of
+// structure l: the same checks as the bin build) and tests every atom j of
+// the centre's structure.  With f = (r_j - r_i) . Hinv the fractional
+// difference and w_k the width of the cell across lattice direction k, an
+// image s within rcut has |f_k + s_k| <= rcut / w_k, so only the s in that
+// box (one image when every width is at least 2 rcut) are tried, in
+// lexicographic order; the hit test is |r_j - r_i + s.H|^2 < rcut^2 in
+// double, as in the binned enumeration.  Counting and filling are two
+// launches; the fill ranks a centre's pairs by (species_j, j, s) in LDS,
+// as k_fill1 does, and forms the offsets from the counts itself.
+constexpr int kBruteAtoms = 2048;
+constexpr int kBruteStructs = 64;
+constexpr int kBrutePerStruct = 256;
+constexpr int kBruteBatch = 4;   // rounds of 64 candidates whose positions are loaded together
+
+struct BruteCentre {
+    bool ok;          // the whole input is valid
+    int64_t lo, hi;   // atoms of the centre's structure
+    double ri[3];
+    double e[3];      // rcut / width per periodic axis (with a margin), 0 otherwise
+};
+
+// validity of the input and the centre's structure geometry (in gs)
+__device__ BruteCentre brute_centre(const NeighborArgs& a, int64_t i, StructGeom& gs)
+{
+    const int lane = threadIdx.x & 63;
+    const int ns = a.n_structures;
+    StructGeom g;
+    bool bad = false;
+    if (lane < ns) {
+        bad = !make_geometry(a, lane, g);
+        if (lane == 0 && g.atom_lo != 0) bad = true;
+        if (lane == ns - 1 && g.atom_hi != a.n_atoms) bad = true;
+    }
+    BruteCentre c;
+    c.ok = __ballot(bad) == 0;
+    // structure of i: the structures before it end at or before i
+    const int s = __popcll(__ballot(lane < ns && g.atom_hi <= i));
+    if (lane == s && s < ns) gs = g;
+    wave_fence();
+    c.lo = gs.atom_lo;
+    c.hi = gs.atom_hi;
+    if (s >= ns) c.ok = false;
+    for (int k = 0; k < 3; ++k) {
+        c.ri[k] = a.positions[3 * i + k];
+        const double bk = sqrt(gs.Hinv[0 * 3 + k] * gs.Hinv[0 * 3 + k] + gs.Hinv[1 * 3 + k] * gs.Hinv[1 * 3 + k] +
+                               gs.Hinv[2 * 3 + k] * gs.Hinv[2 * 3 + k]);
+        c.e[k] = gs.pbc[k] ? a.rcut * bk * (1.0 + 1e-9) + 1e-12 : 0.0;
+    }
+    return c;
+}
+
+// every candidate j of centre i, kBruteBatch rounds of 64 at a time:
+// emit(hit, j, s0, s1, s2, vx, vy, vz) by every lane for every image step
+template <class F>
+__device__ void brute_visit(const NeighborArgs& a, int64_t i, const BruteCentre& c, const StructGeom& g, F&& emit)
+{
+    const int lane = threadIdx.x & 63;
+    const double rc2 = a.rcut * a.rcut;
+    const int64_t lo = c.ok ? c.lo : 0, hi = c.ok ? c.hi : 0;
+    for (int64_t j0 = lo; j0 < hi; j0 += 64 * kBruteBatch) {
+        double rj[kBruteBatch][3];
+#pragma unroll
+        for (int r = 0; r < kBruteBatch; ++r) {
+            const int64_t j = j0 + 64 * r + lane;
+            const int64_t jj = j < hi ? j : lo;
+            for (int k = 0; k < 3; ++k) rj[r][k] = a.positions[3 * jj + k];
+        }
+#pragma unroll
+        for (int r = 0; r < kBruteBatch; ++r) {
+            const int64_t j = j0 + 64 * r + lane;
+            if (__ballot(j < hi) == 0) break;
+            const double d0 = rj[r][0] - c.ri[0], d1 = rj[r][1] - c.ri[1], d2 = rj[r][2] - c.ri[2];
+            // box of shifts: s_k in [ceil(-f_k - e_k), floor(-f_k + e_k)]
+            int smin[3], cnt[3];
+            int n_img = j < hi ? 1 : 0;
+            for (int k = 0; k < 3; ++k) {
+                smin[k] = 0;
+                cnt[k] = 1;
+                if (g.pbc[k]) {
+                    const double f = d0 * g.Hinv[0 * 3 + k] + d1 * g.Hinv[1 * 3 + k] + d2 * g.Hinv[2 * 3 + k];
+                    const int a0 = int(ceil(-f - c.e[k])), a1 = int(floor(-f + c.e[k]));
+                    smin[k] = a0;
+                    cnt[k] = a1 >= a0 ? a1 - a0 + 1 : 0;
+                }
+                n_img *= cnt[k];
+            }
+            int n_max = n_img;
+            for (int off = 32; off > 0; off >>= 1) n_max = max(n_max, __shfl_xor(n_max, off, 64));
+            for (int t = 0; t < n_max; ++t) {
+                bool hit = false;
+                int s0 = 0, s1 = 0, s2 = 0;
+                double vx = 0.0, vy = 0.0, vz = 0.0;
+                if (t < n_img) {
+                    s2 = smin[2] + t % cnt[2];
+                    s1 = smin[1] + (t / cnt[2]) % cnt[1];
+                    s0 = smin[0] + t / (cnt[2] * cnt[1]);
+                    if (!(j == i && s0 == 0 && s1 == 0 && s2 == 0)) {
+                        vx = d0 + s0 * g.H[0] + s1 * g.H[3] + s2 * g.H[6];
+                        vy = d1 + s0 * g.H[1] + s1 * g.H[4] + s2 * g.H[7];
+                        vz = d2 + s0 * g.H[2] + s1 * g.H[5] + s2 * g.H[8];
+                        const double r2 = vx * vx + vy * vy + vz * vz;
+                        if (r2 < rc2) {
+                            if (r2 == 0.0) put_status(a.status, SOAP_EGEOMETRY);
+                            else hit = true;
+                        }
+                    }
+                }
+                emit(hit, int(j), s0, s1, s2, vx, vy, vz);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_count_bf(NeighborArgs a)
+{
+    __shared__ StructGeom gs;
+    const int64_t i = blockIdx.x;
+    const BruteCentre c = brute_centre(a, i, gs);
+    if (threadIdx.x == 0) {
+        if (!c.ok) put_status(a.status, SOAP_EINVAL);
+        const int sp = a.species[i];
+        if (sp < 0 || sp >= a.n_species) put_status(a.status, SOAP_ESPECIES);
+    }
+    int n = 0;
+    brute_visit(a, i, c, gs, [&](bool hit, int, int, int, int, double, double, double) { n += hit ? 1 : 0; });
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+    if (threadIdx.x == 0) a.centre_count[i] = n;
+}
+
+// offsets from all counts (N <= kBruteAtoms), the centre's pairs ranked by
+// key in LDS and written sorted
+template <bool F64>
+__global__ void __launch_bounds__(64) k_fill_bf(NeighborArgs a)
+{
+    using VT = typename std::conditional<F64, double, float>::type;
+    __shared__ StructGeom gs;
+    __shared__ int64_t khi[kSortCap], klo[kSortCap];
+    __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
+    __shared__ VT kv[3 * kSortCap];
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    constexpr int R = kBruteAtoms / 64;
+    int64_t cv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t k = lane + 64 * r;
+        cv[r] = k < a.n_atoms ? a.centre_count[k] : 0;
+    }
+    const int n = int(a.centre_count[i]);
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        all += cv[r];
+        before += lane + 64 * r < i ? cv[r] : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        before += __shfl_xor(before, off, 64);
+        all += __shfl_xor(all, off, 64);
+    }
+    const int64_t o0 = before, total = all;
+    if (lane == 0) {
+        a.pair_offsets[i] = o0;
+        if (i == a.n_atoms - 1) {
+            a.pair_offsets[a.n_atoms] = total;
+            if (total > a.capacity) put_status(a.status, SOAP_ECAPACITY);
+        }
+    }
+    if (total > a.capacity || n == 0) return;
+    const BruteCentre c = brute_centre(a, i, gs);
+    const bool in_lds = n <= kSortCap;
+    int count = 0;
+    brute_visit(a, i, c, gs, [&](bool hit, int j, int s0, int s1, int s2, double vx, double vy, double vz) {
+        const uint64_t mask = __ballot(hit);
+        const int idx = count + __popcll(mask & ((uint64_t(1) << lane) - 1));
+        if (hit && idx < n) {
+            if (in_lds) {
+                kj[idx] = j;
+                ks[3 * idx] = s0; ks[3 * idx + 1] = s1; ks[3 * idx + 2] = s2;
+                kv[3 * idx] = VT(vx); kv[3 * idx + 1] = VT(vy); kv[3 * idx + 2] = VT(vz);
+            } else {
+                a.pair_j[o0 + idx] = j;
+                a.pair_shift[3 * (o0 + idx)] = s0;
+                a.pair_shift[3 * (o0 + idx) + 1] = s1;
+                a.pair_shift[3 * (o0 + idx) + 2] = s2;
+            }
+        }
+        count += __popcll(mask);
+    });
+    __syncthreads();
+    if (in_lds) {
+        for (int p = lane; p < n; p += 64) make_key(a.species[kj[p]], kj[p], ks[3 * p], ks[3 * p + 1], ks[3 * p + 2],
+                                                    khi[p], klo[p]);
+        __syncthreads();
+        VT* vec = static_cast<VT*>(a.pair_vec);
+        for (int p = lane; p < n; p += 64) {
+            const int64_t h = khi[p], l = klo[p];
+            int rank = 0;
+            for (int q = 0; q < n; ++q) rank += key_less(khi[q], klo[q], h, l) ? 1 : 0;
+            const int64_t q = o0 + rank;
+            a.pair_j[q] = kj[p];
+            a.pair_shift[3 * q] = ks[3 * p];
+            a.pair_shift[3 * q + 1] = ks[3 * p + 1];
+            a.pair_shift[3 * q + 2] = ks[3 * p + 2];
+            vec[3 * q] = kv[3 * p];
+            vec[3 * q + 1] = kv[3 * p + 1];
+            vec[3 * q + 2] = kv[3 * p + 2];
+        }
+        return;
+    }
+    // long environments: insertion sort in place in global memory
+    if (lane == 0) {
+        for (int64_t p = o0 + 1; p < o0 + n; ++p) {
+            const int j = a.pair_j[p];
+            const int s0 = a.pair_shift[3 * p], s1 = a.pair_shift[3 * p + 1], s2 = a.pair_shift[3 * p + 2];
+            int64_t h, l;
+            make_key(a.species[j], j, s0, s1, s2, h, l);
+            int64_t q = p - 1;
+            while (q >= o0) {
+                const int jq = a.pair_j[q];
+                int64_t hq, lq;
+                make_key(a.species[jq], jq, a.pair_shift[3 * q], a.pair_shift[3 * q + 1], a.pair_shift[3 * q + 2], hq,
+                         lq);
+                if (!key_less(h, l, hq, lq)) break;
+                a.pair_j[q + 1] = jq;
+                for (int x = 0; x < 3; ++x) a.pair_shift[3 * (q + 1) + x] = a.pair_shift[3 * q + x];
+                --q;
+            }
+            a.pair_j[q + 1] = j;
+            a.pair_shift[3 * (q + 1)] = s0; a.pair_shift[3 * (q + 1) + 1] = s1; a.pair_shift[3 * (q + 1) + 2] = s2;
+        }
+    }
+    __syncthreads();
+    for (int p = lane; p < n; p += 64) {
+        const int64_t q = o0 + p;
+        write_pair<F64>(a, gs, i, q, a.pair_j[q], a.pair_shift[3 * q], a.pair_shift[3 * q + 1], a.pair_shift[3 * q + 2]);
+    }
+}
+
 // Large systems: kFillWaves centres per work-group (one wave each) that
 // draw their sort records from one pool of kSortCap, so that four times as
 // many centres are resident as with a pool per wave; a centre whose records
@@ -1045,6 +1287,18 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
         hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<int64_t, int64_t>), dim3(1), dim3(1024), 0, stream,
                            a.centre_count, a.pair_offsets, (int64_t*)nullptr, int64_t(0), a.capacity, a.status);
+        return hipGetLastError();
+    }
+    // all pairs when the structures are small (on average at most
+    // kBrutePerStruct atoms: a 1024-atom cell is faster with bins)
+    if (N <= kBruteAtoms && a.n_structures <= kBruteStructs && N <= kBrutePerStruct * int64_t(a.n_structures) &&
+        a.capacity > 0) {
+        const dim3 grid{unsigned(N)}, wave{64};
+        hipLaunchKernelGGL(k_count_bf, grid, wave, 0, stream, a);
+        if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<true>), grid, wave, 0, stream, a);
+        else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false>), grid, wave, 0, stream, a);
+        if (a.pair_transpose)
+            hipLaunchKernelGGL(k_transpose, dim3(blocks(a.n_atoms, 4)), dim3(256), 0, stream, a);
         return hipGetLastError();
     }
     const bool small = B <= kSmallBins && N <= kSmallAtoms;
