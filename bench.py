@@ -409,7 +409,11 @@ def measure_config(wl: str, steps: int, warmup: int):
         def ph_features():
             calc.features(nl, spc, td, out=out)
 
-        kname = f"k_expansion_lanes<{'double' if td == torch.float64 else 'float'}, {lmax}, true>"
+        tn = 'double' if td == torch.float64 else 'float'
+        if N >= 4096:   # c with pairs packed across centres, then p from c (two kernels)
+            kname = f"k_expansion_packed<{tn}, {lmax}, {max(2, (nmax + 3) // 4)}> + k_power_spectrum<{tn}, false>"
+        else:
+            kname = f"k_expansion_lanes<{tn}, {lmax}, true>"
         phases.append(("features", ph_features, (kname, "features")))
         if wl == "gpr":
             n_active, zeta = 2000, 4

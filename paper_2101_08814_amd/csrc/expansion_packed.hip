@@ -368,7 +368,7 @@ struct PackedFn {
 
 }  // namespace
 
-PackLayout pack_layout(int nmax, int lmax, int64_t n_atoms)
+PackLayout pack_layout(int nmax, int lmax, int64_t n_atoms, int64_t pair_capacity)
 {
     PackLayout W{};
     const int lm1 = lmax + 1;
@@ -376,8 +376,12 @@ PackLayout pack_layout(int nmax, int lmax, int64_t n_atoms)
     W.gmax = W.G < 2 ? 2 : W.G;   // the kernel's radial rows hold 4 gmax n per l
     const int nls = lm1 * 4 * W.gmax + 4, l2s = (lm1 * lm1) | 1;   // a spare quad per row
     W.total = kPackCh * (nls + l2s) + kPackMaxN;
-    // enough waves to fill the chip before centres are packed
-    W.cpw = n_atoms >= 8192 ? 4 : n_atoms >= 2048 ? 2 : 1;
+    // enough waves to fill the chip before centres are packed; centres with
+    // a chunk of pairs or more each gain little from sharing a wave
+    // (4096-atom liquid, 45 pairs per centre: 86 us at one centre per wave,
+    // 96 at two or four)
+    const bool long_envs = pair_capacity >= int64_t(kPackCh) * n_atoms;
+    W.cpw = long_envs ? 1 : n_atoms >= 8192 ? 4 : n_atoms >= 2048 ? 2 : 1;
     return W;
 }
 
@@ -385,7 +389,7 @@ hipError_t launch_expansion_packed(const FeatureArgs& a, bool f64, hipStream_t s
 {
     if (a.p != nullptr || a.nmax > kPackMaxN) return hipErrorNotSupported;
     if (a.n_atoms == 0) return hipSuccess;
-    const PackLayout W = pack_layout(a.nmax, a.lmax, a.n_atoms);
+    const PackLayout W = pack_layout(a.nmax, a.lmax, a.n_atoms, a.pair_capacity);
     if (size_t(W.total) * (f64 ? 8 : 4) > 64 * 1024) return hipErrorNotSupported;
     return f64 ? by_degree<double, PackedFn>(a.lmax, a, W, stream) : by_degree<float, PackedFn>(a.lmax, a, W, stream);
 }

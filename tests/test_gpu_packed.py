@@ -1,9 +1,10 @@
 """GPU parity of the expansion with pairs packed across centres (c alone):
 against the FP64 oracle for several (nmax, lmax) shapes, including nmax not
 a multiple of four, nmax = 1 and lmax = 0, with centres that have no pairs
-at all, and at the molecules' full size (four centres per wave) against the
-oracle and against c from the one-wave-per-centre kernel that forms c and p
-together (same sums in the same order).
+at all, against c from the one-wave-per-centre kernel that forms c and p
+together (same sums in the same order; used below 4096 centres), and at the
+molecules' full size (four centres per wave), where features come from the
+packed c and the power-spectrum kernel, against the oracle's c and p.
 
 Tolerances as in test_gpu_parity.py: FP64 <= 1e-7, FP32 c <= 1e-6
 (relative Frobenius error), per centre WORST_ROW_F32 in FP32."""
@@ -57,16 +58,20 @@ def test_packed_expansion_matches_oracle(dt, nmax, lmax):
     b = _with_isolated(mol, hyp)
     calc = P.Calculator.from_hypers(hyp)
     nl, pos, spc = gpu_neighbors(calc, b, dt)
-    c = calc.spherical_expansion(nl, spc, dt)
+    c = calc.spherical_expansion(nl, spc, dt).clone()
+    c2, _ = calc.features(nl, spc, dt)
     assert calc.device_status() == 0
+    d = rel(_np(c), _np(c2))
     ref_nl = oracle.neighbors(b)
     ref_c = oracle.expansion(hyp, b.species, ref_nl)
     assert np.all(np.diff(ref_nl.pair_offsets)[:5] == 0)
     e, w = rel(_np(c), ref_c), _worst_centre(_np(c), ref_c)
-    print(f"[packed {dt} nmax={nmax} lmax={lmax}] N={b.n_atoms} rel={e:.3e} worst centre={w:.3e}")
+    print(f"[packed {dt} nmax={nmax} lmax={lmax}] N={b.n_atoms} rel={e:.3e} worst centre={w:.3e} "
+          f"vs one wave per centre={d:.3e}")
     f64 = dt == torch.float64
     assert e <= (1e-7 if f64 else 1e-6)
     assert w <= (1e-7 if f64 else WORST_ROW_F32)
+    assert d <= (1e-12 if f64 else 1e-6)
     # isolated centres: only the centre term (lm = 0 of their own species),
     # to the spline's accuracy
     ci = _np(c)[:5]
@@ -76,26 +81,29 @@ def test_packed_expansion_matches_oracle(dt, nmax, lmax):
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
-def test_packed_full_molecules_matches_oracle_and_lanes(dt):
+def test_packed_full_molecules_matches_oracle(dt):
     """All 256 molecules (28,929 atoms with five isolated ones at the end:
     four centres per wave, a partly filled last wave) at nmax 13, lmax 3:
-    c alone against the oracle, and against c from the kernel that forms
-    c and p together."""
+    c alone, and c and p from soap_features (the packed c, then p from it),
+    against the oracle."""
     mol = synthetic.molecule_batch()
     hyp = dict(mol.hypers, nmax=13, lmax=3)
     b = _with_isolated(mol, hyp, at_front=False)
     calc = P.Calculator.from_hypers(hyp)
     nl, pos, spc = gpu_neighbors(calc, b, dt)
     c = calc.spherical_expansion(nl, spc, dt).clone()
-    c2, _ = calc.features(nl, spc, dt)
+    c2, p2 = calc.features(nl, spc, dt)
     assert calc.device_status() == 0
     ref_nl = oracle.neighbors(b)
     ref_c = oracle.expansion(hyp, b.species, ref_nl)
+    ref_p = oracle.power_spectrum(hyp, ref_c)
     e, w = rel(_np(c), ref_c), _worst_centre(_np(c), ref_c)
-    d = rel(_np(c), _np(c2))
-    print(f"[packed full {dt}] N={b.n_atoms} rel={e:.3e} worst centre={w:.3e} vs lanes={d:.3e} "
-          f"bitwise={bool(torch.equal(c, c2))}")
+    ep, wp = rel(_np(p2), ref_p), _worst_centre(_np(p2), ref_p)
+    print(f"[packed full {dt}] N={b.n_atoms} c rel={e:.3e} worst centre={w:.3e}; features c same="
+          f"{bool(torch.equal(c, c2))}, p rel={ep:.3e} worst centre={wp:.3e}")
     f64 = dt == torch.float64
     assert e <= (1e-7 if f64 else 1e-6)
     assert w <= (1e-7 if f64 else WORST_ROW_F32)
-    assert d <= (1e-12 if f64 else 1e-6)
+    assert torch.equal(c, c2)
+    assert ep <= (1e-7 if f64 else 1e-6)
+    assert wp <= (1e-7 if f64 else WORST_ROW_F32)
