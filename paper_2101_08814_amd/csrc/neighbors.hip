@@ -873,6 +873,7 @@ __global__ void __launch_bounds__(64) k_fill1(NeighborArgs a)
 constexpr int kBruteAtoms = 2048;
 constexpr int kBruteStructs = 64;
 constexpr int kBrutePerStruct = 256;
+constexpr int kBruteSortCap = 128;   // sort records per fill wave (more: sorted in global memory)
 constexpr int kBruteBatch = 4;   // rounds of 64 candidates whose positions are loaded together
 
 struct BruteCentre {
@@ -882,27 +883,43 @@ struct BruteCentre {
     double e[3];      // rcut / width per periodic axis (with a margin), 0 otherwise
 };
 
-// validity of the input and the centre's structure geometry (in gs)
+// Validity of the input and the centre's structure geometry (in gs).
+// GEOM: from the geometry phase (a.geom, a.ok; the structure found by a
+// binary search over the structures' ends, the same address in every
+// lane); otherwise built by the wave (at most 64 structures).
+template <bool GEOM>
 __device__ BruteCentre brute_centre(const NeighborArgs& a, int64_t i, StructGeom& gs)
 {
     const int lane = threadIdx.x & 63;
     const int ns = a.n_structures;
-    StructGeom g;
-    bool bad = false;
-    if (lane < ns) {
-        bad = !make_geometry(a, lane, g);
-        if (lane == 0 && g.atom_lo != 0) bad = true;
-        if (lane == ns - 1 && g.atom_hi != a.n_atoms) bad = true;
-    }
     BruteCentre c;
-    c.ok = __ballot(bad) == 0;
-    // structure of i: the structures before it end at or before i
-    const int s = __popcll(__ballot(lane < ns && g.atom_hi <= i));
-    if (lane == s && s < ns) gs = g;
+    int s;
+    if constexpr (GEOM) {
+        c.ok = *a.ok != 0;
+        int lo = 0, hi = ns - 1;   // first structure ending after i (the offsets are contiguous and cached)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a.atom_offsets[mid + 1] > i) hi = mid; else lo = mid + 1;
+        }
+        s = lo;
+        if (lane == 0) gs = a.geom[s];
+    } else {
+        StructGeom g;
+        bool bad = false;
+        if (lane < ns) {
+            bad = !make_geometry(a, lane, g);
+            if (lane == 0 && g.atom_lo != 0) bad = true;
+            if (lane == ns - 1 && g.atom_hi != a.n_atoms) bad = true;
+        }
+        c.ok = __ballot(bad) == 0;
+        // structure of i: the structures before it end at or before i
+        s = __popcll(__ballot(lane < ns && g.atom_hi <= i));
+        if (lane == s && s < ns) gs = g;
+    }
     wave_fence();
     c.lo = gs.atom_lo;
     c.hi = gs.atom_hi;
-    if (s >= ns) c.ok = false;
+    if (s >= ns || !(c.lo <= i && i < c.hi)) c.ok = false;
     for (int k = 0; k < 3; ++k) {
         c.ri[k] = a.positions[3 * i + k];
         const double bk = sqrt(gs.Hinv[0 * 3 + k] * gs.Hinv[0 * 3 + k] + gs.Hinv[1 * 3 + k] * gs.Hinv[1 * 3 + k] +
@@ -974,11 +991,12 @@ __device__ void brute_visit(const NeighborArgs& a, int64_t i, const BruteCentre&
     }
 }
 
+template <bool GEOM>
 __global__ void __launch_bounds__(64) k_count_bf(NeighborArgs a)
 {
     __shared__ StructGeom gs;
     const int64_t i = blockIdx.x;
-    const BruteCentre c = brute_centre(a, i, gs);
+    const BruteCentre c = brute_centre<GEOM>(a, i, gs);
     if (threadIdx.x == 0) {
         if (!c.ok) put_status(a.status, SOAP_EINVAL);
         const int sp = a.species[i];
@@ -990,47 +1008,56 @@ __global__ void __launch_bounds__(64) k_count_bf(NeighborArgs a)
     if (threadIdx.x == 0) a.centre_count[i] = n;
 }
 
-// offsets from all counts (N <= kBruteAtoms), the centre's pairs ranked by
-// key in LDS and written sorted
-template <bool F64>
+// Offsets from all counts (without GEOM: N <= kBruteAtoms) or from the
+// scan (GEOM); the centre's pairs ranked by key in LDS and written sorted.
+template <bool GEOM, bool F64>
 __global__ void __launch_bounds__(64) k_fill_bf(NeighborArgs a)
 {
     using VT = typename std::conditional<F64, double, float>::type;
     __shared__ StructGeom gs;
-    __shared__ int64_t khi[kSortCap], klo[kSortCap];
-    __shared__ int32_t kj[kSortCap], ks[3 * kSortCap];
-    __shared__ VT kv[3 * kSortCap];
+    __shared__ int64_t khi[kBruteSortCap], klo[kBruteSortCap];
+    __shared__ int32_t kj[kBruteSortCap], ks[3 * kBruteSortCap];
+    __shared__ VT kv[3 * kBruteSortCap];
     const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
-    constexpr int R = kBruteAtoms / 64;
-    int64_t cv[R];
+    int64_t o0, total;
+    int n;
+    if constexpr (GEOM) {
+        o0 = a.pair_offsets[i];
+        n = int(a.pair_offsets[i + 1] - o0);
+        total = a.pair_offsets[a.n_atoms];
+    } else {
+        constexpr int R = kBruteAtoms / 64;
+        int64_t cv[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t k = lane + 64 * r;
-        cv[r] = k < a.n_atoms ? a.centre_count[k] : 0;
-    }
-    const int n = int(a.centre_count[i]);
-    int64_t before = 0, all = 0;
+        for (int r = 0; r < R; ++r) {
+            const int64_t k = lane + 64 * r;
+            cv[r] = k < a.n_atoms ? a.centre_count[k] : 0;
+        }
+        n = int(a.centre_count[i]);
+        int64_t before = 0, all = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        all += cv[r];
-        before += lane + 64 * r < i ? cv[r] : 0;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        before += __shfl_xor(before, off, 64);
-        all += __shfl_xor(all, off, 64);
-    }
-    const int64_t o0 = before, total = all;
-    if (lane == 0) {
-        a.pair_offsets[i] = o0;
-        if (i == a.n_atoms - 1) {
-            a.pair_offsets[a.n_atoms] = total;
-            if (total > a.capacity) put_status(a.status, SOAP_ECAPACITY);
+        for (int r = 0; r < R; ++r) {
+            all += cv[r];
+            before += lane + 64 * r < i ? cv[r] : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            before += __shfl_xor(before, off, 64);
+            all += __shfl_xor(all, off, 64);
+        }
+        o0 = before;
+        total = all;
+        if (lane == 0) {
+            a.pair_offsets[i] = o0;
+            if (i == a.n_atoms - 1) {
+                a.pair_offsets[a.n_atoms] = total;
+                if (total > a.capacity) put_status(a.status, SOAP_ECAPACITY);
+            }
         }
     }
     if (total > a.capacity || n == 0) return;
-    const BruteCentre c = brute_centre(a, i, gs);
-    const bool in_lds = n <= kSortCap;
+    const BruteCentre c = brute_centre<GEOM>(a, i, gs);
+    const bool in_lds = n <= kBruteSortCap;
     int count = 0;
     brute_visit(a, i, c, gs, [&](bool hit, int j, int s0, int s1, int s2, double vx, double vy, double vz) {
         const uint64_t mask = __ballot(hit);
@@ -1291,12 +1318,22 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
     }
     // all pairs when the structures are small (on average at most
     // kBrutePerStruct atoms: a 1024-atom cell is faster with bins)
-    if (N <= kBruteAtoms && a.n_structures <= kBruteStructs && N <= kBrutePerStruct * int64_t(a.n_structures) &&
-        a.capacity > 0) {
+    if (N <= kBrutePerStruct * int64_t(a.n_structures) && a.capacity > 0) {
         const dim3 grid{unsigned(N)}, wave{64};
-        hipLaunchKernelGGL(k_count_bf, grid, wave, 0, stream, a);
-        if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<true>), grid, wave, 0, stream, a);
-        else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false>), grid, wave, 0, stream, a);
+        if (N <= kBruteAtoms && a.n_structures <= kBruteStructs) {
+            // each wave checks the input; the fill sums the counts itself
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count_bf<false>), grid, wave, 0, stream, a);
+            if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false, true>), grid, wave, 0, stream, a);
+            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false, false>), grid, wave, 0, stream, a);
+        } else {
+            // many structures: the geometry phase, then counts, a scan, the fill
+            hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count_bf<true>), grid, wave, 0, stream, a);
+            scan<int64_t, int64_t>(a.centre_count, a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.scan_tmp,
+                                   a.status, stream);
+            if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<true, true>), grid, wave, 0, stream, a);
+            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<true, false>), grid, wave, 0, stream, a);
+        }
         if (a.pair_transpose)
             hipLaunchKernelGGL(k_transpose, dim3(blocks(a.n_atoms, 4)), dim3(256), 0, stream, a);
         return hipGetLastError();
