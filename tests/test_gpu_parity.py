@@ -778,6 +778,45 @@ def test_invalid_structures_report_status(what):
     assert int(nl.pair_offsets[-1]) == 0
 
 
+def _all_pairs_batch(path):
+    """A batch that the neighbour list builds without bins: a 40-atom slab
+    (one wave checks the input itself), or 64 cells of 256 atoms (geometry
+    kernel, then counts, scan and fill)."""
+    if path == "small":
+        return NEIGHBOR_CASES["slab_pbc_xy"]()
+    return synthetic.multi_species_cells().subset(list(range(64)))
+
+
+@pytest.mark.parametrize("path", ["small", "many"])
+@pytest.mark.parametrize("what", ["singular_cell", "bad_offsets"])
+def test_invalid_structures_report_status_all_pairs(path, what):
+    """The all-pairs neighbour paths check the input as the bin build does:
+    SOAP_EINVAL and an empty list."""
+    b = _all_pairs_batch(path)
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    cells, offs = b.cells.copy(), b.atom_offsets.copy()
+    if what == "singular_cell":
+        s = cells.shape[0] - 1
+        cells[s, 1] = cells[s, 0]
+    else:
+        offs[-1] -= 1
+    nl = calc.compute_neighbors(pos, spc, offs, cells, b.pbc, capacity=100)
+    assert calc.device_status() == P._lib.SOAP_EINVAL
+    assert int(nl.pair_offsets[-1]) == 0
+
+
+@pytest.mark.parametrize("path", ["small", "many"])
+def test_capacity_exceeded_reports_status_all_pairs(path):
+    b = _all_pairs_batch(path)
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos, spc = to_dev(b)
+    nl = calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc, capacity=50)
+    assert calc.device_status() == P._lib.SOAP_ECAPACITY
+    assert int(nl.pair_offsets[-1]) > 50
+    assert int(nl.pair_offsets[-1]) == oracle.neighbors(b).n_pairs
+
+
 def test_coincident_atoms_report_status():
     b = synthetic.clusters_2species().subset([0])
     pos = b.positions.copy()
