@@ -1318,23 +1318,30 @@ hipError_t launch_neighbors(const NeighborArgs& a, hipStream_t stream)
     }
     // all pairs when the structures are small (on average at most
     // kBrutePerStruct atoms: a 1024-atom cell is faster with bins)
-    if (N <= kBrutePerStruct * int64_t(a.n_structures) && a.capacity > 0) {
+    if (N <= kBrutePerStruct * int64_t(a.n_structures)) {
         const dim3 grid{unsigned(N)}, wave{64};
-        if (N <= kBruteAtoms && a.n_structures <= kBruteStructs) {
-            // each wave checks the input; the fill sums the counts itself
+        const bool self_check = N <= kBruteAtoms && a.n_structures <= kBruteStructs;
+        if (self_check) {
+            // each wave checks the input; with pairs to write the fill sums
+            // the counts itself
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count_bf<false>), grid, wave, 0, stream, a);
-            if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false, true>), grid, wave, 0, stream, a);
-            else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false, false>), grid, wave, 0, stream, a);
+            if (a.capacity > 0) {
+                if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false, true>), grid, wave, 0, stream, a);
+                else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<false, false>), grid, wave, 0, stream, a);
+            }
         } else {
-            // many structures: the geometry phase, then counts, a scan, the fill
+            // many structures: the geometry phase, then the counts
             hipLaunchKernelGGL(k_geometry, dim3(1), dim3(1024), 0, stream, a);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_count_bf<true>), grid, wave, 0, stream, a);
+        }
+        if (!self_check || a.capacity <= 0)   // offsets by a scan (which reports the count at capacity 0)
             scan<int64_t, int64_t>(a.centre_count, a.pair_offsets, (int64_t*)nullptr, N, a.capacity, a.scan_tmp,
                                    a.status, stream);
+        if (!self_check && a.capacity > 0) {
             if (a.vec_f64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<true, true>), grid, wave, 0, stream, a);
             else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill_bf<true, false>), grid, wave, 0, stream, a);
         }
-        if (a.pair_transpose)
+        if (a.capacity > 0 && a.pair_transpose)
             hipLaunchKernelGGL(k_transpose, dim3(blocks(a.n_atoms, 4)), dim3(256), 0, stream, a);
         return hipGetLastError();
     }
