@@ -67,7 +67,8 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     if (i >= a.n_atoms) return;
     // {H, L} of every element of C: H in the low half, L in the high half;
     // then the packed P_l of the current l
-    const int HLS = (KL2 + 32 + 3) & ~3, OBS = (KK + 3) & ~3;   // 16-byte aligned regions
+    // 16-byte aligned regions; the packed P_l region ends in four spare words
+    const int HLS = (KL2 + 32 + 3) & ~3, OBS = ((KK + 3) & ~3) + 4;
     unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * (HLS + OBS);
     float* ob = reinterpret_cast<float*>(hl + HLS);
     const float* c_in = static_cast<const float*>(a.coeffs) + i * KL2;
@@ -96,50 +97,67 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
         __syncthreads();   // one centre per work-group
     }
     const int T = (K + 15) / 16;
-    const int n_tiles = T * (T + 1) / 2;
     const int row = lane & 15, kg = lane >> 4;
     float* p_out = static_cast<float*>(a.p) + i * int64_t(lmax + 1) * KK;
+    const int spare = OBS - 4;   // a dump word past the packed P_l for outputs outside it
     for (int l = 0; l <= lmax; ++l) {
         const int w = 2 * l + 1;   // <= 25 for lmax <= 12: one 32-wide step per product
+        const int nj = w - 8 * kg;  // this lane's operand values m = 8 kg + j with j < nj are inside the row
         float* dst = p_out + int64_t(l) * KK;
-        for (int t = wc; t < n_tiles; t += W) {
-            // tile t -> (I, J), I <= J, row-major over the upper triangle
-            int I = 0, rem = t;
-            while (rem >= T - I) { rem -= T - I; ++I; }
-            const int J = I + rem;
-            const int ka = I * 16 + row, kb = J * 16 + row;
-            // this lane's operand values: m = 8 kg + j of rows ka and kb (zero past w or past K)
-            const unsigned int* ra = hl + (ka < K ? ka : 0) * L2 + l * l + kg * 8;
-            const unsigned int* rb = hl + (kb < K ? kb : 0) * L2 + l * l + kg * 8;
-            unsigned int xa[8], xb[8];
+        // tiles (I, J), I <= J, row-major over the upper triangle, dealt
+        // round-robin over the centre's waves; a lane's operand values of
+        // row I are read once per I.  Rows past K read row 0 (inside the
+        // region, which is padded by 32 words past C) and are zeroed.
+        int t = 0;
+        for (int I = 0; I < T; ++I) {
+            const int ka = I * 16 + row;
+            u16x8 ha, la;
+            {
+                const unsigned int* ra = hl + (ka < K ? ka : 0) * L2 + l * l + kg * 8;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const bool ok = kg * 8 + j < w;
-                xa[j] = ok && ka < K ? ra[j] : 0u;
-                xb[j] = ok && kb < K ? rb[j] : 0u;
+                for (int j = 0; j < 8; ++j) {
+                    unsigned int x = ra[j];
+                    asm volatile("" : "+v"(x));   // read every word, then select: no branch around the load
+                    x = j < nj && ka < K ? x : 0u;
+                    ha[j] = (unsigned short)(x & 0xFFFFu);
+                    la[j] = (unsigned short)(x >> 16);
+                }
             }
-            u16x8 ha, la, hb, lb;
+            for (int J = I; J < T; ++J, ++t) {
+                if (W > 1 && t % W != wc) continue;
+                const int kb = J * 16 + row;
+                const unsigned int* rb = hl + (kb < K ? kb : 0) * L2 + l * l + kg * 8;
+                u16x8 hb, lb;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                ha[j] = (unsigned short)(xa[j] & 0xFFFFu);
-                la[j] = (unsigned short)(xa[j] >> 16);
-                hb[j] = (unsigned short)(xb[j] & 0xFFFFu);
-                lb[j] = (unsigned short)(xb[j] >> 16);
-            }
-            // P ~= H H^T + H L^T + L H^T
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, hb),
-                                                          acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, lb),
-                                                          acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, la), __builtin_bit_cast(bf16x8, hb),
-                                                          acc, 0, 0, 0);
-            // lane holds D[4*kg + v][row] = P[k1][k2] with k1 = 16 I + 4 kg + v, k2 = 16 J + row
-            const int k2 = J * 16 + row;
+                for (int j = 0; j < 8; ++j) {
+                    unsigned int x = rb[j];
+                    asm volatile("" : "+v"(x));
+                    x = j < nj && kb < K ? x : 0u;
+                    hb[j] = (unsigned short)(x & 0xFFFFu);
+                    lb[j] = (unsigned short)(x >> 16);
+                }
+                // P ~= H H^T + H L^T + L H^T
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha),
+                                                              __builtin_bit_cast(bf16x8, hb), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha),
+                                                              __builtin_bit_cast(bf16x8, lb), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, la),
+                                                              __builtin_bit_cast(bf16x8, hb), acc, 0, 0, 0);
+                // lane holds D[4 kg + v][row] = P[k1][k2] with k1 = 16 I + 4 kg + v,
+                // k2 = 16 J + row; packed index of (k1, k2) is
+                // k1 K - k1 (k1 - 1) / 2 + k2 - k1, which grows by K - k1 - 1
+                // from k1 to k1 + 1.  Outputs below the diagonal or past K go
+                // to the dump word.
+                const int k2 = J * 16 + row;
+                int k1 = I * 16 + 4 * kg;
+                int idx = k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int k1 = I * 16 + 4 * kg + v;
-                if (k1 <= k2 && k2 < K) ob[k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1)] = acc[v];
+                for (int v = 0; v < 4; ++v) {
+                    ob[k2 < K && (I < J || k1 <= k2) ? idx : spare] = acc[v];
+                    idx += K - k1 - 1;
+                    ++k1;
+                }
             }
         }
         {
@@ -157,11 +175,12 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     }
 }
 
-// LDS words of one centre's slot: {H, L} of C, then the packed P_l
+// LDS words of one centre's slot: {H, L} of C, then the packed P_l and a
+// dump word
 size_t bf16_slot_words(int S, int nmax, int lmax, int W)
 {
     const size_t K = size_t(S) * nmax, KL2 = K * (lmax + 1) * (lmax + 1), KK = K * (K + 1) / 2;
-    return ((KL2 + 32 + 3) & ~size_t(3)) + ((KK + 3) & ~size_t(3));
+    return ((KL2 + 32 + 3) & ~size_t(3)) + ((KK + 3) & ~size_t(3)) + 4;
 }
 
 // waves per centre: one when four centres' slots fit 40 KB of LDS
