@@ -15,10 +15,12 @@
 // W waves own one centre (W = 1, four centres per work-group, when C is
 // small; W = 4, one centre per work-group, otherwise): the centre's waves
 // split C into their LDS region as {H, L} pairs, then for each l run the
-// 16 x 16 output tiles (I <= J), dealt round-robin, as three
-// v_mfma_f32_16x16x32_bf16 each (a lane reads 8 consecutive {H, L} words of
-// each of its two rows), put the packed upper triangle in LDS and store it
-// as contiguous float4 rows (the accumulators alone give 64-byte pieces).
+// 16 x 16 output tiles (I <= J) as three v_mfma_f32_16x16x32_bf16 each (a
+// lane reads 8 consecutive {H, L} words of each of its two rows; one wave
+// walks the tiles row by row and reads row I's words once per I, four
+// waves deal the tiles round-robin), put the packed upper triangle in LDS
+// and store it as contiguous float4 rows (the accumulators alone give
+// 64-byte pieces).
 // One wave per centre needs no work-group barrier; four take two per l.
 #include "soap_internal.hpp"
 
@@ -52,6 +54,50 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A lane's operand values of row k of C_l (hl_l points at m = 8 kg of row
+// 0): {H, L} words m = 8 kg + j, zero for j >= nj (past 2l+1) or k >= K.
+// Rows past K read row 0, and every read stays inside the {H, L} region
+// (padded by 32 words past C).
+__device__ __forceinline__ void row_operands(const unsigned int* hl_l, int k, int K, int L2, int nj, u16x8& h,
+                                             u16x8& lo)
+{
+    const unsigned int* r = hl_l + (k < K ? k : 0) * L2;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const unsigned int x = j < nj && k < K ? r[j] : 0u;
+        h[j] = (unsigned short)(x & 0xFFFFu);
+        lo[j] = (unsigned short)(x >> 16);
+    }
+}
+
+// The 16 x 16 tile (I, J) of P_l ~= H H^T + H L^T + L H^T into the packed
+// upper triangle ob, given row I's operand values (ha, la).
+__device__ __forceinline__ void tile(const unsigned int* hl_l, float* ob, int I, int J, int row, int kg, int K,
+                                     int L2, int nj, const u16x8& ha, const u16x8& la)
+{
+    u16x8 hb, lb;
+    row_operands(hl_l, J * 16 + row, K, L2, nj, hb, lb);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, hb), acc,
+                                                  0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, lb), acc,
+                                                  0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, la), __builtin_bit_cast(bf16x8, hb), acc,
+                                                  0, 0, 0);
+    // lane holds D[4 kg + v][row] = P[k1][k2] with k1 = 16 I + 4 kg + v,
+    // k2 = 16 J + row; the packed index k1 K - k1 (k1 - 1) / 2 + k2 - k1
+    // grows by K - k1 - 1 from k1 to k1 + 1
+    const int k2 = J * 16 + row;
+    int k1 = I * 16 + 4 * kg;
+    int idx = k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        if (k1 <= k2 && k2 < K) ob[idx] = acc[v];
+        idx += K - k1 - 1;
+        ++k1;
+    }
+}
+
 template <int W>
 __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
 {
@@ -67,8 +113,7 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     if (i >= a.n_atoms) return;
     // {H, L} of every element of C: H in the low half, L in the high half;
     // then the packed P_l of the current l
-    // 16-byte aligned regions; the packed P_l region ends in four spare words
-    const int HLS = (KL2 + 32 + 3) & ~3, OBS = ((KK + 3) & ~3) + 4;
+    const int HLS = (KL2 + 32 + 3) & ~3, OBS = (KK + 3) & ~3;   // 16-byte aligned regions
     unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw) + size_t(slot) * (HLS + OBS);
     float* ob = reinterpret_cast<float*>(hl + HLS);
     const float* c_in = static_cast<const float*>(a.coeffs) + i * KL2;
@@ -99,65 +144,28 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     const int T = (K + 15) / 16;
     const int row = lane & 15, kg = lane >> 4;
     float* p_out = static_cast<float*>(a.p) + i * int64_t(lmax + 1) * KK;
-    const int spare = OBS - 4;   // a dump word past the packed P_l for outputs outside it
     for (int l = 0; l <= lmax; ++l) {
         const int w = 2 * l + 1;   // <= 25 for lmax <= 12: one 32-wide step per product
         const int nj = w - 8 * kg;  // this lane's operand values m = 8 kg + j with j < nj are inside the row
+        const unsigned int* hl_l = hl + l * l + kg * 8;
         float* dst = p_out + int64_t(l) * KK;
-        // tiles (I, J), I <= J, row-major over the upper triangle, dealt
-        // round-robin over the centre's waves; a lane's operand values of
-        // row I are read once per I.  Rows past K read row 0 (inside the
-        // region, which is padded by 32 words past C) and are zeroed.
-        int t = 0;
-        for (int I = 0; I < T; ++I) {
-            const int ka = I * 16 + row;
-            u16x8 ha, la;
-            {
-                const unsigned int* ra = hl + (ka < K ? ka : 0) * L2 + l * l + kg * 8;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    unsigned int x = ra[j];
-                    asm volatile("" : "+v"(x));   // read every word, then select: no branch around the load
-                    x = j < nj && ka < K ? x : 0u;
-                    ha[j] = (unsigned short)(x & 0xFFFFu);
-                    la[j] = (unsigned short)(x >> 16);
-                }
+        // tiles (I, J), I <= J, row-major over the upper triangle
+        if constexpr (W == 1) {
+            // one wave: row I's operand values are read once per I
+            for (int I = 0; I < T; ++I) {
+                u16x8 ha, la;
+                row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+                for (int J = I; J < T; ++J) tile(hl_l, ob, I, J, row, kg, K, L2, nj, ha, la);
             }
-            for (int J = I; J < T; ++J, ++t) {
-                if (W > 1 && t % W != wc) continue;
-                const int kb = J * 16 + row;
-                const unsigned int* rb = hl + (kb < K ? kb : 0) * L2 + l * l + kg * 8;
-                u16x8 hb, lb;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    unsigned int x = rb[j];
-                    asm volatile("" : "+v"(x));
-                    x = j < nj && kb < K ? x : 0u;
-                    hb[j] = (unsigned short)(x & 0xFFFFu);
-                    lb[j] = (unsigned short)(x >> 16);
-                }
-                // P ~= H H^T + H L^T + L H^T
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha),
-                                                              __builtin_bit_cast(bf16x8, hb), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha),
-                                                              __builtin_bit_cast(bf16x8, lb), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, la),
-                                                              __builtin_bit_cast(bf16x8, hb), acc, 0, 0, 0);
-                // lane holds D[4 kg + v][row] = P[k1][k2] with k1 = 16 I + 4 kg + v,
-                // k2 = 16 J + row; packed index of (k1, k2) is
-                // k1 K - k1 (k1 - 1) / 2 + k2 - k1, which grows by K - k1 - 1
-                // from k1 to k1 + 1.  Outputs below the diagonal or past K go
-                // to the dump word.
-                const int k2 = J * 16 + row;
-                int k1 = I * 16 + 4 * kg;
-                int idx = k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    ob[k2 < K && (I < J || k1 <= k2) ? idx : spare] = acc[v];
-                    idx += K - k1 - 1;
-                    ++k1;
-                }
+        } else {
+            // tiles dealt round-robin over the centre's waves
+            const int n_tiles = T * (T + 1) / 2;
+            for (int t = wc; t < n_tiles; t += W) {
+                int I = 0, rem = t;
+                while (rem >= T - I) { rem -= T - I; ++I; }
+                u16x8 ha, la;
+                row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+                tile(hl_l, ob, I, I + rem, row, kg, K, L2, nj, ha, la);
             }
         }
         {
@@ -175,12 +183,11 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     }
 }
 
-// LDS words of one centre's slot: {H, L} of C, then the packed P_l and a
-// dump word
+// LDS words of one centre's slot: {H, L} of C, then the packed P_l
 size_t bf16_slot_words(int S, int nmax, int lmax, int W)
 {
     const size_t K = size_t(S) * nmax, KL2 = K * (lmax + 1) * (lmax + 1), KK = K * (K + 1) / 2;
-    return ((KL2 + 32 + 3) & ~size_t(3)) + ((KK + 3) & ~size_t(3)) + 4;
+    return ((KL2 + 32 + 3) & ~size_t(3)) + ((KK + 3) & ~size_t(3));
 }
 
 // waves per centre: one when four centres' slots fit 40 KB of LDS
