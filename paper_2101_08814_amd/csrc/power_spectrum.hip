@@ -13,14 +13,14 @@
 // relative error of order 2^-16.
 //
 // W waves own one centre (W = 1, four centres per work-group, when C is
-// small; W = 4, one centre per work-group, otherwise): the centre's waves
-// split C into their LDS region as {H, L} pairs, then for each l run the
-// 16 x 16 output tiles (I <= J) as three v_mfma_f32_16x16x32_bf16 each (a
-// lane reads 8 consecutive {H, L} words of each of its two rows; one wave
-// walks the tiles row by row and reads row I's words once per I, four
-// waves deal the tiles round-robin), put the packed upper triangle in LDS
-// and store it as contiguous float4 rows (the accumulators alone give
-// 64-byte pieces).
+// small and K <= 48; W = 4, one centre per work-group, otherwise): the
+// centre's waves split C into their LDS region as {H, L} pairs, then for
+// each l run the 16 x 16 output tiles (I <= J) as three
+// v_mfma_f32_16x16x32_bf16 each (a lane reads 8 consecutive {H, L} words
+// of each of its two rows; one wave per centre reads every row block's
+// words into registers once per l, four waves deal the tiles round-robin),
+// put the packed upper triangle in LDS and store it as contiguous float4
+// rows (the accumulators alone give 64-byte pieces).
 // One wave per centre needs no work-group barrier; four take two per l.
 #include "soap_internal.hpp"
 
@@ -36,6 +36,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kLoadBatch = 16;   // coefficient loads a lane keeps in flight
+constexpr int kRows1 = 3;        // row blocks of 16 (K <= 48) a one-wave centre holds in registers
 
 // round to nearest even (finite inputs)
 __device__ __forceinline__ unsigned short to_bf16(float f)
@@ -71,12 +72,11 @@ __device__ __forceinline__ void row_operands(const unsigned int* hl_l, int k, in
 }
 
 // The 16 x 16 tile (I, J) of P_l ~= H H^T + H L^T + L H^T into the packed
-// upper triangle ob, given row I's operand values (ha, la).
-__device__ __forceinline__ void tile(const unsigned int* hl_l, float* ob, int I, int J, int row, int kg, int K,
-                                     int L2, int nj, const u16x8& ha, const u16x8& la)
+// upper triangle ob, given the operand values of rows I (ha, la) and J
+// (hb, lb).
+__device__ __forceinline__ void tile(float* ob, int I, int J, int row, int kg, int K, const u16x8& ha,
+                                     const u16x8& la, const u16x8& hb, const u16x8& lb)
 {
-    u16x8 hb, lb;
-    row_operands(hl_l, J * 16 + row, K, L2, nj, hb, lb);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ha), __builtin_bit_cast(bf16x8, hb), acc,
                                                   0, 0, 0);
@@ -151,21 +151,27 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
         float* dst = p_out + int64_t(l) * KK;
         // tiles (I, J), I <= J, row-major over the upper triangle
         if constexpr (W == 1) {
-            // one wave: row I's operand values are read once per I
-            for (int I = 0; I < T; ++I) {
-                u16x8 ha, la;
-                row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
-                for (int J = I; J < T; ++J) tile(hl_l, ob, I, J, row, kg, K, L2, nj, ha, la);
-            }
+            // one wave: the operand values of every row block read once
+            // (T <= kRows1), all reads issued before the first product
+            u16x8 rh[kRows1], rl[kRows1];
+#pragma unroll
+            for (int I = 0; I < kRows1; ++I)
+                if (I < T) row_operands(hl_l, I * 16 + row, K, L2, nj, rh[I], rl[I]);
+#pragma unroll
+            for (int I = 0; I < kRows1; ++I)
+#pragma unroll
+                for (int J = I; J < kRows1; ++J)
+                    if (J < T) tile(ob, I, J, row, kg, K, rh[I], rl[I], rh[J], rl[J]);
         } else {
             // tiles dealt round-robin over the centre's waves
             const int n_tiles = T * (T + 1) / 2;
             for (int t = wc; t < n_tiles; t += W) {
                 int I = 0, rem = t;
                 while (rem >= T - I) { rem -= T - I; ++I; }
-                u16x8 ha, la;
+                u16x8 ha, la, hb, lb;
                 row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
-                tile(hl_l, ob, I, I + rem, row, kg, K, L2, nj, ha, la);
+                row_operands(hl_l, (I + rem) * 16 + row, K, L2, nj, hb, lb);
+                tile(ob, I, I + rem, row, kg, K, ha, la, hb, lb);
             }
         }
         {
@@ -190,10 +196,11 @@ size_t bf16_slot_words(int S, int nmax, int lmax, int W)
     return ((KL2 + 32 + 3) & ~size_t(3)) + ((KK + 3) & ~size_t(3));
 }
 
-// waves per centre: one when four centres' slots fit 40 KB of LDS
+// waves per centre: one when four centres' slots fit 40 KB of LDS (and
+// K <= 16 kRows1)
 int bf16_waves_per_centre(int S, int nmax, int lmax)
 {
-    return 4 * 4 * bf16_slot_words(S, nmax, lmax, 1) <= 40 * 1024 ? 1 : 4;
+    return 4 * 4 * bf16_slot_words(S, nmax, lmax, 1) <= 40 * 1024 && S * nmax <= 16 * kRows1 ? 1 : 4;
 }
 
 }  // namespace
