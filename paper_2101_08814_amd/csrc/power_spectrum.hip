@@ -18,7 +18,8 @@
 // each l run the 16 x 16 output tiles (I <= J) as three
 // v_mfma_f32_16x16x32_bf16 each (a lane reads 8 consecutive {H, L} words
 // of each of its two rows; one wave per centre reads every row block's
-// words into registers once per l, four waves deal the tiles round-robin),
+// words into registers once per l, four waves take contiguous runs of
+// tiles in row-major order and read a row block once per row they touch),
 // put the packed upper triangle in LDS and store it as contiguous float4
 // rows (the accumulators alone give 64-byte pieces).
 // One wave per centre needs no work-group barrier; four take two per l.
@@ -163,15 +164,25 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
                 for (int J = I; J < kRows1; ++J)
                     if (J < T) tile(ob, I, J, row, kg, K, rh[I], rl[I], rh[J], rl[J]);
         } else {
-            // tiles dealt round-robin over the centre's waves
+            // each wave a contiguous run of tiles in row-major order, so
+            // that row I's operand values are read once per row it touches
             const int n_tiles = T * (T + 1) / 2;
-            for (int t = wc; t < n_tiles; t += W) {
-                int I = 0, rem = t;
-                while (rem >= T - I) { rem -= T - I; ++I; }
-                u16x8 ha, la, hb, lb;
-                row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
-                row_operands(hl_l, (I + rem) * 16 + row, K, L2, nj, hb, lb);
-                tile(ob, I, I + rem, row, kg, K, ha, la, hb, lb);
+            const int per = (n_tiles + W - 1) / W;
+            const int t0 = wc * per, t1 = t0 + per < n_tiles ? t0 + per : n_tiles;
+            int I = 0, rem = t0;
+            while (I < T && rem >= T - I) { rem -= T - I; ++I; }
+            int J = I + rem;
+            u16x8 ha, la;
+            if (t0 < t1) row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+            for (int t = t0; t < t1; ++t) {
+                u16x8 hb, lb;
+                row_operands(hl_l, J * 16 + row, K, L2, nj, hb, lb);
+                tile(ob, I, J, row, kg, K, ha, la, hb, lb);
+                if (++J == T && t + 1 < t1) {
+                    ++I;
+                    J = I;
+                    row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+                }
             }
         }
         {
