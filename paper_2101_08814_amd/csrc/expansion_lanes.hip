@@ -330,7 +330,7 @@ hipError_t launch_expansion_lanes(const FeatureArgs& a, bool f64, hipStream_t st
         if (e == hipSuccess) {
             FeatureArgs q = a;
             q.dcoeffs = q.dcoeffs_self = q.dp = q.dp_self = nullptr;
-            e = launch_power_spectrum_valu(q, f64, stream);
+            e = launch_power_spectrum(q, f64 ? SOAP_F64 : SOAP_F32, stream);
             if (e != hipErrorNotSupported) return e;
         } else if (e != hipErrorNotSupported) {
             return e;

@@ -1,5 +1,7 @@
 // Power spectrum on the matrix cores (gfx950 MFMA), bfloat16 operands with
-// float accumulation.
+// float accumulation, and the same kernel with FP32 operands
+// (v_mfma_f32_16x16x4_f32, four of the 2l+1 values per step) for the FP32
+// path of many centres.
 //
 // For a centre and a degree l the power spectrum is the Gram matrix
 //   P_l = C_l C_l^T,   C_l = [c_{k, l^2 .. l^2+2l}]  (K x (2l+1)),
@@ -38,6 +40,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kLoadBatch = 16;   // coefficient loads a lane keeps in flight
 constexpr int kRows1 = 3;        // row blocks of 16 (K <= 48) a one-wave centre holds in registers
+constexpr int kStepsF32 = 7;     // 4-wide MFMA steps of a row of 2l+1 <= 25 values (lmax <= 12)
+constexpr int64_t kF32MfmaAtoms = 8192;   // FP32 spectra of at least this many centres use the matrix cores
 
 // round to nearest even (finite inputs)
 __device__ __forceinline__ unsigned short to_bf16(float f)
@@ -99,8 +103,44 @@ __device__ __forceinline__ void tile(float* ob, int I, int J, int row, int kg, i
     }
 }
 
-template <int W>
-__global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
+// FP32 operands (v_mfma_f32_16x16x4_f32, one step per 4 of the 2l+1
+// values): lane (row, kg) supplies the values m = kg NS + s, s < NS =
+// ceil((2l+1) / 4), of row k of C_l (c_l points at m = 0 of row 0), so that
+// its NS reads are consecutive; A and B take the same order of m, which
+// leaves the product unchanged.  Zero past 2l+1 or K; rows past K read row
+// 0, and every read stays inside the region (padded by 32 words past C).
+__device__ __forceinline__ void row_operands_f32(const float* c_l, int k, int K, int L2, int w, int NS, int kg,
+                                                 float (&x)[kStepsF32])
+{
+    const float* r = c_l + (k < K ? k : 0) * L2 + kg * NS;
+#pragma unroll
+    for (int s = 0; s < kStepsF32; ++s) x[s] = s < NS && kg * NS + s < w && k < K ? r[s] : 0.f;
+}
+
+// The tile (I, J) of P_l = C_l C_l^T from FP32 operands, into the packed
+// upper triangle ob (the same output layout as the bfloat16 tile)
+__device__ __forceinline__ void tile_f32(float* ob, int I, int J, int row, int kg, int K, int NS,
+                                         const float (&xa)[kStepsF32], const float (&xb)[kStepsF32])
+{
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < kStepsF32; ++s)
+        if (s < NS) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s], xb[s], acc, 0, 0, 0);
+    const int k2 = J * 16 + row;
+    int k1 = I * 16 + 4 * kg;
+    int idx = k1 * K - k1 * (k1 - 1) / 2 + (k2 - k1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        if (k1 <= k2 && k2 < K) ob[idx] = acc[v];
+        idx += K - k1 - 1;
+        ++k1;
+    }
+}
+
+// One body for both operand forms: F32 keeps C in FP32 (the FP32 path),
+// otherwise the {H, L} bfloat16 split.
+template <int W, bool F32>
+__device__ __forceinline__ void spectrum_body(const FeatureArgs& a)
 {
     constexpr int CPG = kThreads / 64 / W;   // centres per work-group
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -130,8 +170,12 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
         for (int u = 0; u < kLoadBatch; ++u) {
             const int e = e0 + u * W * 64;
             if (e < KL2) {
-                const unsigned short h = to_bf16(v[u]);
-                hl[e] = (unsigned int)h | ((unsigned int)to_bf16(v[u] - from_bf16(h)) << 16);
+                if constexpr (F32) {
+                    hl[e] = __float_as_uint(v[u]);
+                } else {
+                    const unsigned short h = to_bf16(v[u]);
+                    hl[e] = (unsigned int)h | ((unsigned int)to_bf16(v[u] - from_bf16(h)) << 16);
+                }
             }
         }
     }
@@ -151,18 +195,32 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
         const unsigned int* hl_l = hl + l * l + kg * 8;
         float* dst = p_out + int64_t(l) * KK;
         // tiles (I, J), I <= J, row-major over the upper triangle
+        const int NS = (w + 3) / 4;   // FP32: 4-wide steps per product
+        const float* c_l = reinterpret_cast<const float*>(hl) + l * l;
         if constexpr (W == 1) {
             // one wave: the operand values of every row block read once
             // (T <= kRows1), all reads issued before the first product
-            u16x8 rh[kRows1], rl[kRows1];
+            if constexpr (F32) {
+                float rx[kRows1][kStepsF32];
 #pragma unroll
-            for (int I = 0; I < kRows1; ++I)
-                if (I < T) row_operands(hl_l, I * 16 + row, K, L2, nj, rh[I], rl[I]);
+                for (int I = 0; I < kRows1; ++I)
+                    if (I < T) row_operands_f32(c_l, I * 16 + row, K, L2, w, NS, kg, rx[I]);
 #pragma unroll
-            for (int I = 0; I < kRows1; ++I)
+                for (int I = 0; I < kRows1; ++I)
 #pragma unroll
-                for (int J = I; J < kRows1; ++J)
-                    if (J < T) tile(ob, I, J, row, kg, K, rh[I], rl[I], rh[J], rl[J]);
+                    for (int J = I; J < kRows1; ++J)
+                        if (J < T) tile_f32(ob, I, J, row, kg, K, NS, rx[I], rx[J]);
+            } else {
+                u16x8 rh[kRows1], rl[kRows1];
+#pragma unroll
+                for (int I = 0; I < kRows1; ++I)
+                    if (I < T) row_operands(hl_l, I * 16 + row, K, L2, nj, rh[I], rl[I]);
+#pragma unroll
+                for (int I = 0; I < kRows1; ++I)
+#pragma unroll
+                    for (int J = I; J < kRows1; ++J)
+                        if (J < T) tile(ob, I, J, row, kg, K, rh[I], rl[I], rh[J], rl[J]);
+            }
         } else {
             // each wave a contiguous run of tiles in row-major order, so
             // that row I's operand values are read once per row it touches
@@ -172,16 +230,31 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
             int I = 0, rem = t0;
             while (I < T && rem >= T - I) { rem -= T - I; ++I; }
             int J = I + rem;
-            u16x8 ha, la;
-            if (t0 < t1) row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
-            for (int t = t0; t < t1; ++t) {
-                u16x8 hb, lb;
-                row_operands(hl_l, J * 16 + row, K, L2, nj, hb, lb);
-                tile(ob, I, J, row, kg, K, ha, la, hb, lb);
-                if (++J == T && t + 1 < t1) {
-                    ++I;
-                    J = I;
-                    row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+            if constexpr (F32) {
+                float xa[kStepsF32];
+                if (t0 < t1) row_operands_f32(c_l, I * 16 + row, K, L2, w, NS, kg, xa);
+                for (int t = t0; t < t1; ++t) {
+                    float xb[kStepsF32];
+                    row_operands_f32(c_l, J * 16 + row, K, L2, w, NS, kg, xb);
+                    tile_f32(ob, I, J, row, kg, K, NS, xa, xb);
+                    if (++J == T && t + 1 < t1) {
+                        ++I;
+                        J = I;
+                        row_operands_f32(c_l, I * 16 + row, K, L2, w, NS, kg, xa);
+                    }
+                }
+            } else {
+                u16x8 ha, la;
+                if (t0 < t1) row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+                for (int t = t0; t < t1; ++t) {
+                    u16x8 hb, lb;
+                    row_operands(hl_l, J * 16 + row, K, L2, nj, hb, lb);
+                    tile(ob, I, J, row, kg, K, ha, la, hb, lb);
+                    if (++J == T && t + 1 < t1) {
+                        ++I;
+                        J = I;
+                        row_operands(hl_l, I * 16 + row, K, L2, nj, ha, la);
+                    }
                 }
             }
         }
@@ -200,7 +273,19 @@ __global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
     }
 }
 
-// LDS words of one centre's slot: {H, L} of C, then the packed P_l
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_power_spectrum_bf16(FeatureArgs a)
+{
+    spectrum_body<W, false>(a);
+}
+
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_power_spectrum_f32mfma(FeatureArgs a)
+{
+    spectrum_body<W, true>(a);
+}
+
+// LDS words of one centre's slot: {H, L} of C (or C), then the packed P_l
 size_t bf16_slot_words(int S, int nmax, int lmax, int W)
 {
     const size_t K = size_t(S) * nmax, KL2 = K * (lmax + 1) * (lmax + 1), KK = K * (K + 1) / 2;
@@ -222,28 +307,49 @@ size_t power_spectrum_bf16_lds(int S, int nmax, int lmax)
     return size_t(kThreads / 64 / W) * 4 * bf16_slot_words(S, nmax, lmax, W);
 }
 
-template <int W>
-hipError_t launch_bf16(const FeatureArgs& a, size_t lds, hipStream_t stream)
+template <int W, bool F32>
+hipError_t launch_mfma(const FeatureArgs& a, size_t lds, hipStream_t stream)
 {
+    const void* fn = F32 ? reinterpret_cast<const void*>(k_power_spectrum_f32mfma<W>)
+                         : reinterpret_cast<const void*>(k_power_spectrum_bf16<W>);
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_power_spectrum_bf16<W>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
     }
     constexpr int cpg = kThreads / 64 / W;
     const unsigned groups = unsigned((a.n_atoms + cpg - 1) / cpg);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_power_spectrum_bf16<W>), dim3(groups), dim3(kThreads), lds, stream, a);
+    if constexpr (F32)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_power_spectrum_f32mfma<W>), dim3(groups), dim3(kThreads), lds, stream, a);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_power_spectrum_bf16<W>), dim3(groups), dim3(kThreads), lds, stream, a);
     return hipGetLastError();
+}
+
+hipError_t launch_power_spectrum_f32mfma(const FeatureArgs& a, hipStream_t stream)
+{
+    const size_t lds = power_spectrum_bf16_lds(a.S, a.nmax, a.lmax);
+    if (lds > 160 * 1024 || a.lmax > 12) return hipErrorNotSupported;
+    if (a.n_atoms == 0) return hipSuccess;
+    return bf16_waves_per_centre(a.S, a.nmax, a.lmax) == 1 ? launch_mfma<1, true>(a, lds, stream)
+                                                             : launch_mfma<4, true>(a, lds, stream);
 }
 
 hipError_t launch_power_spectrum(const FeatureArgs& a, soap_precision prec, hipStream_t stream)
 {
+    // FP32 without gradient rows from kF32MfmaAtoms centres on: FP32
+    // operands on the matrix cores (28,924 centres at K = 32: 165 -> 124 us,
+    // 131k at K = 96: 9.0 -> 6.9 ms); below, the VALU kernel (4096 centres
+    // at K = 20: 20 us against 24)
+    if (prec == SOAP_F32 && a.dp == nullptr && a.n_atoms >= kF32MfmaAtoms) {
+        const hipError_t e = launch_power_spectrum_f32mfma(a, stream);
+        if (e != hipErrorNotSupported) return e;
+    }
     if (prec != SOAP_BF16_F32ACC) return launch_power_spectrum_valu(a, prec == SOAP_F64, stream);
     const size_t lds = power_spectrum_bf16_lds(a.S, a.nmax, a.lmax);
     if (lds > 160 * 1024) return hipErrorNotSupported;
     if (a.n_atoms == 0) return hipSuccess;
-    return bf16_waves_per_centre(a.S, a.nmax, a.lmax) == 1 ? launch_bf16<1>(a, lds, stream)
-                                                             : launch_bf16<4>(a, lds, stream);
+    return bf16_waves_per_centre(a.S, a.nmax, a.lmax) == 1 ? launch_mfma<1, false>(a, lds, stream)
+                                                             : launch_mfma<4, false>(a, lds, stream);
 }
 
 }  // namespace soap

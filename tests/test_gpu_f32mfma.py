@@ -1,0 +1,83 @@
+"""GPU parity of the FP32 power spectrum on the matrix cores
+(v_mfma_f32_16x16x4_f32, used for FP32 spectra of at least 8192 centres
+without gradient rows) against the FP64 oracle.
+
+Seeded N(0, 1) coefficients; shapes cover one wave per centre (K <= 48) and
+four (K > 48 or a large C), K not a multiple of 16, lmax 0 and 12, and the
+size threshold itself (8191 centres take the VALU kernel, 8192 the matrix
+cores).  The oracle checks a sample of centres (the first, the last and
+random ones; p of a centre depends on that centre's c alone); every centre
+is checked against a float64 product on the device and for non-negative
+diagonals.  Bound: FP32 p <= 1e-6 relative Frobenius error, per centre
+WORST_ROW_F32, as for the VALU kernel."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2101_08814_amd as P
+
+from test_gpu_parity import rel, worst_centre, WORST_ROW_F32
+
+pytestmark = pytest.mark.gpu
+
+
+def _hypers(S, nmax, lmax):
+    return dict(n_species=S, nmax=nmax, lmax=lmax, rcut=5.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+
+
+@pytest.mark.parametrize("S,nmax,lmax,N", [
+    (4, 8, 6, 9000),     # K = 32: one wave per centre
+    (1, 7, 0, 8192),     # K = 7, lmax 0, exactly at the threshold
+    (4, 13, 3, 8200),    # K = 52: four waves, ragged last row block
+    (8, 12, 8, 8192),    # K = 96: four waves, six row blocks
+    (2, 10, 12, 8192),   # lmax 12: seven 4-wide steps for l = 12
+    (3, 5, 4, 8191),     # below the threshold: the VALU kernel
+])
+def test_f32_spectrum_matches_oracle(S, nmax, lmax, N):
+    hyp = _hypers(S, nmax, lmax)
+    K, L2 = S * nmax, (lmax + 1) ** 2
+    calc = P.Calculator.from_hypers(hyp)
+    rng = np.random.default_rng(2024 + K + lmax)
+    c = rng.standard_normal((N, K, L2)).astype(np.float32)
+    cd = torch.tensor(c, device="cuda")
+    p = calc.power_spectrum(cd, torch.float32)
+    assert calc.device_status() == 0
+    assert p.shape == (N, lmax + 1, K * (K + 1) // 2)
+    idx = np.unique(np.concatenate([[0, 1, 2, N - 3, N - 2, N - 1], rng.integers(0, N, 26)]))
+    ref = oracle.power_spectrum(hyp, c[idx].astype(np.float64))
+    got = p[torch.tensor(idx, device="cuda")].double().cpu().numpy()
+    e, w = rel(got, ref), worst_centre(got, ref)
+    # every centre: a float64 product of the same FP32 coefficients
+    c64 = cd.double()
+    iu = torch.triu_indices(K, K, device="cuda")
+    err2 = ref2 = 0.0
+    for l in range(lmax + 1):
+        cl = c64[:, :, l * l:(l + 1) ** 2].contiguous()
+        pl = torch.bmm(cl, cl.transpose(1, 2).contiguous())[:, iu[0], iu[1]]
+        err2 += float(((p[:, l].double() - pl) ** 2).sum())
+        ref2 += float((pl ** 2).sum())
+    e_all = (err2 / ref2) ** 0.5
+    diag = torch.tensor([k * K - k * (k - 1) // 2 for k in range(K)], device="cuda")
+    print(f"[f32 spectrum S={S} nmax={nmax} lmax={lmax} N={N}] oracle sample rel={e:.3e} worst centre={w:.3e}, "
+          f"all centres vs float64 product rel={e_all:.3e}")
+    assert e <= 1e-6 and w <= WORST_ROW_F32
+    assert e_all <= 1e-6
+    assert bool((p[:, :, diag] >= 0).all())
+
+
+def test_f32_spectrum_of_features_from_8192_centres():
+    """soap_features without gradients from 8192 centres (c packed across
+    centres, then p from c): p as soap_power_spectrum gives it from the same
+    c, bit for bit."""
+    import synthetic
+    b = synthetic.molecule_batch()
+    calc = P.Calculator.from_hypers(b.hypers)
+    pos = torch.tensor(b.positions, dtype=torch.float64, device="cuda")
+    spc = torch.tensor(b.species, dtype=torch.int32, device="cuda")
+    nl = calc.compute_neighbors(pos, spc, b.atom_offsets, b.cells, b.pbc)
+    c, p = calc.features(nl, spc, torch.float32)
+    p2 = calc.power_spectrum(c, torch.float32)
+    assert calc.device_status() == 0
+    assert b.n_atoms >= 8192
+    assert torch.equal(p, p2)
