@@ -718,9 +718,10 @@ def main() -> int:
         runs = steps
     n_ph = len(runs)
 
-    for _ in range(args.warmup):
-        for f in runs:
-            f()
+    # the replayed (or launched) results against the eager ones, before the
+    # warm-up, so that the timed steps follow the warm-up directly
+    for f in runs:
+        f()
     torch.cuda.synchronize()
     for a, b in zip(out, ref):
         if not torch.equal(a, b):
@@ -730,10 +731,13 @@ def main() -> int:
     K = args.steps
     # ev[k][j] is recorded after phase j of step k (same stream as the kernels)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ph)] for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
     end_all = torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        for f in runs:
+            f()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     start_all.record()
     for k in range(K):
         for j, f in enumerate(runs):
