@@ -449,14 +449,16 @@ def measure_config(wl: str, steps: int, warmup: int):
                     state["virial"] = calc.virial(nl, state["gpair"], ao)
 
                 phases.append(("virial", ph_virial, ("k_virial_centres + k_virial_structures", "virial")))
-    for _ in range(max(3, warmup)):
-        for _, f, _ in phases:
-            f()
-    torch.cuda.synchronize()
-    calc.reset_status()
+    # events made and the status word cleared before the warm-up, so that
+    # the timed steps follow it directly
     K = steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(K)]
     t_all0, t_all1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    calc.reset_status()
+    for _ in range(max(3, warmup)):
+        for _, f, _ in phases:
+            f()
     torch.cuda.synchronize()
     t_all0.record()
     for k in range(K):
