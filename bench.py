@@ -37,26 +37,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+SPECTRUM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spectrum_bf16_molecules_counters.txt")
+SPECTRUM_SOURCES = ["power_spectrum.hip"]
+
+
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2101_08814_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_bytes_alg: float):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(n_launch_bytes_alg: float, path: str = TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.lstrip().startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(sources):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -505,6 +509,8 @@ def measure_config(wl: str, steps: int, warmup: int):
                 "frac": d["GB_s"] / HBM_PEAK_GBS, "traffic": None, "kernel_ms": d["ms"],
                 "algorithmic_bytes_per_launch": d["algorithmic_bytes"]}
     if wl == "molecules":
+        if d["kernel"].startswith("k_power_spectrum_bf16"):
+            roof["traffic"] = measured_traffic(d["algorithmic_bytes"], SPECTRUM_TRAFFIC_FILE, SPECTRUM_SOURCES)
         KK = (S * nmax) * (S * nmax + 1) // 2
         flops = 2.0 * N * KK * (lmax + 1) ** 2                 # packed p: K(K+1)/2 dot products of L2 terms
         tf = flops / (rows["spectrum_bf16_mfma"]["ms"] * 1e-3) / 1e12
