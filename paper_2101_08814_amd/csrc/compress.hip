@@ -818,10 +818,13 @@ __global__ void __launch_bounds__(kThreads, 2) k_cmp_fwd_bf16_r(CompressArgs a)
 }
 
 // One wave per centre, cpw centres per work-group sharing the weights of
-// the current l in LDS.  The centre's c goes to LDS once, read as float4
-// with consecutive lanes on consecutive addresses, as bfloat16 rows
-// X[lm][k].  Per l the columns of every product are the m of the centre
-// (one 16-wide tile, two when 2l + 1 > 16):
+// the current l in LDS.  The centre's c of degree l goes to the wave's LDS
+// as FP32 rows [k][2l+1], copied straight from global memory to LDS while
+// the previous l computes (after its layer 1 has read its own), and is
+// rounded to bfloat16 as the layer-1 operands are read; holding one l
+// rather than every lm lets twice as many centres share a work-group.  Per
+// l the columns of every product are the m of the centre (one 16-wide
+// tile, two when 2l + 1 > 16):
 //   layer 1  h = W1_l X_m, 16-row tiles of hidden units, 32-wide k-steps;
 //            h stays in registers for the whole l;
 //   gate     |h_q|^2 over m, summed across the 16 column lanes of a row
@@ -837,7 +840,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_cmp_fwd_bf16_r(CompressArgs a)
 // Two work-group barriers per l (the shared weights); none per m.
 constexpr int kWaveCentres = 8;   // most centres (waves) per work-group
 constexpr int kCB = 36;           // row stride of the c~ staging (floats, 16-byte rows)
-constexpr int kXLoads = 16;       // float4 loads of c a lane keeps in flight
 constexpr int kWQuads = 12;       // weight float4s a lane stages per l from kept offsets
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -876,7 +878,7 @@ __host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax,
 {
     WaveLayout W;
     W.Kp = (K + 31) / 32 * 32;
-    W.XS = W.Kp + 8;   // row stride (bf16) of X and W1: 16 consecutive rows hit distinct banks
+    W.XS = W.Kp + 8;   // row stride (bf16) of W1: 16 consecutive rows hit distinct banks
     W.Hp = (H + 31) / 32 * 32;
     W.HS = W.Hp + 8;
     W.HT = W.Hp / 16;
@@ -888,7 +890,8 @@ __host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax,
     W.E2 = W.QT * 16 * (W.Hp / 4);
     W.E = W.E1 + W.E2 + W.Hp / 2;
     const int L2 = (lmax + 1) * (lmax + 1);
-    W.x_bytes = up16(L2 * W.XS * 2);
+    // c of one l in FP32, [k][2l+1] rows, whole 64-element pieces
+    W.x_bytes = up16(((K * (2 * lmax + 1) + 63) / 64) * 64 * 4);
     W.cb_bytes = up16(W.QT * 16 * kCB * 4);
     int o = 0;
     W.w1 = o; o += up16(W.HT * 16 * W.XS * 2);
@@ -902,12 +905,6 @@ __host__ __device__ inline WaveLayout wave_layout(int K, int Q, int H, int lmax,
     W.total = o;
     return W;
 }
-
-// column of element (lm, k) in the LDS rows of X: 8-element groups swapped
-// within their 32-wide k-step by bits 4-5 of lm, so the stores of a wave
-// (consecutive lanes 4 lm apart) spread over the banks while the 16 rows of
-// an operand read keep one swizzle
-__device__ __forceinline__ int xcol(int lm, int k) { return k ^ (((lm >> 4) & 3) << 3); }
 
 // hidden unit held by LDS row `row` of the staged W1
 __device__ __forceinline__ int wave_unit(int row)
@@ -968,6 +965,19 @@ __global__ void __launch_bounds__(256) k_cmp_image(CompressArgs a, WaveLayout W)
 }
 
 
+// the layer-1 operand of column m: X[k0 + j][m], j < 8, as bfloat16 (zero
+// for k >= K), from the FP32 rows [k][w] of one l
+__device__ __forceinline__ u16x8 x_operand(const float* Xf, int w, int m, int k0, int K)
+{
+    float x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = k0 + j < K ? Xf[(k0 + j) * w + m] : 0.0f;
+    u32x4 p;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) p[j] = pack_bf16(x[2 * j], x[2 * j + 1]);
+    return __builtin_bit_cast(u16x8, p);
+}
+
 template <bool WANT_CT, bool WANT_PT, int QT, bool IMG>
 __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs a, WaveLayout W)
 {
@@ -980,7 +990,7 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
     const unsigned short* W1s = reinterpret_cast<const unsigned short*>(smem_raw + W.w1);
     const unsigned short* W2s = reinterpret_cast<const unsigned short*>(smem_raw + W.w2);
     const float* ab = reinterpret_cast<const float*>(smem_raw + W.ab);   // (buffer l % 2 with the image)
-    unsigned short* X = reinterpret_cast<unsigned short*>(smem_raw + W.x + wave * W.x_bytes);
+    float* Xf = reinterpret_cast<float*>(smem_raw + W.x + wave * W.x_bytes);
     float* cb = reinterpret_cast<float*>(smem_raw + W.cb + wave * W.cb_bytes);
     const int lsize = H * K + Q * H + 2 * H;
 
@@ -1009,42 +1019,22 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
     };
     if constexpr (IMG) fetch_image(0);
 
-    // X[lm][k] of this centre, bfloat16 (zero for k in [K, Kp))
-    if (live) {
-        const float4* src = reinterpret_cast<const float4*>(a.c + i * int64_t(K) * L2);
-        const int n4 = K * L2 / 4;
-        const int dk = 256 / L2, dlm = 256 - dk * L2;   // element-index advance per step of 64 float4s
-        int k = (4 * lane) / L2, lm = 4 * lane - k * L2;
-        for (int e0 = lane; e0 < n4; e0 += 64 * kXLoads) {
-            float4 v[kXLoads];
-#pragma unroll
-            for (int u = 0; u < kXLoads; ++u) {
-                const int e = e0 + 64 * u;
-                v[u] = src[e < n4 ? e : n4 - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < kXLoads; ++u) {
-                if (e0 + 64 * u < n4) {
-                    const unsigned int p01 = pack_bf16(v[u].x, v[u].y), p23 = pack_bf16(v[u].z, v[u].w);
-                    const unsigned short hv[4] = {(unsigned short)p01, (unsigned short)(p01 >> 16),
-                                                  (unsigned short)p23, (unsigned short)(p23 >> 16)};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        int kj = k, lj = lm + j;
-                        if (lj >= L2) { lj -= L2; ++kj; }
-                        X[lj * W.XS + xcol(lj, kj)] = hv[j];
-                    }
-                }
-                k += dk;
-                lm += dlm;
-                if (lm >= L2) { lm -= L2; ++k; }
-            }
+    // c of degree l of this centre into the wave's X, FP32 rows [k][2l+1],
+    // straight from global memory to LDS (64 elements per instruction; the
+    // lanes past the end of the last piece read the first element and write
+    // the piece's tail, which nothing reads), issued one l ahead
+    const float* cc = a.c + (live ? i : 0) * int64_t(K) * L2;
+    auto fetch_x = [&](int l) __attribute__((always_inline)) {
+        const int w = 2 * l + 1, n = K * w;
+        const float inv = 1.0f / float(w);
+        for (int e0 = 0; e0 < n; e0 += 64) {
+            const int e = e0 + lane < n ? e0 + lane : 0;
+            const int k = int((float(e) + 0.5f) * inv), m = e - k * w;
+            __builtin_amdgcn_global_load_lds(cc + k * L2 + l * l + m,
+                                             (__attribute__((address_space(3))) void*)(Xf + e0), 4, 0, 0);
         }
-        for (int e = lane; e < L2 * (W.Kp - K); e += 64) {
-            const int lr = e / (W.Kp - K);
-            X[lr * W.XS + xcol(lr, K + (e - lr * (W.Kp - K)))] = 0;
-        }
-    }
+    };
+    if (live) fetch_x(0);
 
     const float* wl = a.w;
     for (int l = 0; l <= lmax; ++l, wl += lsize) {
@@ -1060,6 +1050,7 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
             W2s = reinterpret_cast<const unsigned short*>(wb + W.w2);
             ab = reinterpret_cast<const float*>(wb + W.ab);
         } else {
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's X of l
             float4 wv[kWQuads];
 #pragma unroll
             for (int u = 0; u < kWQuads; ++u)   // every load issued before any is used
@@ -1089,9 +1080,8 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
         for (int kk = 0; kk < 4; ++kk) {
             if (kk < W.KS) {
                 u16x8 B0 = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, B1 = B0;
-                if (r < M) B0 = *reinterpret_cast<const u16x8*>(&X[(b + r) * W.XS + xcol(b + r, 32 * kk + 8 * g)]);
-                if (16 + r < M)
-                    B1 = *reinterpret_cast<const u16x8*>(&X[(b + 16 + r) * W.XS + xcol(b + 16 + r, 32 * kk + 8 * g)]);
+                if (r < M) B0 = x_operand(Xf, M, r, 32 * kk + 8 * g, K);
+                if (16 + r < M) B1 = x_operand(Xf, M, 16 + r, 32 * kk + 8 * g, K);
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     if (t < W.HT) {
@@ -1105,6 +1095,8 @@ __global__ void __launch_bounds__(kWaveCentres * 64) k_cmp_fwd_wave(CompressArgs
                 }
             }
         }
+        wave_sync();   // every read of X of l is done
+        if (l < lmax) fetch_x(l + 1);
         // gate factor 2 sigma(alpha |h| + beta) of unit q (row 4g + v of
         // tile t), |h_q|^2 summed over the m columns (zero where not
         // computed); h is scaled in place
