@@ -90,6 +90,33 @@ def test_forward_bf16_mfma(cells, n_centres, Q, H):
     assert torch.equal(ct_only, ct) and torch.equal(pt_only, pt)
 
 
+@pytest.mark.parametrize("S,nmax,lmax,Q,H,n", [(2, 10, 6, 16, 128, 133), (3, 12, 12, 32, 64, 70),
+                                                (1, 8, 1, 8, 32, 257)])
+def test_forward_bf16_other_shapes(S, nmax, lmax, Q, H, n):
+    """The one-wave-per-centre bfloat16 forward away from the workload's
+    shape: K = 20 (rows past K padded to the 32-wide k-step), K = 36 at
+    lmax 12 (two m tiles for 2l+1 > 16, seven-wide rows of c per l) and
+    K = 8 at lmax 1; seeded N(0, 1) coefficients, the same bounds as the
+    workload's shape, and the workspace form bit for bit the plain one."""
+    hyp = dict(n_species=S, nmax=nmax, lmax=lmax, rcut=5.0, sigma=0.5, cutoff_width=0.5, include_center=1)
+    calc = P.Calculator.from_hypers(hyp)
+    K, L2 = S * nmax, (lmax + 1) ** 2
+    c32 = np.random.default_rng(600 + K + lmax).standard_normal((n, K * L2)).astype(np.float32)
+    cd = torch.tensor(c32.reshape(n, S, nmax, L2), device="cuda")
+    cmp_ = P.Compressor(calc, Q, H)
+    w = random_weights(7, K, Q, H, lmax)
+    cmp_.weights.copy_(torch.tensor(w))
+    ct, pt = cmp_.forward(cd, precision="bf16", want_coeffs=True)
+    ct_b, pt_b = cmp_.forward_plain(cd, precision="bf16", want_coeffs=True)
+    assert calc.device_status() == 0
+    ref_ct = C.compress(c32.reshape(n, K, L2).astype(np.float64), w.astype(np.float64), Q, H)
+    ref_pt = C.power_spectrum(ref_ct)
+    e1, e2 = rel(ct, ref_ct), rel(pt, ref_pt)
+    print(f"[compress bf16 K={K} lmax={lmax} Q={Q} H={H} n={n}] c~ {e1:.2e}  p~ {e2:.2e}")
+    assert e1 <= BF16_CT and e2 <= BF16_PT
+    assert torch.equal(ct, ct_b) and torch.equal(pt, pt_b)
+
+
 def test_identity_network_on_gpu():
     """K = 8 channels, W1 = W2 = I, gate off: p~ is the plain spectrum."""
     b = synthetic.clusters_2species().subset([0])
