@@ -32,6 +32,7 @@ def _hypers(S, nmax, lmax):
     (4, 12, 2, 777),     # K = 48: three full row blocks in registers
     (7, 7, 2, 1030),     # K = 49: four waves per centre
     (4, 13, 3, 333),     # K = 52: four waves, ragged last row block
+    (8, 16, 8, 600),     # K = 128: more than 64 KB of LDS per work-group
 ])
 def test_bf16_spectrum_shapes_match_oracle(S, nmax, lmax, N):
     hyp = _hypers(S, nmax, lmax)

@@ -33,6 +33,7 @@ def _hypers(S, nmax, lmax):
     (8, 12, 8, 8192),    # K = 96: four waves, six row blocks
     (2, 10, 12, 8192),   # lmax 12: seven 4-wide steps for l = 12
     (3, 5, 4, 8191),     # below the threshold: the VALU kernel
+    (8, 16, 8, 8192),    # K = 128: more than 64 KB of LDS per work-group
 ])
 def test_f32_spectrum_matches_oracle(S, nmax, lmax, N):
     hyp = _hypers(S, nmax, lmax)
